@@ -1,0 +1,255 @@
+"""The agent of the paper's appendix "Agent Design", in float64.
+
+  visual encoder  2x2 average pool, then either the tiny two-conv trunk or
+                  the ResNet50 bottleneck layout with every width halved and
+                  every BatchNorm replaced by GroupNorm (Sec. 4 "Agent";
+                  appendix "Visual Encoder"), then a 3x3 compression conv to
+                  a 128 x h x w map
+  policy          flatten, FC to the hidden size (+ReLU), concatenated with
+                  the goal encoding ([d, cos(theta), sin(theta)] -> FC-32)
+                  and a 32-d embedding of the previous action (index 0 is the
+                  start token), a stacked LSTM, and one FC giving the softmax
+                  logits and the value (appendix "Navigation Policy")
+Readings where the paper is silent (each listed in the design notes):
+stem 7x7/2 + GroupNorm + ReLU + 3x3/2 max pool; stride on the bottleneck's
+3x3; projection shortcut (1x1/s conv + GroupNorm) on the first block of a
+stage; convolutions without bias; 16 groups; compression conv followed by
+GroupNorm and ReLU; ReLU after the visual FC; the episode mask m_t
+multiplies h and c of every layer and selects the start token.
+
+Parity pins: forward against torch CPU float64 library modules, backward
+against torch autograd and central finite differences (tests/test_oracle_policy.py).
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from . import nn
+
+
+# ------------------------------------------------------------------ encoder
+def prep_obs(net, obs):
+    x = np.asarray(obs, dtype=np.float64)
+    return nn.avg_pool2(x) if net.avgpool else x
+
+
+def _conv_gn(P, net, name, x, s, p, relu, tape):
+    u = nn.conv2d(x, P[name], s, p)
+    y, gc = nn.group_norm(u, P[name + ".gn.g"], P[name + ".gn.b"], net.gn_groups)
+    if relu:
+        y = nn.relu(y)
+    if tape is not None:
+        tape[name] = (x, s, p, gc, y if relu else None)
+    return y
+
+
+def _conv_gn_bwd(P, name, dy, tape, grads, need_dx=True):
+    x, s, p, gc, a = tape[name]
+    if a is not None:
+        dy = dy * (a > 0)
+    du, dg, db = nn.group_norm_backward(gc, P[name + ".gn.g"], dy)
+    dx, dw = nn.conv2d_backward(x, P[name], s, p, du, need_dx)
+    grads[name] = grads.get(name, 0) + dw
+    grads[name + ".gn.g"] = grads.get(name + ".gn.g", 0) + dg
+    grads[name + ".gn.b"] = grads.get(name + ".gn.b", 0) + db
+    return dx
+
+
+def _blocks(net):
+    """(prefix, stride, has_projection) of every bottleneck in order."""
+    out = []
+    for s in range(4):
+        for j in range(net.blocks[s]):
+            out.append(("s%d.b%d." % (s, j), 2 if (j == 0 and s > 0) else 1, j == 0))
+    return out
+
+
+def encoder_forward(P, net, x, tape=None):
+    """x: [F, C, h, w] after the optional pooling -> features [F, flat_dim]
+    in channel, row, column order."""
+    if net.trunk == "tiny":
+        a = _conv_gn(P, net, "conv1", x, 2, 1, True, tape)
+        a = _conv_gn(P, net, "conv2", a, 2, 1, True, tape)
+        return a.reshape(a.shape[0], -1)
+    a = _conv_gn(P, net, "stem", x, 2, 3, True, tape)
+    a, mc = nn.max_pool3s2(a)
+    if tape is not None:
+        tape["maxpool"] = mc
+    for pre, st, proj in _blocks(net):
+        y = _conv_gn(P, net, pre + "c1", a, 1, 0, True, tape)
+        y = _conv_gn(P, net, pre + "c2", y, st, 1, True, tape)
+        y = _conv_gn(P, net, pre + "c3", y, 1, 0, False, tape)
+        sc = _conv_gn(P, net, pre + "ds", a, st, 0, False, tape) if proj else a
+        a = nn.relu(y + sc)
+        if tape is not None:
+            tape[pre + "out"] = a
+    a = _conv_gn(P, net, "compress", a, 1, 1, True, tape)
+    return a.reshape(a.shape[0], -1)
+
+
+def encoder_backward(P, net, tape, dfeat, grads):
+    """Accumulate parameter gradients for one recorded encoder forward."""
+    if net.trunk == "tiny":
+        c2 = net.tiny_ch[1]
+        hw = net.feat_hw
+        d = dfeat.reshape(-1, c2, hw, hw)
+        d = _conv_gn_bwd(P, "conv2", d, tape, grads)
+        _conv_gn_bwd(P, "conv1", d, tape, grads, need_dx=False)
+        return
+    hw = net.feat_hw
+    d = dfeat.reshape(-1, net.compress_ch, hw, hw)
+    d = _conv_gn_bwd(P, "compress", d, tape, grads)
+    for pre, st, proj in reversed(_blocks(net)):
+        d = d * (tape[pre + "out"] > 0)
+        dy = _conv_gn_bwd(P, pre + "c3", d, tape, grads)
+        dy = _conv_gn_bwd(P, pre + "c2", dy, tape, grads)
+        dx = _conv_gn_bwd(P, pre + "c1", dy, tape, grads)
+        dx = dx + (_conv_gn_bwd(P, pre + "ds", d, tape, grads) if proj else d)
+        d = dx
+    d = nn.max_pool3s2_backward(tape["maxpool"], d)
+    _conv_gn_bwd(P, "stem", d, tape, grads, need_dx=False)
+
+
+def encode(P, net, obs, chunk=64):
+    """Features of many frames, processed in chunks of frames to bound the
+    im2col memory (frames are independent)."""
+    F = obs.shape[0]
+    out = np.zeros((F, net.flat_dim))
+    for s in range(0, F, chunk):
+        out[s:s + chunk] = encoder_forward(P, net, prep_obs(net, obs[s:s + chunk]))
+    return out
+
+
+def encode_backward(P, net, obs, dfeat, grads, chunk=64):
+    """Recompute each chunk's forward with a tape, then run its backward;
+    the chunk gradients are summed."""
+    F = obs.shape[0]
+    for s in range(0, F, chunk):
+        tape = {}
+        encoder_forward(P, net, prep_obs(net, obs[s:s + chunk]), tape)
+        encoder_backward(P, net, tape, dfeat[s:s + chunk], grads)
+
+
+# ------------------------------------------------------------- policy core
+def polar(goal):
+    """[d, theta] -> [d, cos(theta), sin(theta)]."""
+    d, th = goal[..., 0], goal[..., 1]
+    return np.stack([d, np.cos(th), np.sin(th)], axis=-1)
+
+
+def core_forward(P, net, feat, goal, prev_a, masks, h0, c0, keep=False):
+    """Run the policy over a sequence.
+
+    feat [T,B,flat], goal [T,B,2], prev_a [T,B] (action taken at t-1),
+    masks [T,B] (0 at an episode start), h0/c0 [L,B,H].
+    Returns logits [T,B,A], values [T,B], final (h, c), and a tape."""
+    T, B = feat.shape[:2]
+    L, A = net.lstm_layers, net.num_actions
+    h = [np.asarray(h0[l], np.float64).copy() for l in range(L)]
+    c = [np.asarray(c0[l], np.float64).copy() for l in range(L)]
+    logits = np.zeros((T, B, A))
+    values = np.zeros((T, B))
+    tape = [] if keep else None
+    for t in range(T):
+        m = np.asarray(masks[t], np.float64)[:, None]
+        vis = nn.relu(nn.linear(feat[t], P["fc.w"], P["fc.b"]))
+        parts = [vis]
+        g3 = None
+        if net.goal_mode == "polar":
+            g3 = polar(np.asarray(goal[t], np.float64))
+            parts.append(nn.linear(g3, P["goal.w"], P["goal.b"]))
+        else:
+            parts.append(np.asarray(goal[t], np.float64))
+        idx = None
+        if net.prev_act_dim:
+            idx = np.where(masks[t] == 0, 0, np.asarray(prev_a[t]) + 1)
+            parts.append(P["emb"][idx])
+        x = np.concatenate(parts, axis=1)
+        cells = []
+        for l in range(L):
+            h[l], c[l], cc = nn.lstm_cell(x, m * h[l], m * c[l],
+                                          P["lstm%d.w" % l], P["lstm%d.b" % l])
+            cells.append(cc)
+            x = h[l]
+        out = nn.linear(x, P["head.w"], P["head.b"])
+        logits[t] = out[:, :A]
+        values[t] = out[:, A]
+        if keep:
+            tape.append((feat[t], vis, g3, idx, m, cells, x))
+    return logits, values, (np.stack(h), np.stack(c)), tape
+
+
+def core_backward(P, net, tape, dlogits, dvalues, grads):
+    """BPTT through the policy core; accumulates parameter gradients and
+    returns d(feat) [T,B,flat]."""
+    T = len(tape)
+    L, A = net.lstm_layers, net.num_actions
+    B = dlogits.shape[1]
+    H = net.hidden
+    dh = [np.zeros((B, H)) for _ in range(L)]
+    dc = [np.zeros((B, H)) for _ in range(L)]
+    dfeat = np.zeros((T, B, net.flat_dim))
+    g = {k: 0 for k in ("fc.w", "fc.b", "goal.w", "goal.b", "emb", "head.w", "head.b")}
+    for l in range(L):
+        g["lstm%d.w" % l] = 0
+        g["lstm%d.b" % l] = 0
+    emb_grad = np.zeros((A + 1, net.prev_act_dim)) if net.prev_act_dim else None
+    for t in reversed(range(T)):
+        f_t, vis, g3, idx, m, cells, top = tape[t]
+        dout = np.concatenate([dlogits[t], dvalues[t][:, None]], axis=1)
+        dtop, dwh, dbh = nn.linear_backward(top, P["head.w"], dout)
+        g["head.w"] = g["head.w"] + dwh
+        g["head.b"] = g["head.b"] + dbh
+        dx = dtop
+        for l in reversed(range(L)):
+            dxl, dhp, dcp, dw, db = nn.lstm_cell_backward(
+                cells[l], P["lstm%d.w" % l], dh[l] + dx, dc[l])
+            g["lstm%d.w" % l] = g["lstm%d.w" % l] + dw
+            g["lstm%d.b" % l] = g["lstm%d.b" % l] + db
+            dh[l] = m * dhp
+            dc[l] = m * dcp
+            dx = dxl
+        nv = net.vis_hidden
+        dvis = dx[:, :nv] * (vis > 0)
+        dft, dwf, dbf = nn.linear_backward(f_t, P["fc.w"], dvis)
+        dfeat[t] = dft
+        g["fc.w"] = g["fc.w"] + dwf
+        g["fc.b"] = g["fc.b"] + dbf
+        if net.goal_mode == "polar":
+            dgf = dx[:, nv:nv + net.goal_dim]
+            _, dwg, dbg = nn.linear_backward(g3, P["goal.w"], dgf)
+            g["goal.w"] = g["goal.w"] + dwg
+            g["goal.b"] = g["goal.b"] + dbg
+        if net.prev_act_dim:
+            de = dx[:, nv + net.goal_dim:]
+            np.add.at(emb_grad, idx, de)
+    if emb_grad is not None:
+        g["emb"] = emb_grad
+    for k, v in g.items():
+        if not isinstance(v, int):
+            grads[k] = grads.get(k, 0) + v
+    return dfeat
+
+
+# ------------------------------------------------------------------ act step
+def sample(logp, u):
+    """Inverse CDF: the smallest k with sum_{j<=k} p_j > u; the last action
+    if rounding leaves none."""
+    cdf = np.cumsum(np.exp(logp), axis=-1)
+    A = logp.shape[-1]
+    hit = cdf > np.asarray(u, np.float64)[..., None]
+    a = np.where(hit.any(axis=-1), hit.argmax(axis=-1), A - 1)
+    return a.astype(np.int32)
+
+
+def act(P, net, obs, goal, prev_a, mask, h, c, u):
+    """One batched act step for B envs: returns action, logp(action), value,
+    logits, h', c'."""
+    feat = encoder_forward(P, net, prep_obs(net, obs))
+    logits, values, (h2, c2), _ = core_forward(
+        P, net, feat[None], np.asarray(goal)[None], np.asarray(prev_a)[None],
+        np.asarray(mask)[None], h, c)
+    lp = nn.log_softmax(logits[0])
+    a = sample(lp, u)
+    return {"action": a, "logp": lp[np.arange(len(a)), a], "value": values[0],
+            "logits": logits[0], "h": h2, "c": c2}

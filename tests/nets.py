@@ -1,0 +1,23 @@
+"""Small network variants used by the gradient and parity tests; together
+they reach every branch of the agent (tiny trunk, bottleneck trunk with
+projection and identity shortcuts, max pool, goal FC, previous-action
+embedding, stacked LSTM)."""
+from synth.configs import NetDesc, PPOCfg, Workload, TINY_NET
+
+TINY_PLUS = NetDesc(in_hw=32, avgpool=False, trunk="tiny", gn_groups=8, vis_hidden=16,
+                    goal_mode="polar", goal_dim=8, prev_act_dim=8, lstm_layers=2, hidden=16)
+
+MINI_RESNET = NetDesc(in_hw=64, avgpool=True, trunk="resnet", base_width=4, blocks=(1, 2, 1, 1),
+                      gn_groups=2, compress_ch=8, vis_hidden=16, goal_mode="polar", goal_dim=8,
+                      prev_act_dim=8, lstm_layers=2, hidden=16)
+
+# a bottleneck trunk with the real widths but a 64x64 frame (feature map 1x1)
+RESNET_64 = NetDesc(in_hw=64)
+
+
+def wl(net, T=4, N=3, dtype="f32", ragged=False, **ppo):
+    return Workload("test", net, T=T, N=N, dtype=dtype, ragged=ragged,
+                    ppo=PPOCfg(**ppo) if ppo else PPOCfg())
+
+
+__all__ = ["TINY_NET", "TINY_PLUS", "MINI_RESNET", "RESNET_64", "wl"]

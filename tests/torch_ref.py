@@ -1,0 +1,119 @@
+"""An independent float64 PyTorch (CPU) model of the agent, built from
+torch library modules, used only to pin the oracle.
+
+It reads the flat parameter format through synth.layout (a reader separate
+from the oracle's), runs conv2d / group_norm / max_pool2d / avg_pool2d /
+LSTMCell / log_softmax from torch, and gets gradients from autograd.
+"""
+from __future__ import annotations
+
+import numpy as np
+import torch
+import torch.nn.functional as F
+
+from synth.layout import tensor_list
+
+GN_EPS = 1e-5
+
+
+def unpack(net, flat, requires_grad=True):
+    flat_t = torch.tensor(np.asarray(flat, np.float64), requires_grad=requires_grad)
+    P = {}
+    for t in tensor_list(net):
+        n = int(np.prod(t.shape))
+        a = flat_t[t.offset:t.offset + n].view(t.shape)
+        if t.kind == "conv":
+            a = a.permute(0, 3, 1, 2)       # O,KH,KW,I -> O,I,KH,KW
+        P[t.name] = a
+    return flat_t, P
+
+
+def _cgn(P, net, x, conv, gn, s, p, relu):
+    y = F.conv2d(x, P[conv], stride=s, padding=p)
+    y = F.group_norm(y, net.gn_groups, P[gn + ".g"], P[gn + ".b"], eps=GN_EPS)
+    return F.relu(y) if relu else y
+
+
+def encoder(P, net, obs):
+    x = obs
+    if net.avgpool:
+        x = F.avg_pool2d(x, 2)
+    if net.trunk == "tiny":
+        x = _cgn(P, net, x, "enc.conv1", "enc.gn1", 2, 1, True)
+        x = _cgn(P, net, x, "enc.conv2", "enc.gn2", 2, 1, True)
+        return x.flatten(1)
+    x = _cgn(P, net, x, "enc.stem", "enc.stem.gn", 2, 3, True)
+    x = F.max_pool2d(x, 3, 2, 1)
+    for s, nb in enumerate(net.blocks):
+        for j in range(nb):
+            p = f"enc.s{s}.b{j}"
+            st = 2 if (j == 0 and s > 0) else 1
+            y = _cgn(P, net, x, p + ".c1", p + ".gn1", 1, 0, True)
+            y = _cgn(P, net, y, p + ".c2", p + ".gn2", st, 1, True)
+            y = _cgn(P, net, y, p + ".c3", p + ".gn3", 1, 0, False)
+            sc = _cgn(P, net, x, p + ".ds", p + ".ds.gn", st, 0, False) if j == 0 else x
+            x = F.relu(y + sc)
+    x = _cgn(P, net, x, "enc.compress", "enc.compress.gn", 1, 1, True)
+    return x.flatten(1)
+
+
+def policy_seq(P, net, obs, goal, prev_a, masks, h0, c0):
+    """obs [T,B,C,H,W] -> logits [T,B,A], values [T,B]."""
+    T, B = obs.shape[:2]
+    feat = encoder(P, net, obs.reshape(T * B, *obs.shape[2:])).reshape(T, B, -1)
+    H = net.hidden
+    cells = []
+    for l in range(net.lstm_layers):
+        w = P[f"lstm{l}.w"]
+        din = w.shape[1] - H
+        cells.append((w[:, :din], w[:, din:], P[f"lstm{l}.b"]))
+    h = [h0[l] for l in range(net.lstm_layers)]
+    c = [c0[l] for l in range(net.lstm_layers)]
+    logits, values = [], []
+    for t in range(T):
+        m = masks[t][:, None]
+        v = F.relu(F.linear(feat[t], P["fc.w"], P["fc.b"]))
+        parts = [v]
+        if net.goal_mode == "polar":
+            d, th = goal[t][:, 0], goal[t][:, 1]
+            g3 = torch.stack([d, torch.cos(th), torch.sin(th)], 1)
+            parts.append(F.linear(g3, P["goal.w"], P["goal.b"]))
+        else:
+            parts.append(goal[t])
+        if net.prev_act_dim:
+            idx = torch.where(masks[t] == 0, torch.zeros_like(prev_a[t]), prev_a[t] + 1)
+            parts.append(P["emb"][idx])
+        x = torch.cat(parts, 1)
+        for l, (wih, whh, b) in enumerate(cells):
+            # torch's fused LSTM cell (gate order i, f, g, o)
+            h[l], c[l] = torch._VF.lstm_cell(x, (m * h[l], m * c[l]), wih, whh, b,
+                                             torch.zeros_like(b))
+            x = h[l]
+        o = F.linear(x, P["head.w"], P["head.b"])
+        logits.append(o[:, :net.num_actions])
+        values.append(o[:, net.num_actions])
+    return torch.stack(logits), torch.stack(values)
+
+
+def ppo_loss(net, ppo, flat, mb):
+    """Loss of one minibatch dict (as made by oracle.ppo.minibatch_inputs),
+    its gradient by autograd, and the logits/values."""
+    flat_t, P = unpack(net, flat)
+    tt = lambda a, dt=torch.float64: torch.tensor(np.asarray(a), dtype=dt)
+    lens = tt(mb["lens"])
+    TB, B = mb["action"].shape
+    valid = (torch.arange(TB, dtype=torch.float64)[:, None] < lens[None, :]).double()
+    w = valid / (B * lens[None, :])
+    logits, values = policy_seq(P, net, tt(mb["obs"]), tt(mb["goal"]),
+                                tt(mb["prev_action"], torch.int64), tt(mb["mask"]),
+                                tt(mb["h0"]), tt(mb["c0"]))
+    lp = F.log_softmax(logits, -1)
+    lpa = lp.gather(2, tt(mb["action"], torch.int64)[..., None])[..., 0]
+    adv = tt(mb["adv"])
+    ratio = torch.exp(lpa - tt(mb["logp_old"]))
+    surr = torch.min(ratio * adv, torch.clamp(ratio, 1 - ppo.clip, 1 + ppo.clip) * adv)
+    ent = -(lp.exp() * lp).sum(-1)
+    L = (-(w * surr).sum() + ppo.value_coef * (w * 0.5 * (values - tt(mb["ret"])) ** 2).sum()
+         - ppo.entropy_coef * (w * ent).sum())
+    L.backward()
+    return L.item(), flat_t.grad.numpy().copy(), logits.detach().numpy(), values.detach().numpy()
