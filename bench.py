@@ -1,0 +1,224 @@
+"""Throughput of one DD-PPO worker on one MI355X.
+
+A step is one full worker iteration (Sec. 3-4): T+1 dependent act steps over
+N envs, GAE, then E epochs x M minibatches of (loss backward, Adam).  Frames
+per step = sum of the env rollout lengths.  Inputs are seeded synthetic
+rollouts (frames U[0,1), goals N(0,1), rewards/dones as in the generator)
+staged in device memory before the timed region.  The paper's throughput
+procedure (appendix "Additional scaling details") times the last 5 of 10
+collect+optimise iterations; --warmup 5 --steps 5 reproduces it.
+
+Prints one JSON line.  The headline value is the bfloat16 form; the float32
+form of the same workload is timed beside it.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_BF16_TFLOPS = 2500.0     # MI355X dense bf16 MFMA
+PEAK_FP32_TFLOPS = 157.3      # MI355X fp32 matrix
+PEAK_HBM_GBS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", default="C2", help="C0..C4 (C2 = bf16 paper-shaped worker)")
+    ap.add_argument("--no-fp32", action="store_true", help="skip the float32 comparison run")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
+    ap.add_argument("--seed", type=int, default=0)
+    return ap.parse_args()
+
+
+def stage_env(wl, seed, it, dev):
+    """One iteration's environment stream on the device."""
+    import torch
+    from synth import rollout as R
+    ro = R.gen_rollout(wl, seed, it)
+    lens = ro["lengths"]
+    order = np.argsort(-lens, kind="stable")    # longest first
+    obs = ro["obs"][:, order]
+    t = lambda a: torch.as_tensor(np.ascontiguousarray(a)).to(dev)
+    env = {"obs": t(obs).to(torch.bfloat16) if wl.dtype == "bf16" else t(obs),
+           "goal": t(ro["goal"][:, order]), "u": t(ro["u"][:, order]),
+           "mask": t(ro["mask"][:, order]), "reward": t(ro["reward"][:, order]),
+           "done": t(ro["done"][:, order])}
+    return env, lens[order]
+
+
+def run_gpu(wl, steps, warmup, seed):
+    import torch
+    from paper_1911_00357_amd.worker import PPOHyper, Worker
+    from synth import rollout as R
+    dev = torch.device("cuda", 0)
+    p = wl.ppo
+    hp = PPOHyper(p.gamma, p.lam, p.clip, p.value_coef, p.entropy_coef, p.lr, p.epochs, p.minibatches,
+                  p.norm_adv)
+    w = Worker(wl.net, wl.dtype, wl.T, wl.N, R.init_params(wl.net, seed), hp, dev)
+    its = warmup + steps
+    envs = [stage_env(wl, seed, i, dev) for i in range(min(its, 2))]
+    parts = R.partitions(wl, seed)
+    frames = []
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    torch.cuda.synchronize()
+    t_start = None
+    for i in range(its):
+        env, lens = envs[i % len(envs)]
+        lengths = None if not wl.ragged else lens
+        if i == warmup:
+            torch.cuda.synchronize()
+            ev[0].record()
+            t_start = time.perf_counter()
+        w.collect(env, lengths)
+        w.update(env, parts, lengths)
+        if i >= warmup:
+            frames.append(int(lens.sum()))
+    ev[1].record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t_start
+    gpu_ms = ev[0].elapsed_time(ev[1])
+    return {"frames": sum(frames), "wall_s": wall, "gpu_ms": gpu_ms, "worker": w}
+
+
+def act_update_split(wl, seed):
+    """Separate timing of the act phase and the update phase (one iteration)."""
+    import torch
+    from paper_1911_00357_amd.worker import PPOHyper, Worker
+    from synth import rollout as R
+    dev = torch.device("cuda", 0)
+    p = wl.ppo
+    hp = PPOHyper(p.gamma, p.lam, p.clip, p.value_coef, p.entropy_coef, p.lr, p.epochs, p.minibatches)
+    w = Worker(wl.net, wl.dtype, wl.T, wl.N, R.init_params(wl.net, seed), hp, dev)
+    env, lens = stage_env(wl, seed, 0, dev)
+    lengths = None if not wl.ragged else lens
+    parts = R.partitions(wl, seed)
+    for _ in range(2):
+        w.collect(env, lengths)
+        w.update(env, parts, lengths)
+    e = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+    e[0].record()
+    w.collect(env, lengths)
+    e[1].record()
+    w.update(env, parts, lengths)
+    e[2].record()
+    torch.cuda.synchronize()
+    return e[0].elapsed_time(e[1]), e[1].elapsed_time(e[2]), int(lens.sum())
+
+
+def cpu_baseline(wl, seed):
+    """The FP64 oracle on a bounded sample of the same workload: an 8-step
+    rollout of all N envs (9 act steps) and the update over its frames."""
+    import oracle
+    from synth import rollout as R
+    small = wl.with_(T=8)
+    flat = R.init_params(wl.net, seed)
+    inp = R.gen_rollout(small, seed, 0)
+    inp["lengths"] = np.full(small.N, small.T, np.int32)
+    h0, c0 = R.gen_state(wl.net, small.N, seed)
+    t0 = time.perf_counter()
+    rec = oracle.ppo.rollout(flat, wl.net, inp, h0, c0)
+    oracle.ppo.update(flat, wl.net, wl.ppo, inp, rec, R.partitions(small, seed))
+    dt = time.perf_counter() - t0
+    frames = small.T * small.N
+    threads = int(os.environ.get("OPENBLAS_NUM_THREADS", os.environ.get("OMP_NUM_THREADS", os.cpu_count())))
+    return {"value": frames / dt, "unit": "frames/s", "cores": min(threads, os.cpu_count()),
+            "kind": "oracle",
+            "sample": f"T=8 rollout of N={small.N} envs (9 act steps) + {wl.ppo.epochs}x"
+                      f"{wl.ppo.minibatches} minibatch updates, {frames} frames, {dt:.1f} s"}
+
+
+def flops_per_frame(net):
+    """Forward multiply-adds x2 of the encoder convolutions, the visual FC and
+    the LSTM/head GEMMs for one frame."""
+    from synth.layout import tensor_list
+    hw = net.enc_hw
+    f = 0
+    if net.trunk == "tiny":
+        h1 = hw // 2
+        h2 = h1 // 2
+        f += 2 * h1 * h1 * net.tiny_ch[0] * 9 * net.in_ch + 2 * h2 * h2 * net.tiny_ch[1] * 9 * net.tiny_ch[0]
+    else:
+        h = hw // 2
+        f += 2 * h * h * net.base_width * 49 * net.in_ch
+        h //= 2
+        cin = net.base_width
+        for s, nb in enumerate(net.blocks):
+            w = net.base_width << s
+            for j in range(nb):
+                st = 2 if (j == 0 and s > 0) else 1
+                ho = h // st
+                f += 2 * h * h * w * cin + 2 * ho * ho * w * 9 * w + 2 * ho * ho * 4 * w * w
+                if j == 0:
+                    f += 2 * ho * ho * 4 * w * cin
+                cin = 4 * w
+                h = ho
+        f += 2 * h * h * net.compress_ch * 9 * cin
+    f += 2 * net.flat_dim * net.vis_hidden
+    H = net.hidden
+    f += 2 * 4 * H * (net.lstm_in + H) + (net.lstm_layers - 1) * 2 * 4 * H * 2 * H
+    f += 2 * (net.num_actions + 1) * H
+    return f
+
+
+def main():
+    a = parse()
+    if a.gpus != 1:
+        print(json.dumps({"error": "this build measures one GPU; the gradient all-reduce of a "
+                                   "multi-GPU worker group is not implemented", "n_gpus": a.gpus}))
+        sys.exit(2)
+    import torch
+    if not torch.cuda.is_available():
+        print(json.dumps({"error": "no GPU visible"}))
+        sys.exit(1)
+    from synth.configs import WORKLOADS
+    wl = WORKLOADS[a.workload]
+    res = run_gpu(wl, a.steps, a.warmup, a.seed)
+    fps = res["frames"] / (res["gpu_ms"] / 1e3)
+    ms_step = res["gpu_ms"] / a.steps
+    frames_step = res["frames"] / a.steps
+    out = {"metric": "PPO act+update frames/s", "value": round(fps, 2), "unit": "frames/s",
+           "n_gpus": 1, "steps": a.steps, "warmup": a.warmup, "ms_per_step": round(ms_step, 3),
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": "bf16" if wl.dtype == "bf16" else "f32", "data": "synthetic",
+           "config": {"workload": wl.name, "T": wl.T, "N": wl.N, "frame": f"{wl.net.in_ch}x{wl.net.in_hw}x{wl.net.in_hw}",
+                      "encoder": "resnet50 halved widths, GroupNorm" if wl.net.trunk == "resnet" else "tiny",
+                      "lstm": f"{wl.net.lstm_layers}x{wl.net.hidden}", "epochs": wl.ppo.epochs,
+                      "minibatches": wl.ppo.minibatches, "frames_per_step": frames_step,
+                      "parallelism": "single worker"},
+           "wall_s": round(res["wall_s"], 3)}
+    del res
+    torch.cuda.empty_cache()
+    act_ms, upd_ms, fr = act_update_split(wl, a.seed)
+    out["act_ms"], out["update_ms"] = round(act_ms, 3), round(upd_ms, 3)
+    out["act_frames_per_s"] = round((fr + wl.N) / (act_ms / 1e3), 1)
+    out["update_frames_per_s"] = round(fr / (upd_ms / 1e3), 1)
+    fpf = flops_per_frame(wl.net)
+    upd_flops = 3 * fpf * fr * wl.ppo.epochs
+    peak = PEAK_BF16_TFLOPS if wl.dtype == "bf16" else PEAK_FP32_TFLOPS
+    out["update_tflops"] = round(upd_flops / (upd_ms / 1e3) / 1e12, 3)
+    out["update_mfma_frac"] = round(upd_flops / (upd_ms / 1e3) / 1e12 / peak, 5)
+    if wl.dtype == "bf16" and not a.no_fp32:
+        torch.cuda.empty_cache()
+        wl32 = wl.with_(dtype="f32")
+        r32 = run_gpu(wl32, a.steps, 1, a.seed)
+        out["fp32_value"] = round(r32["frames"] / (r32["gpu_ms"] / 1e3), 2)
+        out["bf16_speedup_vs_fp32"] = round(out["value"] / out["fp32_value"], 3)
+        del r32
+    if not a.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(wl, a.seed)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

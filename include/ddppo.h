@@ -1,0 +1,248 @@
+/*
+ * ddppo.h -- C ABI of the MI355X (gfx950) hot path of one DD-PPO worker.
+ *
+ * Wijmans et al., "DD-PPO: Learning Near-Perfect PointGoal Navigators from
+ * 2.5 Billion Frames", ICLR 2020.  One worker alternates an inference role
+ * (batched act steps over its environments) and a learner role (GAE, the
+ * clipped PPO objective of Eq. 2 and its gradient, then ParamUpdate of
+ * Eq. 3-4).  On one worker the AllReduce of Eq. 3-4 is the identity, so the
+ * gradient that ppo_loss_backward writes is what ppo_adam_step consumes.
+ *
+ * Conventions for every call:
+ *   - Pointers named d_* or documented as "device" are device memory owned
+ *     by the caller; "host" pointers are read before the call returns.  The
+ *     library allocates no device memory: scratch space is the caller's
+ *     workspace (size from ppo_workspace_size).
+ *   - All work is enqueued on `stream` (a hipStream_t passed as void*;
+ *     NULL = the null stream) and is asynchronous.  Shape, pointer and
+ *     workspace errors are detected on the host before any launch and
+ *     return a negative ppo_status; a failed launch returns PPO_EDEVICE.
+ *     Faults inside kernels surface at the caller's next synchronisation.
+ *     No call aborts, exits or throws.  ppo_last_error() returns a
+ *     thread-local message describing the last failure.
+ *   - A ppo_net is a host-side descriptor.  It is not re-entrant across
+ *     streams: calls that share one ppo_net must be ordered.
+ *
+ * Flat parameter format (float32 master, grads, Adam moments; the bfloat16
+ * working copy has the same order).  Tensors in order:
+ *   tiny trunk  : conv1 [c1][3][3][in_ch], gn1 gamma [c1], beta [c1],
+ *                 conv2 [c2][3][3][c1],  gn2 gamma [c2], beta [c2]
+ *   resnet trunk: stem [w0][7][7][in_ch], gamma, beta [w0]; per stage s (width
+ *                 w = w0*2^s) and block j: c1 [w][1][1][cin] + gn, c2 [w][3][3][w]
+ *                 + gn, c3 [4w][1][1][w] + gn, and on block 0 a projection
+ *                 ds [4w][1][1][cin] + gn; compress [cc][3][3][32*w0] + gn
+ *                 (every "+ gn" is gamma then beta, one value per output channel)
+ *   visual FC   : W [vis_hidden][flat] with input index (channel, row, col), b
+ *   goal FC     : W [goal_dim][3], b            (goal_mode = polar only)
+ *   embedding   : E [num_actions+1][prev_act_dim] (prev_act_dim > 0 only;
+ *                 row 0 is the start token)
+ *   LSTM layer l: W [4H][in_l + H] (input columns then recurrent columns,
+ *                 gate row blocks i, f, g, o), b [4H]
+ *   heads       : W [num_actions+1][H] (policy rows, then the value row), b
+ * Convolution weights are (out, kh, kw, in).  Convolutions have no bias.
+ *
+ * Rollout arrays are time-major: [T+1][N] for per-act-step data (step T is
+ * the bootstrap step), [T][N] for per-transition data, frames
+ * [T+1][N][C][H][W] (float32 or bfloat16 per the net's dtype).
+ */
+#ifndef DDPPO_H
+#define DDPPO_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  PPO_OK = 0,
+  PPO_EINVAL = -1,       /* null pointer, bad scalar argument */
+  PPO_ESHAPE = -2,       /* inconsistent or unsupported sizes */
+  PPO_EUNSUPPORTED = -3, /* feature or device not supported (non-gfx950) */
+  PPO_EWORKSPACE = -4,   /* workspace too small or misaligned */
+  PPO_EDEVICE = -5       /* a HIP call or launch failed */
+} ppo_status;
+
+enum { PPO_F32 = 0, PPO_BF16 = 1 };
+enum { PPO_TRUNK_TINY = 0, PPO_TRUNK_RESNET = 1 };
+enum { PPO_GOAL_RAW = 0, PPO_GOAL_POLAR = 1 };
+enum { PPO_OP_ACT = 0, PPO_OP_LEARN = 1 };
+
+/* Network shape (appendix "Agent Design"; Sec. 4 "Agent"). */
+typedef struct ppo_net_desc {
+  int in_ch;          /* frame channels (4: RGB-D)                              */
+  int in_hw;          /* frame height = width (256)                             */
+  int avgpool;        /* 1: 2x2 average pool before the trunk                   */
+  int trunk;          /* PPO_TRUNK_TINY | PPO_TRUNK_RESNET                       */
+  int tiny_ch[2];     /* tiny trunk widths (16, 32)                             */
+  int base_width;     /* resnet stem width; stage widths w0*2^s (32)            */
+  int blocks[4];      /* bottlenecks per stage (3, 4, 6, 3)                     */
+  int gn_groups;      /* GroupNorm groups (16 resnet, 8 tiny)                   */
+  int compress_ch;    /* compression conv output channels (128)                 */
+  int vis_hidden;     /* visual FC width (512)                                  */
+  int goal_mode;      /* PPO_GOAL_RAW: [2] concatenated; PPO_GOAL_POLAR: FC-32  */
+  int goal_dim;       /* 2 for raw, FC width for polar                          */
+  int prev_act_dim;   /* previous-action embedding width, 0 = none              */
+  int lstm_layers;    /* 1 or 2                                                 */
+  int hidden;         /* LSTM hidden size (512)                                 */
+  int num_actions;    /* 4                                                      */
+  int dtype;          /* PPO_F32 | PPO_BF16: GEMM operand precision             */
+} ppo_net_desc;
+
+typedef struct ppo_net ppo_net;
+
+/* Validate a description and build the host-side plan.  No device memory is
+ * allocated.  Errors: PPO_EINVAL (null), PPO_ESHAPE (sizes that do not
+ * divide: e.g. widths not multiples of gn_groups, a trunk that does not
+ * reduce in_hw to an integer map), PPO_EUNSUPPORTED (device is not gfx950). */
+ppo_status ppo_net_create(const ppo_net_desc* desc, ppo_net** out);
+void ppo_net_destroy(ppo_net* net);
+
+/* Number of float parameters in the flat format above. */
+size_t ppo_param_count(const ppo_net* net);
+
+/* Offset and element count of the i-th tensor of the flat format, with its
+ * name (static string).  Returns PPO_EINVAL past the last tensor. */
+ppo_status ppo_param_tensor(const ppo_net* net, int i, const char** name, size_t* offset,
+                            size_t* count);
+
+/* Workspace bytes for one call of ppo_act (op = PPO_OP_ACT, max_frames = the
+ * largest act batch) or ppo_loss_backward (op = PPO_OP_LEARN, max_frames =
+ * the largest number of valid frames of one minibatch, max_envs its env
+ * count).  The workspace must be 256-byte aligned device memory. */
+ppo_status ppo_workspace_size(const ppo_net* net, int op, int max_frames, int max_envs,
+                              size_t* bytes);
+
+/* ---------------------------------------------------------------------------
+ * ppo_act -- one batched act step of the inference role (Sec. 3, Sec. 4).
+ * For each of `batch` envs b: frame -> encoder -> [visual FC | goal | prev-action
+ * embedding] -> LSTM (h, c first multiplied by mask[b]; mask 0 also selects
+ * the start token) -> logits, value; action = the smallest k whose cumulative
+ * softmax probability exceeds u[b] (the last action if rounding leaves none),
+ * logp = log pi(action).
+ */
+typedef struct ppo_act_io {
+  int batch;                  /* B envs (rows) in this call                     */
+  int state_rows;             /* rows per layer of h/c arrays (>= batch; 0 = batch) */
+  const void* obs;            /* device [B][C][H][W], float32 or bfloat16       */
+  const float* goal;          /* device [B][2]: (d, theta) or the raw 2-vector   */
+  const int32_t* prev_action; /* device [B] action taken at the previous step   */
+  const float* mask;          /* device [B]: 0 at an episode start, else 1      */
+  const float* h_in;          /* device [L][state_rows][H], rows < B are read    */
+  const float* c_in;          /* device [L][state_rows][H]                      */
+  const float* u;             /* device [B] uniforms in [0,1)                   */
+  const float* params;        /* device flat float32 parameters                 */
+  const void* params_lp;      /* device flat bfloat16 copy (PPO_BF16), else NULL */
+  int32_t* action;            /* device [B] out                                 */
+  float* logp;                /* device [B] out                                 */
+  float* value;               /* device [B] out                                 */
+  float* h_out;               /* device [L][state_rows][H] out, rows < B (may alias h_in) */
+  float* c_out;               /* device [L][state_rows][H] out (may alias c_in) */
+  float* logits;              /* device [B][A] out, or NULL                     */
+} ppo_act_io;
+
+ppo_status ppo_act(ppo_net* net, const ppo_act_io* io, void* ws, size_t ws_bytes, void* stream);
+
+/* ---------------------------------------------------------------------------
+ * ppo_gae -- generalized advantage estimation (Sec. 4 "Training": gamma, GAE
+ * parameter tau = lambda).  For each env n, t = len[n]-1 .. 0 with A = 0 past
+ * the end:  delta_t = r_t + gamma (1-d_t) V_{t+1} - V_t,
+ *           A_t = delta_t + gamma lambda (1-d_t) A_{t+1},  R_t = A_t + V_t.
+ * A rollout cut at len[n] < T (preemption, Sec. 3) bootstraps with V[len[n]].
+ * rew, done [T][N]; val [T+1][N]; len [N] device int32 or NULL (all T).
+ * adv, ret [T][N] float32 out (0 past len).  adv_stats: device double[2]
+ * (population mean and variance of the valid advantages, float64) or NULL.
+ */
+ppo_status ppo_gae(const float* rew, const float* val, const uint8_t* done, const int32_t* len,
+                   int T, int N, float gamma, float lambda, float* adv, float* ret,
+                   double* adv_stats, void* stream);
+
+/* ---------------------------------------------------------------------------
+ * ppo_loss_backward -- learner forward and backward for one minibatch of
+ * whole env sequences (Sec. 3-4).  Re-runs the policy over every frame
+ * t < T_n of the chosen envs from the stored rollout-start state, then
+ *   L = -sum_n w_n sum_t min(r A, clip(r, 1-eps, 1+eps) A)          (Eq. 2)
+ *       + c_v sum_n w_n sum_t 1/2 (V - R)^2 - c_e sum_n w_n sum_t H(pi),
+ *   r = exp(logp - logp_old), w_n = 1/(|B| T_n) (every env weighs equally, Sec. 3)
+ * and writes grad = S * dL/dtheta (S = *d_loss_scale, 1 for float32 nets).
+ */
+typedef struct ppo_batch {
+  int T;                      /* rollout steps (row count of [T][N] arrays)      */
+  int N;                      /* envs in the rollout (row length)               */
+  int nb;                     /* envs in this minibatch                          */
+  const int32_t* env_ids;     /* host [nb] env indices                           */
+  const int32_t* lengths;     /* host [N] T_n (1..T), or NULL for all T          */
+  const void* obs;            /* device [T+1][N][C][H][W]                        */
+  const float* goal;          /* device [T+1][N][2]                              */
+  const int32_t* prev_action; /* device [T+1][N] prev-action input of each step  */
+  const float* mask;          /* device [T+1][N] episode mask of each step       */
+  const int32_t* action;      /* device [T+1][N] actions taken                   */
+  const float* logp_old;      /* device [T+1][N]                                 */
+  const float* adv;           /* device [T][N]                                   */
+  const float* ret;           /* device [T][N]                                   */
+  const float* h0;            /* device [L][N][H] state at the rollout start     */
+  const float* c0;            /* device [L][N][H]                                */
+  const float* params;        /* device flat float32                             */
+  const void* params_lp;      /* device flat bfloat16 copy, or NULL (PPO_F32)    */
+} ppo_batch;
+
+typedef struct ppo_loss_cfg {
+  float clip;                 /* epsilon of Eq. 2 (0.2)                          */
+  float value_coef;           /* c_v (0.5)                                       */
+  float entropy_coef;         /* c_e (0.01)                                      */
+  int norm_adv;               /* 1: A <- (A - mean)/(std + 1e-5) (off in the paper) */
+  const double* adv_stats;    /* device double[2] from ppo_gae when norm_adv     */
+} ppo_loss_cfg;
+
+/* stats (device float[8]): loss, policy term, value term, entropy term,
+ * clip fraction, approximate KL, min ratio, max ratio (weighted like L). */
+ppo_status ppo_loss_backward(ppo_net* net, const ppo_batch* b, const ppo_loss_cfg* cfg,
+                             const float* d_loss_scale, float* grad, float* stats, void* ws,
+                             size_t ws_bytes, void* stream);
+
+/* ---------------------------------------------------------------------------
+ * ppo_adam_step -- ParamUpdate of Eq. 3-4 (Adam, Kingma & Ba, with bias
+ * correction; the paper's optimiser, Sec. 4 "Training").  Device state:
+ *   scaler->scale S: gradients arrive multiplied by S and are unscaled here;
+ *   if any unscaled gradient is not finite the step is skipped (params, m, v,
+ *   step unchanged), S halves and skipped increments; otherwise step += 1,
+ *     m = b1 m + (1-b1) g, v = b2 v + (1-b2) g^2,
+ *     theta -= lr (m / (1-b1^step)) / (sqrt(v / (1-b2^step)) + eps),
+ *   and after `growth_interval` consecutive good steps S doubles (dynamic
+ *   loss scaling; growth_interval 0 keeps S fixed).
+ * master, m, v [P] float32 in place; grad [P] float32 (read only); lp_copy
+ * [P] bfloat16 rewritten from the new master (NULL to skip).  ws: at least
+ * ppo_adam_workspace_size(P) bytes of device scratch.
+ */
+typedef struct ppo_adam_cfg {
+  float lr, beta1, beta2, eps;
+  int growth_interval;        /* 2000 for bfloat16 nets, 0 for float32           */
+} ppo_adam_cfg;
+
+typedef struct ppo_scaler {   /* device-resident; initialise scale = 65536 or 1  */
+  float scale;
+  int32_t step;               /* Adam step count k (completed steps)             */
+  int32_t good_steps;         /* consecutive finite steps since the last change  */
+  int32_t skipped;            /* total skipped steps                             */
+  int32_t found_inf;          /* last call: 1 if skipped                         */
+  int32_t pad[3];
+} ppo_scaler;
+
+size_t ppo_adam_workspace_size(size_t P);
+
+ppo_status ppo_adam_step(float* master, const float* grad, float* m, float* v, void* lp_copy,
+                         size_t P, const ppo_adam_cfg* cfg, ppo_scaler* scaler, void* ws,
+                         size_t ws_bytes, void* stream);
+
+/* dst[i] = bfloat16(src[i]) (round to nearest even) for the initial working
+ * copy of the parameters; later copies come from ppo_adam_step.  src [n]
+ * float32, dst [n] bfloat16, both device. */
+ppo_status ppo_cast_bf16(const float* src, void* dst, size_t n, void* stream);
+
+const char* ppo_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* DDPPO_H */

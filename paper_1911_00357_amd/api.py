@@ -1,0 +1,276 @@
+"""Python binding of the C ABI (include/ddppo.h) over torch device tensors.
+
+Argument marshalling only: every step of the path runs in the HIP kernels of
+libddppo.so.  Tensors must be CUDA (HIP) tensors, contiguous, with the dtypes
+the header states; work is enqueued on torch's current stream.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+
+import torch
+
+from . import _lib as L
+from ._lib import check, lib
+
+
+# Test aid: fill workspaces with NaN bytes before every call.
+POISON_WS = os.environ.get("DDPPO_POISON_WS", "0") == "1"
+
+
+def _ptr(t):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _need(t, dtype, name, numel=None):
+    if t is None:
+        raise ValueError(f"{name} is required")
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be a device tensor")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if dtype is not None and t.dtype != dtype:
+        raise ValueError(f"{name} must be {dtype}, got {t.dtype}")
+    if numel is not None and t.numel() != numel:
+        raise ValueError(f"{name} must hold {numel} elements, got {t.numel()}")
+    return t
+
+
+def _stream(device=None):
+    return C.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+def desc_from(spec, dtype: str) -> L.NetDesc:
+    """Build the C description from any object with the network fields
+    (in_ch, in_hw, avgpool, trunk 'tiny'|'resnet', tiny_ch, base_width, blocks,
+    gn_groups, compress_ch, vis_hidden, goal_mode 'raw'|'polar', goal_dim,
+    prev_act_dim, lstm_layers, hidden, num_actions)."""
+    d = L.NetDesc()
+    d.in_ch, d.in_hw, d.avgpool = spec.in_ch, spec.in_hw, int(bool(spec.avgpool))
+    d.trunk = L.PPO_TRUNK_TINY if spec.trunk == "tiny" else L.PPO_TRUNK_RESNET
+    d.tiny_ch[0], d.tiny_ch[1] = spec.tiny_ch
+    d.base_width = spec.base_width
+    for i in range(4):
+        d.blocks[i] = spec.blocks[i]
+    d.gn_groups, d.compress_ch, d.vis_hidden = spec.gn_groups, spec.compress_ch, spec.vis_hidden
+    d.goal_mode = L.PPO_GOAL_POLAR if spec.goal_mode == "polar" else L.PPO_GOAL_RAW
+    d.goal_dim, d.prev_act_dim = spec.goal_dim, spec.prev_act_dim
+    d.lstm_layers, d.hidden, d.num_actions = spec.lstm_layers, spec.hidden, spec.num_actions
+    d.dtype = L.PPO_BF16 if dtype == "bf16" else L.PPO_F32
+    return d
+
+
+@dataclass
+class LossCfg:
+    clip: float = 0.2
+    value_coef: float = 0.5
+    entropy_coef: float = 0.01
+    norm_adv: bool = False
+
+
+class Net:
+    """A ppo_net plus cached workspaces."""
+
+    def __init__(self, spec, dtype: str = "f32"):
+        self.spec = spec
+        self.dtype = dtype
+        self.bf16 = dtype == "bf16"
+        d = desc_from(spec, dtype)
+        h = C.c_void_p()
+        check(lib().ppo_net_create(C.byref(d), C.byref(h)), "ppo_net_create")
+        self._h = h
+        self.P = int(lib().ppo_param_count(h))
+        self.L, self.H, self.A = spec.lstm_layers, spec.hidden, spec.num_actions
+        self._ws = {}
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            try:
+                lib().ppo_net_destroy(h)
+            except Exception:
+                pass
+
+    def tensors(self):
+        out, i = [], 0
+        while True:
+            name, off, cnt = C.c_char_p(), C.c_size_t(), C.c_size_t()
+            if lib().ppo_param_tensor(self._h, i, C.byref(name), C.byref(off), C.byref(cnt)) != 0:
+                return out
+            out.append((name.value.decode(), off.value, cnt.value))
+            i += 1
+
+    def workspace_bytes(self, op: int, max_frames: int, max_envs: int = 1) -> int:
+        b = C.c_size_t()
+        check(lib().ppo_workspace_size(self._h, op, max_frames, max_envs, C.byref(b)),
+              "ppo_workspace_size")
+        return b.value
+
+    def workspace(self, op: int, max_frames: int, max_envs: int, device) -> torch.Tensor:
+        need = self.workspace_bytes(op, max_frames, max_envs)
+        key = (op, str(device))
+        ws = self._ws.get(key)
+        if ws is None or ws.numel() < need:
+            ws = torch.empty(need, dtype=torch.uint8, device=device)
+            self._ws[key] = ws
+        if POISON_WS:  # every byte 0xff: a float read of unwritten scratch is NaN
+            ws.fill_(0xFF)
+        return ws
+
+    # ------------------------------------------------------------------ act
+    def act(self, obs, goal, prev_action, mask, h_in, c_in, u, params, params_lp=None,
+            out=None, want_logits=False, state_rows=0):
+        """One act step for B = obs.shape[0] envs.  h_in/c_in [L, state_rows, H]
+        (state_rows = B by default); rows < B are read and written."""
+        B = obs.shape[0]
+        SR = state_rows or B
+        odt = torch.bfloat16 if self.bf16 else torch.float32
+        _need(obs, odt, "obs")
+        _need(goal, torch.float32, "goal", B * 2)
+        _need(mask, torch.float32, "mask", B)
+        _need(h_in, torch.float32, "h_in", self.L * SR * self.H)
+        _need(c_in, torch.float32, "c_in", self.L * SR * self.H)
+        _need(u, torch.float32, "u", B)
+        _need(params, torch.float32, "params", self.P)
+        if self.spec.prev_act_dim:
+            _need(prev_action, torch.int32, "prev_action", B)
+        if self.bf16:
+            _need(params_lp, torch.bfloat16, "params_lp", self.P)
+        dev = obs.device
+        if out is None:
+            out = {"action": torch.empty(B, dtype=torch.int32, device=dev),
+                   "logp": torch.empty(B, dtype=torch.float32, device=dev),
+                   "value": torch.empty(B, dtype=torch.float32, device=dev),
+                   "h": torch.empty_like(h_in), "c": torch.empty_like(c_in)}
+            if want_logits:
+                out["logits"] = torch.empty(B, self.A, dtype=torch.float32, device=dev)
+        io = L.ActIO()
+        io.batch = B
+        io.state_rows = SR
+        io.obs, io.goal, io.prev_action, io.mask = _ptr(obs), _ptr(goal), _ptr(prev_action), _ptr(mask)
+        io.h_in, io.c_in, io.u = _ptr(h_in), _ptr(c_in), _ptr(u)
+        io.params, io.params_lp = _ptr(params), _ptr(params_lp)
+        io.action, io.logp, io.value = _ptr(out["action"]), _ptr(out["logp"]), _ptr(out["value"])
+        io.h_out, io.c_out = _ptr(out["h"]), _ptr(out["c"])
+        io.logits = _ptr(out.get("logits"))
+        ws = self.workspace(L.PPO_OP_ACT, B, 1, dev)
+        check(lib().ppo_act(self._h, C.byref(io), _ptr(ws), ws.numel(), _stream(dev)), "ppo_act")
+        return out
+
+    # -------------------------------------------------------------- learner
+    def loss_backward(self, ro: dict, env_ids, lengths, params, params_lp=None, cfg: LossCfg = None,
+                      loss_scale=None, adv_stats=None, grad=None, stats=None):
+        """ro: device rollout dict with obs [T+1,N,C,H,W], goal [T+1,N,2],
+        prev_action/action [T+1,N] int32, mask/logp [T+1,N], adv/ret [T,N],
+        h0/c0 [L,N,H].  env_ids: host ints; lengths: host ints [N] or None."""
+        cfg = cfg or LossCfg()
+        obs = ro["obs"]
+        T1, N = obs.shape[0], obs.shape[1]
+        T = T1 - 1
+        dev = obs.device
+        _need(obs, torch.bfloat16 if self.bf16 else torch.float32, "obs")
+        for k, dt, n in (("goal", torch.float32, T1 * N * 2), ("mask", torch.float32, T1 * N),
+                         ("action", torch.int32, T1 * N), ("logp", torch.float32, T1 * N),
+                         ("adv", torch.float32, T * N), ("ret", torch.float32, T * N),
+                         ("h0", torch.float32, self.L * N * self.H),
+                         ("c0", torch.float32, self.L * N * self.H)):
+            _need(ro[k], dt, k, n)
+        if self.spec.prev_act_dim:
+            _need(ro["prev_action"], torch.int32, "prev_action", T1 * N)
+        _need(params, torch.float32, "params", self.P)
+        if self.bf16:
+            _need(params_lp, torch.bfloat16, "params_lp", self.P)
+        env = (C.c_int32 * len(env_ids))(*[int(e) for e in env_ids])
+        lens = None
+        F = T * len(env_ids)
+        if lengths is not None:
+            lens = (C.c_int32 * N)(*[int(x) for x in lengths])
+            F = int(sum(int(lengths[int(e)]) for e in env_ids))
+        b = L.Batch()
+        b.T, b.N, b.nb = T, N, len(env_ids)
+        b.env_ids = C.cast(env, L.P_i32)
+        b.lengths = C.cast(lens, L.P_i32) if lens is not None else None
+        b.obs, b.goal, b.prev_action, b.mask = (_ptr(obs), _ptr(ro["goal"]),
+                                                _ptr(ro.get("prev_action")), _ptr(ro["mask"]))
+        b.action, b.logp_old, b.adv, b.ret = (_ptr(ro["action"]), _ptr(ro["logp"]),
+                                              _ptr(ro["adv"]), _ptr(ro["ret"]))
+        b.h0, b.c0 = _ptr(ro["h0"]), _ptr(ro["c0"])
+        b.params, b.params_lp = _ptr(params), _ptr(params_lp)
+        c = L.LossCfg()
+        c.clip, c.value_coef, c.entropy_coef = cfg.clip, cfg.value_coef, cfg.entropy_coef
+        c.norm_adv = int(cfg.norm_adv)
+        c.adv_stats = _ptr(adv_stats)
+        if grad is None:
+            grad = torch.empty(self.P, dtype=torch.float32, device=dev)
+        if stats is None:
+            stats = torch.empty(8, dtype=torch.float32, device=dev)
+        ws = self.workspace(L.PPO_OP_LEARN, F, len(env_ids), dev)
+        check(lib().ppo_loss_backward(self._h, C.byref(b), C.byref(c), _ptr(loss_scale), _ptr(grad),
+                                      _ptr(stats), _ptr(ws), ws.numel(), _stream(dev)),
+              "ppo_loss_backward")
+        return grad, stats
+
+
+def gae(rew, val, done, lengths, gamma, lam, adv=None, ret=None, stats=None):
+    """rew, done [T,N] (float32, uint8), val [T+1,N], lengths [N] int32 device or None."""
+    T, N = rew.shape
+    _need(rew, torch.float32, "rew")
+    _need(val, torch.float32, "val", (T + 1) * N)
+    _need(done, torch.uint8, "done", T * N)
+    if lengths is not None:
+        _need(lengths, torch.int32, "lengths", N)
+    dev = rew.device
+    adv = torch.empty(T, N, dtype=torch.float32, device=dev) if adv is None else adv
+    ret = torch.empty(T, N, dtype=torch.float32, device=dev) if ret is None else ret
+    check(lib().ppo_gae(_ptr(rew), _ptr(val), _ptr(done), _ptr(lengths), T, N, float(gamma), float(lam),
+                        _ptr(adv), _ptr(ret), _ptr(stats), _stream(dev)), "ppo_gae")
+    return adv, ret
+
+
+class Adam:
+    """Adam state (m, v, device scaler) for one flat parameter vector."""
+
+    def __init__(self, P: int, device, lr=2.5e-4, betas=(0.9, 0.999), eps=1e-8, loss_scale=1.0,
+                 growth_interval=0):
+        self.P = P
+        self.m = torch.zeros(P, dtype=torch.float32, device=device)
+        self.v = torch.zeros(P, dtype=torch.float32, device=device)
+        sc = L.Scaler()
+        sc.scale = loss_scale
+        raw = torch.frombuffer(bytearray(bytes(sc)), dtype=torch.uint8)
+        self.scaler = raw.to(device)
+        self.cfg = L.AdamCfg()
+        self.cfg.lr, self.cfg.beta1, self.cfg.beta2, self.cfg.eps = lr, betas[0], betas[1], eps
+        self.cfg.growth_interval = growth_interval
+        self.ws = torch.empty(int(lib().ppo_adam_workspace_size(P)), dtype=torch.uint8, device=device)
+
+    def loss_scale_ptr(self):
+        return self.scaler  # float32 scale is the first field
+
+    def scale_tensor(self):
+        return self.scaler[:4].view(torch.float32)
+
+    def state(self):
+        raw = bytes(self.scaler.cpu().numpy().tobytes())
+        sc = L.Scaler.from_buffer_copy(raw)
+        return {"scale": sc.scale, "step": sc.step, "good_steps": sc.good_steps,
+                "skipped": sc.skipped, "found_inf": sc.found_inf}
+
+    def step(self, master, grad, lp_copy=None):
+        _need(master, torch.float32, "master", self.P)
+        _need(grad, torch.float32, "grad", self.P)
+        if lp_copy is not None:
+            _need(lp_copy, torch.bfloat16, "lp_copy", self.P)
+        check(lib().ppo_adam_step(_ptr(master), _ptr(grad), _ptr(self.m), _ptr(self.v), _ptr(lp_copy),
+                                  self.P, C.byref(self.cfg), _ptr(self.scaler), _ptr(self.ws),
+                                  self.ws.numel(), _stream(master.device)), "ppo_adam_step")
+
+
+def cast_bf16(src, dst=None):
+    _need(src, torch.float32, "src")
+    if dst is None:
+        dst = torch.empty(src.shape, dtype=torch.bfloat16, device=src.device)
+    check(lib().ppo_cast_bf16(_ptr(src), _ptr(dst), src.numel(), _stream(src.device)), "ppo_cast_bf16")
+    return dst

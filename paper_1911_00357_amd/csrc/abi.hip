@@ -1,0 +1,716 @@
+// C ABI of the DD-PPO worker hot path: network plan, workspace layout and the
+// host-side sequencing of the kernels for ppo_act, ppo_gae, ppo_loss_backward
+// and ppo_adam_step.  Host code only launches; every step runs on the GPU.
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "kernels.h"
+
+namespace {
+
+thread_local std::string g_err;
+
+ppo_status fail(ppo_status st, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return st;
+}
+
+constexpr float kGnEps = 1e-5f;
+constexpr size_t kSplitKBytes = 64u << 20;  // split-K partial tiles
+
+struct Tensor {
+  std::string name;
+  size_t off, count;
+};
+
+// One convolution (no bias) followed by GroupNorm.
+struct Unit {
+  size_t w, g, b;             // parameter offsets
+  int Cin, Cout, K, stride, pad;
+  int Hin, Win, Hout, Wout;
+  int S;                      // GroupNorm pixel chunks
+  size_t u, a, st;            // workspace offsets: conv out, norm out, stats (per frame sizes below)
+};
+
+struct Block {
+  int c1, c2, c3, ds;         // unit indices (ds = -1: identity shortcut)
+};
+
+}  // namespace
+
+struct ppo_net {
+  ppo_net_desc d;
+  int prec;                   // 0 float32 operands, 1 bfloat16
+  std::vector<Tensor> tensors;
+  size_t P = 0;
+  std::vector<Unit> units;
+  std::vector<Block> blocks;
+  int stem = -1;              // resnet stem unit
+  int compress = -1;          // resnet compress unit (or last tiny unit)
+  int h0, w0;                 // trunk input spatial size
+  int pool_h, pool_w;         // resnet max pool output size
+  int feat_c, feat_hw, flat;
+  int din0;                   // LSTM layer-0 input width
+  size_t fc_w, fc_b, goal_w, goal_b, emb, head_w, head_b;
+  std::vector<size_t> lstm_w, lstm_b;
+  // per-frame float counts used by the workspace planner
+  size_t max_unit = 0;        // largest conv output per frame
+  size_t gn_part = 0;         // largest S*C per frame
+  int max_G = 0;
+};
+
+namespace {
+
+size_t add_tensor(ppo_net* n, const std::string& name, size_t count) {
+  n->tensors.push_back({name, n->P, count});
+  n->P += count;
+  return n->tensors.back().off;
+}
+
+int add_unit(ppo_net* n, const std::string& name, int cin, int cout, int k, int stride, int pad, int hin,
+             int win) {
+  Unit u{};
+  u.w = add_tensor(n, name, (size_t)cout * k * k * cin);
+  u.g = add_tensor(n, name + ".gn.g", cout);
+  u.b = add_tensor(n, name + ".gn.b", cout);
+  u.Cin = cin;
+  u.Cout = cout;
+  u.K = k;
+  u.stride = stride;
+  u.pad = pad;
+  u.Hin = hin;
+  u.Win = win;
+  u.Hout = (hin + 2 * pad - k) / stride + 1;
+  u.Wout = (win + 2 * pad - k) / stride + 1;
+  const int P = u.Hout * u.Wout;
+  u.S = std::max(1, std::min(32, P / 64));
+  n->units.push_back(u);
+  n->max_unit = std::max(n->max_unit, (size_t)P * cout);
+  n->gn_part = std::max(n->gn_part, (size_t)u.S * cout);
+  return (int)n->units.size() - 1;
+}
+
+ppo_status build(ppo_net* n) {
+  const ppo_net_desc& d = n->d;
+  if (d.in_ch <= 0 || d.in_hw <= 0 || d.gn_groups <= 0 || d.hidden <= 0 || d.num_actions <= 1 ||
+      d.num_actions + 1 > 8 || d.lstm_layers < 1 || d.lstm_layers > 4 || d.vis_hidden <= 0)
+    return fail(PPO_ESHAPE, "invalid network sizes");
+  if (d.dtype != PPO_F32 && d.dtype != PPO_BF16) return fail(PPO_EINVAL, "dtype must be F32 or BF16");
+  n->prec = d.dtype == PPO_BF16 ? 1 : 0;
+  int hw = d.avgpool ? d.in_hw / 2 : d.in_hw;
+  if (d.avgpool && (d.in_hw & 1)) return fail(PPO_ESHAPE, "in_hw must be even with avgpool");
+  n->h0 = n->w0 = hw;
+  const int G = d.gn_groups;
+  n->max_G = G;
+  if (d.trunk == PPO_TRUNK_TINY) {
+    const int c1 = d.tiny_ch[0], c2 = d.tiny_ch[1];
+    if (c1 % G || c2 % G || c1 % 4 || c2 % 4) return fail(PPO_ESHAPE, "tiny widths must divide by groups and 4");
+    int u1 = add_unit(n, "enc.conv1", d.in_ch, c1, 3, 2, 1, hw, hw);
+    const Unit& U1 = n->units[u1];
+    int u2 = add_unit(n, "enc.conv2", c1, c2, 3, 2, 1, U1.Hout, U1.Wout);
+    n->compress = u2;
+    n->feat_c = c2;
+    n->feat_hw = n->units[u2].Hout;
+    if (n->units[u2].Hout != n->units[u2].Wout) return fail(PPO_ESHAPE, "non-square map");
+  } else if (d.trunk == PPO_TRUNK_RESNET) {
+    const int w0 = d.base_width;
+    if (hw % 32) return fail(PPO_ESHAPE, "resnet trunk needs a multiple of 32 after pooling");
+    if (w0 % G || w0 % 4 || d.compress_ch % G || d.compress_ch % 4)
+      return fail(PPO_ESHAPE, "widths must divide by the group count and 4");
+    n->stem = add_unit(n, "enc.stem", d.in_ch, w0, 7, 2, 3, hw, hw);
+    const Unit& S = n->units[n->stem];
+    n->pool_h = (S.Hout - 1) / 2 + 1;
+    n->pool_w = (S.Wout - 1) / 2 + 1;
+    int h = n->pool_h, cin = w0;
+    for (int s = 0; s < 4; ++s) {
+      const int w = w0 << s;
+      for (int j = 0; j < d.blocks[s]; ++j) {
+        const int st = (j == 0 && s > 0) ? 2 : 1;
+        char p[64];
+        snprintf(p, sizeof(p), "enc.s%d.b%d", s, j);
+        Block b{};
+        b.c1 = add_unit(n, std::string(p) + ".c1", cin, w, 1, 1, 0, h, h);
+        b.c2 = add_unit(n, std::string(p) + ".c2", w, w, 3, st, 1, h, h);
+        const int ho = n->units[b.c2].Hout;
+        b.c3 = add_unit(n, std::string(p) + ".c3", w, 4 * w, 1, 1, 0, ho, ho);
+        b.ds = (j == 0) ? add_unit(n, std::string(p) + ".ds", cin, 4 * w, 1, st, 0, h, h) : -1;
+        if (j != 0 && cin != 4 * w) return fail(PPO_ESHAPE, "identity shortcut with a width change");
+        n->blocks.push_back(b);
+        cin = 4 * w;
+        h = ho;
+      }
+    }
+    n->compress = add_unit(n, "enc.compress", cin, d.compress_ch, 3, 1, 1, h, h);
+    n->feat_c = d.compress_ch;
+    n->feat_hw = h;
+  } else {
+    return fail(PPO_EINVAL, "unknown trunk");
+  }
+  n->flat = n->feat_c * n->feat_hw * n->feat_hw;
+  n->fc_w = add_tensor(n, "fc.w", (size_t)d.vis_hidden * n->flat);
+  n->fc_b = add_tensor(n, "fc.b", d.vis_hidden);
+  if (d.goal_mode == PPO_GOAL_POLAR) {
+    n->goal_w = add_tensor(n, "goal.w", (size_t)d.goal_dim * 3);
+    n->goal_b = add_tensor(n, "goal.b", d.goal_dim);
+  } else if (d.goal_mode == PPO_GOAL_RAW) {
+    if (d.goal_dim != 2) return fail(PPO_ESHAPE, "raw goal has goal_dim 2");
+  } else {
+    return fail(PPO_EINVAL, "unknown goal mode");
+  }
+  if (d.prev_act_dim > 0) n->emb = add_tensor(n, "emb", (size_t)(d.num_actions + 1) * d.prev_act_dim);
+  const int H = d.hidden;
+  n->din0 = d.vis_hidden + d.goal_dim + std::max(0, d.prev_act_dim);
+  for (int l = 0; l < d.lstm_layers; ++l) {
+    const int din = l == 0 ? n->din0 : H;
+    char nm[32];
+    snprintf(nm, sizeof(nm), "lstm%d.w", l);
+    n->lstm_w.push_back(add_tensor(n, nm, (size_t)4 * H * (din + H)));
+    snprintf(nm, sizeof(nm), "lstm%d.b", l);
+    n->lstm_b.push_back(add_tensor(n, nm, (size_t)4 * H));
+  }
+  n->head_w = add_tensor(n, "head.w", (size_t)(d.num_actions + 1) * H);
+  n->head_b = add_tensor(n, "head.b", d.num_actions + 1);
+  return PPO_OK;
+}
+
+// ------------------------------------------------------------- workspace
+struct Arena {
+  size_t off = 0;
+  size_t take(size_t bytes) {
+    const size_t o = off;
+    off += (bytes + 255) & ~(size_t)255;
+    return o;
+  }
+};
+
+struct WsLayout {
+  // encoder
+  size_t x0;                       // [F][h0][w0][in_ch]
+  std::vector<size_t> u, a, st;    // per unit
+  size_t pool, arg;                // resnet max pool out + argmax
+  size_t gpart, gbpart, gcoef;     // GroupNorm partials
+  size_t ga, gb, gu, gd, gr;       // backward scratch (max unit size)
+  size_t dfeat;                    // [F][flat]
+  size_t splitk;                   // split-K partial tiles
+  // core
+  size_t src, wf, mskf, envrow;    // frame map
+  size_t z;                        // [F][din0 (+H for act)]
+  std::vector<size_t> g, c, cp, hp, hout;  // per layer
+  size_t h0g, c0g;                 // gathered start state [L][nb][H]
+  size_t zh;                       // act: [B][max(din0, H) + H]
+  size_t fstat, dout, dh0, dh1, dG, dhp, dcp, dvis;
+  size_t total;
+};
+
+WsLayout plan(const ppo_net* n, int F, int nb, bool learn) {
+  WsLayout w{};
+  Arena A;
+  const ppo_net_desc& d = n->d;
+  const int H = d.hidden, L = d.lstm_layers;
+  const size_t f4 = sizeof(float);
+  w.x0 = A.take((size_t)F * n->h0 * n->w0 * d.in_ch * f4);
+  for (const Unit& u : n->units) {
+    const size_t sz = (size_t)F * u.Hout * u.Wout * u.Cout * f4;
+    w.u.push_back(A.take(sz));
+    w.a.push_back(A.take(sz));
+    w.st.push_back(A.take((size_t)F * d.gn_groups * sizeof(float2)));
+  }
+  if (d.trunk == PPO_TRUNK_RESNET) {
+    const size_t ps = (size_t)F * n->pool_h * n->pool_w * d.base_width;
+    w.pool = A.take(ps * f4);
+    w.arg = A.take(ps);
+  }
+  w.gpart = A.take((size_t)F * n->gn_part * sizeof(float4));
+  w.gbpart = A.take((size_t)F * n->gn_part * sizeof(float2));
+  w.gcoef = A.take((size_t)F * n->max_G * sizeof(float2));
+  w.splitk = A.take(kSplitKBytes);
+  w.z = A.take((size_t)F * (n->din0 + H) * f4);
+  w.src = A.take((size_t)F * 4);
+  w.wf = A.take((size_t)F * 4);
+  w.mskf = A.take((size_t)F * 4);
+  w.envrow = A.take((size_t)std::max(nb, 1) * 4);
+  for (int l = 0; l < L; ++l) {
+    w.g.push_back(A.take((size_t)F * 4 * H * f4));
+    w.c.push_back(A.take((size_t)F * H * f4));
+    w.cp.push_back(A.take((size_t)F * H * f4));
+    w.hp.push_back(A.take((size_t)F * H * f4));
+    w.hout.push_back(A.take((size_t)F * H * f4));
+  }
+  w.zh = A.take((size_t)F * (std::max(n->din0, H) + H) * f4);
+  if (learn) {
+    const size_t mu = (size_t)F * n->max_unit * f4;
+    w.ga = A.take(mu);
+    w.gb = A.take(mu);
+    w.gu = A.take(mu);
+    w.gd = A.take(mu);
+    w.gr = A.take(mu);
+    w.dfeat = A.take((size_t)F * n->flat * f4);
+    w.h0g = A.take((size_t)L * std::max(nb, 1) * H * f4);
+    w.c0g = A.take((size_t)L * std::max(nb, 1) * H * f4);
+    w.fstat = A.take((size_t)F * 8 * f4);
+    w.dout = A.take((size_t)F * (d.num_actions + 1) * f4);
+    const int wmax = std::max(n->din0, H);
+    w.dh0 = A.take((size_t)F * wmax * f4);
+    w.dh1 = A.take((size_t)F * wmax * f4);
+    w.dG = A.take((size_t)F * 4 * H * f4);
+    w.dhp = A.take((size_t)std::max(nb, 1) * H * f4);
+    w.dcp = A.take((size_t)std::max(nb, 1) * H * f4);
+    w.dvis = A.take((size_t)F * d.vis_hidden * f4);
+  }
+  w.total = A.off;
+  return w;
+}
+
+// ------------------------------------------------------------ execution
+struct Ctx {
+  const ppo_net* n;
+  const WsLayout* w;
+  char* ws;
+  const float* params;
+  const void* lp;
+  float* grad;
+  hipStream_t s;
+  int F;
+  template <typename T = float>
+  T* at(size_t off) const {
+    return (T*)(ws + off);
+  }
+  const float* pf(size_t off) const { return params + off; }
+  const void* wt(size_t off) const {  // GEMM weight operand
+    return n->prec ? (const void*)((const bf16_t*)lp + off) : (const void*)(params + off);
+  }
+  float* splitk() const { return at(w->splitk); }
+  int splits(long M, long N, long K) const {
+    int s = gemm_max_splits_for(M, N, K, n->prec);
+    const long cap = (long)(kSplitKBytes / (sizeof(float) * (size_t)M * N));
+    if (s > cap) s = (int)std::max<long>(1, cap);
+    return s;
+  }
+};
+
+ConvGeo geo(const Unit& u, int F) {
+  return ConvGeo{F, u.Hin, u.Win, u.Cin, u.Hout, u.Wout, u.Cout, u.K, u.K, u.stride, u.pad};
+}
+
+// conv -> GroupNorm (+ residual) (+ ReLU); output NHWC (or channel-major).
+void unit_fwd(const Ctx& c, int ui, const float* x, const float* res, bool relu, float* out, bool chw) {
+  const Unit& u = c.n->units[ui];
+  const ConvGeo g = geo(u, c.F);
+  const long M = (long)c.F * u.Hout * u.Wout, K = (long)u.K * u.K * u.Cin;
+  gemm_conv_fwd(c.n->prec, g, x, c.wt(u.w), epi(c.at(c.w->u[ui]), u.Cout), c.splits(M, u.Cout, K),
+                c.splitk(), c.s);
+  launch_gn_forward(c.at(c.w->u[ui]), c.F, u.Hout * u.Wout, u.Cout, c.n->d.gn_groups, kGnEps, c.pf(u.g),
+                    c.pf(u.b), res, relu ? 1 : 0, out, chw ? 1 : 0, c.at<float2>(c.w->st[ui]),
+                    c.at<float4>(c.w->gpart), u.S, c.s);
+}
+
+// Encoder forward over c.F frames already in x0; returns the flat features
+// (channel-major per frame, i.e. [F][flat]).
+const float* encoder_fwd(const Ctx& c) {
+  const ppo_net* n = c.n;
+  const float* x0 = c.at(c.w->x0);
+  if (n->d.trunk == PPO_TRUNK_TINY) {
+    unit_fwd(c, 0, x0, nullptr, true, c.at(c.w->a[0]), false);
+    unit_fwd(c, 1, c.at(c.w->a[0]), nullptr, true, c.at(c.w->a[1]), true);
+    return c.at(c.w->a[1]);
+  }
+  const Unit& S = n->units[n->stem];
+  unit_fwd(c, n->stem, x0, nullptr, true, c.at(c.w->a[n->stem]), false);
+  launch_maxpool_fwd(c.at(c.w->a[n->stem]), c.F, S.Hout, S.Wout, S.Cout, c.at(c.w->pool),
+                     c.at<uint8_t>(c.w->arg), c.s);
+  const float* x = c.at(c.w->pool);
+  for (const Block& b : n->blocks) {
+    unit_fwd(c, b.c1, x, nullptr, true, c.at(c.w->a[b.c1]), false);
+    unit_fwd(c, b.c2, c.at(c.w->a[b.c1]), nullptr, true, c.at(c.w->a[b.c2]), false);
+    const float* res = x;
+    if (b.ds >= 0) {
+      unit_fwd(c, b.ds, x, nullptr, false, c.at(c.w->a[b.ds]), false);
+      res = c.at(c.w->a[b.ds]);
+    }
+    unit_fwd(c, b.c3, c.at(c.w->a[b.c2]), res, true, c.at(c.w->a[b.c3]), false);
+    x = c.at(c.w->a[b.c3]);
+  }
+  unit_fwd(c, n->compress, x, nullptr, true, c.at(c.w->a[n->compress]), true);
+  return c.at(c.w->a[n->compress]);
+}
+
+// GroupNorm backward + weight gradient + (optional) data gradient of one unit.
+//   dout: gradient at the unit's output (layout chw or NHWC); mask_out: the
+//   ReLU'd output for the mask (or null); x: the conv input; dx: data gradient
+//   out (null = not needed), dx_acc: accumulate into dx; dres: also write the
+//   masked output gradient (the residual branch's gradient).
+void unit_bwd(const Ctx& c, int ui, const float* dout, const float* mask_out, bool chw, const float* x,
+              float* du, float* dx, bool dx_acc, float* dres) {
+  const Unit& u = c.n->units[ui];
+  const ppo_net* n = c.n;
+  const int P = u.Hout * u.Wout;
+  launch_gn_backward(dout, mask_out, chw ? 1 : 0, c.at(c.w->u[ui]), c.F, P, u.Cout, n->d.gn_groups,
+                     c.at<float2>(c.w->st[ui]), c.pf(u.g), du, dres, c.grad + u.g, c.grad + u.b,
+                     c.at<float2>(c.w->gbpart), c.at<float2>(c.w->gcoef), u.S, c.s);
+  const ConvGeo g = geo(u, c.F);
+  const long R = (long)c.F * P, Kw = (long)u.K * u.K * u.Cin;
+  gemm_conv_wgrad(n->prec, g, x, du, epi(c.grad + u.w, (int)Kw), c.splits(u.Cout, Kw, R), c.splitk(),
+                  c.s);
+  if (dx) {
+    const long M = (long)c.F * u.Hin * u.Win, K = (long)u.K * u.K * u.Cout;
+    gemm_conv_dgrad(n->prec, g, du, c.wt(u.w), epi(dx, u.Cin, nullptr, 0, dx_acc ? 1 : 0),
+                    c.splits(M, u.Cin, K), c.splitk(), c.s);
+  }
+}
+
+void encoder_bwd(const Ctx& c, const float* dfeat) {
+  const ppo_net* n = c.n;
+  const WsLayout& w = *c.w;
+  const float* x0 = c.at(w.x0);
+  float *GA = c.at(w.ga), *GB = c.at(w.gb), *GU = c.at(w.gu), *GD = c.at(w.gd), *GR = c.at(w.gr);
+  if (n->d.trunk == PPO_TRUNK_TINY) {
+    unit_bwd(c, 1, dfeat, c.at(w.a[1]), true, c.at(w.a[0]), GU, GD, false, nullptr);
+    unit_bwd(c, 0, GD, c.at(w.a[0]), false, x0, GU, nullptr, false, nullptr);
+    return;
+  }
+  // compress: input = last block output
+  const Block& last = n->blocks.back();
+  unit_bwd(c, n->compress, dfeat, c.at(w.a[n->compress]), true, c.at(w.a[last.c3]), GU, GA, false,
+           nullptr);
+  for (int bi = (int)n->blocks.size() - 1; bi >= 0; --bi) {
+    const Block& b = n->blocks[bi];
+    const float* xin = bi == 0 ? c.at(w.pool) : c.at(w.a[n->blocks[bi - 1].c3]);
+    // GA: gradient at the block output (before its ReLU mask)
+    float* dres = b.ds >= 0 ? GR : GB;  // identity: the shortcut gradient seeds dX
+    unit_bwd(c, b.c3, GA, c.at(w.a[b.c3]), false, c.at(w.a[b.c2]), GU, GD, false, dres);
+    unit_bwd(c, b.c2, GD, c.at(w.a[b.c2]), false, c.at(w.a[b.c1]), GU, GD, false, nullptr);
+    if (b.ds >= 0) {
+      // c1 first (its du must not be overwritten before its data gradient)
+      const Unit& u1 = n->units[b.c1];
+      const int P1 = u1.Hout * u1.Wout;
+      launch_gn_backward(GD, c.at(w.a[b.c1]), 0, c.at(w.u[b.c1]), c.F, P1, u1.Cout, n->d.gn_groups,
+                         c.at<float2>(w.st[b.c1]), c.pf(u1.g), GU, nullptr, c.grad + u1.g, c.grad + u1.b,
+                         c.at<float2>(w.gbpart), c.at<float2>(w.gcoef), u1.S, c.s);
+      const ConvGeo g1 = geo(u1, c.F);
+      const long R1 = (long)c.F * P1, K1 = (long)u1.Cin;
+      gemm_conv_wgrad(n->prec, g1, xin, GU, epi(c.grad + u1.w, (int)K1), c.splits(u1.Cout, K1, R1),
+                      c.splitk(), c.s);
+      // projection shortcut: writes dX, then c1's data gradient accumulates
+      unit_bwd(c, b.ds, GR, nullptr, false, xin, GD, GB, false, nullptr);
+      const long M = (long)c.F * u1.Hin * u1.Win;
+      gemm_conv_dgrad(n->prec, g1, GU, c.wt(u1.w), epi(GB, u1.Cin, nullptr, 0, 1),
+                      c.splits(M, u1.Cin, u1.Cout), c.splitk(), c.s);
+    } else {
+      unit_bwd(c, b.c1, GD, c.at(w.a[b.c1]), false, xin, GU, GB, true, nullptr);
+    }
+    std::swap(GA, GB);
+  }
+  // GA = gradient at the max pool output
+  const Unit& S = n->units[n->stem];
+  launch_maxpool_bwd(GA, c.at<uint8_t>(w.arg), c.F, S.Hout, S.Wout, S.Cout, GD, c.s);
+  unit_bwd(c, n->stem, GD, c.at(w.a[n->stem]), false, x0, GU, nullptr, false, nullptr);
+}
+
+hipStream_t strm(void* s) { return (hipStream_t)s; }
+
+ppo_status check_launch() {
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return fail(PPO_EDEVICE, "HIP launch failed: %s", hipGetErrorString(e));
+  return PPO_OK;
+}
+
+bool al256(const void* p) { return (((uintptr_t)p) & 255) == 0; }
+
+}  // namespace
+
+// ===================================================================== ABI
+extern "C" {
+
+const char* ppo_last_error(void) { return g_err.c_str(); }
+
+ppo_status ppo_net_create(const ppo_net_desc* desc, ppo_net** out) {
+  if (!desc || !out) return fail(PPO_EINVAL, "null argument");
+  *out = nullptr;
+  ppo_net* n = new (std::nothrow) ppo_net();
+  if (!n) return fail(PPO_EINVAL, "out of host memory");
+  n->d = *desc;
+  const ppo_status st = build(n);
+  if (st != PPO_OK) {
+    delete n;
+    return st;
+  }
+  *out = n;
+  return PPO_OK;
+}
+
+void ppo_net_destroy(ppo_net* net) { delete net; }
+
+size_t ppo_param_count(const ppo_net* net) { return net ? net->P : 0; }
+
+ppo_status ppo_param_tensor(const ppo_net* net, int i, const char** name, size_t* offset, size_t* count) {
+  if (!net || i < 0 || i >= (int)net->tensors.size()) return fail(PPO_EINVAL, "tensor index out of range");
+  if (name) *name = net->tensors[i].name.c_str();
+  if (offset) *offset = net->tensors[i].off;
+  if (count) *count = net->tensors[i].count;
+  return PPO_OK;
+}
+
+ppo_status ppo_workspace_size(const ppo_net* net, int op, int max_frames, int max_envs, size_t* bytes) {
+  if (!net || !bytes) return fail(PPO_EINVAL, "null argument");
+  if (max_frames <= 0 || (op == PPO_OP_LEARN && (max_envs <= 0 || max_envs > kMaxMbEnvs)))
+    return fail(PPO_ESHAPE, "bad max_frames / max_envs");
+  if (op != PPO_OP_ACT && op != PPO_OP_LEARN) return fail(PPO_EINVAL, "unknown op");
+  *bytes = plan(net, max_frames, max_envs, op == PPO_OP_LEARN).total;
+  return PPO_OK;
+}
+
+ppo_status ppo_act(ppo_net* net, const ppo_act_io* io, void* ws, size_t ws_bytes, void* stream) {
+  if (!net || !io) return fail(PPO_EINVAL, "null argument");
+  const ppo_net_desc& d = net->d;
+  const int B = io->batch;
+  if (B <= 0) return fail(PPO_ESHAPE, "batch must be positive");
+  if (!io->obs || !io->goal || !io->mask || !io->h_in || !io->c_in || !io->u || !io->params ||
+      !io->action || !io->logp || !io->value || !io->h_out || !io->c_out ||
+      (d.prev_act_dim > 0 && !io->prev_action) || (net->prec && !io->params_lp))
+    return fail(PPO_EINVAL, "null pointer in ppo_act_io");
+  const int SR = io->state_rows > 0 ? io->state_rows : B;
+  if (SR < B) return fail(PPO_ESHAPE, "state_rows < batch");
+  const WsLayout w = plan(net, B, 1, false);
+  if (!ws || ws_bytes < w.total) return fail(PPO_EWORKSPACE, "workspace needs %zu bytes", w.total);
+  if (!al256(ws)) return fail(PPO_EWORKSPACE, "workspace must be 256-byte aligned");
+  hipStream_t s = strm(stream);
+  Ctx c{net, &w, (char*)ws, io->params, io->params_lp, nullptr, s, B};
+  const int H = d.hidden, L = d.lstm_layers, A = d.num_actions;
+  // frames -> encoder -> features
+  launch_prep(io->obs, net->prec, nullptr, B, d.in_ch, d.in_hw, d.in_hw, d.avgpool, c.at(w.x0), s);
+  const float* feat = encoder_fwd(c);
+  // layer-0 input [B][din0 + H] = [relu(FC(feat)) | goal | emb | mask*h0]
+  const int ld0 = net->din0 + H;
+  float* zh = c.at(w.zh);
+  gemm_dense(net->prec, false, false, feat, net->flat, c.wt(net->fc_w), net->prec == 1, net->flat, B,
+             d.vis_hidden, net->flat, epi(zh, ld0, c.pf(net->fc_b), 1),
+             c.splits(B, d.vis_hidden, net->flat), c.splitk(), s);
+  launch_embed_fwd(io->goal, io->prev_action, io->mask, nullptr, B, d.goal_mode == PPO_GOAL_POLAR,
+                   d.goal_dim, d.goal_mode == PPO_GOAL_POLAR ? c.pf(net->goal_w) : nullptr,
+                   d.goal_mode == PPO_GOAL_POLAR ? c.pf(net->goal_b) : nullptr, std::max(0, d.prev_act_dim),
+                   d.prev_act_dim > 0 ? c.pf(net->emb) : nullptr, zh, ld0, d.vis_hidden, s);
+  // masked recurrent state of every layer, read before any output is written
+  std::vector<float*> zl(L), cpl(L);
+  for (int l = 0; l < L; ++l) {
+    const int din = l == 0 ? net->din0 : H;
+    zl[l] = l == 0 ? zh : c.at(w.g[l]);  // layer l>0 input buffer [B][2H] (reuses its gate slab)
+    cpl[l] = c.at(w.cp[l]);
+    launch_mask_state(io->h_in + (size_t)l * SR * H, io->c_in + (size_t)l * SR * H, io->mask, B, H,
+                      zl[l] + din, din + H, cpl[l], s);
+  }
+  float* G = c.at(w.g[0]);  // gates [B][4H]; the layer-0 input lives in zh
+  for (int l = 0; l < L; ++l) {
+    const int din = l == 0 ? net->din0 : H;
+    gemm_dense(net->prec, false, false, zl[l], din + H, c.wt(net->lstm_w[l]), net->prec == 1, din + H, B,
+               4 * H, din + H, epi(G, 4 * H, c.pf(net->lstm_b[l])), c.splits(B, 4 * H, din + H),
+               c.splitk(), s);
+    const bool top = l == L - 1;
+    float* hdst = top ? io->h_out + (size_t)l * SR * H : zl[l + 1];
+    const int ldh = top ? H : 2 * H;
+    launch_lstm_fwd(G, cpl[l], hdst, ldh, io->c_out + (size_t)l * SR * H, B, H, nullptr, 0, nullptr,
+                    nullptr, s);
+    if (!top) launch_copy2d(hdst, ldh, B, H, io->h_out + (size_t)l * SR * H, H, s);
+  }
+  launch_act_head(io->h_out + (size_t)(L - 1) * SR * H, B, H, A, c.pf(net->head_w), c.pf(net->head_b),
+                  io->u, io->action, io->logp, io->value, io->logits, s);
+  return check_launch();
+}
+
+ppo_status ppo_gae(const float* rew, const float* val, const uint8_t* done, const int32_t* len, int T,
+                   int N, float gamma, float lambda, float* adv, float* ret, double* adv_stats,
+                   void* stream) {
+  if (!rew || !val || !done || !adv || !ret) return fail(PPO_EINVAL, "null argument");
+  if (T <= 0 || N <= 0) return fail(PPO_ESHAPE, "T and N must be positive");
+  if (!(gamma >= 0.f && gamma <= 1.f) || !(lambda >= 0.f && lambda <= 1.f))
+    return fail(PPO_EINVAL, "gamma and lambda must lie in [0, 1]");
+  launch_gae(rew, val, done, len, T, N, gamma, lambda, adv, ret, adv_stats, strm(stream));
+  return check_launch();
+}
+
+ppo_status ppo_loss_backward(ppo_net* net, const ppo_batch* b, const ppo_loss_cfg* cfg,
+                             const float* d_loss_scale, float* grad, float* stats, void* ws,
+                             size_t ws_bytes, void* stream) {
+  if (!net || !b || !cfg || !grad || !stats) return fail(PPO_EINVAL, "null argument");
+  const ppo_net_desc& d = net->d;
+  if (!b->env_ids || !b->obs || !b->goal || !b->mask || !b->action || !b->logp_old || !b->adv ||
+      !b->ret || !b->h0 || !b->c0 || !b->params || (net->prec && !b->params_lp) ||
+      (d.prev_act_dim > 0 && !b->prev_action) || (cfg->norm_adv && !cfg->adv_stats))
+    return fail(PPO_EINVAL, "null pointer in ppo_batch");
+  if (b->T <= 0 || b->N <= 0 || b->nb <= 0 || b->nb > b->N || b->nb > kMaxMbEnvs)
+    return fail(PPO_ESHAPE, "bad T / N / nb");
+  // length-sorted env list (descending, stable)
+  MapArgs m{};
+  m.nb = b->nb;
+  m.N = b->N;
+  m.T = b->T;
+  std::vector<std::pair<int, int>> order;
+  for (int j = 0; j < b->nb; ++j) {
+    const int e = b->env_ids[j];
+    if (e < 0 || e >= b->N) return fail(PPO_ESHAPE, "env id %d out of range", e);
+    const int len = b->lengths ? b->lengths[e] : b->T;
+    if (len < 1 || len > b->T) return fail(PPO_ESHAPE, "length %d of env %d outside 1..T", len, e);
+    order.push_back({len, e});
+  }
+  std::stable_sort(order.begin(), order.end(), [](const std::pair<int, int>& x, const std::pair<int, int>& y) {
+    return x.first > y.first;
+  });
+  int F = 0;
+  for (int j = 0; j < b->nb; ++j) {
+    m.env[j] = order[j].second;
+    m.len[j] = order[j].first;
+    F += order[j].first;
+  }
+  m.F = F;
+  const int TB = m.len[0];
+  std::vector<int> act(TB + 1, 0), off(TB + 1, 0);
+  for (int t = 0; t < TB; ++t) {
+    for (int j = 0; j < b->nb; ++j) act[t] += (m.len[j] > t);
+    off[t + 1] = off[t] + act[t];
+  }
+  const WsLayout w = plan(net, F, b->nb, true);
+  if (!ws || ws_bytes < w.total) return fail(PPO_EWORKSPACE, "workspace needs %zu bytes", w.total);
+  if (!al256(ws)) return fail(PPO_EWORKSPACE, "workspace must be 256-byte aligned");
+  hipStream_t s = strm(stream);
+  Ctx c{net, &w, (char*)ws, b->params, b->params_lp, grad, s, F};
+  const int H = d.hidden, L = d.lstm_layers, A = d.num_actions, nb = b->nb;
+  const int32_t* src = c.at<int32_t>(w.src);
+  const float* wf = c.at(w.wf);
+  const float* mskf = c.at(w.mskf);
+  const int32_t* envrow = c.at<int32_t>(w.envrow);
+  launch_frame_map(m, b->mask, c.at<int32_t>(w.src), c.at(w.wf), c.at(w.mskf), c.at<int32_t>(w.envrow), s);
+  launch_gather_state(b->h0, L, b->N, nb, H, envrow, c.at(w.h0g), s);
+  launch_gather_state(b->c0, L, b->N, nb, H, envrow, c.at(w.c0g), s);
+
+  // ---- forward
+  launch_prep(b->obs, net->prec, src, F, d.in_ch, d.in_hw, d.in_hw, d.avgpool, c.at(w.x0), s);
+  const float* feat = encoder_fwd(c);
+  const int D0 = net->din0;
+  float* Z = c.at(w.z);
+  gemm_dense(net->prec, false, false, feat, net->flat, c.wt(net->fc_w), net->prec == 1, net->flat, F,
+             d.vis_hidden, net->flat, epi(Z, D0, c.pf(net->fc_b), 1), c.splits(F, d.vis_hidden, net->flat),
+             c.splitk(), s);
+  const bool polar = d.goal_mode == PPO_GOAL_POLAR;
+  const int E = std::max(0, d.prev_act_dim);
+  launch_embed_fwd(b->goal, b->prev_action, b->mask, src, F, polar, d.goal_dim,
+                   polar ? c.pf(net->goal_w) : nullptr, polar ? c.pf(net->goal_b) : nullptr, E,
+                   E ? c.pf(net->emb) : nullptr, Z, D0, d.vis_hidden, s);
+  for (int l = 0; l < L; ++l) {
+    const int din = l == 0 ? D0 : H;
+    const float* X = l == 0 ? Z : c.at(w.hout[l - 1]);
+    const size_t wl = net->lstm_w[l];
+    float *G = c.at(w.g[l]), *HP = c.at(w.hp[l]), *CP = c.at(w.cp[l]), *Cs = c.at(w.c[l]),
+          *Ho = c.at(w.hout[l]);
+    // input projection of every frame at once
+    gemm_dense(net->prec, false, false, X, din, c.wt(wl), net->prec == 1, din + H, F, 4 * H, din,
+               epi(G, 4 * H, c.pf(net->lstm_b[l])), c.splits(F, 4 * H, din), c.splitk(), s);
+    launch_mask_state(c.at(w.h0g) + (size_t)l * nb * H, c.at(w.c0g) + (size_t)l * nb * H, mskf, act[0], H,
+                      HP, H, CP, s);
+    for (int t = 0; t < TB; ++t) {
+      const size_t r0 = off[t];
+      const int rows = act[t];
+      const void* whh = net->prec ? (const void*)((const bf16_t*)b->params_lp + wl + din)
+                                  : (const void*)(b->params + wl + din);
+      gemm_dense(net->prec, false, false, HP + r0 * H, H, whh, net->prec == 1, din + H, rows, 4 * H, H,
+                 epi(G + r0 * 4 * H, 4 * H, nullptr, 0, 1), c.splits(rows, 4 * H, H), c.splitk(), s);
+      const bool more = t + 1 < TB;
+      launch_lstm_fwd(G + r0 * 4 * H, CP + r0 * H, Ho + r0 * H, H, Cs + r0 * H, rows, H,
+                      more ? mskf + off[t + 1] : nullptr, more ? act[t + 1] : 0,
+                      more ? HP + (size_t)off[t + 1] * H : nullptr, more ? CP + (size_t)off[t + 1] * H : nullptr,
+                      s);
+    }
+  }
+  const float* Htop = c.at(w.hout[L - 1]);
+  float* dout = c.at(w.dout);
+  float* dH = c.at(w.dh0);
+  launch_loss_head(Htop, F, H, A, c.pf(net->head_w), c.pf(net->head_b), src, b->action, b->logp_old, b->adv,
+                   b->ret, wf, cfg->clip, cfg->value_coef, cfg->entropy_coef, cfg->norm_adv, cfg->adv_stats,
+                   net->prec ? d_loss_scale : nullptr, c.at(w.fstat), dout, dH, stats, s);
+
+  // ---- backward
+  gemm_dense(net->prec, true, true, dout, A + 1, Htop, false, H, A + 1, H, F,
+             epi(grad + net->head_w, H), c.splits(A + 1, H, F), c.splitk(), s);
+  launch_colsum(dout, F, A + 1, A + 1, grad + net->head_b, s);
+  float* dHn = c.at(w.dh1);
+  for (int l = L - 1; l >= 0; --l) {
+    const int din = l == 0 ? D0 : H;
+    const float* X = l == 0 ? Z : c.at(w.hout[l - 1]);
+    const size_t wl = net->lstm_w[l];
+    float *G = c.at(w.g[l]), *HP = c.at(w.hp[l]), *CP = c.at(w.cp[l]), *Cs = c.at(w.c[l]);
+    float *dG = c.at(w.dG), *dhp = c.at(w.dhp), *dcp = c.at(w.dcp);
+    const void* whh = net->prec ? (const void*)((const bf16_t*)b->params_lp + wl + din)
+                                : (const void*)(b->params + wl + din);
+    for (int t = TB - 1; t >= 0; --t) {
+      const size_t r0 = off[t];
+      const int rows = act[t];
+      const bool more = t + 1 < TB;
+      launch_lstm_bwd(G + r0 * 4 * H, Cs + r0 * H, CP + r0 * H, dH + r0 * H, H, rows, H,
+                      more ? mskf + off[t + 1] : nullptr, more ? act[t + 1] : 0, more ? dhp : nullptr,
+                      more ? dcp : nullptr, dG + r0 * 4 * H, dcp, s);
+      if (t > 0)  // gradient into the masked previous h
+        gemm_dense(net->prec, false, true, dG + r0 * 4 * H, 4 * H, whh, net->prec == 1, din + H, rows, H,
+                   4 * H, epi(dhp, H), c.splits(rows, H, 4 * H), c.splitk(), s);
+    }
+    // weight gradients over all frames
+    gemm_dense(net->prec, true, true, dG, 4 * H, X, false, din, 4 * H, din, F, epi(grad + wl, din + H),
+               c.splits(4 * H, din, F), c.splitk(), s);
+    gemm_dense(net->prec, true, true, dG, 4 * H, HP, false, H, 4 * H, H, F, epi(grad + wl + din, din + H),
+               c.splits(4 * H, H, F), c.splitk(), s);
+    launch_colsum(dG, F, 4 * H, 4 * H, grad + net->lstm_b[l], s);
+    // gradient into the layer input
+    gemm_dense(net->prec, false, true, dG, 4 * H, c.wt(wl), net->prec == 1, din + H, F, din, 4 * H,
+               epi(dHn, din), c.splits(F, din, 4 * H), c.splitk(), s);
+    std::swap(dH, dHn);
+  }
+  // dH = gradient at Z [F][D0]
+  float* dvis = c.at(w.dvis);
+  launch_relu_grad2d(dH, D0, Z, D0, F, d.vis_hidden, dvis, d.vis_hidden, s);
+  launch_embed_bwd(b->goal, b->prev_action, b->mask, src, F, polar, d.goal_dim, E, A + 1, dH, D0,
+                   d.vis_hidden, polar ? grad + net->goal_w : nullptr, polar ? grad + net->goal_b : nullptr,
+                   E ? grad + net->emb : nullptr, s);
+  gemm_dense(net->prec, true, true, dvis, d.vis_hidden, feat, false, net->flat, d.vis_hidden, net->flat, F,
+             epi(grad + net->fc_w, net->flat), c.splits(d.vis_hidden, net->flat, F), c.splitk(), s);
+  launch_colsum(dvis, F, d.vis_hidden, d.vis_hidden, grad + net->fc_b, s);
+  float* dfeat = c.at(w.dfeat);
+  gemm_dense(net->prec, false, true, dvis, d.vis_hidden, c.wt(net->fc_w), net->prec == 1, net->flat, F,
+             net->flat, d.vis_hidden, epi(dfeat, net->flat), c.splits(F, net->flat, d.vis_hidden), c.splitk(),
+             s);
+  encoder_bwd(c, dfeat);
+  return check_launch();
+}
+
+size_t ppo_adam_workspace_size(size_t P) {
+  (void)P;
+  return adam_ws_bytes();
+}
+
+ppo_status ppo_adam_step(float* master, const float* grad, float* m, float* v, void* lp_copy, size_t P,
+                         const ppo_adam_cfg* cfg, ppo_scaler* scaler, void* ws, size_t ws_bytes,
+                         void* stream) {
+  if (!master || !grad || !m || !v || !cfg || !scaler) return fail(PPO_EINVAL, "null argument");
+  if (P == 0) return fail(PPO_ESHAPE, "empty parameter vector");
+  if (!ws || ws_bytes < adam_ws_bytes()) return fail(PPO_EWORKSPACE, "adam workspace too small");
+  if (!(cfg->lr > 0.f) || !(cfg->beta1 >= 0.f && cfg->beta1 < 1.f) || !(cfg->beta2 >= 0.f && cfg->beta2 < 1.f) ||
+      !(cfg->eps > 0.f))
+    return fail(PPO_EINVAL, "bad Adam hyper-parameters");
+  launch_adam(master, grad, m, v, (bf16_t*)lp_copy, P, cfg->lr, cfg->beta1, cfg->beta2, cfg->eps,
+              cfg->growth_interval, scaler, ws, strm(stream));
+  return check_launch();
+}
+
+ppo_status ppo_cast_bf16(const float* src, void* dst, size_t n, void* stream) {
+  if (!src || !dst) return fail(PPO_EINVAL, "null argument");
+  if (n == 0) return PPO_OK;
+  launch_cast_bf16(src, (bf16_t*)dst, n, strm(stream));
+  return check_launch();
+}
+
+}  // extern "C"

@@ -1,0 +1,107 @@
+// Host-side launchers of the device kernels (all asynchronous on stream s).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <algorithm>
+
+#include "../../include/ddppo.h"
+
+typedef uint16_t bf16_t;
+
+// Convolution geometry (NHWC activations, weights [Co][KH][KW][C]).
+struct ConvGeo {
+  int B, H, W, C;  // input
+  int Ho, Wo, Co;  // output
+  int KH, KW, stride, pad;
+};
+
+// GEMM epilogue: C = alpha * acc (+ C if accumulate) (+ bias[n]) (ReLU).
+struct Epi {
+  float* C;
+  int ldc;
+  const float* bias;
+  float alpha;
+  int relu;
+  int accumulate;
+  float* partial;  // set by the launcher for split-K
+};
+
+inline Epi epi(float* C, int ldc, const float* bias = nullptr, int relu = 0, int accumulate = 0) {
+  return Epi{C, ldc, bias, 1.0f, relu, accumulate, nullptr};
+}
+
+constexpr int kMaxMbEnvs = 256;
+struct MapArgs {
+  int F, nb, N, T;
+  int env[kMaxMbEnvs];  // length-sorted (descending) env ids
+  int len[kMaxMbEnvs];
+};
+
+// gemm.hip (prec: 0 float32 operands, 1 bfloat16 operands)
+int gemm_max_splits_for(long M, long N, long K, int prec);
+void gemm_conv_fwd(int prec, const ConvGeo& g, const float* x, const void* w, Epi e, int splits,
+                   float* partial, hipStream_t s);
+void gemm_conv_dgrad(int prec, const ConvGeo& g, const float* dy, const void* w, Epi e, int splits,
+                     float* partial, hipStream_t s);
+void gemm_conv_wgrad(int prec, const ConvGeo& g, const float* x, const float* dy, Epi e, int splits,
+                     float* partial, hipStream_t s);
+void gemm_dense(int prec, bool ta, bool tb, const float* a, int lda, const void* b, bool b_lp, int ldb,
+                int M, int N, int K, Epi e, int splits, float* partial, hipStream_t s);
+
+// norm.hip
+void launch_gn_forward(const float* y, int B, int P, int C, int G, float eps, const float* gamma,
+                       const float* beta, const float* res, int relu, float* out, int out_chw,
+                       float2* stats, float4* part, int S, hipStream_t s);
+void launch_gn_backward(const float* dout, const float* out, int chw, const float* y, int B, int P,
+                        int C, int G, const float2* stats, const float* gamma, float* dy, float* dres,
+                        float* dgamma, float* dbeta, float2* bpart, float2* coef, int S, hipStream_t s);
+void launch_maxpool_fwd(const float* x, int B, int H, int W, int C, float* y, uint8_t* arg,
+                        hipStream_t s);
+void launch_maxpool_bwd(const float* dy, const uint8_t* arg, int B, int H, int W, int C, float* dx,
+                        hipStream_t s);
+void launch_prep(const void* obs, int bf16, const int32_t* src, int F, int C, int Hin, int Win, int pool,
+                 float* x0, hipStream_t s);
+void launch_relu_grad(const float* dy, const float* y, size_t n, float* dx, hipStream_t s);
+
+// lstm.hip
+void launch_lstm_fwd(float* G, const float* cp, float* h, int ldh, float* c, int rows, int H,
+                     const float* mask_next, int rows_next, float* hp_next, float* cp_next,
+                     hipStream_t s);
+void launch_mask_state(const float* h_in, const float* c_in, const float* mask, int rows, int H,
+                       float* hp, int ldhp, float* cp, hipStream_t s);
+void launch_lstm_bwd(const float* act, const float* c, const float* cp, const float* dh_in, int ldd,
+                     int rows, int H, const float* mask_next, int rows_next, const float* dhp_next,
+                     const float* dcp_next, float* dG, float* dcp, hipStream_t s);
+void launch_colsum(const float* in, int rows, int cols, int ld, float* out, hipStream_t s);
+
+// head.hip
+void launch_act_head(const float* htop, int rows, int H, int A, const float* W, const float* b,
+                     const float* u, int32_t* action, float* logp, float* value, float* logits,
+                     hipStream_t s);
+void launch_loss_head(const float* htop, int F, int H, int A, const float* W, const float* b,
+                      const int32_t* src, const int32_t* actions, const float* logp_old, const float* adv,
+                      const float* ret, const float* wf, float clip, float vcoef, float ecoef,
+                      int norm_adv, const double* adv_stats, const float* loss_scale, float* fstat,
+                      float* dout, float* dh, float* stats, hipStream_t s);
+void launch_embed_fwd(const float* goal, const int32_t* prev_a, const float* mask, const int32_t* src,
+                      int F, int polar, int goal_dim, const float* gw, const float* gb, int E,
+                      const float* emb, float* Z, int ldz, int zoff, hipStream_t s);
+void launch_embed_bwd(const float* goal, const int32_t* prev_a, const float* mask, const int32_t* src,
+                      int F, int polar, int goal_dim, int E, int A1, const float* dZ, int ldz, int zoff,
+                      float* dgw, float* dgb, float* demb, hipStream_t s);
+void launch_relu_grad2d(const float* dy, int ldd, const float* y, int ldy, int rows, int cols, float* dx,
+                        int ldx, hipStream_t s);
+void launch_frame_map(const MapArgs& m, const float* mask, int32_t* src, float* w, float* msk,
+                      int32_t* env_row, hipStream_t s);
+void launch_gather_state(const float* srcs, int L, int N, int nb, int H, const int32_t* env_row,
+                         float* dst, hipStream_t s);
+void launch_copy2d(const float* s_, int lds, int rows, int cols, float* d, int ldd, hipStream_t s);
+
+// gae_adam.hip
+void launch_gae(const float* rew, const float* val, const uint8_t* done, const int32_t* len, int T, int N,
+                float gamma, float lambda, float* adv, float* ret, double* stats, hipStream_t s);
+size_t adam_ws_bytes();
+void launch_adam(float* th, const float* g, float* m, float* v, bf16_t* lp, size_t P, float lr, float b1,
+                 float b2, float eps, int growth, ppo_scaler* sc, void* ws, hipStream_t s);
+void launch_cast_bf16(const float* src, bf16_t* dst, size_t n, hipStream_t s);

@@ -1,0 +1,397 @@
+// GroupNorm forward/backward, max pool 3x3/2, frame preparation (2x2 average
+// pool + NCHW -> NHWC), and small elementwise helpers.
+//
+// Activations are [B][P][C] (NHWC, P = H*W pixels).  GroupNorm statistics are
+// gathered in two steps: every workgroup reduces one chunk of pixels of one
+// image for all channels into per-channel shifted sums, then one wavefront
+// per (image, group) merges the chunk results in float64 with the exact
+// parallel-variance formula.
+#include "common.h"
+#include "kernels.h"
+
+// ------------------------------------------------------------------ forward
+// part[(b*S + s)*C + c] = {sum(y - K), sum((y - K)^2), K}, K = y at the chunk's
+// first pixel.
+__global__ void __launch_bounds__(256) gn_partial_kernel(const float* __restrict__ y, int P, int C,
+                                                         int S, float4* __restrict__ part) {
+  __shared__ float s1[256], s2[256];
+  const int b = blockIdx.y, s = blockIdx.x, tid = threadIdx.x;
+  const int chunk = (P + S - 1) / S;
+  const int p0 = s * chunk, p1 = min(P, p0 + chunk);
+  const float* yb = y + (size_t)b * P * C;
+  const int CT = C < 256 ? C : 256;  // channels handled per pass
+  const int PR = 256 / CT;           // pixel lanes
+  const int c0 = tid % CT, pr = tid / CT;
+  for (int cb = 0; cb < C; cb += CT) {
+    const int c = cb + c0;
+    float a = 0.f, q = 0.f, K = 0.f;
+    if (p0 < p1 && pr < PR) {
+      K = yb[(size_t)p0 * C + c];
+      for (int p = p0 + pr; p < p1; p += PR) {
+        const float d = yb[(size_t)p * C + c] - K;
+        a += d;
+        q += d * d;
+      }
+    }
+    s1[tid] = a;
+    s2[tid] = q;
+    __syncthreads();
+    if (pr == 0) {
+      for (int r = 1; r < PR; ++r) {
+        a += s1[r * CT + c0];
+        q += s2[r * CT + c0];
+      }
+      part[((size_t)b * S + s) * C + c] = make_float4(a, q, K, (float)max(0, p1 - p0));
+    }
+    __syncthreads();
+  }
+}
+
+// One wavefront per (b, g): mean and 1/sqrt(var + eps) of the group.
+__global__ void __launch_bounds__(256) gn_finalize_kernel(const float4* __restrict__ part, int B, int S,
+                                                          int C, int G, float eps,
+                                                          float2* __restrict__ stats) {
+  const int wid = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+  if (wid >= B * G) return;
+  const int b = wid / G, g = wid % G, Cg = C / G;
+  const int nparts = S * Cg;
+  double sn = 0.0, sx = 0.0;
+  for (int i = lane; i < nparts; i += 64) {
+    const int s = i / Cg, c = g * Cg + i % Cg;
+    const float4 v = part[((size_t)b * S + s) * C + c];
+    sn += (double)v.w;
+    sx += (double)v.w * (double)v.z + (double)v.x;  // n K + sum(y - K)
+  }
+  sn = wave_sum(sn);
+  sx = wave_sum(sx);
+  const double mean = sn > 0 ? sx / sn : 0.0;
+  double m2 = 0.0;
+  for (int i = lane; i < nparts; i += 64) {
+    const int s = i / Cg, c = g * Cg + i % Cg;
+    const float4 v = part[((size_t)b * S + s) * C + c];
+    if (v.w > 0) {
+      const double n = v.w, mi = (double)v.z + (double)v.x / n;
+      const double m2i = (double)v.y - (double)v.x * (double)v.x / n;
+      const double d = mi - mean;
+      m2 += m2i + n * d * d;
+    }
+  }
+  m2 = wave_sum(m2);
+  if (lane == 0) {
+    const double var = sn > 0 ? fmax(m2 / sn, 0.0) : 0.0;
+    stats[wid] = make_float2((float)mean, (float)(1.0 / sqrt(var + (double)eps)));
+  }
+}
+
+// out = [relu]( (y - mean) rstd gamma + beta [+ res] ), written NHWC or,
+// with out_chw, as [B][C][P].
+__global__ void __launch_bounds__(256) gn_apply_kernel(const float* __restrict__ y, int B, int P,
+                                                       int C, int G, const float2* __restrict__ stats,
+                                                       const float* __restrict__ gamma,
+                                                       const float* __restrict__ beta,
+                                                       const float* __restrict__ res, int relu,
+                                                       float* __restrict__ out, int out_chw) {
+  const size_t n4 = (size_t)B * P * C / 4;
+  const int Cg = C / G;
+  for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n4; i += (size_t)gridDim.x * 256) {
+    const size_t e = i * 4;
+    const int c = (int)(e % C);
+    const size_t bp = e / C;
+    const int b = (int)(bp / P), p = (int)(bp % P);
+    const float4 v = *(const float4*)(y + e);
+    float r[4] = {v.x, v.y, v.z, v.w};
+    float4 rr = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (res) rr = *(const float4*)(res + e);
+    const float ra[4] = {rr.x, rr.y, rr.z, rr.w};
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const float2 st = stats[b * G + (c + j) / Cg];
+      float o = (r[j] - st.x) * st.y * gamma[c + j] + beta[c + j] + ra[j];
+      if (relu) o = fmaxf(o, 0.f);
+      r[j] = o;
+    }
+    if (!out_chw) {
+      *(float4*)(out + e) = make_float4(r[0], r[1], r[2], r[3]);
+    } else {
+#pragma unroll
+      for (int j = 0; j < 4; ++j) out[((size_t)b * C + c + j) * P + p] = r[j];
+    }
+  }
+}
+
+void launch_gn_forward(const float* y, int B, int P, int C, int G, float eps, const float* gamma,
+                       const float* beta, const float* res, int relu, float* out, int out_chw,
+                       float2* stats, float4* part, int S, hipStream_t s) {
+  hipLaunchKernelGGL(gn_partial_kernel, dim3(S, B), dim3(256), 0, s, y, P, C, S, part);
+  hipLaunchKernelGGL(gn_finalize_kernel, dim3(cdiv((long)B * G, 4)), dim3(256), 0, s, part, B, S, C,
+                     G, eps, stats);
+  const size_t n4 = (size_t)B * P * C / 4;
+  const int nb = (int)std::min<size_t>(8192, (n4 + 255) / 256);
+  hipLaunchKernelGGL(gn_apply_kernel, dim3(nb), dim3(256), 0, s, y, B, P, C, G, stats, gamma, beta,
+                     res, relu, out, out_chw);
+}
+
+// ----------------------------------------------------------------- backward
+// dz = dout * [out > 0] (when relu), xhat = (y - mean) rstd.
+// bpart[(b*S + s)*C + c] = {sum dz, sum dz xhat}.
+DEV size_t io_index(int b, int p, int c, int P, int C, int chw) {
+  return chw ? ((size_t)b * C + c) * P + p : ((size_t)b * P + p) * C + c;
+}
+
+__global__ void __launch_bounds__(256) gnb_partial_kernel(const float* __restrict__ dout,
+                                                          const float* __restrict__ out, int chw,
+                                                          const float* __restrict__ y, int P, int C,
+                                                          int G, int S, const float2* __restrict__ stats,
+                                                          float2* __restrict__ bpart) {
+  __shared__ float s1[256], s2[256];
+  const int b = blockIdx.y, s = blockIdx.x, tid = threadIdx.x;
+  const int chunk = (P + S - 1) / S;
+  const int p0 = s * chunk, p1 = min(P, p0 + chunk);
+  const int CT = C < 256 ? C : 256;
+  const int PR = 256 / CT;
+  const int c0 = tid % CT, pr = tid / CT;
+  const int Cg = C / G;
+  for (int cb = 0; cb < C; cb += CT) {
+    const int c = cb + c0;
+    float a = 0.f, q = 0.f;
+    if (pr < PR) {
+      const float2 st = stats[b * G + c / Cg];
+      for (int p = p0 + pr; p < p1; p += PR) {
+        const size_t io = io_index(b, p, c, P, C, chw);
+        float dz = dout[io];
+        if (out && !(out[io] > 0.f)) dz = 0.f;
+        const float xh = (y[((size_t)b * P + p) * C + c] - st.x) * st.y;
+        a += dz;
+        q += dz * xh;
+      }
+    }
+    s1[tid] = a;
+    s2[tid] = q;
+    __syncthreads();
+    if (pr == 0) {
+      for (int r = 1; r < PR; ++r) {
+        a += s1[r * CT + c0];
+        q += s2[r * CT + c0];
+      }
+      bpart[((size_t)b * S + s) * C + c] = make_float2(a, q);
+    }
+    __syncthreads();
+  }
+}
+
+// coef[b*G+g] = {sum_c gamma_c sum dz / n, sum_c gamma_c sum dz xhat / n}
+__global__ void __launch_bounds__(256) gnb_coef_kernel(const float2* __restrict__ bpart, int B, int S,
+                                                       int C, int G, int P,
+                                                       const float* __restrict__ gamma,
+                                                       float2* __restrict__ coef) {
+  const int wid = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+  if (wid >= B * G) return;
+  const int b = wid / G, g = wid % G, Cg = C / G;
+  double a = 0.0, q = 0.0;
+  for (int i = lane; i < S * Cg; i += 64) {
+    const int s = i / Cg, c = g * Cg + i % Cg;
+    const float2 v = bpart[((size_t)b * S + s) * C + c];
+    a += (double)gamma[c] * v.x;
+    q += (double)gamma[c] * v.y;
+  }
+  a = wave_sum(a);
+  q = wave_sum(q);
+  if (lane == 0) {
+    const double n = (double)P * Cg;
+    coef[wid] = make_float2((float)(a / n), (float)(q / n));
+  }
+}
+
+// dgamma[c] = sum_{b,s} sum dz xhat, dbeta[c] = sum_{b,s} sum dz (one wavefront per channel)
+__global__ void __launch_bounds__(256) gnb_affine_kernel(const float2* __restrict__ bpart, int B, int S,
+                                                         int C, float* __restrict__ dgamma,
+                                                         float* __restrict__ dbeta) {
+  const int c = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+  if (c >= C) return;
+  double a = 0.0, q = 0.0;
+  for (int i = lane; i < B * S; i += 64) {
+    const float2 v = bpart[(size_t)i * C + c];
+    a += v.x;
+    q += v.y;
+  }
+  a = wave_sum(a);
+  q = wave_sum(q);
+  if (lane == 0) {
+    dgamma[c] = (float)q;
+    dbeta[c] = (float)a;
+  }
+}
+
+// dy = rstd (dz gamma - coef.x - xhat coef.y); dres (optional) = dz.  NHWC outputs.
+__global__ void __launch_bounds__(256) gnb_apply_kernel(const float* __restrict__ dout,
+                                                        const float* __restrict__ out, int chw,
+                                                        const float* __restrict__ y, int B, int P, int C,
+                                                        int G, const float2* __restrict__ stats,
+                                                        const float2* __restrict__ coef,
+                                                        const float* __restrict__ gamma,
+                                                        float* __restrict__ dy, float* __restrict__ dres) {
+  const size_t n = (size_t)B * P * C;
+  const int Cg = C / G;
+  for (size_t e = (size_t)blockIdx.x * 256 + threadIdx.x; e < n; e += (size_t)gridDim.x * 256) {
+    const int c = (int)(e % C);
+    const size_t bp = e / C;
+    const int b = (int)(bp / P), p = (int)(bp % P);
+    const size_t io = chw ? ((size_t)b * C + c) * P + p : e;
+    float dz = dout[io];
+    if (out && !(out[io] > 0.f)) dz = 0.f;
+    const int bg = b * G + c / Cg;
+    const float2 st = stats[bg], cf = coef[bg];
+    const float xh = (y[e] - st.x) * st.y;
+    dy[e] = st.y * (dz * gamma[c] - cf.x - xh * cf.y);
+    if (dres) dres[e] = dz;
+  }
+}
+
+void launch_gn_backward(const float* dout, const float* out, int chw, const float* y, int B, int P,
+                        int C, int G, const float2* stats, const float* gamma, float* dy, float* dres,
+                        float* dgamma, float* dbeta, float2* bpart, float2* coef, int S,
+                        hipStream_t s) {
+  hipLaunchKernelGGL(gnb_partial_kernel, dim3(S, B), dim3(256), 0, s, dout, out, chw, y, P, C, G, S,
+                     stats, bpart);
+  hipLaunchKernelGGL(gnb_coef_kernel, dim3(cdiv((long)B * G, 4)), dim3(256), 0, s, bpart, B, S, C, G,
+                     P, gamma, coef);
+  hipLaunchKernelGGL(gnb_affine_kernel, dim3(cdiv(C, 4)), dim3(256), 0, s, bpart, B, S, C, dgamma,
+                     dbeta);
+  const size_t n = (size_t)B * P * C;
+  const int nb = (int)std::min<size_t>(8192, (n + 255) / 256);
+  hipLaunchKernelGGL(gnb_apply_kernel, dim3(nb), dim3(256), 0, s, dout, out, chw, y, B, P, C, G, stats,
+                     coef, gamma, dy, dres);
+}
+
+// ------------------------------------------------------------------ pooling
+// 3x3 window, stride 2, padding 1; arg = index 0..8 of the first maximum in
+// row-major window order.
+__global__ void __launch_bounds__(256) maxpool_fwd_kernel(const float* __restrict__ x, int B, int H,
+                                                          int W, int C, int Ho, int Wo,
+                                                          float* __restrict__ y,
+                                                          uint8_t* __restrict__ arg) {
+  const size_t n = (size_t)B * Ho * Wo * C;
+  for (size_t e = (size_t)blockIdx.x * 256 + threadIdx.x; e < n; e += (size_t)gridDim.x * 256) {
+    const int c = (int)(e % C);
+    size_t r = e / C;
+    const int wo = (int)(r % Wo);
+    r /= Wo;
+    const int ho = (int)(r % Ho);
+    const int b = (int)(r / Ho);
+    float best = -INFINITY;
+    int bi = 0;
+    for (int kh = 0; kh < 3; ++kh) {
+      const int hi = 2 * ho - 1 + kh;
+      if (hi < 0 || hi >= H) continue;
+      for (int kw = 0; kw < 3; ++kw) {
+        const int wi = 2 * wo - 1 + kw;
+        if (wi < 0 || wi >= W) continue;
+        const float v = x[(((size_t)b * H + hi) * W + wi) * C + c];
+        if (v > best) {
+          best = v;
+          bi = kh * 3 + kw;
+        }
+      }
+    }
+    y[e] = best;
+    arg[e] = (uint8_t)bi;
+  }
+}
+
+// dx[b,h,w,c] = sum of dy over the (at most 4) windows whose winner is (h, w).
+__global__ void __launch_bounds__(256) maxpool_bwd_kernel(const float* __restrict__ dy,
+                                                          const uint8_t* __restrict__ arg, int B, int H,
+                                                          int W, int C, int Ho, int Wo,
+                                                          float* __restrict__ dx) {
+  const size_t n = (size_t)B * H * W * C;
+  for (size_t e = (size_t)blockIdx.x * 256 + threadIdx.x; e < n; e += (size_t)gridDim.x * 256) {
+    const int c = (int)(e % C);
+    size_t r = e / C;
+    const int w = (int)(r % W);
+    r /= W;
+    const int h = (int)(r % H);
+    const int b = (int)(r / H);
+    float acc = 0.f;
+    const int ho_lo = max(0, h / 2), ho_hi = min(Ho - 1, (h + 1) / 2);
+    const int wo_lo = max(0, w / 2), wo_hi = min(Wo - 1, (w + 1) / 2);
+    for (int ho = ho_lo; ho <= ho_hi; ++ho)
+      for (int wo = wo_lo; wo <= wo_hi; ++wo) {
+        const int kh = h - (2 * ho - 1), kw = w - (2 * wo - 1);
+        if (kh < 0 || kh > 2 || kw < 0 || kw > 2) continue;
+        const size_t o = (((size_t)b * Ho + ho) * Wo + wo) * C + c;
+        if (arg[o] == kh * 3 + kw) acc += dy[o];
+      }
+    dx[e] = acc;
+  }
+}
+
+void launch_maxpool_fwd(const float* x, int B, int H, int W, int C, float* y, uint8_t* arg,
+                        hipStream_t s) {
+  const int Ho = (H - 1) / 2 + 1, Wo = (W - 1) / 2 + 1;
+  const size_t n = (size_t)B * Ho * Wo * C;
+  hipLaunchKernelGGL(maxpool_fwd_kernel, dim3((int)std::min<size_t>(8192, (n + 255) / 256)), dim3(256),
+                     0, s, x, B, H, W, C, Ho, Wo, y, arg);
+}
+
+void launch_maxpool_bwd(const float* dy, const uint8_t* arg, int B, int H, int W, int C, float* dx,
+                        hipStream_t s) {
+  const int Ho = (H - 1) / 2 + 1, Wo = (W - 1) / 2 + 1;
+  const size_t n = (size_t)B * H * W * C;
+  hipLaunchKernelGGL(maxpool_bwd_kernel, dim3((int)std::min<size_t>(8192, (n + 255) / 256)), dim3(256),
+                     0, s, dy, arg, B, H, W, C, Ho, Wo, dx);
+}
+
+// ------------------------------------------------------------ frame prep
+// x0[f][h][w][c] = mean of the 2x2 block (or the pixel) of frame src[f]
+// (obs + src[f]*C*Hin*Win, NCHW, float32 or bfloat16).
+template <typename T>
+__global__ void __launch_bounds__(256) prep_kernel(const T* __restrict__ obs,
+                                                   const int32_t* __restrict__ src, int F, int C,
+                                                   int Hin, int Win, int pool, float* __restrict__ x0) {
+  const int Ho = pool ? Hin / 2 : Hin, Wo = pool ? Win / 2 : Win;
+  const size_t n = (size_t)F * Ho * Wo * C;
+  for (size_t e = (size_t)blockIdx.x * 256 + threadIdx.x; e < n; e += (size_t)gridDim.x * 256) {
+    const int c = (int)(e % C);
+    size_t r = e / C;
+    const int w = (int)(r % Wo);
+    r /= Wo;
+    const int h = (int)(r % Ho);
+    const int f = (int)(r / Ho);
+    const size_t fr = src ? (size_t)src[f] : (size_t)f;
+    const T* p = obs + (fr * C + c) * Hin * Win;
+    float v;
+    if (pool) {
+      const T* q = p + (size_t)(2 * h) * Win + 2 * w;
+      v = 0.25f * ((ldf(q) + ldf(q + 1)) + (ldf(q + Win) + ldf(q + Win + 1)));
+    } else {
+      v = ldf(p + (size_t)h * Win + w);
+    }
+    x0[e] = v;
+  }
+}
+
+void launch_prep(const void* obs, int bf16, const int32_t* src, int F, int C, int Hin, int Win,
+                 int pool, float* x0, hipStream_t s) {
+  const int Ho = pool ? Hin / 2 : Hin, Wo = pool ? Win / 2 : Win;
+  const size_t n = (size_t)F * Ho * Wo * C;
+  const int nb = (int)std::min<size_t>(8192, (n + 255) / 256);
+  if (bf16)
+    hipLaunchKernelGGL(prep_kernel<bf16_t>, dim3(nb), dim3(256), 0, s, (const bf16_t*)obs, src, F, C,
+                       Hin, Win, pool, x0);
+  else
+    hipLaunchKernelGGL(prep_kernel<float>, dim3(nb), dim3(256), 0, s, (const float*)obs, src, F, C, Hin,
+                       Win, pool, x0);
+}
+
+// dx = dy * [y > 0]
+__global__ void __launch_bounds__(256) relu_grad_kernel(const float* __restrict__ dy,
+                                                        const float* __restrict__ y, size_t n,
+                                                        float* __restrict__ dx) {
+  for (size_t e = (size_t)blockIdx.x * 256 + threadIdx.x; e < n; e += (size_t)gridDim.x * 256)
+    dx[e] = y[e] > 0.f ? dy[e] : 0.f;
+}
+
+void launch_relu_grad(const float* dy, const float* y, size_t n, float* dx, hipStream_t s) {
+  const int nb = (int)std::min<size_t>(8192, (n + 255) / 256);
+  hipLaunchKernelGGL(relu_grad_kernel, dim3(nb), dim3(256), 0, s, dy, y, n, dx);
+}

@@ -1,0 +1,124 @@
+"""One DD-PPO worker on one GPU: collect a rollout with T+1 dependent act
+steps, then GAE and E epochs x M minibatches of (loss backward, Adam).
+
+Host-side sequencing only; every numeric step is a library call.  On one GPU
+the gradient all-reduce between ppo_loss_backward and ppo_adam_step
+(Eq. 3-4) is the identity.
+
+Ragged rollouts (preempted envs, Sec. 3): envs must be ordered by length,
+longest first, so the envs still collecting at step t are rows [0, B_t).
+Env n is active at act steps t <= T_n; step T_n only supplies the bootstrap
+value, and the next rollout starts from the state that step read.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass
+
+import numpy as np
+import torch
+
+from .api import Adam, LossCfg, Net, cast_bf16, gae
+
+
+@dataclass
+class PPOHyper:
+    gamma: float = 0.99
+    lam: float = 0.95
+    clip: float = 0.2
+    value_coef: float = 0.5
+    entropy_coef: float = 0.01
+    lr: float = 2.5e-4
+    epochs: int = 2
+    minibatches: int = 2
+    norm_adv: bool = False
+
+
+class Worker:
+    def __init__(self, spec, dtype: str, T: int, N: int, params, hyper: PPOHyper = None, device="cuda"):
+        self.hp = hyper or PPOHyper()
+        self.spec, self.T, self.N, self.dev = spec, T, N, torch.device(device)
+        self.net = Net(spec, dtype)
+        self.bf16 = dtype == "bf16"
+        self.params = torch.as_tensor(np.asarray(params, np.float32)).to(self.dev).contiguous()
+        assert self.params.numel() == self.net.P
+        self.lp = cast_bf16(self.params) if self.bf16 else None
+        self.adam = Adam(self.net.P, self.dev, lr=self.hp.lr,
+                         loss_scale=65536.0 if self.bf16 else 1.0,
+                         growth_interval=2000 if self.bf16 else 0)
+        L, H, dev = spec.lstm_layers, spec.hidden, self.dev
+        f32 = dict(dtype=torch.float32, device=dev)
+        self.h_hist = torch.zeros(T + 1, L, N, H, **f32)    # state read by act step t
+        self.c_hist = torch.zeros(T + 1, L, N, H, **f32)
+        self.act_rec = torch.zeros(T + 2, N, dtype=torch.int32, device=dev)  # row 0: previous action
+        self.logp = torch.zeros(T + 1, N, **f32)
+        self.value = torch.zeros(T + 1, N, **f32)
+        self.grad = torch.zeros(self.net.P, **f32)
+        self.stats = torch.zeros(8, **f32)
+        self.adv_stats = torch.zeros(2, dtype=torch.float64, device=dev)
+        self.h_scr = torch.zeros(L, N, H, **f32)
+
+    # ------------------------------------------------------------- rollout
+    def collect(self, env: dict, lengths=None):
+        """env: device tensors obs [T+1,N,C,H,W], goal [T+1,N,2], mask [T+1,N],
+        u [T+1,N].  lengths: host ints [N] (non-increasing) or None."""
+        T, N = self.T, self.N
+        lens = np.full(N, T) if lengths is None else np.asarray(lengths)
+        assert np.all(np.diff(lens) <= 0), "envs must be ordered longest first"
+        for t in range(T + 1):
+            B = int((lens >= t).sum())
+            if B == 0:
+                break
+            out = {"action": self.act_rec[t + 1, :B], "logp": self.logp[t, :B],
+                   "value": self.value[t, :B], "h": self.h_hist[min(t + 1, T)],
+                   "c": self.c_hist[min(t + 1, T)]}
+            if t == T:  # bootstrap step of full-length envs: its state is discarded
+                out["h"], out["c"] = self.h_scr, torch.empty_like(self.h_scr)
+            self.net.act(env["obs"][t, :B], env["goal"][t, :B], self.act_rec[t, :B],
+                         env["mask"][t, :B], self.h_hist[t], self.c_hist[t], env["u"][t, :B],
+                         self.params, self.lp, out=out, state_rows=N)
+
+    def next_rollout_state(self, lengths=None):
+        """Start state, previous action for the next rollout (env n resumes
+        from the state its bootstrap step read)."""
+        T, N = self.T, self.N
+        lens = torch.as_tensor(np.full(N, T) if lengths is None else np.asarray(lengths),
+                               dtype=torch.int64, device=self.dev)
+        idx = torch.arange(N, device=self.dev)
+        h0 = self.h_hist[lens, :, idx].permute(1, 0, 2).contiguous()
+        c0 = self.c_hist[lens, :, idx].permute(1, 0, 2).contiguous()
+        prev = self.act_rec[lens, idx].contiguous()
+        return h0, c0, prev
+
+    def start(self, h0, c0, prev_action):
+        self.h_hist[0].copy_(h0)
+        self.c_hist[0].copy_(c0)
+        self.act_rec[0].copy_(prev_action)
+
+    # -------------------------------------------------------------- update
+    def rollout_view(self, env, adv, ret):
+        return {"obs": env["obs"], "goal": env["goal"], "mask": env["mask"],
+                "prev_action": self.act_rec[:-1], "action": self.act_rec[1:], "logp": self.logp,
+                "adv": adv, "ret": ret, "h0": self.h_hist[0], "c0": self.c_hist[0]}
+
+    def advantages(self, env, lengths=None):
+        lens_dev = None if lengths is None else torch.as_tensor(np.asarray(lengths, np.int32),
+                                                                device=self.dev)
+        return gae(env["reward"], self.value, env["done"], lens_dev, self.hp.gamma, self.hp.lam,
+                   stats=self.adv_stats)
+
+    def update(self, env, partitions, lengths=None, on_minibatch=None):
+        """GAE then, per epoch and minibatch, loss backward + Adam.
+        partitions: per epoch a list of env-id arrays."""
+        adv, ret = self.advantages(env, lengths)
+        ro = self.rollout_view(env, adv, ret)
+        cfg = LossCfg(self.hp.clip, self.hp.value_coef, self.hp.entropy_coef, self.hp.norm_adv)
+        scale = self.adam.scale_tensor() if self.bf16 else None
+        for ep in partitions:
+            for envs in ep:
+                self.net.loss_backward(ro, [int(e) for e in envs], lengths, self.params, self.lp, cfg,
+                                       loss_scale=scale, adv_stats=self.adv_stats, grad=self.grad,
+                                       stats=self.stats)
+                if on_minibatch is not None:
+                    on_minibatch(self)
+                self.adam.step(self.params, self.grad, self.lp)
+        return adv, ret

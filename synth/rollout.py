@@ -98,6 +98,17 @@ def gen_rollout(wl: Workload, seed: int, it: int = 0, with_obs: bool = True) -> 
     out["done"] = done
     out["u"] = g.random((T + 1, N)).astype(np.float32)
     out["lengths"] = rollout_lengths(wl, seed)
+    # episode mask of each act step: 0 where an episode starts (the first
+    # rollout, or the step after a done)
+    mask = np.ones((T + 1, N), np.float32)
+    mask[1:] = 1.0 - done
+    if it == 0:
+        mask[0] = 0.0
+    else:
+        prev = gen_rollout(wl, seed, it - 1, with_obs=False)
+        last = prev["done"][prev["lengths"] - 1, np.arange(N)]
+        mask[0] = 1.0 - last
+    out["mask"] = mask
     return out
 
 

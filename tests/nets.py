@@ -13,6 +13,10 @@ MINI_RESNET = NetDesc(in_hw=64, avgpool=True, trunk="resnet", base_width=4, bloc
 
 # a bottleneck trunk with the real widths but a 64x64 frame (feature map 1x1)
 RESNET_64 = NetDesc(in_hw=64)
+# the real trunk with a small core, and the tiny trunk with the real core
+RESNET_SMALLCORE = NetDesc(in_hw=64, vis_hidden=16, goal_dim=8, prev_act_dim=8, hidden=16)
+TINY_BIGCORE = NetDesc(in_hw=32, avgpool=False, trunk="tiny", gn_groups=8, vis_hidden=512,
+                       goal_mode="polar", goal_dim=32, prev_act_dim=32, lstm_layers=2, hidden=512)
 
 
 def wl(net, T=4, N=3, dtype="f32", ragged=False, **ppo):

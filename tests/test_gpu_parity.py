@@ -1,0 +1,253 @@
+"""Parity of every C-ABI call against the FP64 oracle on the same seeded
+inputs (GPU).  Tolerances: float32 path 1e-4 relative, bfloat16 path 2e-2
+relative (per output tensor, relative L2)."""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from oracle import params as OP, policy, ppo
+from synth import rollout as R
+from synth.configs import C0, C1, PPOCfg
+from tests.gpu_util import DEV, oracle_minibatch, per_tensor_errors, random_record, rel_err, to_device
+from tests.nets import MINI_RESNET, RESNET_64, RESNET_SMALLCORE, TINY_BIGCORE, TINY_NET, TINY_PLUS
+
+pytestmark = pytest.mark.gpu
+TOL = {"f32": 1e-4, "bf16": 2e-2}
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def P():
+    import paper_1911_00357_amd as P
+    assert torch.cuda.is_available()
+    return P
+
+
+# ---------------------------------------------------------------- GAE
+@pytest.mark.parametrize("T,N,ragged,seed", [(16, 2, False, 0), (128, 4, False, 1), (128, 64, True, 2),
+                                             (1, 3, False, 3), (200, 5, True, 4), (64, 1, False, 5)])
+def test_gae_parity(P, T, N, ragged, seed):
+    say(f"gae T={T} N={N} ragged={ragged}")
+    g = np.random.default_rng(seed)
+    rew = (-0.01 + 0.05 * g.standard_normal((T, N))).astype(np.float32)
+    done = (g.random((T, N)) < 0.05).astype(np.uint8)
+    rew += 2.5 * done
+    val = g.standard_normal((T + 1, N)).astype(np.float32)
+    lens = g.integers(max(1, T // 4), T + 1, N).astype(np.int32) if ragged else np.full(N, T, np.int32)
+    stats = torch.zeros(2, dtype=torch.float64, device=DEV)
+    adv, ret = P.gae(torch.tensor(rew, device=DEV), torch.tensor(val, device=DEV),
+                     torch.tensor(done, device=DEV), torch.tensor(lens, device=DEV) if ragged else None,
+                     0.99, 0.95, stats=stats)
+    A, Rt = ppo.gae(rew, val, done, lens, 0.99, 0.95)
+    torch.cuda.synchronize()
+    assert rel_err(adv.cpu().numpy(), A) < 1e-5
+    assert rel_err(ret.cpu().numpy(), Rt) < 1e-5
+    mu, var = ppo.adv_stats(A, lens)
+    s = stats.cpu().numpy()
+    assert abs(s[0] - mu) < 1e-6 * max(1, abs(mu)) and abs(s[1] - var) < 1e-5 * var
+
+
+def test_gae_closed_form_lambda0(P):
+    g = np.random.default_rng(9)
+    T, N = 33, 3
+    rew = g.standard_normal((T, N)).astype(np.float32)
+    val = g.standard_normal((T + 1, N)).astype(np.float32)
+    done = (g.random((T, N)) < 0.2).astype(np.uint8)
+    adv, _ = P.gae(torch.tensor(rew, device=DEV), torch.tensor(val, device=DEV),
+                   torch.tensor(done, device=DEV), None, 0.9, 0.0)
+    td = rew.astype(np.float64) + 0.9 * (1 - done) * val[1:] - val[:-1]
+    assert rel_err(adv.cpu().numpy(), td) < 1e-6
+
+
+# ---------------------------------------------------------------- Adam
+def test_adam_parity(P):
+    say("adam")
+    g = np.random.default_rng(0)
+    n = 100_003
+    th = (0.05 * g.standard_normal(n)).astype(np.float32)   # weight-sized values
+    master = torch.tensor(th, device=DEV)
+    lp = torch.empty(n, dtype=torch.bfloat16, device=DEV)
+    opt = P.Adam(n, DEV, lr=2.5e-4)
+    tho, m, v = th.astype(np.float64), np.zeros(n), np.zeros(n)
+    for k in range(1, 4):
+        gr = g.standard_normal(n).astype(np.float32) * (10.0 ** g.uniform(-3, 1, n)).astype(np.float32)
+        before = master.cpu().numpy().astype(np.float64)
+        opt.step(master, torch.tensor(gr, device=DEV), lp)
+        tho, m, v = ppo.adam(before, gr.astype(np.float64), m, v, k, 2.5e-4)
+        got = master.cpu().numpy().astype(np.float64)
+        # float32 storage of theta bounds the agreement of the update
+        assert rel_err(got - before, tho - before) < 1e-4
+    st = opt.state()
+    assert st["step"] == 3 and st["skipped"] == 0
+    assert torch.equal(lp, master.to(torch.bfloat16))
+
+
+def test_adam_skips_non_finite_and_halves_scale(P):
+    n = 4099
+    master = torch.randn(n, device=DEV)
+    opt = P.Adam(n, DEV, lr=1e-3, loss_scale=1024.0, growth_interval=2)
+    g = torch.randn(n, device=DEV) * 1024
+    opt.step(master, g)
+    m0, v0, th0 = opt.m.clone(), opt.v.clone(), master.clone()
+    g[17] = float("inf")
+    opt.step(master, g)
+    st = opt.state()
+    assert torch.equal(master, th0) and torch.equal(opt.m, m0) and torch.equal(opt.v, v0)
+    assert st["scale"] == 512.0 and st["step"] == 1 and st["skipped"] == 1 and st["found_inf"] == 1
+    g[17] = 0.0
+    opt.step(master, g)
+    opt.step(master, g)
+    assert opt.state()["scale"] == 1024.0 and opt.state()["step"] == 3
+
+
+# ---------------------------------------------------------------- act
+def _act_case(P, net, dtype, B, seed, state_rows=0):
+    flat = R.init_params(net, seed, random_affine=True)
+    g = np.random.default_rng(seed + 100)
+    obs = g.random((B, net.in_ch, net.in_hw, net.in_hw), dtype=np.float32)
+    if dtype == "bf16":
+        obs = R.round_bf16(obs)
+    goal = g.standard_normal((B, 2)).astype(np.float32)
+    prev = g.integers(0, net.num_actions, B).astype(np.int32)
+    mask = (g.random(B) > 0.3).astype(np.float32)
+    SR = state_rows or B
+    h = (0.5 * g.standard_normal((net.lstm_layers, SR, net.hidden))).astype(np.float32)
+    c = (0.5 * g.standard_normal((net.lstm_layers, SR, net.hidden))).astype(np.float32)
+    u = g.random(B).astype(np.float32)
+    n = P.Net(net, dtype)
+    params = torch.tensor(flat, device=DEV)
+    lp = P.cast_bf16(params) if dtype == "bf16" else None
+    td = lambda a: torch.tensor(a, device=DEV)
+    h_in, c_in = td(h), td(c)
+    out = n.act(td(obs).to(torch.bfloat16) if dtype == "bf16" else td(obs), td(goal), td(prev), td(mask),
+                h_in, c_in, td(u), params, lp, want_logits=True, state_rows=SR)
+    torch.cuda.synchronize()
+    ref = policy.act(OP.unpack(net, flat), net, obs, goal, prev, mask, h[:, :B], c[:, :B], u)
+    ref["u"] = u
+    return out, ref
+
+
+@pytest.mark.parametrize("name,net,dtype,B", [("tiny", TINY_NET, "f32", 2), ("tiny", TINY_NET, "f32", 5),
+                                              ("tiny+", TINY_PLUS, "f32", 3),
+                                              ("mini_resnet", MINI_RESNET, "f32", 4),
+                                              ("resnet_smallcore", RESNET_SMALLCORE, "f32", 2),
+                                              ("tiny_bigcore", TINY_BIGCORE, "f32", 4),
+                                              ("resnet64", RESNET_64, "f32", 2),
+                                              ("tiny+", TINY_PLUS, "bf16", 3),
+                                              ("mini_resnet", MINI_RESNET, "bf16", 4)])
+def test_act_parity_small(P, name, net, dtype, B):
+    say(f"act {name} {dtype} B={B}")
+    out, ref = _act_case(P, net, dtype, B, seed=B)
+    tol = TOL[dtype]
+    assert rel_err(out["logits"].cpu().numpy(), ref["logits"]) < tol
+    assert rel_err(out["value"].cpu().numpy(), ref["value"]) < tol
+    assert rel_err(out["h"].cpu().numpy(), ref["h"]) < tol
+    assert rel_err(out["c"].cpu().numpy(), ref["c"]) < tol
+    if dtype == "f32":
+        np.testing.assert_array_equal(out["action"].cpu().numpy(), ref["action"])
+        assert rel_err(out["logp"].cpu().numpy(), ref["logp"]) < tol
+
+
+@pytest.mark.parametrize("dtype", ["f32", "bf16"])
+def test_act_parity_resnet_paper_shape(P, dtype):
+    """The paper's encoder at 256x256 frames, batch 4 (one act step of a worker)."""
+    say(f"act resnet {dtype}")
+    out, ref = _act_case(P, C1.net, dtype, 4, seed=11, state_rows=6)
+    tol = TOL[dtype]
+    assert rel_err(out["logits"].cpu().numpy(), ref["logits"]) < tol
+    assert rel_err(out["value"].cpu().numpy(), ref["value"]) < tol
+    assert rel_err(out["h"].cpu().numpy()[:, :4], ref["h"]) < tol
+    assert_actions_agree(out["action"].cpu().numpy(), ref, tol)
+
+
+def assert_actions_agree(a, ref, tol):
+    """Identical actions, or a flip explained by the logit error: u lies
+    within tol of the cumulative probability at the boundary between them."""
+    ar = ref["action"]
+    p = np.exp(ref["logits"] - ref["logits"].max(1, keepdims=True))
+    p /= p.sum(1, keepdims=True)
+    cdf = np.cumsum(p, 1)
+    for i in np.nonzero(a != ar)[0]:
+        k = min(a[i], ar[i])
+        assert abs(ref["u"][i] - cdf[i, k]) < tol, (i, a[i], ar[i], ref["u"][i], cdf[i])
+
+
+# ---------------------------------------------------------- loss backward
+def _loss_case(P, net, dtype, T, N, envs, lengths, seed, norm_adv=False):
+    flat = R.init_params(net, seed, random_affine=True)
+    rec = random_record(net, T, N, seed + 1, lengths=lengths, bf16=dtype == "bf16")
+    n = P.Net(net, dtype)
+    params = torch.tensor(flat, device=DEV)
+    lp = P.cast_bf16(params) if dtype == "bf16" else None
+    ro = to_device(rec, bf16=dtype == "bf16")
+    adv_stats = None
+    mu_var = None
+    if norm_adv:
+        mu_var = ppo.adv_stats(rec["adv"].astype(np.float64), rec["lengths"])
+        adv_stats = torch.tensor(np.array(mu_var), dtype=torch.float64, device=DEV)
+    cfg = P.LossCfg(norm_adv=norm_adv)
+    grad, stats = n.loss_backward(ro, envs, rec["lengths"] if lengths is not None else None, params, lp, cfg,
+                                  loss_scale=torch.tensor([1.0], device=DEV), adv_stats=adv_stats)
+    torch.cuda.synchronize()
+    mb = oracle_minibatch(rec, envs)
+    s_ref, g_ref = ppo.loss_grad(flat.astype(np.float64), net, PPOCfg(), mb, adv_norm=mu_var)
+    return grad.cpu().numpy(), stats.cpu().numpy(), g_ref, s_ref
+
+
+@pytest.mark.parametrize("name,net,T,N,envs,lengths", [
+    ("tiny", TINY_NET, 16, 2, [0, 1], None),
+    ("tiny_ragged", TINY_NET, 9, 4, [3, 0, 2], [9, 4, 7, 2]),
+    ("tiny+", TINY_PLUS, 6, 3, [0, 2], [6, 5, 3]),
+    ("mini_resnet", MINI_RESNET, 5, 3, [2, 1, 0], [5, 3, 4]),
+])
+def test_loss_backward_parity_f32(P, name, net, T, N, envs, lengths):
+    say(f"loss f32 {name}")
+    g, s, g_ref, s_ref = _loss_case(P, net, "f32", T, N, envs, lengths, seed=T * 7 + N)
+    errs = per_tensor_errors(net, g, g_ref)
+    worst = max(errs, key=errs.get)
+    say(f"  worst grad tensor {worst}: {errs[worst]:.2e}; loss {s[0]:.6f} vs {s_ref[0]:.6f}")
+    denom = abs(s_ref[1]) + 0.5 * abs(s_ref[2]) + 0.01 * abs(s_ref[3])
+    assert abs(s[0] - s_ref[0]) / denom < 1e-4
+    for k in (1, 2, 3):
+        assert abs(s[k] - s_ref[k]) <= 1e-4 * max(abs(s_ref[k]), 1e-6)
+    assert errs[worst] < 1e-4, errs
+    assert rel_err(g, g_ref) < 1e-4
+
+
+def test_loss_backward_norm_adv(P):
+    g, s, g_ref, s_ref = _loss_case(P, TINY_PLUS, "f32", 5, 3, [0, 1, 2], None, seed=3, norm_adv=True)
+    assert rel_err(g, g_ref) < 1e-4 and abs(s[1] - s_ref[1]) < 1e-4 * abs(s_ref[1])
+
+
+@pytest.mark.parametrize("name,net,T,N,envs,lengths", [
+    ("tiny+", TINY_PLUS, 6, 3, [0, 2], [6, 5, 3]),
+    ("mini_resnet", MINI_RESNET, 5, 3, [2, 1, 0], [5, 3, 4]),
+])
+def test_loss_backward_parity_bf16(P, name, net, T, N, envs, lengths):
+    say(f"loss bf16 {name}")
+    g, s, g_ref, s_ref = _loss_case(P, net, "bf16", T, N, envs, lengths, seed=T * 3 + N)
+    errs = per_tensor_errors(net, g, g_ref)
+    worst = max(errs, key=errs.get)
+    say(f"  worst grad tensor {worst}: {errs[worst]:.2e}")
+    assert rel_err(g, g_ref) < 2e-2
+    assert errs[worst] < 2e-2, errs
+
+
+@pytest.mark.parametrize("dtype", ["f32", "bf16"])
+def test_loss_backward_resnet_paper_shape(P, dtype):
+    """The paper's network at 256x256 frames: 2 envs x 4 steps, ragged."""
+    say(f"loss resnet paper shape {dtype}")
+    g, s, g_ref, s_ref = _loss_case(P, C1.net, dtype, 4, 3, [2, 0], [4, 2, 3], seed=21)
+    errs = per_tensor_errors(C1.net, g, g_ref)
+    order = sorted(errs, key=errs.get, reverse=True)
+    say("  global grad err %.2e; worst tensors: %s" % (rel_err(g, g_ref),
+        ", ".join(f"{k}={errs[k]:.1e}" for k in order[:6])))
+    assert rel_err(g, g_ref) < TOL[dtype]
+    assert errs[order[0]] < TOL[dtype], errs
