@@ -235,6 +235,23 @@ ppo_status ppo_adam_step(float* master, const float* grad, float* m, float* v, v
                          size_t P, const ppo_adam_cfg* cfg, ppo_scaler* scaler, void* ws,
                          size_t ws_bytes, void* stream);
 
+/* Test introspection of a workspace laid out for (op, max_frames, max_envs):
+ * where a call leaves the forward activations that decided each ReLU and
+ * max pool, so a checker can take the same decisions.  Frames are in the
+ * call's packed order (time-major; envs sorted by length, longest first,
+ * ties in the given order).
+ *   kind 0: normalised output of trunk unit `index` (conv + GroupNorm [+ residual]
+ *           [+ ReLU]) as float32; dims = {Ho, Wo, C, channel_major}
+ *           (channel_major 1: [F][C][Ho*Wo], else [F][Ho][Wo][C]); *name = the
+ *           unit's convolution tensor name; *relu = 1 if a ReLU produced it
+ *   kind 1: max-pool winner (uint8 kh*3+kw) [F][h][w][C]; dims = {h, w, C, 0}
+ *   kind 2: LSTM layer-0 input rows float32 [F][din0], columns < vis_hidden
+ *           being the post-ReLU visual FC output; dims = {din0, vis_hidden, 0, 0}
+ *   kind 3: dims[0] = number of trunk units
+ * Returns PPO_EINVAL for an index or kind that does not exist. */
+ppo_status ppo_workspace_probe(const ppo_net* net, int op, int max_frames, int max_envs, int kind,
+                               int index, const char** name, int* relu, size_t* offset, int dims[4]);
+
 /* dst[i] = bfloat16(src[i]) (round to nearest even) for the initial working
  * copy of the parameters; later copies come from ppo_adam_step.  src [n]
  * float32, dst [n] bfloat16, both device. */

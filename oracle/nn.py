@@ -94,15 +94,16 @@ def avg_pool2(x):
     return x.reshape(B, C, H // 2, 2, W // 2, 2).mean(axis=(3, 5))
 
 
-def max_pool3s2(x):
+def max_pool3s2(x, winner=None):
     """3x3 window, stride 2, padding 1 (padding never wins).  Returns the
     output and, per output, the flat input index of the first maximum in
-    row-major window order."""
+    row-major window order.  `winner` ([B,C,Ho,Wo] window index kh*3+kw)
+    imposes the choice instead (a decision taken elsewhere)."""
     B, C, H, W = x.shape
     Ho, Wo = conv_out(H, 3, 2, 1), conv_out(W, 3, 2, 1)
     xp = np.pad(x, ((0, 0), (0, 0), (1, 1), (1, 1)), constant_values=-np.inf)
     win = _im2col(xp, 3, 3, 2, Ho, Wo).reshape(B, C, Ho, Wo, 9)
-    k = win.argmax(axis=4)                       # first maximum
+    k = win.argmax(axis=4) if winner is None else np.asarray(winner, np.int64)
     y = np.take_along_axis(win, k[..., None], axis=4)[..., 0]
     kh, kw = k // 3, k % 3
     ii = 2 * np.arange(Ho)[:, None] + kh - 1    # input row of the winner

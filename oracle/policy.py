@@ -19,6 +19,11 @@ multiplies h and c of every layer and selects the start token.
 
 Parity pins: forward against torch CPU float64 library modules, backward
 against torch autograd and central finite differences (tests/test_oracle_policy.py).
+
+Discrete decisions (each ReLU's on/off pattern, each max-pool winner) can be
+imposed through a `decide` dict, so that a comparison against an
+implementation in another precision takes the same decisions; without it
+they are taken here in float64.
 """
 from __future__ import annotations
 
@@ -33,20 +38,27 @@ def prep_obs(net, obs):
     return nn.avg_pool2(x) if net.avgpool else x
 
 
-def _conv_gn(P, net, name, x, s, p, relu, tape):
+def _relu(y, key, decide):
+    """ReLU with its on/off pattern taken here (y > 0) or imposed."""
+    m = (y > 0) if (decide is None or key not in decide) else np.asarray(decide[key], bool)
+    return np.where(m, y, 0.0), m
+
+
+def _conv_gn(P, net, name, x, s, p, relu, tape, decide=None):
     u = nn.conv2d(x, P[name], s, p)
     y, gc = nn.group_norm(u, P[name + ".gn.g"], P[name + ".gn.b"], net.gn_groups)
+    m = None
     if relu:
-        y = nn.relu(y)
+        y, m = _relu(y, name, decide)
     if tape is not None:
-        tape[name] = (x, s, p, gc, y if relu else None)
+        tape[name] = (x, s, p, gc, m)
     return y
 
 
 def _conv_gn_bwd(P, name, dy, tape, grads, need_dx=True):
-    x, s, p, gc, a = tape[name]
-    if a is not None:
-        dy = dy * (a > 0)
+    x, s, p, gc, m = tape[name]
+    if m is not None:
+        dy = dy * m
     du, dg, db = nn.group_norm_backward(gc, P[name + ".gn.g"], dy)
     dx, dw = nn.conv2d_backward(x, P[name], s, p, du, need_dx)
     grads[name] = grads.get(name, 0) + dw
@@ -64,26 +76,28 @@ def _blocks(net):
     return out
 
 
-def encoder_forward(P, net, x, tape=None):
+def encoder_forward(P, net, x, tape=None, decide=None):
     """x: [F, C, h, w] after the optional pooling -> features [F, flat_dim]
-    in channel, row, column order."""
+    in channel, row, column order.  decide: optional imposed decisions keyed
+    by unit name (ReLU masks, NCHW), 'sS.bJ.out' (block output ReLU) and
+    'maxpool' (winner index)."""
     if net.trunk == "tiny":
-        a = _conv_gn(P, net, "conv1", x, 2, 1, True, tape)
-        a = _conv_gn(P, net, "conv2", a, 2, 1, True, tape)
+        a = _conv_gn(P, net, "conv1", x, 2, 1, True, tape, decide)
+        a = _conv_gn(P, net, "conv2", a, 2, 1, True, tape, decide)
         return a.reshape(a.shape[0], -1)
-    a = _conv_gn(P, net, "stem", x, 2, 3, True, tape)
-    a, mc = nn.max_pool3s2(a)
+    a = _conv_gn(P, net, "stem", x, 2, 3, True, tape, decide)
+    a, mc = nn.max_pool3s2(a, None if decide is None else decide.get("maxpool"))
     if tape is not None:
         tape["maxpool"] = mc
     for pre, st, proj in _blocks(net):
-        y = _conv_gn(P, net, pre + "c1", a, 1, 0, True, tape)
-        y = _conv_gn(P, net, pre + "c2", y, st, 1, True, tape)
-        y = _conv_gn(P, net, pre + "c3", y, 1, 0, False, tape)
-        sc = _conv_gn(P, net, pre + "ds", a, st, 0, False, tape) if proj else a
-        a = nn.relu(y + sc)
+        y = _conv_gn(P, net, pre + "c1", a, 1, 0, True, tape, decide)
+        y = _conv_gn(P, net, pre + "c2", y, st, 1, True, tape, decide)
+        y = _conv_gn(P, net, pre + "c3", y, 1, 0, False, tape, decide)
+        sc = _conv_gn(P, net, pre + "ds", a, st, 0, False, tape, decide) if proj else a
+        a, m = _relu(y + sc, pre + "out", decide)
         if tape is not None:
-            tape[pre + "out"] = a
-    a = _conv_gn(P, net, "compress", a, 1, 1, True, tape)
+            tape[pre + "out"] = m
+    a = _conv_gn(P, net, "compress", a, 1, 1, True, tape, decide)
     return a.reshape(a.shape[0], -1)
 
 
@@ -100,7 +114,7 @@ def encoder_backward(P, net, tape, dfeat, grads):
     d = dfeat.reshape(-1, net.compress_ch, hw, hw)
     d = _conv_gn_bwd(P, "compress", d, tape, grads)
     for pre, st, proj in reversed(_blocks(net)):
-        d = d * (tape[pre + "out"] > 0)
+        d = d * tape[pre + "out"]
         dy = _conv_gn_bwd(P, pre + "c3", d, tape, grads)
         dy = _conv_gn_bwd(P, pre + "c2", dy, tape, grads)
         dx = _conv_gn_bwd(P, pre + "c1", dy, tape, grads)
@@ -110,23 +124,28 @@ def encoder_backward(P, net, tape, dfeat, grads):
     _conv_gn_bwd(P, "stem", d, tape, grads, need_dx=False)
 
 
-def encode(P, net, obs, chunk=64):
+def _slice(decide, s, e):
+    return None if decide is None else {k: v[s:e] for k, v in decide.items()}
+
+
+def encode(P, net, obs, chunk=64, decide=None):
     """Features of many frames, processed in chunks of frames to bound the
     im2col memory (frames are independent)."""
     F = obs.shape[0]
     out = np.zeros((F, net.flat_dim))
     for s in range(0, F, chunk):
-        out[s:s + chunk] = encoder_forward(P, net, prep_obs(net, obs[s:s + chunk]))
+        out[s:s + chunk] = encoder_forward(P, net, prep_obs(net, obs[s:s + chunk]),
+                                           decide=_slice(decide, s, s + chunk))
     return out
 
 
-def encode_backward(P, net, obs, dfeat, grads, chunk=64):
+def encode_backward(P, net, obs, dfeat, grads, chunk=64, decide=None):
     """Recompute each chunk's forward with a tape, then run its backward;
     the chunk gradients are summed."""
     F = obs.shape[0]
     for s in range(0, F, chunk):
         tape = {}
-        encoder_forward(P, net, prep_obs(net, obs[s:s + chunk]), tape)
+        encoder_forward(P, net, prep_obs(net, obs[s:s + chunk]), tape, _slice(decide, s, s + chunk))
         encoder_backward(P, net, tape, dfeat[s:s + chunk], grads)
 
 
@@ -137,11 +156,12 @@ def polar(goal):
     return np.stack([d, np.cos(th), np.sin(th)], axis=-1)
 
 
-def core_forward(P, net, feat, goal, prev_a, masks, h0, c0, keep=False):
+def core_forward(P, net, feat, goal, prev_a, masks, h0, c0, keep=False, vis_mask=None):
     """Run the policy over a sequence.
 
     feat [T,B,flat], goal [T,B,2], prev_a [T,B] (action taken at t-1),
     masks [T,B] (0 at an episode start), h0/c0 [L,B,H].
+    vis_mask [T,B,vis_hidden] optionally imposes the visual-FC ReLU pattern.
     Returns logits [T,B,A], values [T,B], final (h, c), and a tape."""
     T, B = feat.shape[:2]
     L, A = net.lstm_layers, net.num_actions
@@ -152,7 +172,8 @@ def core_forward(P, net, feat, goal, prev_a, masks, h0, c0, keep=False):
     tape = [] if keep else None
     for t in range(T):
         m = np.asarray(masks[t], np.float64)[:, None]
-        vis = nn.relu(nn.linear(feat[t], P["fc.w"], P["fc.b"]))
+        vis, vmask = _relu(nn.linear(feat[t], P["fc.w"], P["fc.b"]), t,
+                           None if vis_mask is None else {t: vis_mask[t]})
         parts = [vis]
         g3 = None
         if net.goal_mode == "polar":
@@ -175,7 +196,7 @@ def core_forward(P, net, feat, goal, prev_a, masks, h0, c0, keep=False):
         logits[t] = out[:, :A]
         values[t] = out[:, A]
         if keep:
-            tape.append((feat[t], vis, g3, idx, m, cells, x))
+            tape.append((feat[t], vmask, g3, idx, m, cells, x))
     return logits, values, (np.stack(h), np.stack(c)), tape
 
 
@@ -195,7 +216,7 @@ def core_backward(P, net, tape, dlogits, dvalues, grads):
         g["lstm%d.b" % l] = 0
     emb_grad = np.zeros((A + 1, net.prev_act_dim)) if net.prev_act_dim else None
     for t in reversed(range(T)):
-        f_t, vis, g3, idx, m, cells, top = tape[t]
+        f_t, vmask, g3, idx, m, cells, top = tape[t]
         dout = np.concatenate([dlogits[t], dvalues[t][:, None]], axis=1)
         dtop, dwh, dbh = nn.linear_backward(top, P["head.w"], dout)
         g["head.w"] = g["head.w"] + dwh
@@ -210,7 +231,7 @@ def core_backward(P, net, tape, dlogits, dvalues, grads):
             dc[l] = m * dcp
             dx = dxl
         nv = net.vis_hidden
-        dvis = dx[:, :nv] * (vis > 0)
+        dvis = dx[:, :nv] * vmask
         dft, dwf, dbf = nn.linear_backward(f_t, P["fc.w"], dvis)
         dfeat[t] = dft
         g["fc.w"] = g["fc.w"] + dwf

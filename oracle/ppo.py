@@ -113,12 +113,14 @@ def minibatch_inputs(net, inp, rec, adv, ret, envs):
     }
 
 
-def loss_grad(flat, net, ppo, mb, with_grad=True, adv_norm=None):
+def loss_grad(flat, net, ppo, mb, with_grad=True, adv_norm=None, decide=None):
     """PPO loss of one minibatch and (optionally) its flat gradient.
 
     L = -sum_n w_n sum_t min(r A, clip(r, 1-eps, 1+eps) A)
         + c_v sum_n w_n sum_t 1/2 (V - R)^2 - c_e sum_n w_n sum_t H(pi),
-    w_n = 1 / (|B| T_n).  adv_norm = (mean, var) applies (A - mean)/(std + 1e-5)."""
+    w_n = 1 / (|B| T_n).  adv_norm = (mean, var) applies (A - mean)/(std + 1e-5).
+    decide: optional imposed ReLU / max-pool decisions (policy.encoder_forward),
+    per valid frame in time-major order, plus 'vis' [T_B, B, vis_hidden]."""
     P = params.unpack(net, flat)
     lens = mb["lens"]
     TB, B = mb["action"].shape
@@ -128,9 +130,11 @@ def loss_grad(flat, net, ppo, mb, with_grad=True, adv_norm=None):
     # encoder over valid frames only
     tt, jj = np.nonzero(valid)
     feat = np.zeros((TB, B, net.flat_dim))
-    feat[tt, jj] = policy.encode(P, net, mb["obs"][tt, jj])
+    enc_decide = None if decide is None else {k: v for k, v in decide.items() if k != "vis"}
+    feat[tt, jj] = policy.encode(P, net, mb["obs"][tt, jj], decide=enc_decide)
     logits, values, _, tape = policy.core_forward(
-        P, net, feat, mb["goal"], mb["prev_action"], mb["mask"], mb["h0"], mb["c0"], keep=with_grad)
+        P, net, feat, mb["goal"], mb["prev_action"], mb["mask"], mb["h0"], mb["c0"], keep=with_grad,
+        vis_mask=None if decide is None else decide.get("vis"))
     lp = nn.log_softmax(logits)
     p = np.exp(lp)
     a = mb["action"]
@@ -161,7 +165,7 @@ def loss_grad(flat, net, ppo, mb, with_grad=True, adv_norm=None):
     dvalues = ppo.value_coef * w * (values - mb["ret"])
     grads = {}
     dfeat = policy.core_backward(P, net, tape, dlogits, dvalues, grads)
-    policy.encode_backward(P, net, mb["obs"][tt, jj], dfeat[tt, jj], grads)
+    policy.encode_backward(P, net, mb["obs"][tt, jj], dfeat[tt, jj], grads, decide=enc_decide)
     return stats, params.pack(net, grads)
 
 

@@ -74,6 +74,8 @@ EXPORTS = {
     "ppo_adam_step": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_size_t,
                               C.POINTER(AdamCfg), c_void_p, c_void_p, c_size_t, c_void_p]),
     "ppo_cast_bf16": (c_int, [c_void_p, c_void_p, c_size_t, c_void_p]),
+    "ppo_workspace_probe": (c_int, [c_void_p, c_int, c_int, c_int, c_int, c_int, C.POINTER(C.c_char_p),
+                                    C.POINTER(c_int), C.POINTER(c_size_t), C.POINTER(c_int)]),
     "ppo_last_error": (C.c_char_p, []),
 }
 

@@ -119,6 +119,18 @@ class Net:
             ws.fill_(0xFF)
         return ws
 
+    def probe(self, op: int, max_frames: int, max_envs: int, kind: int, index: int = 0):
+        """Location of saved forward activations in a workspace (test aid):
+        (name, relu, byte offset, dims)."""
+        name, relu, off = C.c_char_p(), C.c_int(), C.c_size_t()
+        dims = (C.c_int * 4)()
+        check(lib().ppo_workspace_probe(self._h, op, max_frames, max_envs, kind, index, C.byref(name),
+                                        C.byref(relu), C.byref(off), dims), "ppo_workspace_probe")
+        return (name.value.decode() if name.value else ""), relu.value, off.value, list(dims)
+
+    def last_workspace(self, op: int):
+        return self._ws.get((op, "cuda:0")) if self._ws else None
+
     # ------------------------------------------------------------------ act
     def act(self, obs, goal, prev_action, mask, h_in, c_in, u, params, params_lp=None,
             out=None, want_logits=False, state_rows=0):

@@ -34,6 +34,8 @@ struct Tensor {
 
 // One convolution (no bias) followed by GroupNorm.
 struct Unit {
+  std::string name;           // convolution tensor name
+  int relu;                   // 1: the stored output is post-ReLU
   size_t w, g, b;             // parameter offsets
   int Cin, Cout, K, stride, pad;
   int Hin, Win, Hout, Wout;
@@ -79,6 +81,8 @@ size_t add_tensor(ppo_net* n, const std::string& name, size_t count) {
 int add_unit(ppo_net* n, const std::string& name, int cin, int cout, int k, int stride, int pad, int hin,
              int win) {
   Unit u{};
+  u.name = name;
+  u.relu = 1;
   u.w = add_tensor(n, name, (size_t)cout * k * k * cin);
   u.g = add_tensor(n, name + ".gn.g", cout);
   u.b = add_tensor(n, name + ".gn.b", cout);
@@ -143,6 +147,7 @@ ppo_status build(ppo_net* n) {
         const int ho = n->units[b.c2].Hout;
         b.c3 = add_unit(n, std::string(p) + ".c3", w, 4 * w, 1, 1, 0, ho, ho);
         b.ds = (j == 0) ? add_unit(n, std::string(p) + ".ds", cin, 4 * w, 1, st, 0, h, h) : -1;
+        if (b.ds >= 0) n->units[b.ds].relu = 0;  // projection shortcut: GroupNorm only
         if (j != 0 && cin != 4 * w) return fail(PPO_ESHAPE, "identity shortcut with a width change");
         n->blocks.push_back(b);
         cin = 4 * w;
@@ -704,6 +709,48 @@ ppo_status ppo_adam_step(float* master, const float* grad, float* m, float* v, v
   launch_adam(master, grad, m, v, (bf16_t*)lp_copy, P, cfg->lr, cfg->beta1, cfg->beta2, cfg->eps,
               cfg->growth_interval, scaler, ws, strm(stream));
   return check_launch();
+}
+
+ppo_status ppo_workspace_probe(const ppo_net* net, int op, int max_frames, int max_envs, int kind,
+                               int index, const char** name, int* relu, size_t* offset, int dims[4]) {
+  if (!net || !offset || !dims) return fail(PPO_EINVAL, "null argument");
+  if (max_frames <= 0 || max_envs <= 0 || max_envs > kMaxMbEnvs) return fail(PPO_ESHAPE, "bad sizes");
+  const WsLayout w = plan(net, max_frames, max_envs, op == PPO_OP_LEARN);
+  dims[0] = dims[1] = dims[2] = dims[3] = 0;
+  if (name) *name = "";
+  if (relu) *relu = 0;
+  *offset = 0;
+  if (kind == 0) {
+    if (index < 0 || index >= (int)net->units.size()) return fail(PPO_EINVAL, "unit index out of range");
+    const Unit& u = net->units[index];
+    *offset = w.a[index];
+    dims[0] = u.Hout;
+    dims[1] = u.Wout;
+    dims[2] = u.Cout;
+    dims[3] = index == net->compress ? 1 : 0;
+    if (name) *name = u.name.c_str();
+    if (relu) *relu = u.relu;
+    return PPO_OK;
+  }
+  if (kind == 1) {
+    if (net->d.trunk != PPO_TRUNK_RESNET) return fail(PPO_EINVAL, "no max pool in this trunk");
+    *offset = w.arg;
+    dims[0] = net->pool_h;
+    dims[1] = net->pool_w;
+    dims[2] = net->d.base_width;
+    return PPO_OK;
+  }
+  if (kind == 2) {
+    *offset = w.z;
+    dims[0] = net->din0;
+    dims[1] = net->d.vis_hidden;
+    return PPO_OK;
+  }
+  if (kind == 3) {
+    dims[0] = (int)net->units.size();
+    return PPO_OK;
+  }
+  return fail(PPO_EINVAL, "unknown probe kind");
 }
 
 ppo_status ppo_cast_bf16(const float* src, void* dst, size_t n, void* stream) {
