@@ -27,6 +27,7 @@ sys.path.insert(0, ROOT)
 PEAK_BF16_TFLOPS = 2500.0     # MI355X dense bf16 MFMA
 PEAK_FP32_TFLOPS = 157.3      # MI355X fp32 matrix
 PEAK_HBM_GBS = 8000.0
+GRAPH = True                  # act loop replayed as one captured HIP graph
 
 
 def parse():
@@ -38,6 +39,7 @@ def parse():
     ap.add_argument("--no-fp32", action="store_true", help="skip the float32 comparison run")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--eager", action="store_true", help="launch the act loop eagerly (no HIP graph)")
     return ap.parse_args()
 
 
@@ -80,7 +82,7 @@ def run_gpu(wl, steps, warmup, seed):
             torch.cuda.synchronize()
             ev[0].record()
             t_start = time.perf_counter()
-        w.collect(env, lengths)
+        w.collect(env, lengths, graph=GRAPH)
         w.update(env, parts, lengths)
         if i >= warmup:
             frames.append(int(lens.sum()))
@@ -104,13 +106,68 @@ def act_update_split(wl, seed):
     lengths = None if not wl.ragged else lens
     parts = R.partitions(wl, seed)
     for _ in range(2):
-        w.collect(env, lengths)
+        w.collect(env, lengths, graph=GRAPH)
         w.update(env, parts, lengths)
     e = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
     e[0].record()
-    w.collect(env, lengths)
+    w.collect(env, lengths, graph=GRAPH)
     e[1].record()
     w.update(env, parts, lengths)
+    e[2].record()
+    torch.cuda.synchronize()
+    return e[0].elapsed_time(e[1]), e[1].elapsed_time(e[2]), int(lens.sum())
+
+
+def unpacked_split(wl, seed):
+    """The same ragged iteration without packing: one act call per active env
+    per step (batch 1) and one learner call per env of each minibatch (each
+    followed by its own Adam step is not needed for timing; the per-env calls
+    are what packing replaces).  Returns (act ms, update ms, frames)."""
+    import torch
+    from paper_1911_00357_amd.api import LossCfg
+    from paper_1911_00357_amd.worker import PPOHyper, Worker
+    from synth import rollout as R
+    dev = torch.device("cuda", 0)
+    p = wl.ppo
+    hp = PPOHyper(p.gamma, p.lam, p.clip, p.value_coef, p.entropy_coef, p.lr, p.epochs, p.minibatches)
+    w = Worker(wl.net, wl.dtype, wl.T, wl.N, R.init_params(wl.net, seed), hp, dev)
+    env, lens = stage_env(wl, seed, 0, dev)
+    parts = R.partitions(wl, seed)
+    w.collect(env, lens)
+    adv, ret = w.advantages(env, lens)
+    ro = w.rollout_view(env, adv, ret)
+    cfg = LossCfg(hp.clip, hp.value_coef, hp.entropy_coef)
+    scale = w.adam.scale_tensor() if w.bf16 else None
+
+    def act_unpacked():
+        for t in range(wl.T + 1):
+            for n in range(wl.N):
+                if lens[n] < t:
+                    break
+                # env n's state rows, read and written in place (layer stride N rows)
+                H = wl.net.hidden
+                row = lambda x: x.reshape(-1)[n * H:]
+                out = {"action": w.act_rec[t + 1, n:n + 1], "logp": w.logp[t, n:n + 1],
+                       "value": w.value[t, n:n + 1], "h": row(w.h_hist[min(t + 1, wl.T)]),
+                       "c": row(w.c_hist[min(t + 1, wl.T)])}
+                w.net.act(env["obs"][t, n:n + 1], env["goal"][t, n:n + 1], w.act_rec[t, n:n + 1],
+                          env["mask"][t, n:n + 1], row(w.h_hist[t]), row(w.c_hist[t]), env["u"][t, n:n + 1],
+                          w.params, w.lp, out=out, state_rows=wl.N)
+
+    def update_unpacked():
+        for ep in parts:
+            for envs in ep:
+                for e in envs:
+                    w.net.loss_backward(ro, [int(e)], lens, w.params, w.lp, cfg, loss_scale=scale,
+                                        adv_stats=w.adv_stats, grad=w.grad, stats=w.stats)
+    act_unpacked()
+    update_unpacked()
+    e = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+    torch.cuda.synchronize()
+    e[0].record()
+    act_unpacked()
+    e[1].record()
+    update_unpacked()
     e[2].record()
     torch.cuda.synchronize()
     return e[0].elapsed_time(e[1]), e[1].elapsed_time(e[2]), int(lens.sum())
@@ -136,6 +193,48 @@ def cpu_baseline(wl, seed):
             "kind": "oracle",
             "sample": f"T=8 rollout of N={small.N} envs (9 act steps) + {wl.ppo.epochs}x"
                       f"{wl.ppo.minibatches} minibatch updates, {frames} frames, {dt:.1f} s"}
+
+
+def roofline(wl, seed, reps=10):
+    """The dominant kernel launch of the learner: every trunk unit's
+    convolution GEMM (forward, data gradient, weight gradient) at the
+    learner's minibatch size, each timed with HIP events on the stream it is
+    launched on; the slowest launch is reported against the MFMA peak of its
+    operand type (algorithmic FLOPs 2*M*N*K per launch)."""
+    import torch
+    import paper_1911_00357_amd as P
+    from paper_1911_00357_amd._lib import PPO_OP_LEARN
+    from synth import rollout as R
+    dev = torch.device("cuda", 0)
+    n = P.Net(wl.net, wl.dtype)
+    params = torch.tensor(R.init_params(wl.net, seed), device=dev)
+    lp = P.cast_bf16(params) if wl.dtype == "bf16" else None
+    grad = torch.zeros_like(params)
+    F = wl.T * wl.N // wl.ppo.minibatches
+    nunits = n.probe(PPO_OP_LEARN, F, 1, 3)[3][0]
+    rows = []
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    for u in range(nunits):
+        name = n.probe(PPO_OP_LEARN, F, 1, 0, u)[0]
+        for op in (0, 1, 2):
+            if op == 1 and u == 0:
+                continue              # the first convolution needs no data gradient
+            n.bench_unit_gemm(op, u, F, params, lp, grad, 2)
+            ev[0].record()
+            fl = n.bench_unit_gemm(op, u, F, params, lp, grad, reps)
+            ev[1].record()
+            torch.cuda.synchronize()
+            rows.append((ev[0].elapsed_time(ev[1]) / reps, fl, name, op))
+    t_ms, fl, name, op = max(rows)
+    peak = PEAK_BF16_TFLOPS if wl.dtype == "bf16" else PEAK_FP32_TFLOPS
+    ach = fl / (t_ms / 1e3) / 1e12
+    tot_t = sum(r[0] for r in rows)
+    tot_f = sum(r[1] for r in rows)
+    return {"bound": "mfma", "achieved": round(ach, 3), "peak": peak, "unit": "TFLOP/s",
+            "frac": round(ach / peak, 5), "traffic": None,
+            "kernel": f"{['conv forward', 'conv data gradient', 'conv weight gradient'][op]} GEMM of {name}",
+            "frames": F, "avg_launch_us": round(t_ms * 1e3, 2), "flops_per_launch": fl,
+            "all_conv_gemms_tflops": round(tot_f / (tot_t / 1e3) / 1e12, 3)}
 
 
 def flops_per_frame(net):
@@ -173,6 +272,8 @@ def flops_per_frame(net):
 
 def main():
     a = parse()
+    global GRAPH
+    GRAPH = not a.eager
     if a.gpus != 1:
         print(json.dumps({"error": "this build measures one GPU; the gradient all-reduce of a "
                                    "multi-GPU worker group is not implemented", "n_gpus": a.gpus}))
@@ -215,6 +316,15 @@ def main():
         out["fp32_value"] = round(r32["frames"] / (r32["gpu_ms"] / 1e3), 2)
         out["bf16_speedup_vs_fp32"] = round(out["value"] / out["fp32_value"], 3)
         del r32
+    if wl.ragged:
+        torch.cuda.empty_cache()
+        ua, uu, ufr = unpacked_split(wl, a.seed)
+        out["unpacked_act_frames_per_s"] = round((ufr + wl.N) / (ua / 1e3), 1)
+        out["unpacked_update_frames_per_s"] = round(ufr / (uu / 1e3), 1)
+        out["packed_speedup_act"] = round(out["act_frames_per_s"] / out["unpacked_act_frames_per_s"], 3)
+        out["packed_speedup_update"] = round(out["update_frames_per_s"] / out["unpacked_update_frames_per_s"], 3)
+    torch.cuda.empty_cache()
+    out["roofline"] = roofline(wl, a.seed)
     if not a.no_cpu:
         out["cpu_baseline"] = cpu_baseline(wl, a.seed)
     print(json.dumps(out), flush=True)

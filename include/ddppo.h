@@ -202,6 +202,28 @@ ppo_status ppo_loss_backward(ppo_net* net, const ppo_batch* b, const ppo_loss_cf
                              size_t ws_bytes, void* stream);
 
 /* ---------------------------------------------------------------------------
+ * The learner split in two, for callers that form their own loss on the
+ * policy outputs (e.g. an autograd function).  Both use the minibatch of
+ * ppo_batch; the action/logp_old/adv/ret fields are not read.
+ *
+ * ppo_policy_forward: logits [F][A] and values [F] of every valid frame of
+ * the minibatch (F = sum of the chosen envs' lengths), frames in the packed
+ * order (time-major; envs sorted by length, longest first, ties in the given
+ * order); frame_src [F] (device int32, or NULL) receives t*N + env of each
+ * frame.  Nothing is kept in the workspace between calls.
+ *
+ * ppo_policy_backward: recomputes the same forward (activations are not
+ * stored between the calls), then writes grad = d(sum dlogits*logits +
+ * dvalues*values)/dtheta for the given dlogits [F][A], dvalues [F] in that
+ * frame order.  Workspace sizes as for ppo_loss_backward.
+ */
+ppo_status ppo_policy_forward(ppo_net* net, const ppo_batch* b, float* logits, float* values,
+                              int32_t* frame_src, void* ws, size_t ws_bytes, void* stream);
+ppo_status ppo_policy_backward(ppo_net* net, const ppo_batch* b, const float* dlogits,
+                               const float* dvalues, float* grad, void* ws, size_t ws_bytes,
+                               void* stream);
+
+/* ---------------------------------------------------------------------------
  * ppo_adam_step -- ParamUpdate of Eq. 3-4 (Adam, Kingma & Ba, with bias
  * correction; the paper's optimiser, Sec. 4 "Training").  Device state:
  *   scaler->scale S: gradients arrive multiplied by S and are unscaled here;
@@ -251,6 +273,16 @@ ppo_status ppo_adam_step(float* master, const float* grad, float* m, float* v, v
  * Returns PPO_EINVAL for an index or kind that does not exist. */
 ppo_status ppo_workspace_probe(const ppo_net* net, int op, int max_frames, int max_envs, int kind,
                                int index, const char** name, int* relu, size_t* offset, int dims[4]);
+
+/* Benchmark aid: enqueue `reps` launches of the convolution GEMM of trunk
+ * unit `unit` (op 0 forward, 1 data gradient, 2 weight gradient) at `frames`
+ * frames, with the tile shape and K split that ppo_loss_backward uses for it,
+ * on workspace scratch data (workspace laid out as for ppo_loss_backward with
+ * max_frames = frames, max_envs = 1).  *flops = 2*M*N*K of one launch.  The
+ * weight-gradient op writes that unit's slot of grad. */
+ppo_status ppo_bench_unit_gemm(ppo_net* net, int op, int unit, int frames, const float* params,
+                               const void* params_lp, float* grad, void* ws, size_t ws_bytes, int reps,
+                               double* flops, void* stream);
 
 /* dst[i] = bfloat16(src[i]) (round to nearest even) for the initial working
  * copy of the parameters; later copies come from ppo_adam_step.  src [n]

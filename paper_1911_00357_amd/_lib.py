@@ -70,12 +70,18 @@ EXPORTS = {
                         c_void_p, c_void_p, c_void_p, c_void_p]),
     "ppo_loss_backward": (c_int, [c_void_p, C.POINTER(Batch), C.POINTER(LossCfg), c_void_p, c_void_p,
                                   c_void_p, c_void_p, c_size_t, c_void_p]),
+    "ppo_policy_forward": (c_int, [c_void_p, C.POINTER(Batch), c_void_p, c_void_p, c_void_p, c_void_p,
+                                   c_size_t, c_void_p]),
+    "ppo_policy_backward": (c_int, [c_void_p, C.POINTER(Batch), c_void_p, c_void_p, c_void_p, c_void_p,
+                                    c_size_t, c_void_p]),
     "ppo_adam_workspace_size": (c_size_t, [c_size_t]),
     "ppo_adam_step": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_size_t,
                               C.POINTER(AdamCfg), c_void_p, c_void_p, c_size_t, c_void_p]),
     "ppo_cast_bf16": (c_int, [c_void_p, c_void_p, c_size_t, c_void_p]),
     "ppo_workspace_probe": (c_int, [c_void_p, c_int, c_int, c_int, c_int, c_int, C.POINTER(C.c_char_p),
                                     C.POINTER(c_int), C.POINTER(c_size_t), C.POINTER(c_int)]),
+    "ppo_bench_unit_gemm": (c_int, [c_void_p, c_int, c_int, c_int, c_void_p, c_void_p, c_void_p, c_void_p,
+                                    c_size_t, c_int, C.POINTER(C.c_double), c_void_p]),
     "ppo_last_error": (C.c_char_p, []),
 }
 

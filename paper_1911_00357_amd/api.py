@@ -115,8 +115,8 @@ class Net:
         if ws is None or ws.numel() < need:
             ws = torch.empty(need, dtype=torch.uint8, device=device)
             self._ws[key] = ws
-        if POISON_WS:  # every byte 0xff: a float read of unwritten scratch is NaN
-            ws.fill_(0xFF)
+        if POISON_WS and not torch.cuda.is_current_stream_capturing():
+            ws.fill_(0xFF)  # every byte 0xff: a float read of unwritten scratch is NaN
         return ws
 
     def probe(self, op: int, max_frames: int, max_envs: int, kind: int, index: int = 0):
@@ -127,6 +127,17 @@ class Net:
         check(lib().ppo_workspace_probe(self._h, op, max_frames, max_envs, kind, index, C.byref(name),
                                         C.byref(relu), C.byref(off), dims), "ppo_workspace_probe")
         return (name.value.decode() if name.value else ""), relu.value, off.value, list(dims)
+
+    def bench_unit_gemm(self, op: int, unit: int, frames: int, params, params_lp, grad, reps: int):
+        """Enqueue `reps` launches of one trunk unit's convolution GEMM (benchmark
+        aid); returns the algorithmic FLOPs of one launch."""
+        dev = params.device
+        ws = self.workspace(L.PPO_OP_LEARN, frames, 1, dev)
+        fl = C.c_double()
+        check(lib().ppo_bench_unit_gemm(self._h, op, unit, frames, _ptr(params), _ptr(params_lp), _ptr(grad),
+                                        _ptr(ws), ws.numel(), reps, C.byref(fl), _stream(dev)),
+              "ppo_bench_unit_gemm")
+        return fl.value
 
     def last_workspace(self, op: int):
         return self._ws.get((op, "cuda:0")) if self._ws else None
@@ -142,8 +153,12 @@ class Net:
         _need(obs, odt, "obs")
         _need(goal, torch.float32, "goal", B * 2)
         _need(mask, torch.float32, "mask", B)
-        _need(h_in, torch.float32, "h_in", self.L * SR * self.H)
-        _need(c_in, torch.float32, "c_in", self.L * SR * self.H)
+        # rows < B of every layer are read: at least (L-1)*SR*H + B*H elements
+        need_state = (self.L - 1) * SR * self.H + B * self.H
+        for nm, t in (("h_in", h_in), ("c_in", c_in)):
+            _need(t, torch.float32, nm)
+            if t.numel() < need_state:
+                raise ValueError(f"{nm} holds {t.numel()} elements, needs {need_state}")
         _need(u, torch.float32, "u", B)
         _need(params, torch.float32, "params", self.P)
         if self.spec.prev_act_dim:
@@ -165,6 +180,10 @@ class Net:
         io.h_in, io.c_in, io.u = _ptr(h_in), _ptr(c_in), _ptr(u)
         io.params, io.params_lp = _ptr(params), _ptr(params_lp)
         io.action, io.logp, io.value = _ptr(out["action"]), _ptr(out["logp"]), _ptr(out["value"])
+        for nm in ("h", "c"):
+            _need(out[nm], torch.float32, "out." + nm)
+            if out[nm].numel() < need_state:
+                raise ValueError(f"out.{nm} holds {out[nm].numel()} elements, needs {need_state}")
         io.h_out, io.c_out = _ptr(out["h"]), _ptr(out["c"])
         io.logits = _ptr(out.get("logits"))
         ws = self.workspace(L.PPO_OP_ACT, B, 1, dev)
@@ -172,22 +191,17 @@ class Net:
         return out
 
     # -------------------------------------------------------------- learner
-    def loss_backward(self, ro: dict, env_ids, lengths, params, params_lp=None, cfg: LossCfg = None,
-                      loss_scale=None, adv_stats=None, grad=None, stats=None):
-        """ro: device rollout dict with obs [T+1,N,C,H,W], goal [T+1,N,2],
-        prev_action/action [T+1,N] int32, mask/logp [T+1,N], adv/ret [T,N],
-        h0/c0 [L,N,H].  env_ids: host ints; lengths: host ints [N] or None."""
-        cfg = cfg or LossCfg()
+    def _batch(self, ro, env_ids, lengths, params, params_lp, learner=True):
         obs = ro["obs"]
         T1, N = obs.shape[0], obs.shape[1]
         T = T1 - 1
-        dev = obs.device
         _need(obs, torch.bfloat16 if self.bf16 else torch.float32, "obs")
-        for k, dt, n in (("goal", torch.float32, T1 * N * 2), ("mask", torch.float32, T1 * N),
-                         ("action", torch.int32, T1 * N), ("logp", torch.float32, T1 * N),
-                         ("adv", torch.float32, T * N), ("ret", torch.float32, T * N),
-                         ("h0", torch.float32, self.L * N * self.H),
-                         ("c0", torch.float32, self.L * N * self.H)):
+        fields = [("goal", torch.float32, T1 * N * 2), ("mask", torch.float32, T1 * N),
+                  ("h0", torch.float32, self.L * N * self.H), ("c0", torch.float32, self.L * N * self.H)]
+        if learner:
+            fields += [("action", torch.int32, T1 * N), ("logp", torch.float32, T1 * N),
+                       ("adv", torch.float32, T * N), ("ret", torch.float32, T * N)]
+        for k, dt, n in fields:
             _need(ro[k], dt, k, n)
         if self.spec.prev_act_dim:
             _need(ro["prev_action"], torch.int32, "prev_action", T1 * N)
@@ -206,10 +220,20 @@ class Net:
         b.lengths = C.cast(lens, L.P_i32) if lens is not None else None
         b.obs, b.goal, b.prev_action, b.mask = (_ptr(obs), _ptr(ro["goal"]),
                                                 _ptr(ro.get("prev_action")), _ptr(ro["mask"]))
-        b.action, b.logp_old, b.adv, b.ret = (_ptr(ro["action"]), _ptr(ro["logp"]),
-                                              _ptr(ro["adv"]), _ptr(ro["ret"]))
+        if learner:
+            b.action, b.logp_old, b.adv, b.ret = (_ptr(ro["action"]), _ptr(ro["logp"]),
+                                                  _ptr(ro["adv"]), _ptr(ro["ret"]))
         b.h0, b.c0 = _ptr(ro["h0"]), _ptr(ro["c0"])
         b.params, b.params_lp = _ptr(params), _ptr(params_lp)
+        return b, (env, lens), F, obs.device
+
+    def loss_backward(self, ro: dict, env_ids, lengths, params, params_lp=None, cfg: LossCfg = None,
+                      loss_scale=None, adv_stats=None, grad=None, stats=None):
+        """ro: device rollout dict with obs [T+1,N,C,H,W], goal [T+1,N,2],
+        prev_action/action [T+1,N] int32, mask/logp [T+1,N], adv/ret [T,N],
+        h0/c0 [L,N,H].  env_ids: host ints; lengths: host ints [N] or None."""
+        cfg = cfg or LossCfg()
+        b, keep, F, dev = self._batch(ro, env_ids, lengths, params, params_lp)
         c = L.LossCfg()
         c.clip, c.value_coef, c.entropy_coef = cfg.clip, cfg.value_coef, cfg.entropy_coef
         c.norm_adv = int(cfg.norm_adv)
@@ -223,6 +247,29 @@ class Net:
                                       _ptr(stats), _ptr(ws), ws.numel(), _stream(dev)),
               "ppo_loss_backward")
         return grad, stats
+
+    def policy_forward(self, ro, env_ids, lengths, params, params_lp=None):
+        """logits [F, A], values [F], frame_src [F] (t*N + env) of every valid
+        minibatch frame, in the library's packed order."""
+        b, keep, F, dev = self._batch(ro, env_ids, lengths, params, params_lp, learner=False)
+        logits = torch.empty(F, self.A, dtype=torch.float32, device=dev)
+        values = torch.empty(F, dtype=torch.float32, device=dev)
+        src = torch.empty(F, dtype=torch.int32, device=dev)
+        ws = self.workspace(L.PPO_OP_LEARN, F, len(env_ids), dev)
+        check(lib().ppo_policy_forward(self._h, C.byref(b), _ptr(logits), _ptr(values), _ptr(src), _ptr(ws),
+                                       ws.numel(), _stream(dev)), "ppo_policy_forward")
+        return logits, values, src
+
+    def policy_backward(self, ro, env_ids, lengths, params, params_lp, dlogits, dvalues, grad=None):
+        b, keep, F, dev = self._batch(ro, env_ids, lengths, params, params_lp, learner=False)
+        _need(dlogits, torch.float32, "dlogits", F * self.A)
+        _need(dvalues, torch.float32, "dvalues", F)
+        if grad is None:
+            grad = torch.empty(self.P, dtype=torch.float32, device=dev)
+        ws = self.workspace(L.PPO_OP_LEARN, F, len(env_ids), dev)
+        check(lib().ppo_policy_backward(self._h, C.byref(b), _ptr(dlogits), _ptr(dvalues), _ptr(grad),
+                                        _ptr(ws), ws.numel(), _stream(dev)), "ppo_policy_backward")
+        return grad
 
 
 def gae(rew, val, done, lengths, gamma, lam, adv=None, ret=None, stats=None):

@@ -212,7 +212,7 @@ struct WsLayout {
   std::vector<size_t> g, c, cp, hp, hout;  // per layer
   size_t h0g, c0g;                 // gathered start state [L][nb][H]
   size_t zh;                       // act: [B][max(din0, H) + H]
-  size_t fstat, dout, dh0, dh1, dG, dhp, dcp, dvis;
+  size_t fstat, dout, dh0, dh1, dG, dhp, dcp, dvis, whT;
   size_t total;
 };
 
@@ -270,6 +270,7 @@ WsLayout plan(const ppo_net* n, int F, int nb, bool learn) {
     w.dhp = A.take((size_t)std::max(nb, 1) * H * f4);
     w.dcp = A.take((size_t)std::max(nb, 1) * H * f4);
     w.dvis = A.take((size_t)F * d.vis_hidden * f4);
+    w.whT = A.take((size_t)4 * H * H * f4);
   }
   w.total = A.off;
   return w;
@@ -294,12 +295,7 @@ struct Ctx {
     return n->prec ? (const void*)((const bf16_t*)lp + off) : (const void*)(params + off);
   }
   float* splitk() const { return at(w->splitk); }
-  int splits(long M, long N, long K) const {
-    int s = gemm_max_splits_for(M, N, K, n->prec);
-    const long cap = (long)(kSplitKBytes / (sizeof(float) * (size_t)M * N));
-    if (s > cap) s = (int)std::max<long>(1, cap);
-    return s;
-  }
+  bool keep_u = true;  // store convolution outputs for a backward pass
 };
 
 ConvGeo geo(const Unit& u, int F) {
@@ -310,9 +306,19 @@ ConvGeo geo(const Unit& u, int F) {
 void unit_fwd(const Ctx& c, int ui, const float* x, const float* res, bool relu, float* out, bool chw) {
   const Unit& u = c.n->units[ui];
   const ConvGeo g = geo(u, c.F);
-  const long M = (long)c.F * u.Hout * u.Wout, K = (long)u.K * u.K * u.Cin;
-  gemm_conv_fwd(c.n->prec, g, x, c.wt(u.w), epi(c.at(c.w->u[ui]), u.Cout), c.splits(M, u.Cout, K),
-                c.splitk(), c.s);
+  const int P = u.Hout * u.Wout, G = c.n->d.gn_groups;
+  if (gn_fused_npt(P, u.Cout / G)) {
+    // conv (split-K partials left in place) -> one fused GroupNorm launch
+    float* y = c.at(c.w->u[ui]);
+    const int splits = gemm_conv_fwd(c.n->prec, g, x, c.wt(u.w), epi(y, u.Cout), kSplitKBytes, c.splitk(), c.s,
+                                     true);
+    const float* src = splits > 1 ? c.splitk() : y;
+    launch_gn_fused(src, splits, (size_t)c.F * P * u.Cout, (splits > 1 && c.keep_u) ? y : nullptr, c.F, P,
+                    u.Cout, G, kGnEps, c.pf(u.g), c.pf(u.b), res, relu ? 1 : 0, out, chw ? 1 : 0,
+                    c.at<float2>(c.w->st[ui]), c.s);
+    return;
+  }
+  gemm_conv_fwd(c.n->prec, g, x, c.wt(u.w), epi(c.at(c.w->u[ui]), u.Cout), kSplitKBytes, c.splitk(), c.s);
   launch_gn_forward(c.at(c.w->u[ui]), c.F, u.Hout * u.Wout, u.Cout, c.n->d.gn_groups, kGnEps, c.pf(u.g),
                     c.pf(u.b), res, relu ? 1 : 0, out, chw ? 1 : 0, c.at<float2>(c.w->st[ui]),
                     c.at<float4>(c.w->gpart), u.S, c.s);
@@ -353,22 +359,34 @@ const float* encoder_fwd(const Ctx& c) {
 //   ReLU'd output for the mask (or null); x: the conv input; dx: data gradient
 //   out (null = not needed), dx_acc: accumulate into dx; dres: also write the
 //   masked output gradient (the residual branch's gradient).
+// GroupNorm backward of one unit (fused per image and group when it fits).
+void gn_bwd(const Ctx& c, int ui, const float* dout, const float* mask_out, bool chw, float* du, float* dres) {
+  const Unit& u = c.n->units[ui];
+  const int P = u.Hout * u.Wout, G = c.n->d.gn_groups;
+  if (gn_fused_npt(P, u.Cout / G)) {
+    launch_gnb_fused(dout, mask_out, chw ? 1 : 0, c.at(c.w->u[ui]), c.F, P, u.Cout, G, c.at<float2>(c.w->st[ui]),
+                     c.pf(u.g), du, dres, c.grad + u.g, c.grad + u.b, c.at<float2>(c.w->gbpart), c.s);
+    return;
+  }
+  launch_gn_backward(dout, mask_out, chw ? 1 : 0, c.at(c.w->u[ui]), c.F, P, u.Cout, G, c.at<float2>(c.w->st[ui]),
+                     c.pf(u.g), du, dres, c.grad + u.g, c.grad + u.b, c.at<float2>(c.w->gbpart),
+                     c.at<float2>(c.w->gcoef), u.S, c.s);
+}
+
 void unit_bwd(const Ctx& c, int ui, const float* dout, const float* mask_out, bool chw, const float* x,
               float* du, float* dx, bool dx_acc, float* dres) {
   const Unit& u = c.n->units[ui];
   const ppo_net* n = c.n;
   const int P = u.Hout * u.Wout;
-  launch_gn_backward(dout, mask_out, chw ? 1 : 0, c.at(c.w->u[ui]), c.F, P, u.Cout, n->d.gn_groups,
-                     c.at<float2>(c.w->st[ui]), c.pf(u.g), du, dres, c.grad + u.g, c.grad + u.b,
-                     c.at<float2>(c.w->gbpart), c.at<float2>(c.w->gcoef), u.S, c.s);
+  gn_bwd(c, ui, dout, mask_out, chw, du, dres);
   const ConvGeo g = geo(u, c.F);
   const long R = (long)c.F * P, Kw = (long)u.K * u.K * u.Cin;
-  gemm_conv_wgrad(n->prec, g, x, du, epi(c.grad + u.w, (int)Kw), c.splits(u.Cout, Kw, R), c.splitk(),
+  gemm_conv_wgrad(n->prec, g, x, du, epi(c.grad + u.w, (int)Kw), kSplitKBytes, c.splitk(),
                   c.s);
   if (dx) {
     const long M = (long)c.F * u.Hin * u.Win, K = (long)u.K * u.K * u.Cout;
     gemm_conv_dgrad(n->prec, g, du, c.wt(u.w), epi(dx, u.Cin, nullptr, 0, dx_acc ? 1 : 0),
-                    c.splits(M, u.Cin, K), c.splitk(), c.s);
+                    kSplitKBytes, c.splitk(), c.s);
   }
 }
 
@@ -397,18 +415,15 @@ void encoder_bwd(const Ctx& c, const float* dfeat) {
       // c1 first (its du must not be overwritten before its data gradient)
       const Unit& u1 = n->units[b.c1];
       const int P1 = u1.Hout * u1.Wout;
-      launch_gn_backward(GD, c.at(w.a[b.c1]), 0, c.at(w.u[b.c1]), c.F, P1, u1.Cout, n->d.gn_groups,
-                         c.at<float2>(w.st[b.c1]), c.pf(u1.g), GU, nullptr, c.grad + u1.g, c.grad + u1.b,
-                         c.at<float2>(w.gbpart), c.at<float2>(w.gcoef), u1.S, c.s);
+      gn_bwd(c, b.c1, GD, c.at(w.a[b.c1]), false, GU, nullptr);
       const ConvGeo g1 = geo(u1, c.F);
       const long R1 = (long)c.F * P1, K1 = (long)u1.Cin;
-      gemm_conv_wgrad(n->prec, g1, xin, GU, epi(c.grad + u1.w, (int)K1), c.splits(u1.Cout, K1, R1),
-                      c.splitk(), c.s);
+      gemm_conv_wgrad(n->prec, g1, xin, GU, epi(c.grad + u1.w, (int)K1), kSplitKBytes, c.splitk(), c.s);
       // projection shortcut: writes dX, then c1's data gradient accumulates
       unit_bwd(c, b.ds, GR, nullptr, false, xin, GD, GB, false, nullptr);
       const long M = (long)c.F * u1.Hin * u1.Win;
       gemm_conv_dgrad(n->prec, g1, GU, c.wt(u1.w), epi(GB, u1.Cin, nullptr, 0, 1),
-                      c.splits(M, u1.Cin, u1.Cout), c.splitk(), c.s);
+                      kSplitKBytes, c.splitk(), c.s);
     } else {
       unit_bwd(c, b.c1, GD, c.at(w.a[b.c1]), false, xin, GU, GB, true, nullptr);
     }
@@ -489,6 +504,7 @@ ppo_status ppo_act(ppo_net* net, const ppo_act_io* io, void* ws, size_t ws_bytes
   if (!al256(ws)) return fail(PPO_EWORKSPACE, "workspace must be 256-byte aligned");
   hipStream_t s = strm(stream);
   Ctx c{net, &w, (char*)ws, io->params, io->params_lp, nullptr, s, B};
+  c.keep_u = false;
   const int H = d.hidden, L = d.lstm_layers, A = d.num_actions;
   // frames -> encoder -> features
   launch_prep(io->obs, net->prec, nullptr, B, d.in_ch, d.in_hw, d.in_hw, d.avgpool, c.at(w.x0), s);
@@ -498,7 +514,7 @@ ppo_status ppo_act(ppo_net* net, const ppo_act_io* io, void* ws, size_t ws_bytes
   float* zh = c.at(w.zh);
   gemm_dense(net->prec, false, false, feat, net->flat, c.wt(net->fc_w), net->prec == 1, net->flat, B,
              d.vis_hidden, net->flat, epi(zh, ld0, c.pf(net->fc_b), 1),
-             c.splits(B, d.vis_hidden, net->flat), c.splitk(), s);
+             false, kSplitKBytes, c.splitk(), s);
   launch_embed_fwd(io->goal, io->prev_action, io->mask, nullptr, B, d.goal_mode == PPO_GOAL_POLAR,
                    d.goal_dim, d.goal_mode == PPO_GOAL_POLAR ? c.pf(net->goal_w) : nullptr,
                    d.goal_mode == PPO_GOAL_POLAR ? c.pf(net->goal_b) : nullptr, std::max(0, d.prev_act_dim),
@@ -512,17 +528,15 @@ ppo_status ppo_act(ppo_net* net, const ppo_act_io* io, void* ws, size_t ws_bytes
     launch_mask_state(io->h_in + (size_t)l * SR * H, io->c_in + (size_t)l * SR * H, io->mask, B, H,
                       zl[l] + din, din + H, cpl[l], s);
   }
-  float* G = c.at(w.g[0]);  // gates [B][4H]; the layer-0 input lives in zh
   for (int l = 0; l < L; ++l) {
     const int din = l == 0 ? net->din0 : H;
-    gemm_dense(net->prec, false, false, zl[l], din + H, c.wt(net->lstm_w[l]), net->prec == 1, din + H, B,
-               4 * H, din + H, epi(G, 4 * H, c.pf(net->lstm_b[l])), c.splits(B, 4 * H, din + H),
-               c.splitk(), s);
     const bool top = l == L - 1;
     float* hdst = top ? io->h_out + (size_t)l * SR * H : zl[l + 1];
     const int ldh = top ? H : 2 * H;
-    launch_lstm_fwd(G, cpl[l], hdst, ldh, io->c_out + (size_t)l * SR * H, B, H, nullptr, 0, nullptr,
-                    nullptr, s);
+    // gates = [x | m h] [W_ih | W_hh]^T + b and the cell, in one launch
+    launch_lstm_step_fwd(net->prec, zl[l], din + H, din + H, c.wt(net->lstm_w[l]), din + H, nullptr,
+                         c.pf(net->lstm_b[l]), cpl[l], B, H, nullptr, hdst, ldh,
+                         io->c_out + (size_t)l * SR * H, nullptr, 0, nullptr, 0, nullptr, s);
     if (!top) launch_copy2d(hdst, ldh, B, H, io->h_out + (size_t)l * SR * H, H, s);
   }
   launch_act_head(io->h_out + (size_t)(L - 1) * SR * H, B, H, A, c.pf(net->head_w), c.pf(net->head_b),
@@ -541,22 +555,29 @@ ppo_status ppo_gae(const float* rew, const float* val, const uint8_t* done, cons
   return check_launch();
 }
 
-ppo_status ppo_loss_backward(ppo_net* net, const ppo_batch* b, const ppo_loss_cfg* cfg,
-                             const float* d_loss_scale, float* grad, float* stats, void* ws,
-                             size_t ws_bytes, void* stream) {
-  if (!net || !b || !cfg || !grad || !stats) return fail(PPO_EINVAL, "null argument");
+}  // extern "C"
+
+namespace {
+
+// Minibatch schedule: envs sorted by length (longest first, stable), frames
+// packed time-major; step t holds the first act[t] envs at frames off[t]...
+struct Sched {
+  MapArgs m;
+  int F = 0, TB = 0;
+  std::vector<int> act, off;
+};
+
+ppo_status schedule(const ppo_net* net, const ppo_batch* b, Sched& S) {
   const ppo_net_desc& d = net->d;
-  if (!b->env_ids || !b->obs || !b->goal || !b->mask || !b->action || !b->logp_old || !b->adv ||
-      !b->ret || !b->h0 || !b->c0 || !b->params || (net->prec && !b->params_lp) ||
-      (d.prev_act_dim > 0 && !b->prev_action) || (cfg->norm_adv && !cfg->adv_stats))
+  if (!b->env_ids || !b->obs || !b->goal || !b->mask || !b->h0 || !b->c0 || !b->params ||
+      (net->prec && !b->params_lp) || (d.prev_act_dim > 0 && !b->prev_action))
     return fail(PPO_EINVAL, "null pointer in ppo_batch");
   if (b->T <= 0 || b->N <= 0 || b->nb <= 0 || b->nb > b->N || b->nb > kMaxMbEnvs)
     return fail(PPO_ESHAPE, "bad T / N / nb");
-  // length-sorted env list (descending, stable)
-  MapArgs m{};
-  m.nb = b->nb;
-  m.N = b->N;
-  m.T = b->T;
+  S.m = MapArgs{};
+  S.m.nb = b->nb;
+  S.m.N = b->N;
+  S.m.T = b->T;
   std::vector<std::pair<int, int>> order;
   for (int j = 0; j < b->nb; ++j) {
     const int e = b->env_ids[j];
@@ -565,44 +586,50 @@ ppo_status ppo_loss_backward(ppo_net* net, const ppo_batch* b, const ppo_loss_cf
     if (len < 1 || len > b->T) return fail(PPO_ESHAPE, "length %d of env %d outside 1..T", len, e);
     order.push_back({len, e});
   }
-  std::stable_sort(order.begin(), order.end(), [](const std::pair<int, int>& x, const std::pair<int, int>& y) {
-    return x.first > y.first;
-  });
-  int F = 0;
+  std::stable_sort(order.begin(), order.end(),
+                   [](const std::pair<int, int>& x, const std::pair<int, int>& y) { return x.first > y.first; });
+  S.F = 0;
   for (int j = 0; j < b->nb; ++j) {
-    m.env[j] = order[j].second;
-    m.len[j] = order[j].first;
-    F += order[j].first;
+    S.m.env[j] = order[j].second;
+    S.m.len[j] = order[j].first;
+    S.F += order[j].first;
   }
-  m.F = F;
-  const int TB = m.len[0];
-  std::vector<int> act(TB + 1, 0), off(TB + 1, 0);
-  for (int t = 0; t < TB; ++t) {
-    for (int j = 0; j < b->nb; ++j) act[t] += (m.len[j] > t);
-    off[t + 1] = off[t] + act[t];
+  S.m.F = S.F;
+  S.TB = S.m.len[0];
+  S.act.assign(S.TB + 1, 0);
+  S.off.assign(S.TB + 1, 0);
+  for (int t = 0; t < S.TB; ++t) {
+    for (int j = 0; j < b->nb; ++j) S.act[t] += (S.m.len[j] > t);
+    S.off[t + 1] = S.off[t] + S.act[t];
   }
-  const WsLayout w = plan(net, F, b->nb, true);
-  if (!ws || ws_bytes < w.total) return fail(PPO_EWORKSPACE, "workspace needs %zu bytes", w.total);
-  if (!al256(ws)) return fail(PPO_EWORKSPACE, "workspace must be 256-byte aligned");
-  hipStream_t s = strm(stream);
-  Ctx c{net, &w, (char*)ws, b->params, b->params_lp, grad, s, F};
-  const int H = d.hidden, L = d.lstm_layers, A = d.num_actions, nb = b->nb;
+  return PPO_OK;
+}
+
+// Forward over every frame of the minibatch: encoder, visual FC, goal and
+// previous-action inputs, the LSTM over time.  Returns the flat features;
+// the top LSTM output is left in the layer's hout buffer.
+const float* learner_fwd(const Ctx& c, const ppo_batch* b, const Sched& S) {
+  const ppo_net* net = c.n;
+  const ppo_net_desc& d = net->d;
+  const WsLayout& w = *c.w;
+  hipStream_t s = c.s;
+  const int F = S.F, TB = S.TB;
+  const std::vector<int>& act = S.act;
+  const std::vector<int>& off = S.off;
+  const int H = d.hidden, L = d.lstm_layers, nb = b->nb;
   const int32_t* src = c.at<int32_t>(w.src);
-  const float* wf = c.at(w.wf);
   const float* mskf = c.at(w.mskf);
   const int32_t* envrow = c.at<int32_t>(w.envrow);
-  launch_frame_map(m, b->mask, c.at<int32_t>(w.src), c.at(w.wf), c.at(w.mskf), c.at<int32_t>(w.envrow), s);
+  launch_frame_map(S.m, b->mask, c.at<int32_t>(w.src), c.at(w.wf), c.at(w.mskf), c.at<int32_t>(w.envrow), s);
   launch_gather_state(b->h0, L, b->N, nb, H, envrow, c.at(w.h0g), s);
   launch_gather_state(b->c0, L, b->N, nb, H, envrow, c.at(w.c0g), s);
 
-  // ---- forward
   launch_prep(b->obs, net->prec, src, F, d.in_ch, d.in_hw, d.in_hw, d.avgpool, c.at(w.x0), s);
   const float* feat = encoder_fwd(c);
   const int D0 = net->din0;
   float* Z = c.at(w.z);
   gemm_dense(net->prec, false, false, feat, net->flat, c.wt(net->fc_w), net->prec == 1, net->flat, F,
-             d.vis_hidden, net->flat, epi(Z, D0, c.pf(net->fc_b), 1), c.splits(F, d.vis_hidden, net->flat),
-             c.splitk(), s);
+             d.vis_hidden, net->flat, epi(Z, D0, c.pf(net->fc_b), 1), false, kSplitKBytes, c.splitk(), s);
   const bool polar = d.goal_mode == PPO_GOAL_POLAR;
   const int E = std::max(0, d.prev_act_dim);
   launch_embed_fwd(b->goal, b->prev_action, b->mask, src, F, polar, d.goal_dim,
@@ -616,33 +643,48 @@ ppo_status ppo_loss_backward(ppo_net* net, const ppo_batch* b, const ppo_loss_cf
           *Ho = c.at(w.hout[l]);
     // input projection of every frame at once
     gemm_dense(net->prec, false, false, X, din, c.wt(wl), net->prec == 1, din + H, F, 4 * H, din,
-               epi(G, 4 * H, c.pf(net->lstm_b[l])), c.splits(F, 4 * H, din), c.splitk(), s);
+               epi(G, 4 * H, c.pf(net->lstm_b[l])), false, kSplitKBytes, c.splitk(), s);
     launch_mask_state(c.at(w.h0g) + (size_t)l * nb * H, c.at(w.c0g) + (size_t)l * nb * H, mskf, act[0], H,
                       HP, H, CP, s);
+    const void* whh = net->prec ? (const void*)((const bf16_t*)b->params_lp + wl + din)
+                                : (const void*)(b->params + wl + din);
     for (int t = 0; t < TB; ++t) {
+      // gates_t = (x_t W_ih^T + b) + (m_t h_{t-1}) W_hh^T, then the cell (activations overwrite G)
       const size_t r0 = off[t];
-      const int rows = act[t];
-      const void* whh = net->prec ? (const void*)((const bf16_t*)b->params_lp + wl + din)
-                                  : (const void*)(b->params + wl + din);
-      gemm_dense(net->prec, false, false, HP + r0 * H, H, whh, net->prec == 1, din + H, rows, 4 * H, H,
-                 epi(G + r0 * 4 * H, 4 * H, nullptr, 0, 1), c.splits(rows, 4 * H, H), c.splitk(), s);
       const bool more = t + 1 < TB;
-      launch_lstm_fwd(G + r0 * 4 * H, CP + r0 * H, Ho + r0 * H, H, Cs + r0 * H, rows, H,
-                      more ? mskf + off[t + 1] : nullptr, more ? act[t + 1] : 0,
-                      more ? HP + (size_t)off[t + 1] * H : nullptr, more ? CP + (size_t)off[t + 1] * H : nullptr,
-                      s);
+      launch_lstm_step_fwd(net->prec, HP + r0 * H, H, H, whh, din + H, G + r0 * 4 * H, nullptr, CP + r0 * H,
+                           act[t], H, G + r0 * 4 * H, Ho + r0 * H, H, Cs + r0 * H,
+                           more ? mskf + off[t + 1] : nullptr, more ? act[t + 1] : 0,
+                           more ? HP + (size_t)off[t + 1] * H : nullptr, H,
+                           more ? CP + (size_t)off[t + 1] * H : nullptr, s);
     }
   }
+  return feat;
+}
+
+// Backward from dout [F][A+1] (w.dout) and the gradient at the top LSTM
+// output (w.dh0), through the LSTM, the FC and input parts and the encoder.
+void learner_bwd(const Ctx& c, const ppo_batch* b, const Sched& S, const float* feat) {
+  const ppo_net* net = c.n;
+  const ppo_net_desc& d = net->d;
+  const WsLayout& w = *c.w;
+  hipStream_t s = c.s;
+  float* grad = c.grad;
+  const int F = S.F, TB = S.TB;
+  const std::vector<int>& act = S.act;
+  const std::vector<int>& off = S.off;
+  const int H = d.hidden, L = d.lstm_layers, A = d.num_actions;
+  const int32_t* src = c.at<int32_t>(w.src);
+  const float* mskf = c.at(w.mskf);
+  const int D0 = net->din0;
+  float* Z = c.at(w.z);
+  const bool polar = d.goal_mode == PPO_GOAL_POLAR;
+  const int E = std::max(0, d.prev_act_dim);
   const float* Htop = c.at(w.hout[L - 1]);
   float* dout = c.at(w.dout);
   float* dH = c.at(w.dh0);
-  launch_loss_head(Htop, F, H, A, c.pf(net->head_w), c.pf(net->head_b), src, b->action, b->logp_old, b->adv,
-                   b->ret, wf, cfg->clip, cfg->value_coef, cfg->entropy_coef, cfg->norm_adv, cfg->adv_stats,
-                   net->prec ? d_loss_scale : nullptr, c.at(w.fstat), dout, dH, stats, s);
-
-  // ---- backward
   gemm_dense(net->prec, true, true, dout, A + 1, Htop, false, H, A + 1, H, F,
-             epi(grad + net->head_w, H), c.splits(A + 1, H, F), c.splitk(), s);
+             epi(grad + net->head_w, H), true, kSplitKBytes, c.splitk(), s);
   launch_colsum(dout, F, A + 1, A + 1, grad + net->head_b, s);
   float* dHn = c.at(w.dh1);
   for (int l = L - 1; l >= 0; --l) {
@@ -650,29 +692,28 @@ ppo_status ppo_loss_backward(ppo_net* net, const ppo_batch* b, const ppo_loss_cf
     const float* X = l == 0 ? Z : c.at(w.hout[l - 1]);
     const size_t wl = net->lstm_w[l];
     float *G = c.at(w.g[l]), *HP = c.at(w.hp[l]), *CP = c.at(w.cp[l]), *Cs = c.at(w.c[l]);
-    float *dG = c.at(w.dG), *dhp = c.at(w.dhp), *dcp = c.at(w.dcp);
+    float *dG = c.at(w.dG), *dcp = c.at(w.dcp);
     const void* whh = net->prec ? (const void*)((const bf16_t*)b->params_lp + wl + din)
                                 : (const void*)(b->params + wl + din);
+    void* whT = c.at<void>(w.whT);
+    launch_transpose_whh(net->prec, whh, din + H, H, whT, s);
     for (int t = TB - 1; t >= 0; --t) {
+      // dh_t = dH_t + m_{t+1} dG_{t+1} W_hh, dc_t = m_{t+1} dc_{t+1} f_{t+1}; cell backward -> dG_t
       const size_t r0 = off[t];
-      const int rows = act[t];
       const bool more = t + 1 < TB;
-      launch_lstm_bwd(G + r0 * 4 * H, Cs + r0 * H, CP + r0 * H, dH + r0 * H, H, rows, H,
-                      more ? mskf + off[t + 1] : nullptr, more ? act[t + 1] : 0, more ? dhp : nullptr,
-                      more ? dcp : nullptr, dG + r0 * 4 * H, dcp, s);
-      if (t > 0)  // gradient into the masked previous h
-        gemm_dense(net->prec, false, true, dG + r0 * 4 * H, 4 * H, whh, net->prec == 1, din + H, rows, H,
-                   4 * H, epi(dhp, H), c.splits(rows, H, 4 * H), c.splitk(), s);
+      launch_lstm_step_bwd(net->prec, more ? dG + (size_t)off[t + 1] * 4 * H : nullptr, whT,
+                           more ? mskf + off[t + 1] : nullptr, more ? act[t + 1] : 0, G + r0 * 4 * H,
+                           Cs + r0 * H, CP + r0 * H, dH + r0 * H, H, act[t], H, dG + r0 * 4 * H, dcp, s);
     }
     // weight gradients over all frames
     gemm_dense(net->prec, true, true, dG, 4 * H, X, false, din, 4 * H, din, F, epi(grad + wl, din + H),
-               c.splits(4 * H, din, F), c.splitk(), s);
+               true, kSplitKBytes, c.splitk(), s);
     gemm_dense(net->prec, true, true, dG, 4 * H, HP, false, H, 4 * H, H, F, epi(grad + wl + din, din + H),
-               c.splits(4 * H, H, F), c.splitk(), s);
+               true, kSplitKBytes, c.splitk(), s);
     launch_colsum(dG, F, 4 * H, 4 * H, grad + net->lstm_b[l], s);
     // gradient into the layer input
     gemm_dense(net->prec, false, true, dG, 4 * H, c.wt(wl), net->prec == 1, din + H, F, din, 4 * H,
-               epi(dHn, din), c.splits(F, din, 4 * H), c.splitk(), s);
+               epi(dHn, din), true, kSplitKBytes, c.splitk(), s);
     std::swap(dH, dHn);
   }
   // dH = gradient at Z [F][D0]
@@ -682,13 +723,79 @@ ppo_status ppo_loss_backward(ppo_net* net, const ppo_batch* b, const ppo_loss_cf
                    d.vis_hidden, polar ? grad + net->goal_w : nullptr, polar ? grad + net->goal_b : nullptr,
                    E ? grad + net->emb : nullptr, s);
   gemm_dense(net->prec, true, true, dvis, d.vis_hidden, feat, false, net->flat, d.vis_hidden, net->flat, F,
-             epi(grad + net->fc_w, net->flat), c.splits(d.vis_hidden, net->flat, F), c.splitk(), s);
+             epi(grad + net->fc_w, net->flat), true, kSplitKBytes, c.splitk(), s);
   launch_colsum(dvis, F, d.vis_hidden, d.vis_hidden, grad + net->fc_b, s);
   float* dfeat = c.at(w.dfeat);
   gemm_dense(net->prec, false, true, dvis, d.vis_hidden, c.wt(net->fc_w), net->prec == 1, net->flat, F,
-             net->flat, d.vis_hidden, epi(dfeat, net->flat), c.splits(F, net->flat, d.vis_hidden), c.splitk(),
+             net->flat, d.vis_hidden, epi(dfeat, net->flat), true, kSplitKBytes, c.splitk(),
              s);
   encoder_bwd(c, dfeat);
+}
+
+}  // namespace
+
+extern "C" {
+
+ppo_status ppo_loss_backward(ppo_net* net, const ppo_batch* b, const ppo_loss_cfg* cfg,
+                             const float* d_loss_scale, float* grad, float* stats, void* ws,
+                             size_t ws_bytes, void* stream) {
+  if (!net || !b || !cfg || !grad || !stats) return fail(PPO_EINVAL, "null argument");
+  if (!b->action || !b->logp_old || !b->adv || !b->ret || (cfg->norm_adv && !cfg->adv_stats))
+    return fail(PPO_EINVAL, "null pointer in ppo_batch");
+  Sched S;
+  const ppo_status st = schedule(net, b, S);
+  if (st != PPO_OK) return st;
+  const WsLayout w = plan(net, S.F, b->nb, true);
+  if (!ws || ws_bytes < w.total) return fail(PPO_EWORKSPACE, "workspace needs %zu bytes", w.total);
+  if (!al256(ws)) return fail(PPO_EWORKSPACE, "workspace must be 256-byte aligned");
+  hipStream_t s = strm(stream);
+  Ctx c{net, &w, (char*)ws, b->params, b->params_lp, grad, s, S.F};
+  const ppo_net_desc& d = net->d;
+  const int H = d.hidden, A = d.num_actions;
+  const float* feat = learner_fwd(c, b, S);
+  launch_loss_head(c.at(w.hout[d.lstm_layers - 1]), S.F, H, A, c.pf(net->head_w), c.pf(net->head_b),
+                   c.at<int32_t>(w.src), b->action, b->logp_old, b->adv, b->ret, c.at(w.wf), cfg->clip,
+                   cfg->value_coef, cfg->entropy_coef, cfg->norm_adv, cfg->adv_stats,
+                   net->prec ? d_loss_scale : nullptr, c.at(w.fstat), c.at(w.dout), c.at(w.dh0), stats, s);
+  learner_bwd(c, b, S, feat);
+  return check_launch();
+}
+
+ppo_status ppo_policy_forward(ppo_net* net, const ppo_batch* b, float* logits, float* values, int32_t* frame_src,
+                              void* ws, size_t ws_bytes, void* stream) {
+  if (!net || !b || !logits || !values) return fail(PPO_EINVAL, "null argument");
+  Sched S;
+  const ppo_status st = schedule(net, b, S);
+  if (st != PPO_OK) return st;
+  const WsLayout w = plan(net, S.F, b->nb, true);
+  if (!ws || ws_bytes < w.total) return fail(PPO_EWORKSPACE, "workspace needs %zu bytes", w.total);
+  if (!al256(ws)) return fail(PPO_EWORKSPACE, "workspace must be 256-byte aligned");
+  hipStream_t s = strm(stream);
+  Ctx c{net, &w, (char*)ws, b->params, b->params_lp, nullptr, s, S.F};
+  const ppo_net_desc& d = net->d;
+  learner_fwd(c, b, S);
+  launch_head_fwd(c.at(w.hout[d.lstm_layers - 1]), S.F, d.hidden, d.num_actions, c.pf(net->head_w),
+                  c.pf(net->head_b), logits, values, s);
+  if (frame_src) launch_copy_i32(c.at<int32_t>(w.src), S.F, frame_src, s);
+  return check_launch();
+}
+
+ppo_status ppo_policy_backward(ppo_net* net, const ppo_batch* b, const float* dlogits, const float* dvalues,
+                               float* grad, void* ws, size_t ws_bytes, void* stream) {
+  if (!net || !b || !dlogits || !dvalues || !grad) return fail(PPO_EINVAL, "null argument");
+  Sched S;
+  const ppo_status st = schedule(net, b, S);
+  if (st != PPO_OK) return st;
+  const WsLayout w = plan(net, S.F, b->nb, true);
+  if (!ws || ws_bytes < w.total) return fail(PPO_EWORKSPACE, "workspace needs %zu bytes", w.total);
+  if (!al256(ws)) return fail(PPO_EWORKSPACE, "workspace must be 256-byte aligned");
+  hipStream_t s = strm(stream);
+  Ctx c{net, &w, (char*)ws, b->params, b->params_lp, grad, s, S.F};
+  const ppo_net_desc& d = net->d;
+  const float* feat = learner_fwd(c, b, S);  // activations recomputed here
+  launch_head_bwd(dlogits, dvalues, S.F, d.hidden, d.num_actions, c.pf(net->head_w), c.at(w.dout),
+                  c.at(w.dh0), s);
+  learner_bwd(c, b, S, feat);
   return check_launch();
 }
 
@@ -708,6 +815,34 @@ ppo_status ppo_adam_step(float* master, const float* grad, float* m, float* v, v
     return fail(PPO_EINVAL, "bad Adam hyper-parameters");
   launch_adam(master, grad, m, v, (bf16_t*)lp_copy, P, cfg->lr, cfg->beta1, cfg->beta2, cfg->eps,
               cfg->growth_interval, scaler, ws, strm(stream));
+  return check_launch();
+}
+
+ppo_status ppo_bench_unit_gemm(ppo_net* net, int op, int unit, int frames, const float* params,
+                               const void* params_lp, float* grad, void* ws, size_t ws_bytes, int reps,
+                               double* flops, void* stream) {
+  if (!net || !params || !grad || !flops || (net->prec && !params_lp)) return fail(PPO_EINVAL, "null argument");
+  if (unit < 0 || unit >= (int)net->units.size() || op < 0 || op > 2 || frames <= 0 || reps <= 0)
+    return fail(PPO_EINVAL, "bad unit / op / frames / reps");
+  const WsLayout w = plan(net, frames, 1, true);
+  if (!ws || ws_bytes < w.total) return fail(PPO_EWORKSPACE, "workspace needs %zu bytes", w.total);
+  if (!al256(ws)) return fail(PPO_EWORKSPACE, "workspace must be 256-byte aligned");
+  hipStream_t s = strm(stream);
+  Ctx c{net, &w, (char*)ws, params, params_lp, grad, s, frames};
+  const Unit& u = net->units[unit];
+  const ConvGeo g = geo(u, frames);
+  const double M = (double)frames * u.Hout * u.Wout, N = u.Cout, K = (double)u.K * u.K * u.Cin;
+  *flops = 2.0 * M * N * K;
+  // operands: scratch buffers sized for the largest unit of a learner call
+  float *X = c.at(w.ga), *DY = c.at(w.gb), *OUT = c.at(w.gu);
+  for (int r = 0; r < reps; ++r) {
+    if (op == 0)
+      gemm_conv_fwd(net->prec, g, X, c.wt(u.w), epi(OUT, u.Cout), kSplitKBytes, c.splitk(), s);
+    else if (op == 1)
+      gemm_conv_dgrad(net->prec, g, DY, c.wt(u.w), epi(OUT, u.Cin), kSplitKBytes, c.splitk(), s);
+    else
+      gemm_conv_wgrad(net->prec, g, X, DY, epi(grad + u.w, u.K * u.K * u.Cin), kSplitKBytes, c.splitk(), s);
+  }
   return check_launch();
 }
 

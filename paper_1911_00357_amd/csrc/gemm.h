@@ -1,25 +1,35 @@
 // LDS-tiled MFMA GEMM core and its operand loaders (convolution forward,
 // data gradient, weight gradient as implicit GEMMs; plain dense products).
 //
-// C[m][n] = alpha * sum_k A(m, k) B(n, k)  (+ bias[n]) (ReLU) (+= C)
+// C[m][n] = alpha * sum_k A(m, k) B(n, k)  (+= C) (+ bias[n]) (ReLU)
 //
-// A workgroup of 256 threads (4 wavefronts in a 2x2 grid) owns a BM x BN
-// tile.  Each K step stages an A tile [BM][BK] and a B tile [BN][BK] in LDS
-// (k contiguous, converted to the MFMA operand type), while the next tile's
-// global loads are already in flight in registers.  Every lane reads 16
-// bytes of k per 16-row fragment: one v_mfma_f32_16x16x32_bf16 (bfloat16) or
-// four v_mfma_f32_16x16x4_f32 (float32) per fragment pair.  A and B use the
+// A workgroup of 256 threads (4 wavefronts) owns a BM x BN tile.  Operands
+// are staged through double-buffered LDS as [rows][k] (k contiguous), one
+// barrier per K tile; the next tile's global loads are in flight while the
+// current tile feeds the matrix cores.  Every operand "chunk" is 8
+// consecutive k of one row: for operands contiguous along k it is one or two
+// vector loads, for operands contiguous along rows (transposed reads) the
+// lanes of a wavefront walk the rows so each of the 8 scalar loads is
+// coalesced; either way the chunk lands in LDS with one 16-byte write.
+//
+// bfloat16: v_mfma_f32_32x32x16_bf16 on 32x32 fragments.  float32: four
+// v_mfma_f32_16x16x4_f32 per 16-k step on 16x16 fragments.  A and B use the
 // same lane -> k assignment, so the order of k inside a step is irrelevant.
+// SPLIT (bfloat16 only): A is carried as hi + lo bfloat16 parts (two MFMAs),
+// giving the gradient operand of backward products a 16-bit mantissa.
 // Accumulation is float32; a split over K writes partial tiles that a second
 // kernel sums in a fixed order (no float atomics: results are deterministic).
 #pragma once
 #include "common.h"
 #include "kernels.h"
 
-// ----------------------------------------------------------------- operands
-// Loaders return 8 consecutive values along their contiguous axis:
-//   KCONTIG: A(m, k..k+7) / B(n, k..k+7);  otherwise A(m..m+7, k) / B(n..n+7, k).
-// Out-of-range entries are 0.
+typedef float v16f __attribute__((ext_vector_type(16)));
+
+// ------------------------------------------------------------- loads
+DEV void zero8(float v[8]) {
+#pragma unroll
+  for (int e = 0; e < 8; ++e) v[e] = 0.f;
+}
 
 template <typename T>
 DEV void load8(const T* p, float v[8]);
@@ -42,405 +52,439 @@ DEV void load8<bf16_t>(const bf16_t* p, float v[8]) {
 
 DEV bool aligned16(const void* p) { return (((uintptr_t)p) & 15) == 0; }
 
-// Forward: A(m = (b,ho,wo), k = (kh,kw,ci)) = x[b][ho*s-p+kh][wo*s-p+kw][ci];
-//          B(n = co, k) = w[co][k].
+// ------------------------------------------------------------ problems
+// Each problem exposes, for A (rows m) and B (rows n): a per-row state built
+// once per thread (rowA / rowB) and a chunk loader (a8 / b8) returning the 8
+// values at k .. k+7 (k a multiple of 8; entries past K are 0).
+
+// Forward: A(m = (b,ho,wo), k = (kh,kw,ci)) = x[b][ho*s-p+kh][wo*s-p+kw][ci]; B(n = co, k) = w[co][k].
 template <typename TW>
 struct ConvFwdProb {
-  static constexpr bool A_KCONTIG = true, B_KCONTIG = true;
   ConvGeo g;
+  FastDiv dC, dKW, dHoWo, dWo;
   const float* x;
   const TW* w;
   int M, N, K;
-  DEV void a8(int m, int k, float v[8]) const {
-    if (m >= M) {
-#pragma unroll
-      for (int e = 0; e < 8; ++e) v[e] = 0.f;
-      return;
+  struct RA {
+    int off, h0, w0, ok;
+  };
+  struct RB {
+    const TW* p;
+    int ok;
+  };
+  DEV RA rowA(int m) const {
+    RA r{0, 0, 0, m < M};
+    if (r.ok) {
+      const int b = dHoWo.div(m), q = m - b * g.Ho * g.Wo;
+      const int ho = dWo.div(q), wo = q - ho * g.Wo;
+      r.off = b * g.H * g.W * g.C;
+      r.h0 = ho * g.stride - g.pad;
+      r.w0 = wo * g.stride - g.pad;
     }
-    const int hw = g.Ho * g.Wo;
-    const int b = m / hw, r = m - b * hw;
-    const int ho = r / g.Wo, wo = r - ho * g.Wo;
-    const int h0 = ho * g.stride - g.pad, w0 = wo * g.stride - g.pad;
-    if ((g.C & 7) == 0 && k + 8 <= K) {
-      const int tap = k / g.C, ci = k - tap * g.C;
-      const int kh = tap / g.KW, kw = tap - kh * g.KW;
-      const int hi = h0 + kh, wi = w0 + kw;
-      if ((unsigned)hi < (unsigned)g.H && (unsigned)wi < (unsigned)g.W) {
-        load8(x + (((size_t)b * g.H + hi) * g.W + wi) * g.C + ci, v);
-      } else {
-#pragma unroll
-        for (int e = 0; e < 8; ++e) v[e] = 0.f;
-      }
-      return;
+    return r;
+  }
+  DEV RB rowB(int n) const { return RB{w + (size_t)n * K, n < N}; }
+  DEV void a8(const RA& r, int k, float v[8]) const {
+    if (!r.ok) return zero8(v);
+    if ((g.C & 7) == 0) {
+      if (k >= K) return zero8(v);
+      const int tap = dC.div(k), ci = k - tap * g.C;
+      const int kh = dKW.div(tap), kw = tap - kh * g.KW;
+      const int hi = r.h0 + kh, wi = r.w0 + kw;
+      if ((unsigned)hi < (unsigned)g.H && (unsigned)wi < (unsigned)g.W)
+        return load8(x + r.off + ((size_t)hi * g.W + wi) * g.C + ci, v);
+      return zero8(v);
     }
 #pragma unroll
     for (int e = 0; e < 8; ++e) {
       const int kk = k + e;
       float val = 0.f;
       if (kk < K) {
-        const int tap = kk / g.C, ci = kk - tap * g.C;
-        const int kh = tap / g.KW, kw = tap - kh * g.KW;
-        const int hi = h0 + kh, wi = w0 + kw;
+        const int tap = dC.div(kk), ci = kk - tap * g.C;
+        const int kh = dKW.div(tap), kw = tap - kh * g.KW;
+        const int hi = r.h0 + kh, wi = r.w0 + kw;
         if ((unsigned)hi < (unsigned)g.H && (unsigned)wi < (unsigned)g.W)
-          val = x[(((size_t)b * g.H + hi) * g.W + wi) * g.C + ci];
+          val = x[r.off + ((size_t)hi * g.W + wi) * g.C + ci];
       }
       v[e] = val;
     }
   }
-  DEV void b8(int n, int k, float v[8]) const {
-    const TW* p = w + (size_t)n * K + k;
-    if (n < N && k + 8 <= K && aligned16(p)) {
-      load8(p, v);
-      return;
-    }
+  DEV void b8(const RB& r, int k, float v[8]) const {
+    if (!r.ok) return zero8(v);
+    if (k + 8 <= K && aligned16(r.p + k)) return load8(r.p + k, v);
 #pragma unroll
-    for (int e = 0; e < 8; ++e) v[e] = (n < N && k + e < K) ? ldf(p + e) : 0.f;
+    for (int e = 0; e < 8; ++e) v[e] = (k + e < K) ? ldf(r.p + k + e) : 0.f;
   }
 };
 
 // Data gradient: A(m = (b,hi,wi), k = (kh,kw,co)) = dy[b][(hi+p-kh)/s][(wi+p-kw)/s][co]
 // when the division is exact and in range; B(n = ci, k) = w[co][kh][kw][ci]
-// (contiguous along n).
+// (B is contiguous along n: lanes walk n, 8 strided loads per chunk).
 template <typename TW>
 struct ConvDgradProb {
-  static constexpr bool A_KCONTIG = true, B_KCONTIG = false;
   ConvGeo g;
+  FastDiv dCo, dKW, dHW, dW;
   const float* dy;
   const TW* w;
   int M, N, K;  // M = B*H*W, N = C, K = KH*KW*Co
-  DEV void a8(int m, int k, float v[8]) const {
-    if (m >= M) {
-#pragma unroll
-      for (int e = 0; e < 8; ++e) v[e] = 0.f;
-      return;
+  struct RA {
+    int off, th, tw, ok;
+  };
+  struct RB {
+    int n, ok;
+  };
+  DEV RA rowA(int m) const {
+    RA r{0, 0, 0, m < M};
+    if (r.ok) {
+      const int b = dHW.div(m), q = m - b * g.H * g.W;
+      const int hi = dW.div(q), wi = q - hi * g.W;
+      r.off = b * g.Ho * g.Wo * g.Co;
+      r.th = hi + g.pad;
+      r.tw = wi + g.pad;
     }
-    const int hw = g.H * g.W;
-    const int b = m / hw, r = m - b * hw;
-    const int hi = r / g.W, wi = r - hi * g.W;
-    if ((g.Co & 7) == 0 && k + 8 <= K) {
-      const int tap = k / g.Co, co = k - tap * g.Co;
-      const int kh = tap / g.KW, kw = tap - kh * g.KW;
-      const int th = hi + g.pad - kh, tw = wi + g.pad - kw;
-      bool ok = th >= 0 && tw >= 0;
-      int ho = 0, wo = 0;
-      if (ok) {
-        ho = th / g.stride;
-        wo = tw / g.stride;
-        ok = ho * g.stride == th && wo * g.stride == tw && ho < g.Ho && wo < g.Wo;
-      }
-      if (ok) {
-        load8(dy + (((size_t)b * g.Ho + ho) * g.Wo + wo) * g.Co + co, v);
-      } else {
-#pragma unroll
-        for (int e = 0; e < 8; ++e) v[e] = 0.f;
-      }
-      return;
+    return r;
+  }
+  DEV RB rowB(int n) const { return RB{n, n < N}; }
+  DEV bool src(const RA& r, int kh, int kw, int& pix) const {
+    const int th = r.th - kh, tw = r.tw - kw;
+    if (th < 0 || tw < 0) return false;
+    int ho = th, wo = tw;
+    if (g.stride == 2) {
+      if ((th | tw) & 1) return false;
+      ho >>= 1;
+      wo >>= 1;
+    }
+    if (ho >= g.Ho || wo >= g.Wo) return false;
+    pix = ho * g.Wo + wo;
+    return true;
+  }
+  DEV void a8(const RA& r, int k, float v[8]) const {
+    if (!r.ok || k >= K) return zero8(v);
+    if ((g.Co & 7) == 0) {
+      const int tap = dCo.div(k), co = k - tap * g.Co;
+      const int kh = dKW.div(tap), kw = tap - kh * g.KW;
+      int pix;
+      if (src(r, kh, kw, pix)) return load8(dy + r.off + (size_t)pix * g.Co + co, v);
+      return zero8(v);
     }
 #pragma unroll
     for (int e = 0; e < 8; ++e) {
       const int kk = k + e;
       float val = 0.f;
       if (kk < K) {
-        const int tap = kk / g.Co, co = kk - tap * g.Co;
-        const int kh = tap / g.KW, kw = tap - kh * g.KW;
-        const int th = hi + g.pad - kh, tw = wi + g.pad - kw;
-        if (th >= 0 && tw >= 0) {
-          const int ho = th / g.stride, wo = tw / g.stride;
-          if (ho * g.stride == th && wo * g.stride == tw && ho < g.Ho && wo < g.Wo)
-            val = dy[(((size_t)b * g.Ho + ho) * g.Wo + wo) * g.Co + co];
-        }
+        const int tap = dCo.div(kk), co = kk - tap * g.Co;
+        const int kh = dKW.div(tap), kw = tap - kh * g.KW;
+        int pix;
+        if (src(r, kh, kw, pix)) val = dy[r.off + (size_t)pix * g.Co + co];
       }
       v[e] = val;
     }
   }
-  DEV void b8(int n, int k, float v[8]) const {  // B(n..n+7, k)
-    if (k >= K) {
+  DEV void b8(const RB& r, int k, float v[8]) const {
+    if (!r.ok) return zero8(v);
+    const int khw = g.KH * g.KW;
 #pragma unroll
-      for (int e = 0; e < 8; ++e) v[e] = 0.f;
-      return;
+    for (int e = 0; e < 8; ++e) {
+      const int kk = k + e;
+      float val = 0.f;
+      if (kk < K) {
+        const int tap = dCo.div(kk), co = kk - tap * g.Co;
+        val = ldf(w + ((size_t)co * khw + tap) * g.C + r.n);
+      }
+      v[e] = val;
     }
-    const int tap = k / g.Co, co = k - tap * g.Co;
-    const TW* p = w + ((size_t)co * g.KH * g.KW + tap) * g.C + n;
-    if (n + 8 <= N && aligned16(p)) {
-      load8(p, v);
-      return;
-    }
-#pragma unroll
-    for (int e = 0; e < 8; ++e) v[e] = (n + e < N) ? ldf(p + e) : 0.f;
   }
 };
 
 // Weight gradient: C(m = co, n = (kh,kw,ci)) = sum_r dy[r][co] * im2col(x)[r][n],
-// r = (b,ho,wo) runs over the reduction.  A(m..m+7, r) reads dy along co;
-// B(n..n+7, r) reads the input along ci.
+// r = (b,ho,wo) is the reduction.  Both operands are contiguous along their
+// rows: lanes walk co (A) or n (B); 8 consecutive r per chunk.
 struct ConvWgradProb {
-  static constexpr bool A_KCONTIG = false, B_KCONTIG = false;
   ConvGeo g;
+  FastDiv dC, dKW, dHoWo, dWo;
   const float* x;
   const float* dy;
   int M, N, K;  // M = Co, N = KH*KW*C, K = B*Ho*Wo
-  DEV void a8(int m, int r, float v[8]) const {
-    const float* p = dy + (size_t)r * g.Co + m;
-    if (r < K && m + 8 <= M && aligned16(p)) {
-      load8(p, v);
-      return;
+  struct RA {
+    int co, ok;
+  };
+  struct RB {
+    int kh, kw, ci, ok;
+  };
+  DEV RA rowA(int m) const { return RA{m, m < M}; }
+  DEV RB rowB(int n) const {
+    RB r{0, 0, 0, n < N};
+    if (r.ok) {
+      const int tap = dC.div(n);
+      r.ci = n - tap * g.C;
+      r.kh = dKW.div(tap);
+      r.kw = tap - r.kh * g.KW;
     }
-#pragma unroll
-    for (int e = 0; e < 8; ++e) v[e] = (r < K && m + e < M) ? p[e] : 0.f;
+    return r;
   }
-  DEV void b8(int n, int r, float v[8]) const {
-    if (r >= K) {
+  DEV void a8(const RA& r, int k, float v[8]) const {
+    if (!r.ok) return zero8(v);
 #pragma unroll
-      for (int e = 0; e < 8; ++e) v[e] = 0.f;
-      return;
-    }
+    for (int e = 0; e < 8; ++e) v[e] = (k + e < K) ? dy[(size_t)(k + e) * g.Co + r.co] : 0.f;
+  }
+  DEV void b8(const RB& r, int k, float v[8]) const {
+    if (!r.ok || k >= K) return zero8(v);
     const int hw = g.Ho * g.Wo;
-    const int b = r / hw, q = r - b * hw;
-    const int ho = q / g.Wo, wo = q - ho * g.Wo;
-    const int h0 = ho * g.stride - g.pad, w0 = wo * g.stride - g.pad;
-    if ((g.C & 7) == 0 && n + 8 <= N) {
-      const int tap = n / g.C, ci = n - tap * g.C;
-      const int kh = tap / g.KW, kw = tap - kh * g.KW;
-      const int hi = h0 + kh, wi = w0 + kw;
-      if ((unsigned)hi < (unsigned)g.H && (unsigned)wi < (unsigned)g.W) {
-        load8(x + (((size_t)b * g.H + hi) * g.W + wi) * g.C + ci, v);
-      } else {
-#pragma unroll
-        for (int e = 0; e < 8; ++e) v[e] = 0.f;
-      }
-      return;
-    }
+    int b = dHoWo.div(k);
+    const int q = k - b * hw;
+    int ho = dWo.div(q), wo = q - ho * g.Wo;
 #pragma unroll
     for (int e = 0; e < 8; ++e) {
-      const int nn = n + e;
       float val = 0.f;
-      if (nn < N) {
-        const int tap = nn / g.C, ci = nn - tap * g.C;
-        const int kh = tap / g.KW, kw = tap - kh * g.KW;
-        const int hi = h0 + kh, wi = w0 + kw;
+      if (k + e < K) {
+        const int hi = ho * g.stride - g.pad + r.kh, wi = wo * g.stride - g.pad + r.kw;
         if ((unsigned)hi < (unsigned)g.H && (unsigned)wi < (unsigned)g.W)
-          val = x[(((size_t)b * g.H + hi) * g.W + wi) * g.C + ci];
+          val = x[(((size_t)b * g.H + hi) * g.W + wi) * g.C + r.ci];
       }
       v[e] = val;
+      if (++wo == g.Wo) {
+        wo = 0;
+        if (++ho == g.Ho) {
+          ho = 0;
+          ++b;
+        }
+      }
     }
   }
 };
 
 // Dense: A(m, k) = a[m*lda + k] (or a[k*lda + m] when TA), B(n, k) = b[n*ldb + k]
-// (or b[k*ldb + n] when TB).  Optional per-row scale of A (episode masks).
+// (or b[k*ldb + n] when TB).
 template <typename TAe, typename TBe, bool TA, bool TB>
 struct DenseProb {
-  static constexpr bool A_KCONTIG = !TA, B_KCONTIG = !TB;
   const TAe* a;
   const TBe* b;
   int lda, ldb;
   int M, N, K;
-  DEV void a8(int m, int k, float v[8]) const {
-    if (!TA) {
-      const TAe* p = a + (size_t)m * lda + k;
-      if (m < M && k + 8 <= K && aligned16(p)) {
-        load8(p, v);
-        return;
-      }
+  struct RA {
+    int m, ok;
+  };
+  typedef RA RB;
+  DEV RA rowA(int m) const { return RA{m, m < M}; }
+  DEV RB rowB(int n) const { return RB{n, n < N}; }
+  template <typename T, bool TR>
+  DEV static void get(const T* base, int ld, int row, int k, int K, float v[8]) {
+    if (!TR) {
+      const T* p = base + (size_t)row * ld + k;
+      if (k + 8 <= K && aligned16(p)) return load8(p, v);
 #pragma unroll
-      for (int e = 0; e < 8; ++e) v[e] = (m < M && k + e < K) ? ldf(p + e) : 0.f;
+      for (int e = 0; e < 8; ++e) v[e] = (k + e < K) ? ldf(p + e) : 0.f;
     } else {
-      const TAe* p = a + (size_t)k * lda + m;
-      if (k < K && m + 8 <= M && aligned16(p)) {
-        load8(p, v);
-        return;
-      }
 #pragma unroll
-      for (int e = 0; e < 8; ++e) v[e] = (k < K && m + e < M) ? ldf(p + e) : 0.f;
+      for (int e = 0; e < 8; ++e) v[e] = (k + e < K) ? ldf(base + (size_t)(k + e) * ld + row) : 0.f;
     }
   }
-  DEV void b8(int n, int k, float v[8]) const {
-    if (!TB) {
-      const TBe* p = b + (size_t)n * ldb + k;
-      if (n < N && k + 8 <= K && aligned16(p)) {
-        load8(p, v);
-        return;
-      }
-#pragma unroll
-      for (int e = 0; e < 8; ++e) v[e] = (n < N && k + e < K) ? ldf(p + e) : 0.f;
-    } else {
-      const TBe* p = b + (size_t)k * ldb + n;
-      if (k < K && n + 8 <= N && aligned16(p)) {
-        load8(p, v);
-        return;
-      }
-#pragma unroll
-      for (int e = 0; e < 8; ++e) v[e] = (k < K && n + e < N) ? ldf(p + e) : 0.f;
-    }
+  DEV void a8(const RA& r, int k, float v[8]) const {
+    if (!r.ok) return zero8(v);
+    get<TAe, TA>(a, lda, r.m, k, K, v);
+  }
+  DEV void b8(const RB& r, int k, float v[8]) const {
+    if (!r.ok) return zero8(v);
+    get<TBe, TB>(b, ldb, r.m, k, K, v);
   }
 };
 
-// ------------------------------------------------------------------ kernel
+// Is the operand contiguous along rows (so lanes should walk rows)?
+template <class P> struct Layout;
+template <typename TW> struct Layout<ConvFwdProb<TW>> { static constexpr bool A_ROWS = false, B_ROWS = false; };
+template <typename TW> struct Layout<ConvDgradProb<TW>> { static constexpr bool A_ROWS = false, B_ROWS = true; };
+template <> struct Layout<ConvWgradProb> { static constexpr bool A_ROWS = true, B_ROWS = true; };
+template <typename A_, typename B_, bool TA, bool TB>
+struct Layout<DenseProb<A_, B_, TA, TB>> { static constexpr bool A_ROWS = TA, B_ROWS = TB; };
+
+// ------------------------------------------------------------- MFMA
 template <typename TC>
-struct MmaT;
+struct Mma;
 template <>
-struct MmaT<float> {
-  static constexpr int KS = 16;  // k per step: 4 lane groups x 4 floats
+struct Mma<bf16_t> {  // v_mfma_f32_32x32x16_bf16
+  static constexpr int FR = 32, NOUT = 16;
+  typedef v16f Acc;
+  DEV static int row(int l) { return l & 31; }
+  DEV static int kof(int l) { return (l >> 5) * 8; }
+  DEV static Acc zero() {
+    Acc a;
+#pragma unroll
+    for (int i = 0; i < 16; ++i) a[i] = 0.f;
+    return a;
+  }
+  DEV static Acc mma(const bf16_t* a, const bf16_t* b, Acc c) {
+    const v8bf x = *(const v8bf*)a, y = *(const v8bf*)b;
+    return __builtin_amdgcn_mfma_f32_32x32x16_bf16(x, y, c, 0, 0, 0);
+  }
+  // accumulator element r of lane l
+  DEV static int orow(int l, int r) { return 8 * (r >> 2) + 4 * (l >> 5) + (r & 3); }
+  DEV static int ocol(int l) { return l & 31; }
 };
 template <>
-struct MmaT<bf16_t> {
-  static constexpr int KS = 32;  // 4 lane groups x 8 bfloat16
+struct Mma<float> {  // 4 x v_mfma_f32_16x16x4_f32 per 16-k step
+  static constexpr int FR = 16, NOUT = 4;
+  typedef v4f Acc;
+  DEV static int row(int l) { return l & 15; }
+  DEV static int kof(int l) { return (l >> 4) * 4; }
+  DEV static Acc zero() { return v4f{0.f, 0.f, 0.f, 0.f}; }
+  DEV static Acc mma(const float* a, const float* b, Acc c) {
+    const float4 x = *(const float4*)a, y = *(const float4*)b;
+    c = __builtin_amdgcn_mfma_f32_16x16x4f32(x.x, y.x, c, 0, 0, 0);
+    c = __builtin_amdgcn_mfma_f32_16x16x4f32(x.y, y.y, c, 0, 0, 0);
+    c = __builtin_amdgcn_mfma_f32_16x16x4f32(x.z, y.z, c, 0, 0, 0);
+    c = __builtin_amdgcn_mfma_f32_16x16x4f32(x.w, y.w, c, 0, 0, 0);
+    return c;
+  }
+  DEV static int orow(int l, int r) { return 4 * (l >> 4) + r; }
+  DEV static int ocol(int l) { return l & 15; }
 };
 
-DEV void to_lds(float* d, float v) { *d = v; }
-DEV void to_lds(bf16_t* d, float v) { *d = f2bf(v); }
-
-template <typename TC>
-DEV v4f mma_step(const TC* a, const TC* b, v4f acc);
-template <>
-DEV v4f mma_step<float>(const float* a, const float* b, v4f acc) {
-  const float4 x = *(const float4*)a, y = *(const float4*)b;
-  acc = __builtin_amdgcn_mfma_f32_16x16x4f32(x.x, y.x, acc, 0, 0, 0);
-  acc = __builtin_amdgcn_mfma_f32_16x16x4f32(x.y, y.y, acc, 0, 0, 0);
-  acc = __builtin_amdgcn_mfma_f32_16x16x4f32(x.z, y.z, acc, 0, 0, 0);
-  acc = __builtin_amdgcn_mfma_f32_16x16x4f32(x.w, y.w, acc, 0, 0, 0);
-  return acc;
+// 8 floats -> LDS row segment in the operand type (hi part; lo = residual).
+DEV void put8(float* d, const float v[8], float*) {
+  *(float4*)d = make_float4(v[0], v[1], v[2], v[3]);
+  *(float4*)(d + 4) = make_float4(v[4], v[5], v[6], v[7]);
 }
-template <>
-DEV v4f mma_step<bf16_t>(const bf16_t* a, const bf16_t* b, v4f acc) {
-  const v8bf x = *(const v8bf*)a, y = *(const v8bf*)b;
-  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(x, y, acc, 0, 0, 0);
+// Two floats -> packed bfloat16 pair, round to nearest even (v_cvt_pk_bf16_f32).
+typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));
+typedef float f32x2_t __attribute__((ext_vector_type(2)));
+DEV uint32_t pk_bf16(float a, float b) {
+  const bf16x2_t r = __builtin_convertvector((f32x2_t){a, b}, bf16x2_t);
+  return __builtin_bit_cast(uint32_t, r);
+}
+DEV void put8(bf16_t* d, const float v[8], bf16_t* lo) {
+  uint32_t h[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) h[i] = pk_bf16(v[2 * i], v[2 * i + 1]);
+  *(uint4*)d = make_uint4(h[0], h[1], h[2], h[3]);
+  if (lo) {
+    uint32_t l[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const float a = __uint_as_float(h[i] << 16), b = __uint_as_float(h[i] & 0xffff0000u);
+      l[i] = pk_bf16(v[2 * i] - a, v[2 * i + 1] - b);
+    }
+    *(uint4*)lo = make_uint4(l[0], l[1], l[2], l[3]);
+  }
 }
 
-template <class Prob, typename TC, int BM, int BN, int BK>
+// ------------------------------------------------------------- kernel
+template <class Prob, typename TC, int BM, int BN, int WGM, int WGN, bool SPLIT>
 __global__ void __launch_bounds__(256) gemm_kernel(Prob p, Epi e, int tiles_n, int k_per_split) {
-  constexpr int PAD = 16 / sizeof(TC);
-  constexpr int LDK = BK + PAD;
-  constexpr int KS = MmaT<TC>::KS;
-  constexpr int WM = BM / 2, WN = BN / 2;  // wave tile
-  constexpr int FM = WM / 16, FN = WN / 16;
-  constexpr int QA = BM * BK / 8 / 256, QB = BN * BK / 8 / 256;
-  static_assert(QA >= 1 && QB >= 1, "tile too small for 256 threads");
-  __shared__ __attribute__((aligned(16))) TC As[BM * LDK];
-  __shared__ __attribute__((aligned(16))) TC Bs[BN * LDK];
+  using MM = Mma<TC>;
+  constexpr int BK = 32;
+  constexpr int FR = MM::FR;
+  constexpr int WTM = BM / WGM, WTN = BN / WGN;
+  constexpr int FM = WTM / FR, FN = WTN / FR;
+  static_assert(WGM * WGN == 4 && FM >= 1 && FN >= 1, "bad tile");
+  constexpr int LDK = BK + 16 / (int)sizeof(TC);  // padded LDS row (elements)
+  constexpr int CA = BM * BK / 8, CB = BN * BK / 8;
+  constexpr int QA = (CA + 255) / 256, QB = (CB + 255) / 256;
+  constexpr bool AR = Layout<Prob>::A_ROWS, BR = Layout<Prob>::B_ROWS;
+  constexpr int NSPL = SPLIT ? 2 : 1;
+  __shared__ __attribute__((aligned(16))) TC sA[NSPL][2][BM * LDK];
+  __shared__ __attribute__((aligned(16))) TC sB[2][BN * LDK];
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int tm = blockIdx.x / tiles_n, tn = blockIdx.x - tm * tiles_n;
   const int m0 = tm * BM, n0 = tn * BN;
   const int kbeg = blockIdx.y * k_per_split;
   const int kend = min(p.K, kbeg + k_per_split);
-  const int wm0 = (wave >> 1) * WM, wn0 = (wave & 1) * WN;
+  const int wm0 = (wave / WGN) * WTM, wn0 = (wave % WGN) * WTN;
 
-  v4f acc[FM][FN];
+  // chunk c -> (row, k offset): lanes walk k for k-contiguous operands and
+  // rows for row-contiguous ones
+  auto a_row = [&](int c) { return AR ? c % BM : c / (BK / 8); };
+  auto a_kc = [&](int c) { return AR ? (c / BM) * 8 : (c % (BK / 8)) * 8; };
+  auto b_row = [&](int c) { return BR ? c % BN : c / (BK / 8); };
+  auto b_kc = [&](int c) { return BR ? (c / BN) * 8 : (c % (BK / 8)) * 8; };
+
+  typename Prob::RA ra[QA];
+  typename Prob::RB rb[QB];
+#pragma unroll
+  for (int q = 0; q < QA; ++q) {
+    const int c = tid + 256 * q;
+    ra[q] = p.rowA(c < CA ? m0 + a_row(c) : 1 << 30);
+  }
+#pragma unroll
+  for (int q = 0; q < QB; ++q) {
+    const int c = tid + 256 * q;
+    rb[q] = p.rowB(c < CB ? n0 + b_row(c) : 1 << 30);
+  }
+
+  typename MM::Acc acc[FM][FN];
 #pragma unroll
   for (int i = 0; i < FM; ++i)
 #pragma unroll
-    for (int j = 0; j < FN; ++j) acc[i][j] = v4f{0.f, 0.f, 0.f, 0.f};
+    for (int j = 0; j < FN; ++j) acc[i][j] = MM::zero();
 
-  float ra[QA][8], rb[QB][8];
+  float va[QA][8], vb[QB][8];
   auto gload = [&](int k0) {
 #pragma unroll
     for (int q = 0; q < QA; ++q) {
       const int c = tid + 256 * q;
-      if (Prob::A_KCONTIG) {
-        const int r = c / (BK / 8), kc = (c % (BK / 8)) * 8;
-        const int k = k0 + kc;
-        if (k < kend) p.a8(m0 + r, k, ra[q]);
-        else
-#pragma unroll
-          for (int x = 0; x < 8; ++x) ra[q][x] = 0.f;
-        // entries past kend inside the chunk belong to the next split
-        if (k + 8 > kend && k < kend)
-#pragma unroll
-          for (int x = 0; x < 8; ++x)
-            if (k + x >= kend) ra[q][x] = 0.f;
-      } else {
-        const int kk = c / (BM / 8), mc = (c % (BM / 8)) * 8;
-        if (k0 + kk < kend) p.a8(m0 + mc, k0 + kk, ra[q]);
-        else
-#pragma unroll
-          for (int x = 0; x < 8; ++x) ra[q][x] = 0.f;
-      }
+      const int k = k0 + a_kc(c);
+      if (c < CA && k < kend) p.a8(ra[q], k, va[q]);
+      else zero8(va[q]);
     }
 #pragma unroll
     for (int q = 0; q < QB; ++q) {
       const int c = tid + 256 * q;
-      if (Prob::B_KCONTIG) {
-        const int r = c / (BK / 8), kc = (c % (BK / 8)) * 8;
-        const int k = k0 + kc;
-        if (k < kend) p.b8(n0 + r, k, rb[q]);
-        else
-#pragma unroll
-          for (int x = 0; x < 8; ++x) rb[q][x] = 0.f;
-        if (k + 8 > kend && k < kend)
-#pragma unroll
-          for (int x = 0; x < 8; ++x)
-            if (k + x >= kend) rb[q][x] = 0.f;
-      } else {
-        const int kk = c / (BN / 8), nc = (c % (BN / 8)) * 8;
-        if (k0 + kk < kend) p.b8(n0 + nc, k0 + kk, rb[q]);
-        else
-#pragma unroll
-          for (int x = 0; x < 8; ++x) rb[q][x] = 0.f;
-      }
+      const int k = k0 + b_kc(c);
+      if (c < CB && k < kend) p.b8(rb[q], k, vb[q]);
+      else zero8(vb[q]);
     }
   };
-  auto sstore = [&]() {
+  auto sstore = [&](int buf) {
 #pragma unroll
     for (int q = 0; q < QA; ++q) {
       const int c = tid + 256 * q;
-      if (Prob::A_KCONTIG) {
-        const int r = c / (BK / 8), kc = (c % (BK / 8)) * 8;
-#pragma unroll
-        for (int x = 0; x < 8; ++x) to_lds(&As[r * LDK + kc + x], ra[q][x]);
-      } else {
-        const int kk = c / (BM / 8), mc = (c % (BM / 8)) * 8;
-#pragma unroll
-        for (int x = 0; x < 8; ++x) to_lds(&As[(mc + x) * LDK + kk], ra[q][x]);
+      if (c < CA) {
+        const int o = a_row(c) * LDK + a_kc(c);
+        put8(&sA[0][buf][o], va[q], SPLIT ? &sA[NSPL - 1][buf][o] : (TC*)nullptr);
       }
     }
 #pragma unroll
     for (int q = 0; q < QB; ++q) {
       const int c = tid + 256 * q;
-      if (Prob::B_KCONTIG) {
-        const int r = c / (BK / 8), kc = (c % (BK / 8)) * 8;
-#pragma unroll
-        for (int x = 0; x < 8; ++x) to_lds(&Bs[r * LDK + kc + x], rb[q][x]);
-      } else {
-        const int kk = c / (BN / 8), nc = (c % (BN / 8)) * 8;
-#pragma unroll
-        for (int x = 0; x < 8; ++x) to_lds(&Bs[(nc + x) * LDK + kk], rb[q][x]);
-      }
+      if (c < CB) put8(&sB[buf][b_row(c) * LDK + b_kc(c)], vb[q], (TC*)nullptr);
     }
   };
 
-  if (kbeg < kend) {
+  const int ntiles = kbeg < kend ? (kend - kbeg + BK - 1) / BK : 0;
+  if (ntiles > 0) {
     gload(kbeg);
-    for (int k0 = kbeg; k0 < kend; k0 += BK) {
-      __syncthreads();
-      sstore();
-      __syncthreads();
-      if (k0 + BK < kend) gload(k0 + BK);
-      const int kofs = (lane >> 4) * (KS / 4);
+    sstore(0);
+    __syncthreads();
+    for (int t = 0; t < ntiles; ++t) {
+      const int cur = t & 1;
+      if (t + 1 < ntiles) gload(kbeg + (t + 1) * BK);
 #pragma unroll
-      for (int ks = 0; ks < BK; ks += KS) {
+      for (int ks = 0; ks < BK; ks += 16) {
+        const int ko = ks + MM::kof(lane);
 #pragma unroll
         for (int i = 0; i < FM; ++i) {
-          const TC* ap = &As[(wm0 + i * 16 + (lane & 15)) * LDK + ks + kofs];
+          const int ao = (wm0 + i * FR + MM::row(lane)) * LDK + ko;
 #pragma unroll
           for (int j = 0; j < FN; ++j) {
-            const TC* bp = &Bs[(wn0 + j * 16 + (lane & 15)) * LDK + ks + kofs];
-            acc[i][j] = mma_step<TC>(ap, bp, acc[i][j]);
+            const TC* bp = &sB[cur][(wn0 + j * FR + MM::row(lane)) * LDK + ko];
+            acc[i][j] = MM::mma(&sA[0][cur][ao], bp, acc[i][j]);
+            if (SPLIT) acc[i][j] = MM::mma(&sA[NSPL - 1][cur][ao], bp, acc[i][j]);
           }
         }
       }
+      if (t + 1 < ntiles) sstore(cur ^ 1);
+      __syncthreads();
     }
   }
 
-  // epilogue: lane holds rows 4*(lane/16)+r, column lane%16 of each fragment
 #pragma unroll
   for (int i = 0; i < FM; ++i)
 #pragma unroll
     for (int j = 0; j < FN; ++j) {
-      const int n = n0 + wn0 + j * 16 + (lane & 15);
+      const int n = n0 + wn0 + j * FR + MM::ocol(lane);
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int m = m0 + wm0 + i * 16 + (lane >> 4) * 4 + r;
+      for (int r = 0; r < MM::NOUT; ++r) {
+        const int m = m0 + wm0 + i * FR + MM::orow(lane, r);
         if (m < p.M && n < p.N) {
           float v = acc[i][j][r];
           if (e.partial) {
@@ -457,7 +501,3 @@ __global__ void __launch_bounds__(256) gemm_kernel(Prob p, Epi e, int tiles_n, i
       }
     }
 }
-
-// Sum of split-K partials in split order, then the epilogue.
-__global__ void __launch_bounds__(256) splitk_reduce_kernel(const float* __restrict__ part, int splits,
-                                                            int M, int N, Epi e);

@@ -369,3 +369,55 @@ void launch_copy2d(const float* s_, int lds, int rows, int cols, float* d, int l
   hipLaunchKernelGGL(copy2d_kernel, dim3(std::min(4096, cdiv(n, 256))), dim3(256), 0, s, s_, lds, rows,
                      cols, d, ldd);
 }
+
+// Policy/value head over frames: logits[f][k], values[f] (one wavefront per frame).
+__global__ void __launch_bounds__(256) head_fwd_kernel(const float* __restrict__ htop, int F, int H, int A,
+                                                       const float* __restrict__ W, const float* __restrict__ b,
+                                                       float* __restrict__ logits, float* __restrict__ values) {
+  const int f = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+  if (f >= F) return;
+  float o[kMaxA];
+  head_dots(htop + (size_t)f * H, W, b, H, A + 1, o);
+  if (lane == 0) {
+    for (int k = 0; k < A; ++k) logits[(size_t)f * A + k] = o[k];
+    values[f] = o[A];
+  }
+}
+
+// dout[f] = [dlogits[f], dvalues[f]], dh[f] = dout[f] W.
+__global__ void __launch_bounds__(256) head_bwd_kernel(const float* __restrict__ dlogits,
+                                                       const float* __restrict__ dvalues, int F, int H, int A,
+                                                       const float* __restrict__ W, float* __restrict__ dout,
+                                                       float* __restrict__ dh) {
+  const int f = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+  if (f >= F) return;
+  float d[kMaxA];
+  for (int k = 0; k < A; ++k) d[k] = dlogits[(size_t)f * A + k];
+  d[A] = dvalues[f];
+  if (lane == 0)
+    for (int k = 0; k <= A; ++k) dout[(size_t)f * (A + 1) + k] = d[k];
+  for (int j = lane; j < H; j += 64) {
+    float v = 0.f;
+    for (int k = 0; k <= A; ++k) v += d[k] * W[(size_t)k * H + j];
+    dh[(size_t)f * H + j] = v;
+  }
+}
+
+__global__ void __launch_bounds__(256) copy_i32_kernel(const int32_t* __restrict__ s, int n, int32_t* __restrict__ d) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i < n) d[i] = s[i];
+}
+
+void launch_head_fwd(const float* htop, int F, int H, int A, const float* W, const float* b, float* logits,
+                     float* values, hipStream_t s) {
+  hipLaunchKernelGGL(head_fwd_kernel, dim3(cdiv(F, 4)), dim3(256), 0, s, htop, F, H, A, W, b, logits, values);
+}
+
+void launch_head_bwd(const float* dlogits, const float* dvalues, int F, int H, int A, const float* W, float* dout,
+                     float* dh, hipStream_t s) {
+  hipLaunchKernelGGL(head_bwd_kernel, dim3(cdiv(F, 4)), dim3(256), 0, s, dlogits, dvalues, F, H, A, W, dout, dh);
+}
+
+void launch_copy_i32(const int32_t* src, int n, int32_t* dst, hipStream_t s) {
+  hipLaunchKernelGGL(copy_i32_kernel, dim3(cdiv(n, 256)), dim3(256), 0, s, src, n, dst);
+}

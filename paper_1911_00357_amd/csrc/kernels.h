@@ -9,6 +9,21 @@
 
 typedef uint16_t bf16_t;
 
+// Division by a runtime constant as a multiply-high and shift (round-up
+// method; exact for 0 <= n < 2^31, d >= 1).
+struct FastDiv {
+  uint32_t mul, shift;
+  __device__ __forceinline__ int div(int n) const {
+    return (int)((__umulhi((uint32_t)n, mul) + (uint32_t)n) >> shift);
+  }
+};
+inline FastDiv fast_div(int d) {
+  uint32_t s = 0;
+  while ((1ull << s) < (uint64_t)d) ++s;
+  const uint64_t m = ((1ull << 32) * ((1ull << s) - (uint64_t)d)) / (uint64_t)d + 1;
+  return FastDiv{(uint32_t)m, s};
+}
+
 // Convolution geometry (NHWC activations, weights [Co][KH][KW][C]).
 struct ConvGeo {
   int B, H, W, C;  // input
@@ -40,14 +55,18 @@ struct MapArgs {
 
 // gemm.hip (prec: 0 float32 operands, 1 bfloat16 operands)
 int gemm_max_splits_for(long M, long N, long K, int prec);
-void gemm_conv_fwd(int prec, const ConvGeo& g, const float* x, const void* w, Epi e, int splits,
-                   float* partial, hipStream_t s);
-void gemm_conv_dgrad(int prec, const ConvGeo& g, const float* dy, const void* w, Epi e, int splits,
+// pb: bytes of `partial` available for split-K partial tiles
+// defer: leave split-K partial tiles [splits][M][N] in `partial` (no reduction
+// launch); returns the split count
+int gemm_conv_fwd(int prec, const ConvGeo& g, const float* x, const void* w, Epi e, size_t pb,
+                  float* partial, hipStream_t s, bool defer = false);
+void gemm_conv_dgrad(int prec, const ConvGeo& g, const float* dy, const void* w, Epi e, size_t pb,
                      float* partial, hipStream_t s);
-void gemm_conv_wgrad(int prec, const ConvGeo& g, const float* x, const float* dy, Epi e, int splits,
+void gemm_conv_wgrad(int prec, const ConvGeo& g, const float* x, const float* dy, Epi e, size_t pb,
                      float* partial, hipStream_t s);
+// split_a: carry A as hi + lo bfloat16 parts (gradient operands of backward products)
 void gemm_dense(int prec, bool ta, bool tb, const float* a, int lda, const void* b, bool b_lp, int ldb,
-                int M, int N, int K, Epi e, int splits, float* partial, hipStream_t s);
+                int M, int N, int K, Epi e, bool split_a, size_t pb, float* partial, hipStream_t s);
 
 // norm.hip
 void launch_gn_forward(const float* y, int B, int P, int C, int G, float eps, const float* gamma,
@@ -63,6 +82,14 @@ void launch_maxpool_bwd(const float* dy, const uint8_t* arg, int B, int H, int W
 void launch_prep(const void* obs, int bf16, const int32_t* src, int F, int C, int Hin, int Win, int pool,
                  float* x0, hipStream_t s);
 void launch_relu_grad(const float* dy, const float* y, size_t n, float* dx, hipStream_t s);
+// fused GroupNorm (one workgroup per image and group); 0 = group too large
+int gn_fused_npt(int P, int Cg);
+void launch_gn_fused(const float* src, int nsplit, size_t zstride, float* u_out, int B, int P, int C, int G,
+                     float eps, const float* gamma, const float* beta, const float* res, int relu, float* out,
+                     int out_chw, float2* stats, hipStream_t s);
+void launch_gnb_fused(const float* dout, const float* outm, int chw, const float* y, int B, int P, int C, int G,
+                      const float2* stats, const float* gamma, float* dy, float* dres, float* dgamma,
+                      float* dbeta, float2* bpart, hipStream_t s);
 
 // lstm.hip
 void launch_lstm_fwd(float* G, const float* cp, float* h, int ldh, float* c, int rows, int H,
@@ -74,6 +101,17 @@ void launch_lstm_bwd(const float* act, const float* c, const float* cp, const fl
                      int rows, int H, const float* mask_next, int rows_next, const float* dhp_next,
                      const float* dcp_next, float* dG, float* dcp, hipStream_t s);
 void launch_colsum(const float* in, int rows, int cols, int ld, float* out, hipStream_t s);
+
+// lstm_step.hip: one launch per time step (see the file header)
+void launch_lstm_step_fwd(int prec, const float* X, int ldx, int K, const void* W, int ldw, const float* Gin,
+                          const float* bias, const float* cprev, int rows, int H, float* act, float* h_out,
+                          int ldh, float* c_out, const float* mask_next, int rows_next, float* hp_next,
+                          int ldhp, float* cp_next, hipStream_t s);
+void launch_lstm_step_bwd(int prec, const float* dGn, const void* WT, const float* mask_n, int rows_n,
+                          const float* act, const float* c, const float* cp, const float* dH, int ldd, int rows,
+                          int H, float* dG, float* dcp, hipStream_t s);
+// WT [H][4H] = transpose of the recurrent block W[:, din:din+H] (row stride ldw)
+void launch_transpose_whh(int prec, const void* W, int ldw, int H, void* WT, hipStream_t s);
 
 // head.hip
 void launch_act_head(const float* htop, int rows, int H, int A, const float* W, const float* b,
@@ -97,6 +135,11 @@ void launch_frame_map(const MapArgs& m, const float* mask, int32_t* src, float* 
 void launch_gather_state(const float* srcs, int L, int N, int nb, int H, const int32_t* env_row,
                          float* dst, hipStream_t s);
 void launch_copy2d(const float* s_, int lds, int rows, int cols, float* d, int ldd, hipStream_t s);
+void launch_head_fwd(const float* htop, int F, int H, int A, const float* W, const float* b, float* logits,
+                     float* values, hipStream_t s);
+void launch_head_bwd(const float* dlogits, const float* dvalues, int F, int H, int A, const float* W, float* dout,
+                     float* dh, hipStream_t s);
+void launch_copy_i32(const int32_t* src, int n, int32_t* dst, hipStream_t s);
 
 // gae_adam.hip
 void launch_gae(const float* rew, const float* val, const uint8_t* done, const int32_t* len, int T, int N,

@@ -395,3 +395,171 @@ void launch_relu_grad(const float* dy, const float* y, size_t n, float* dx, hipS
   const int nb = (int)std::min<size_t>(8192, (n + 255) / 256);
   hipLaunchKernelGGL(relu_grad_kernel, dim3(nb), dim3(256), 0, s, dy, y, n, dx);
 }
+
+// ------------------------------------------------------ fused GroupNorm
+// One workgroup per (image b, group g) holds the group's P*Cg values in
+// registers (NPT per thread, element e = p*Cg + cc, so a thread keeps one
+// channel when 256 % Cg == 0): exact two-pass mean / variance, then the
+// apply.  The input is the convolution output, or the sum of its split-K
+// partial tiles (src + z*zstride), in which case the summed output can also
+// be stored (u_out) for the backward.
+DEV float block_sum(float v, float* red) {
+  double d = wave_sum((double)v);
+  const int w = threadIdx.x >> 6;
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) red[w] = (float)d;
+  __syncthreads();
+  return red[0] + red[1] + red[2] + red[3];
+}
+
+template <int NPT>
+__global__ void __launch_bounds__(256) gn_fused_kernel(const float* __restrict__ src, int nsplit, size_t zstride,
+                                                       float* __restrict__ u_out, int P, int C, int G, float eps,
+                                                       const float* __restrict__ gamma,
+                                                       const float* __restrict__ beta,
+                                                       const float* __restrict__ res, int relu,
+                                                       float* __restrict__ out, int out_chw,
+                                                       float2* __restrict__ stats) {
+  __shared__ float red[4];
+  const int b = blockIdx.x / G, g = blockIdx.x - b * G;
+  const int Cg = C / G, n = P * Cg;
+  float x[NPT];
+  float s = 0.f;
+#pragma unroll
+  for (int j = 0; j < NPT; ++j) {
+    const int e = threadIdx.x + 256 * j;
+    float v = 0.f;
+    if (e < n) {
+      const int p = e / Cg, c = g * Cg + (e - p * Cg);
+      const size_t idx = ((size_t)b * P + p) * C + c;
+      v = src[idx];
+      for (int z = 1; z < nsplit; ++z) v += src[(size_t)z * zstride + idx];
+      if (u_out) u_out[idx] = v;
+    }
+    x[j] = v;
+    s += v;
+  }
+  const float mean = block_sum(s, red) / n;
+  float q = 0.f;
+#pragma unroll
+  for (int j = 0; j < NPT; ++j)
+    if (threadIdx.x + 256 * j < n) q += (x[j] - mean) * (x[j] - mean);
+  const float var = block_sum(q, red) / n;
+  const float rstd = 1.0f / sqrtf(var + eps);
+  if (threadIdx.x == 0) stats[blockIdx.x] = make_float2(mean, rstd);
+#pragma unroll
+  for (int j = 0; j < NPT; ++j) {
+    const int e = threadIdx.x + 256 * j;
+    if (e < n) {
+      const int p = e / Cg, c = g * Cg + (e - p * Cg);
+      const size_t idx = ((size_t)b * P + p) * C + c;
+      float o = (x[j] - mean) * rstd * gamma[c] + beta[c];
+      if (res) o += res[idx];
+      if (relu) o = fmaxf(o, 0.f);
+      out[out_chw ? ((size_t)b * C + c) * P + p : idx] = o;
+    }
+  }
+}
+
+// Backward per (b, g): dz = dout [* (out > 0)], xhat = (y - mean) rstd;
+// dy = rstd (dz gamma - mean(dz gamma) - xhat mean(dz gamma xhat)), dres = dz;
+// bpart[b*C + c] = {sum_p dz, sum_p dz xhat} for the dgamma / dbeta reduction.
+template <int NPT>
+__global__ void __launch_bounds__(256) gnb_fused_kernel(const float* __restrict__ dout,
+                                                        const float* __restrict__ outm, int chw,
+                                                        const float* __restrict__ y, int P, int C, int G,
+                                                        const float2* __restrict__ stats,
+                                                        const float* __restrict__ gamma, float* __restrict__ dy,
+                                                        float* __restrict__ dres, float2* __restrict__ bpart) {
+  __shared__ float red[4];
+  __shared__ float2 cred[256];
+  const int b = blockIdx.x / G, g = blockIdx.x - b * G;
+  const int Cg = C / G, n = P * Cg;
+  const float2 st = stats[blockIdx.x];
+  float dz[NPT], xh[NPT];
+  float s1 = 0.f, s2 = 0.f, cz = 0.f, czx = 0.f;
+  const int cc = threadIdx.x % Cg;  // this thread's channel within the group (256 % Cg == 0)
+  const float gm = gamma[g * Cg + cc];
+#pragma unroll
+  for (int j = 0; j < NPT; ++j) {
+    const int e = threadIdx.x + 256 * j;
+    float z = 0.f, xv = 0.f;
+    if (e < n) {
+      const int p = e / Cg, c = g * Cg + cc;
+      const size_t idx = ((size_t)b * P + p) * C + c;
+      const size_t io = chw ? ((size_t)b * C + c) * P + p : idx;
+      z = dout[io];
+      if (outm && !(outm[io] > 0.f)) z = 0.f;
+      xv = (y[idx] - st.x) * st.y;
+    }
+    dz[j] = z;
+    xh[j] = xv;
+    s1 += z * gm;
+    s2 += z * gm * xv;
+    cz += z;
+    czx += z * xv;
+  }
+  const float m1 = block_sum(s1, red) / n;
+  const float m2 = block_sum(s2, red) / n;
+#pragma unroll
+  for (int j = 0; j < NPT; ++j) {
+    const int e = threadIdx.x + 256 * j;
+    if (e < n) {
+      const int p = e / Cg;
+      const size_t idx = ((size_t)b * P + p) * C + g * Cg + cc;
+      dy[idx] = st.y * (dz[j] * gm - m1 - xh[j] * m2);
+      if (dres) dres[idx] = dz[j];
+    }
+  }
+  cred[threadIdx.x] = make_float2(cz, czx);
+  __syncthreads();
+  if (threadIdx.x < Cg) {
+    float a = 0.f, q = 0.f;
+    for (int t = threadIdx.x; t < 256; t += Cg) {
+      a += cred[t].x;
+      q += cred[t].y;
+    }
+    bpart[(size_t)b * C + g * Cg + threadIdx.x] = make_float2(a, q);
+  }
+}
+
+int gn_fused_npt(int P, int Cg) {
+  const int n = P * Cg;
+  if (256 % Cg) return 0;
+  for (int k = 1; k <= 32; k *= 2)
+    if (n <= 256 * k) return k;
+  return 0;
+}
+
+#define GN_NPT_SWITCH(NPT_, CALL) \
+  switch (NPT_) {                 \
+    case 1: CALL(1); break;       \
+    case 2: CALL(2); break;       \
+    case 4: CALL(4); break;       \
+    case 8: CALL(8); break;       \
+    case 16: CALL(16); break;     \
+    default: CALL(32); break;     \
+  }
+
+void launch_gn_fused(const float* src, int nsplit, size_t zstride, float* u_out, int B, int P, int C, int G,
+                     float eps, const float* gamma, const float* beta, const float* res, int relu, float* out,
+                     int out_chw, float2* stats, hipStream_t s) {
+  const int npt = gn_fused_npt(P, C / G);
+#define GN_CALL(K)                                                                                          \
+  hipLaunchKernelGGL(gn_fused_kernel<K>, dim3(B * G), dim3(256), 0, s, src, nsplit, zstride, u_out, P, C, G, \
+                     eps, gamma, beta, res, relu, out, out_chw, stats)
+  GN_NPT_SWITCH(npt, GN_CALL)
+#undef GN_CALL
+}
+
+void launch_gnb_fused(const float* dout, const float* outm, int chw, const float* y, int B, int P, int C, int G,
+                      const float2* stats, const float* gamma, float* dy, float* dres, float* dgamma,
+                      float* dbeta, float2* bpart, hipStream_t s) {
+  const int npt = gn_fused_npt(P, C / G);
+#define GNB_CALL(K)                                                                                           \
+  hipLaunchKernelGGL(gnb_fused_kernel<K>, dim3(B * G), dim3(256), 0, s, dout, outm, chw, y, P, C, G, stats, \
+                     gamma, dy, dres, bpart)
+  GN_NPT_SWITCH(npt, GNB_CALL)
+#undef GNB_CALL
+  hipLaunchKernelGGL(gnb_affine_kernel, dim3(cdiv(C, 4)), dim3(256), 0, s, bpart, B, 1, C, dgamma, dbeta);
+}

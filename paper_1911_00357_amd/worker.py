@@ -56,11 +56,30 @@ class Worker:
         self.stats = torch.zeros(8, **f32)
         self.adv_stats = torch.zeros(2, dtype=torch.float64, device=dev)
         self.h_scr = torch.zeros(L, N, H, **f32)
+        self.c_scr = torch.zeros(L, N, H, **f32)
+        self._graphs = {}
 
     # ------------------------------------------------------------- rollout
-    def collect(self, env: dict, lengths=None):
+    def collect(self, env: dict, lengths=None, graph: bool = False):
         """env: device tensors obs [T+1,N,C,H,W], goal [T+1,N,2], mask [T+1,N],
-        u [T+1,N].  lengths: host ints [N] (non-increasing) or None."""
+        u [T+1,N].  lengths: host ints [N] (non-increasing) or None.
+        graph=True replays the T+1 act calls as one captured HIP graph (captured
+        on the first call for these env buffers, after one eager pass)."""
+        if graph:
+            key = (env["obs"].data_ptr(), env["u"].data_ptr(), None if lengths is None else tuple(lengths))
+            g = self._graphs.get(key)
+            if g is None:
+                self._collect(env, lengths)        # eager pass: workspaces exist before capture
+                torch.cuda.synchronize()
+                g = torch.cuda.CUDAGraph()
+                with torch.cuda.graph(g):
+                    self._collect(env, lengths)
+                self._graphs[key] = g
+            g.replay()
+            return
+        self._collect(env, lengths)
+
+    def _collect(self, env: dict, lengths=None):
         T, N = self.T, self.N
         lens = np.full(N, T) if lengths is None else np.asarray(lengths)
         assert np.all(np.diff(lens) <= 0), "envs must be ordered longest first"
@@ -72,7 +91,7 @@ class Worker:
                    "value": self.value[t, :B], "h": self.h_hist[min(t + 1, T)],
                    "c": self.c_hist[min(t + 1, T)]}
             if t == T:  # bootstrap step of full-length envs: its state is discarded
-                out["h"], out["c"] = self.h_scr, torch.empty_like(self.h_scr)
+                out["h"], out["c"] = self.h_scr, self.c_scr
             self.net.act(env["obs"][t, :B], env["goal"][t, :B], self.act_rec[t, :B],
                          env["mask"][t, :B], self.h_hist[t], self.c_hist[t], env["u"][t, :B],
                          self.params, self.lp, out=out, state_rows=N)

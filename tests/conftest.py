@@ -15,3 +15,12 @@ if ROOT not in sys.path:
 def pytest_configure(config):
     config.addinivalue_line("markers", "gpu: needs an MI355X (runs the HIP library)")
     config.addinivalue_line("markers", "slow: CPU test that takes more than a few seconds")
+
+
+@pytest.fixture(scope="session")
+def P():
+    """The library's Python binding (GPU tests)."""
+    import torch
+    import paper_1911_00357_amd as P
+    assert torch.cuda.is_available()
+    return P

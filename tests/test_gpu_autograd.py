@@ -1,0 +1,108 @@
+"""The policy behind torch.autograd.Function (hand-written backward with
+recomputed encoder activations): against ppo_loss_backward, against the FP64
+oracle on a 3-env x T=8 slice of the 128x128 differentiation workload, and
+against finite differences of its own loss."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import ppo
+from synth import rollout as R
+from synth.configs import C3, PPOCfg
+from tests.gpu_util import DEV, oracle_minibatch, per_tensor_errors, random_record, rel_err, to_device
+from tests.nets import TINY_PLUS
+from tests.test_gpu_parity import TOL, gpu_decisions, say
+
+pytestmark = pytest.mark.gpu
+
+
+def _setup(P, net, dtype, T, N, lengths, seed):
+    flat = R.init_params(net, seed, random_affine=True)
+    rec = random_record(net, T, N, seed + 1, lengths=lengths, bf16=dtype == "bf16")
+    n = P.Net(net, dtype)
+    params = torch.tensor(flat, device=DEV)
+    lp = P.cast_bf16(params) if dtype == "bf16" else None
+    return flat, rec, n, params, lp, to_device(rec, bf16=dtype == "bf16")
+
+
+def _weights(rec, envs, src, N):
+    lens = rec["lengths"]
+    env = (src.cpu().numpy() % N)
+    return torch.tensor(1.0 / (len(envs) * lens[env]), dtype=torch.float32, device=DEV)
+
+
+def _autograd_grad(P, n, ro, rec, envs, params, lp, N):
+    from paper_1911_00357_amd import autograd as AG
+    th = params.clone().requires_grad_(True)
+    logits, values, src = AG.policy(th, n, ro, envs, rec["lengths"], lp)
+    loss = AG.ppo_loss(logits, values, src, ro, _weights(rec, envs, src, N))
+    loss.backward()
+    return th.grad.detach(), loss.detach(), logits.detach(), values.detach(), src
+
+
+@pytest.mark.parametrize("net,T,N,lengths,envs", [(TINY_PLUS, 6, 3, [6, 5, 3], [0, 1, 2]),
+                                                  (C3.net, 8, 3, [8, 8, 8], [0, 1, 2])],
+                         ids=["tiny+", "c3net"])
+def test_autograd_matches_loss_backward(P, net, T, N, lengths, envs):
+    say(f"autograd vs loss_backward {net.in_hw}")
+    flat, rec, n, params, lp, ro = _setup(P, net, "f32", T, N, lengths, 31)
+    g_ag, loss, _, _, _ = _autograd_grad(P, n, ro, rec, envs, params, lp, N)
+    g_lb, stats = n.loss_backward(ro, envs, rec["lengths"], params, lp)
+    torch.cuda.synchronize()
+    assert abs(loss.item() - stats[0].item()) <= 1e-5 * max(1.0, abs(stats[0].item()))
+    assert rel_err(g_ag.cpu().numpy(), g_lb.cpu().numpy()) < 1e-5
+
+
+@pytest.mark.parametrize("dtype", ["f32", "bf16"])
+def test_autograd_c3_slice_vs_oracle(P, dtype):
+    """3 envs x T=8 of the 128x128 network; the oracle takes the GPU's
+    ReLU / max-pool decisions."""
+    say(f"autograd c3 slice {dtype}")
+    net = C3.net
+    flat, rec, n, params, lp, ro = _setup(P, net, dtype, 8, 3, [8, 8, 8], 41)
+    envs = [0, 1, 2]
+    g, loss, _, _, _ = _autograd_grad(P, n, ro, rec, envs, params, lp, 3)
+    torch.cuda.synchronize()
+    mb = oracle_minibatch(rec, envs)
+    F = int(mb["lens"].sum())
+    from paper_1911_00357_amd._lib import PPO_OP_LEARN
+    dec = gpu_decisions(n, net, F, len(envs), mb)
+    s_ref, g_ref = ppo.loss_grad(flat.astype(np.float64), net, PPOCfg(), mb, decide=dec)
+    g = g.cpu().numpy()
+    errs = per_tensor_errors(net, g, g_ref)
+    order = sorted(errs, key=errs.get, reverse=True)
+    say(f"  global {rel_err(g, g_ref):.2e}; worst " + ", ".join(f"{k}={errs[k]:.1e}" for k in order[:4]))
+    assert abs(loss.item() - s_ref[0]) <= TOL[dtype] * (abs(s_ref[1]) + 0.5 * abs(s_ref[2]) + 0.01 * abs(s_ref[3]))
+    assert rel_err(g, g_ref) < TOL[dtype]
+
+
+def test_autograd_c3_slice_finite_differences(P):
+    """Central differences of the GPU's own FP32 loss along the gradient
+    direction and along single-tensor random directions."""
+    from paper_1911_00357_amd import autograd as AG
+    net = C3.net
+    flat, rec, n, params, lp, ro = _setup(P, net, "f32", 8, 3, [8, 8, 8], 43)
+    envs = [0, 1, 2]
+    g, loss, _, _, src = _autograd_grad(P, n, ro, rec, envs, params, lp, 3)
+    w = _weights(rec, envs, src, 3)
+
+    def L(th):
+        with torch.no_grad():
+            lg, v, s = AG.policy(th, n, ro, envs, rec["lengths"], None)
+            return AG.ppo_loss(lg, v, s, ro, w).double().item()
+
+    names = {nm: (off, cnt) for nm, off, cnt in n.tensors()}
+    rng = np.random.default_rng(0)
+    dirs = [g / g.norm()]
+    for nm in ("head.w", "lstm1.w", "fc.w", "enc.s3.b2.c3"):
+        off, cnt = names[nm]
+        d = torch.zeros_like(params)
+        d[off:off + cnt] = torch.tensor(rng.standard_normal(cnt), dtype=torch.float32, device=DEV)
+        dirs.append(d / d.norm())
+    for d in dirs:
+        gd = float((g.double() * d.double()).sum())
+        h = 2e-3
+        fd = (L(params + h * d) - L(params - h * d)) / (2 * h)
+        say(f"  fd {fd:.6e} vs g.d {gd:.6e}")
+        noise = 8 * 6e-8 * abs(float(loss)) / (2 * h)   # float32 rounding of the two losses
+        assert abs(fd - gd) <= 2e-2 * abs(gd) + noise

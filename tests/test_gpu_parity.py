@@ -23,13 +23,6 @@ def say(*a):
     sys.stdout.flush()
 
 
-@pytest.fixture(scope="module")
-def P():
-    import paper_1911_00357_amd as P
-    assert torch.cuda.is_available()
-    return P
-
-
 # ---------------------------------------------------------------- GAE
 @pytest.mark.parametrize("T,N,ragged,seed", [(16, 2, False, 0), (128, 4, False, 1), (128, 64, True, 2),
                                              (1, 3, False, 3), (200, 5, True, 4), (64, 1, False, 5)])
@@ -235,21 +228,34 @@ def _loss_case(P, net, dtype, T, N, envs, lengths, seed, norm_adv=False, same_de
         F = int(mb["lens"].sum())
         dec = gpu_decisions(n, net, F, len(envs), mb)
     s_ref, g_ref = ppo.loss_grad(flat.astype(np.float64), net, PPOCfg(), mb, adv_norm=mu_var, decide=dec)
-    return grad.cpu().numpy(), stats.cpu().numpy(), g_ref, s_ref
+    floor = None
+    if dtype == "bf16" and same_decisions:
+        # the exact gradient at the bfloat16-rounded weights, same decisions: how far
+        # rounding the working copy alone moves each tensor's gradient
+        _, g_w = ppo.loss_grad(R.round_bf16(flat).astype(np.float64), net, PPOCfg(), mb, adv_norm=mu_var,
+                               decide=dec)
+        floor = per_tensor_errors(net, g_w, g_ref)
+    return grad.cpu().numpy(), stats.cpu().numpy(), g_ref, s_ref, floor
 
 
-def check_loss(net, dtype, g, s, g_ref, s_ref, tag):
+def check_loss(net, dtype, g, s, g_ref, s_ref, tag, floor=None):
+    """Loss terms and the whole gradient within the tolerance; each parameter
+    tensor's gradient within the tolerance, or (bfloat16) within 3x the change
+    that rounding the weights to bfloat16 alone causes in the exact gradient
+    (cancellation-heavy tensors such as deep GroupNorm scales)."""
     tol = TOL[dtype]
     errs = per_tensor_errors(net, g, g_ref)
     order = sorted(errs, key=errs.get, reverse=True)
     say(f"  {tag}: global grad err {rel_err(g, g_ref):.2e}; worst tensors: " +
-        ", ".join(f"{k}={errs[k]:.1e}" for k in order[:5]) + f"; loss {s[0]:.6f} vs {s_ref[0]:.6f}")
+        ", ".join(f"{k}={errs[k]:.1e}" + (f"(floor {floor[k]:.1e})" if floor else "") for k in order[:5]) +
+        f"; loss {s[0]:.6f} vs {s_ref[0]:.6f}")
     denom = abs(s_ref[1]) + 0.5 * abs(s_ref[2]) + 0.01 * abs(s_ref[3])
     assert abs(s[0] - s_ref[0]) / denom < tol
     for k in (1, 2, 3):
         assert abs(s[k] - s_ref[k]) <= tol * max(abs(s_ref[k]), 1e-6)
     assert rel_err(g, g_ref) < tol
-    assert errs[order[0]] < tol, errs
+    bad = {k: v for k, v in errs.items() if v >= tol and (floor is None or v >= 3 * floor[k])}
+    assert not bad, bad
 
 
 @pytest.mark.parametrize("name,net,T,N,envs,lengths", [
@@ -260,12 +266,12 @@ def check_loss(net, dtype, g, s, g_ref, s_ref, tag):
 ])
 def test_loss_backward_parity_f32(P, name, net, T, N, envs, lengths):
     say(f"loss f32 {name}")
-    g, s, g_ref, s_ref = _loss_case(P, net, "f32", T, N, envs, lengths, seed=T * 7 + N)
+    g, s, g_ref, s_ref, _ = _loss_case(P, net, "f32", T, N, envs, lengths, seed=T * 7 + N)
     check_loss(net, "f32", g, s, g_ref, s_ref, name)
 
 
 def test_loss_backward_norm_adv(P):
-    g, s, g_ref, s_ref = _loss_case(P, TINY_PLUS, "f32", 5, 3, [0, 1, 2], None, seed=3, norm_adv=True)
+    g, s, g_ref, s_ref, _ = _loss_case(P, TINY_PLUS, "f32", 5, 3, [0, 1, 2], None, seed=3, norm_adv=True)
     assert rel_err(g, g_ref) < 1e-4 and abs(s[1] - s_ref[1]) < 1e-4 * abs(s_ref[1])
 
 
@@ -277,8 +283,9 @@ def test_loss_backward_parity_bf16(P, name, net, T, N, envs, lengths):
     """bfloat16 operands move activations across ReLU kinks; the oracle takes
     the GPU's ReLU / max-pool decisions."""
     say(f"loss bf16 {name}")
-    g, s, g_ref, s_ref = _loss_case(P, net, "bf16", T, N, envs, lengths, seed=T * 3 + N, same_decisions=True)
-    check_loss(net, "bf16", g, s, g_ref, s_ref, name)
+    g, s, g_ref, s_ref, floor = _loss_case(P, net, "bf16", T, N, envs, lengths, seed=T * 3 + N,
+                                           same_decisions=True)
+    check_loss(net, "bf16", g, s, g_ref, s_ref, name, floor)
 
 
 @pytest.mark.parametrize("dtype", ["f32", "bf16"])
@@ -287,5 +294,6 @@ def test_loss_backward_resnet_paper_shape(P, dtype):
     oracle takes the GPU's ReLU / max-pool decisions (a decision made by
     floating point is taken in the kernel's precision on both sides)."""
     say(f"loss resnet paper shape {dtype}")
-    g, s, g_ref, s_ref = _loss_case(P, C1.net, dtype, 4, 3, [2, 0], [4, 2, 3], seed=21, same_decisions=True)
-    check_loss(C1.net, dtype, g, s, g_ref, s_ref, "resnet")
+    g, s, g_ref, s_ref, floor = _loss_case(P, C1.net, dtype, 4, 3, [2, 0], [4, 2, 3], seed=21,
+                                           same_decisions=True)
+    check_loss(C1.net, dtype, g, s, g_ref, s_ref, "resnet", floor)
