@@ -213,6 +213,7 @@ struct WsLayout {
   size_t h0g, c0g;                 // gathered start state [L][nb][H]
   size_t zh;                       // act: [B][max(din0, H) + H]
   size_t fstat, dout, dh0, dh1, dG, dhp, dcp, dvis, whT;
+  size_t sync;                     // persistent recurrence barrier words
   size_t total;
 };
 
@@ -271,6 +272,7 @@ WsLayout plan(const ppo_net* n, int F, int nb, bool learn) {
     w.dcp = A.take((size_t)std::max(nb, 1) * H * f4);
     w.dvis = A.take((size_t)F * d.vis_hidden * f4);
     w.whT = A.take((size_t)4 * H * H * f4);
+    w.sync = A.take(kLstmSyncBytes);
   }
   w.total = A.off;
   return w;
@@ -648,6 +650,9 @@ const float* learner_fwd(const Ctx& c, const ppo_batch* b, const Sched& S) {
                       HP, H, CP, s);
     const void* whh = net->prec ? (const void*)((const bf16_t*)b->params_lp + wl + din)
                                 : (const void*)(b->params + wl + din);
+    if (launch_lstm_seq_fwd(net->prec, S.m, TB, H, whh, din + H, G, HP, CP, Cs, Ho, H, mskf,
+                            c.at<unsigned>(w.sync), s) == 0)
+      continue;
     for (int t = 0; t < TB; ++t) {
       // gates_t = (x_t W_ih^T + b) + (m_t h_{t-1}) W_hh^T, then the cell (activations overwrite G)
       const size_t r0 = off[t];
@@ -696,8 +701,10 @@ void learner_bwd(const Ctx& c, const ppo_batch* b, const Sched& S, const float* 
     const void* whh = net->prec ? (const void*)((const bf16_t*)b->params_lp + wl + din)
                                 : (const void*)(b->params + wl + din);
     void* whT = c.at<void>(w.whT);
-    launch_transpose_whh(net->prec, whh, din + H, H, whT, s);
-    for (int t = TB - 1; t >= 0; --t) {
+    const bool seq = launch_lstm_seq_bwd(net->prec, S.m, TB, H, whh, din + H, G, CP, Cs, dH, H, dG, mskf,
+                                         c.at<unsigned>(w.sync), s) == 0;
+    if (!seq) launch_transpose_whh(net->prec, whh, din + H, H, whT, s);
+    for (int t = seq ? -1 : TB - 1; t >= 0; --t) {
       // dh_t = dH_t + m_{t+1} dG_{t+1} W_hh, dc_t = m_{t+1} dc_{t+1} f_{t+1}; cell backward -> dG_t
       const size_t r0 = off[t];
       const bool more = t + 1 < TB;

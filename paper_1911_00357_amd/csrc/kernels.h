@@ -113,6 +113,18 @@ void launch_lstm_step_bwd(int prec, const float* dGn, const void* WT, const floa
 // WT [H][4H] = transpose of the recurrent block W[:, din:din+H] (row stride ldw)
 void launch_transpose_whh(int prec, const void* W, int ldw, int H, void* WT, hipStream_t s);
 
+// lstm_seq.hip: one cooperative launch for all TB steps of a layer (see the
+// file header).  Return 0 when launched, nonzero when the shape or the device
+// does not allow it (nothing launched; the caller runs the per-step kernels).
+// sync: kLstmSyncBytes of device memory owned by the call.
+constexpr size_t kLstmSyncBytes = 257 * 256;
+int launch_lstm_seq_fwd(int prec, const MapArgs& m, int TB, int H, const void* Whh, int ldw, float* G, float* HP,
+                        float* CP, float* Cs, float* Ho, int ldh, const float* mskf, unsigned* sync,
+                        hipStream_t s);
+int launch_lstm_seq_bwd(int prec, const MapArgs& m, int TB, int H, const void* Whh, int ldw, const float* G,
+                        const float* CP, const float* Cs, const float* dH, int ldd, float* dG, const float* mskf,
+                        unsigned* sync, hipStream_t s);
+
 // head.hip
 void launch_act_head(const float* htop, int rows, int H, int A, const float* W, const float* b,
                      const float* u, int32_t* action, float* logp, float* value, float* logits,
