@@ -53,7 +53,8 @@ Tile choose(long M, long N, int prec) {
 int splits_for(long tiles, long K) {
   if (tiles >= 512) return 1;
   long want = (1024 + tiles - 1) / tiles;
-  const long kmax = std::max<long>(1, K / (4 * BK));  // >= 4 K tiles per split
+  // >= 4 K tiles per split; >= 2 for very few output tiles (latency-bound launches)
+  const long kmax = std::max<long>(1, K / ((tiles < 64 ? 2 : 4) * BK));
   return (int)std::max<long>(1, std::min<long>({want, kmax, 256}));
 }
 

@@ -403,57 +403,73 @@ void launch_relu_grad(const float* dy, const float* y, size_t n, float* dx, hipS
 // apply.  The input is the convolution output, or the sum of its split-K
 // partial tiles (src + z*zstride), in which case the summed output can also
 // be stored (u_out) for the backward.
+template <int NT = 256>
 DEV float block_sum(float v, float* red) {
   double d = wave_sum((double)v);
   const int w = threadIdx.x >> 6;
   __syncthreads();
   if ((threadIdx.x & 63) == 0) red[w] = (float)d;
   __syncthreads();
-  return red[0] + red[1] + red[2] + red[3];
+  float t = 0.f;
+#pragma unroll
+  for (int i = 0; i < NT / 64; ++i) t += red[i];
+  return t;
 }
 
-template <int NPT>
-__global__ void __launch_bounds__(256) gn_fused_kernel(const float* __restrict__ src, int nsplit, size_t zstride,
+template <int NPT, int NT>
+__global__ void __launch_bounds__(NT) gn_fused_kernel(const float* __restrict__ src, int nsplit, size_t zstride,
                                                        float* __restrict__ u_out, int P, int C, int G, float eps,
                                                        const float* __restrict__ gamma,
                                                        const float* __restrict__ beta,
                                                        const float* __restrict__ res, int relu,
                                                        float* __restrict__ out, int out_chw,
                                                        float2* __restrict__ stats) {
-  __shared__ float red[4];
+  __shared__ float red[NT / 64];
   const int b = blockIdx.x / G, g = blockIdx.x - b * G;
   const int Cg = C / G, n = P * Cg;
+  // element j of this thread: pixel p0 + j*pstep, channel c (NT % Cg == 0)
+  const int cc = threadIdx.x % Cg, p0 = threadIdx.x / Cg, pstep = NT / Cg, c = g * Cg + cc;
+  const size_t base = ((size_t)b * P + p0) * C + c, jstr = (size_t)pstep * C;
   float x[NPT];
+#pragma unroll
+  for (int j = 0; j < NPT; ++j) x[j] = p0 + j * pstep < P ? src[base + j * jstr] : 0.f;
+  // remaining split-K partials: NPT x 4 loads in flight per round
+  int z = 1;
+  for (; z + 4 <= nsplit; z += 4) {
+    float y[4][NPT];
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+      for (int j = 0; j < NPT; ++j)
+        y[q][j] = p0 + j * pstep < P ? src[(size_t)(z + q) * zstride + base + j * jstr] : 0.f;
+#pragma unroll
+    for (int j = 0; j < NPT; ++j) x[j] += (y[0][j] + y[1][j]) + (y[2][j] + y[3][j]);
+  }
+  for (; z < nsplit; ++z)
+#pragma unroll
+    for (int j = 0; j < NPT; ++j)
+      if (p0 + j * pstep < P) x[j] += src[(size_t)z * zstride + base + j * jstr];
   float s = 0.f;
 #pragma unroll
   for (int j = 0; j < NPT; ++j) {
-    const int e = threadIdx.x + 256 * j;
-    float v = 0.f;
-    if (e < n) {
-      const int p = e / Cg, c = g * Cg + (e - p * Cg);
-      const size_t idx = ((size_t)b * P + p) * C + c;
-      v = src[idx];
-      for (int z = 1; z < nsplit; ++z) v += src[(size_t)z * zstride + idx];
-      if (u_out) u_out[idx] = v;
-    }
-    x[j] = v;
-    s += v;
+    if (u_out && p0 + j * pstep < P) u_out[base + j * jstr] = x[j];
+    s += x[j];
   }
-  const float mean = block_sum(s, red) / n;
+  const float mean = block_sum<NT>(s, red) / n;
   float q = 0.f;
 #pragma unroll
   for (int j = 0; j < NPT; ++j)
-    if (threadIdx.x + 256 * j < n) q += (x[j] - mean) * (x[j] - mean);
-  const float var = block_sum(q, red) / n;
+    if (p0 + j * pstep < P) q += (x[j] - mean) * (x[j] - mean);
+  const float var = block_sum<NT>(q, red) / n;
   const float rstd = 1.0f / sqrtf(var + eps);
   if (threadIdx.x == 0) stats[blockIdx.x] = make_float2(mean, rstd);
+  const float ga = gamma[c] * rstd, be = beta[c];
 #pragma unroll
   for (int j = 0; j < NPT; ++j) {
-    const int e = threadIdx.x + 256 * j;
-    if (e < n) {
-      const int p = e / Cg, c = g * Cg + (e - p * Cg);
-      const size_t idx = ((size_t)b * P + p) * C + c;
-      float o = (x[j] - mean) * rstd * gamma[c] + beta[c];
+    const int p = p0 + j * pstep;
+    if (p < P) {
+      const size_t idx = base + j * jstr;
+      float o = (x[j] - mean) * ga + be;
       if (res) o += res[idx];
       if (relu) o = fmaxf(o, 0.f);
       out[out_chw ? ((size_t)b * C + c) * P + p : idx] = o;
@@ -464,49 +480,49 @@ __global__ void __launch_bounds__(256) gn_fused_kernel(const float* __restrict__
 // Backward per (b, g): dz = dout [* (out > 0)], xhat = (y - mean) rstd;
 // dy = rstd (dz gamma - mean(dz gamma) - xhat mean(dz gamma xhat)), dres = dz;
 // bpart[b*C + c] = {sum_p dz, sum_p dz xhat} for the dgamma / dbeta reduction.
-template <int NPT>
-__global__ void __launch_bounds__(256) gnb_fused_kernel(const float* __restrict__ dout,
+template <int NPT, int NT>
+__global__ void __launch_bounds__(NT) gnb_fused_kernel(const float* __restrict__ dout,
                                                         const float* __restrict__ outm, int chw,
                                                         const float* __restrict__ y, int P, int C, int G,
                                                         const float2* __restrict__ stats,
                                                         const float* __restrict__ gamma, float* __restrict__ dy,
                                                         float* __restrict__ dres, float2* __restrict__ bpart) {
-  __shared__ float red[4];
-  __shared__ float2 cred[256];
+  __shared__ float red[NT / 64];
+  __shared__ float2 cred[NT];
   const int b = blockIdx.x / G, g = blockIdx.x - b * G;
   const int Cg = C / G, n = P * Cg;
   const float2 st = stats[blockIdx.x];
+  const int cc = threadIdx.x % Cg, p0 = threadIdx.x / Cg, pstep = NT / Cg, c = g * Cg + cc;
+  const size_t base = ((size_t)b * P + p0) * C + c, jstr = (size_t)pstep * C;
+  const float gm = gamma[c];
   float dz[NPT], xh[NPT];
-  float s1 = 0.f, s2 = 0.f, cz = 0.f, czx = 0.f;
-  const int cc = threadIdx.x % Cg;  // this thread's channel within the group (256 % Cg == 0)
-  const float gm = gamma[g * Cg + cc];
 #pragma unroll
   for (int j = 0; j < NPT; ++j) {
-    const int e = threadIdx.x + 256 * j;
-    float z = 0.f, xv = 0.f;
-    if (e < n) {
-      const int p = e / Cg, c = g * Cg + cc;
-      const size_t idx = ((size_t)b * P + p) * C + c;
-      const size_t io = chw ? ((size_t)b * C + c) * P + p : idx;
-      z = dout[io];
-      if (outm && !(outm[io] > 0.f)) z = 0.f;
-      xv = (y[idx] - st.x) * st.y;
+    const int p = p0 + j * pstep;
+    float zv = 0.f, om = 1.f, yv = st.x;
+    if (p < P) {
+      const size_t io = chw ? ((size_t)b * C + c) * P + p : base + j * jstr;
+      zv = dout[io];
+      if (outm) om = outm[io];
+      yv = y[base + j * jstr];
     }
-    dz[j] = z;
-    xh[j] = xv;
-    s1 += z * gm;
-    s2 += z * gm * xv;
-    cz += z;
-    czx += z * xv;
+    dz[j] = om > 0.f ? zv : 0.f;
+    xh[j] = (yv - st.x) * st.y;
   }
-  const float m1 = block_sum(s1, red) / n;
-  const float m2 = block_sum(s2, red) / n;
+  float s1 = 0.f, s2 = 0.f, cz = 0.f, czx = 0.f;
 #pragma unroll
   for (int j = 0; j < NPT; ++j) {
-    const int e = threadIdx.x + 256 * j;
-    if (e < n) {
-      const int p = e / Cg;
-      const size_t idx = ((size_t)b * P + p) * C + g * Cg + cc;
+    s1 += dz[j] * gm;
+    s2 += dz[j] * gm * xh[j];
+    cz += dz[j];
+    czx += dz[j] * xh[j];
+  }
+  const float m1 = block_sum<NT>(s1, red) / n;
+  const float m2 = block_sum<NT>(s2, red) / n;
+#pragma unroll
+  for (int j = 0; j < NPT; ++j) {
+    if (p0 + j * pstep < P) {
+      const size_t idx = base + j * jstr;
       dy[idx] = st.y * (dz[j] * gm - m1 - xh[j] * m2);
       if (dres) dres[idx] = dz[j];
     }
@@ -515,7 +531,7 @@ __global__ void __launch_bounds__(256) gnb_fused_kernel(const float* __restrict_
   __syncthreads();
   if (threadIdx.x < Cg) {
     float a = 0.f, q = 0.f;
-    for (int t = threadIdx.x; t < 256; t += Cg) {
+    for (int t = threadIdx.x; t < NT; t += Cg) {
       a += cred[t].x;
       q += cred[t].y;
     }
@@ -523,43 +539,55 @@ __global__ void __launch_bounds__(256) gnb_fused_kernel(const float* __restrict_
   }
 }
 
+// Elements per thread (1..32) of the fused kernels, 0 when unsupported; the
+// block has 256 threads up to 2048 elements per (image, group), else 1024.
 int gn_fused_npt(int P, int Cg) {
   const int n = P * Cg;
   if (256 % Cg) return 0;
+  const int nt = n <= 256 * 8 ? 256 : 1024;
   for (int k = 1; k <= 32; k *= 2)
-    if (n <= 256 * k) return k;
+    if (n <= nt * k) return k;
   return 0;
 }
 
-#define GN_NPT_SWITCH(NPT_, CALL) \
-  switch (NPT_) {                 \
-    case 1: CALL(1); break;       \
-    case 2: CALL(2); break;       \
-    case 4: CALL(4); break;       \
-    case 8: CALL(8); break;       \
-    case 16: CALL(16); break;     \
-    default: CALL(32); break;     \
+#define GN_NPT_SWITCH(NT_, NPT_, CALL) \
+  if (NT_ == 256) {                    \
+    switch (NPT_) {                    \
+      case 1: CALL(1, 256); break;     \
+      case 2: CALL(2, 256); break;     \
+      case 4: CALL(4, 256); break;     \
+      default: CALL(8, 256); break;    \
+    }                                  \
+  } else {                             \
+    switch (NPT_) {                    \
+      case 1: CALL(1, 1024); break;    \
+      case 2: CALL(2, 1024); break;    \
+      case 4: CALL(4, 1024); break;    \
+      case 8: CALL(8, 1024); break;    \
+      case 16: CALL(16, 1024); break;  \
+      default: CALL(32, 1024); break;  \
+    }                                  \
   }
 
 void launch_gn_fused(const float* src, int nsplit, size_t zstride, float* u_out, int B, int P, int C, int G,
                      float eps, const float* gamma, const float* beta, const float* res, int relu, float* out,
                      int out_chw, float2* stats, hipStream_t s) {
-  const int npt = gn_fused_npt(P, C / G);
-#define GN_CALL(K)                                                                                          \
-  hipLaunchKernelGGL(gn_fused_kernel<K>, dim3(B * G), dim3(256), 0, s, src, nsplit, zstride, u_out, P, C, G, \
-                     eps, gamma, beta, res, relu, out, out_chw, stats)
-  GN_NPT_SWITCH(npt, GN_CALL)
+  const int npt = gn_fused_npt(P, C / G), nt = (long)P * (C / G) <= 256 * 8 ? 256 : 1024;
+#define GN_CALL(K, T)                                                                                        \
+  hipLaunchKernelGGL((gn_fused_kernel<K, T>), dim3(B * G), dim3(T), 0, s, src, nsplit, zstride, u_out, P, C, \
+                     G, eps, gamma, beta, res, relu, out, out_chw, stats)
+  GN_NPT_SWITCH(nt, npt, GN_CALL)
 #undef GN_CALL
 }
 
 void launch_gnb_fused(const float* dout, const float* outm, int chw, const float* y, int B, int P, int C, int G,
                       const float2* stats, const float* gamma, float* dy, float* dres, float* dgamma,
                       float* dbeta, float2* bpart, hipStream_t s) {
-  const int npt = gn_fused_npt(P, C / G);
-#define GNB_CALL(K)                                                                                           \
-  hipLaunchKernelGGL(gnb_fused_kernel<K>, dim3(B * G), dim3(256), 0, s, dout, outm, chw, y, P, C, G, stats, \
+  const int npt = gn_fused_npt(P, C / G), nt = (long)P * (C / G) <= 256 * 8 ? 256 : 1024;
+#define GNB_CALL(K, T)                                                                                       \
+  hipLaunchKernelGGL((gnb_fused_kernel<K, T>), dim3(B * G), dim3(T), 0, s, dout, outm, chw, y, P, C, G, stats, \
                      gamma, dy, dres, bpart)
-  GN_NPT_SWITCH(npt, GNB_CALL)
+  GN_NPT_SWITCH(nt, npt, GNB_CALL)
 #undef GNB_CALL
   hipLaunchKernelGGL(gnb_affine_kernel, dim3(cdiv(C, 4)), dim3(256), 0, s, bpart, B, 1, C, dgamma, dbeta);
 }
