@@ -28,6 +28,7 @@ PEAK_BF16_TFLOPS = 2500.0     # MI355X dense bf16 MFMA
 PEAK_FP32_TFLOPS = 157.3      # MI355X fp32 matrix
 PEAK_HBM_GBS = 8000.0
 GRAPH = True                  # act loop replayed as one captured HIP graph
+AUTOGRAD = False              # update gradient through torch.autograd (C3)
 
 
 def parse():
@@ -40,6 +41,8 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--eager", action="store_true", help="launch the act loop eagerly (no HIP graph)")
+    ap.add_argument("--autograd", choices=["auto", "on", "off"], default="auto",
+                    help="take the update's gradient through torch.autograd (auto: for C3)")
     return ap.parse_args()
 
 
@@ -57,6 +60,13 @@ def stage_env(wl, seed, it, dev):
            "mask": t(ro["mask"][:, order]), "reward": t(ro["reward"][:, order]),
            "done": t(ro["done"][:, order])}
     return env, lens[order]
+
+
+def _update(w, env, parts, lengths):
+    if AUTOGRAD:
+        w.update_autograd(env, parts, lengths)
+    else:
+        w.update(env, parts, lengths)
 
 
 def run_gpu(wl, steps, warmup, seed):
@@ -83,7 +93,7 @@ def run_gpu(wl, steps, warmup, seed):
             ev[0].record()
             t_start = time.perf_counter()
         w.collect(env, lengths, graph=GRAPH)
-        w.update(env, parts, lengths)
+        _update(w, env, parts, lengths)
         if i >= warmup:
             frames.append(int(lens.sum()))
     ev[1].record()
@@ -107,12 +117,12 @@ def act_update_split(wl, seed):
     parts = R.partitions(wl, seed)
     for _ in range(2):
         w.collect(env, lengths, graph=GRAPH)
-        w.update(env, parts, lengths)
+        _update(w, env, parts, lengths)
     e = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
     e[0].record()
     w.collect(env, lengths, graph=GRAPH)
     e[1].record()
-    w.update(env, parts, lengths)
+    _update(w, env, parts, lengths)
     e[2].record()
     torch.cuda.synchronize()
     return e[0].elapsed_time(e[1]), e[1].elapsed_time(e[2]), int(lens.sum())
@@ -272,8 +282,9 @@ def flops_per_frame(net):
 
 def main():
     a = parse()
-    global GRAPH
+    global GRAPH, AUTOGRAD
     GRAPH = not a.eager
+    AUTOGRAD = a.autograd == "on" or (a.autograd == "auto" and a.workload == "C3")
     if a.gpus != 1:
         print(json.dumps({"error": "this build measures one GPU; the gradient all-reduce of a "
                                    "multi-GPU worker group is not implemented", "n_gpus": a.gpus}))
@@ -296,7 +307,9 @@ def main():
                       "encoder": "resnet50 halved widths, GroupNorm" if wl.net.trunk == "resnet" else "tiny",
                       "lstm": f"{wl.net.lstm_layers}x{wl.net.hidden}", "epochs": wl.ppo.epochs,
                       "minibatches": wl.ppo.minibatches, "frames_per_step": frames_step,
-                      "parallelism": "single worker"},
+                      "parallelism": "single worker",
+                      "gradient": "torch.autograd.Function, activations recomputed" if AUTOGRAD
+                      else "ppo_loss_backward"},
            "wall_s": round(res["wall_s"], 3)}
     del res
     torch.cuda.empty_cache()

@@ -106,3 +106,32 @@ def test_autograd_c3_slice_finite_differences(P):
         say(f"  fd {fd:.6e} vs g.d {gd:.6e}")
         noise = 8 * 6e-8 * abs(float(loss)) / (2 * h)   # float32 rounding of the two losses
         assert abs(fd - gd) <= 2e-2 * abs(gd) + noise
+
+
+def test_worker_update_autograd_matches_update(P):
+    """One update through torch.autograd moves the weights as the library's
+    loss backward does (same Adam step on close gradients)."""
+    from paper_1911_00357_amd.worker import Worker
+    say("worker update via autograd vs loss backward")
+    net, T, N = TINY_PLUS, 6, 3
+    flat = R.init_params(net, 5, random_affine=True)
+    g = np.random.default_rng(6)
+    env = {"obs": torch.tensor(g.random((T + 1, N, net.in_ch, net.in_hw, net.in_hw), dtype=np.float32), device=DEV),
+           "goal": torch.tensor(g.standard_normal((T + 1, N, 2)).astype(np.float32), device=DEV),
+           "mask": torch.tensor((g.random((T + 1, N)) > 0.1).astype(np.float32), device=DEV),
+           "u": torch.tensor(g.random((T + 1, N)).astype(np.float32), device=DEV),
+           "reward": torch.tensor(g.normal(0, 0.05, (T, N)).astype(np.float32), device=DEV),
+           "done": torch.tensor((g.random((T, N)) < 0.1).astype(np.uint8), device=DEV)}
+    lengths = [6, 5, 3]
+    parts = [[np.array([0, 2]), np.array([1])]]
+    deltas = []
+    for ag in (False, True):
+        w = Worker(net, "f32", T, N, flat, device=DEV)
+        w.collect(env, lengths)
+        before = w.params.clone()
+        (w.update_autograd if ag else w.update)(env, parts, lengths)
+        torch.cuda.synchronize()
+        deltas.append((w.params - before).cpu().numpy())
+    e = rel_err(deltas[1], deltas[0])
+    say(f"  weight-change rel diff {e:.2e}")
+    assert np.abs(deltas[0]).max() > 0 and e < 1e-2
