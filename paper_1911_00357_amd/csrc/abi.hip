@@ -214,6 +214,7 @@ struct WsLayout {
   size_t zh;                       // act: [B][max(din0, H) + H]
   size_t fstat, dout, dh0, dh1, dG, dhp, dcp, dvis, whT;
   size_t sync;                     // persistent recurrence barrier words
+  size_t wT;                       // one unit's weights reordered for its data gradient
   size_t total;
 };
 
@@ -273,6 +274,9 @@ WsLayout plan(const ppo_net* n, int F, int nb, bool learn) {
     w.dvis = A.take((size_t)F * d.vis_hidden * f4);
     w.whT = A.take((size_t)4 * H * H * f4);
     w.sync = A.take(kLstmSyncBytes);
+    size_t wt_max = 0;
+    for (const Unit& u : n->units) wt_max = std::max(wt_max, (size_t)u.Cout * u.K * u.K * u.Cin);
+    w.wT = A.take(wt_max * f4);
   }
   w.total = A.off;
   return w;
@@ -387,7 +391,7 @@ void unit_bwd(const Ctx& c, int ui, const float* dout, const float* mask_out, bo
                   c.s);
   if (dx) {
     const long M = (long)c.F * u.Hin * u.Win, K = (long)u.K * u.K * u.Cout;
-    gemm_conv_dgrad(n->prec, g, du, c.wt(u.w), epi(dx, u.Cin, nullptr, 0, dx_acc ? 1 : 0),
+    gemm_conv_dgrad(n->prec, g, du, c.wt(u.w), c.at<void>(c.w->wT), epi(dx, u.Cin, nullptr, 0, dx_acc ? 1 : 0),
                     kSplitKBytes, c.splitk(), c.s);
   }
 }
@@ -424,7 +428,7 @@ void encoder_bwd(const Ctx& c, const float* dfeat) {
       // projection shortcut: writes dX, then c1's data gradient accumulates
       unit_bwd(c, b.ds, GR, nullptr, false, xin, GD, GB, false, nullptr);
       const long M = (long)c.F * u1.Hin * u1.Win;
-      gemm_conv_dgrad(n->prec, g1, GU, c.wt(u1.w), epi(GB, u1.Cin, nullptr, 0, 1),
+      gemm_conv_dgrad(n->prec, g1, GU, c.wt(u1.w), c.at<void>(w.wT), epi(GB, u1.Cin, nullptr, 0, 1),
                       kSplitKBytes, c.splitk(), c.s);
     } else {
       unit_bwd(c, b.c1, GD, c.at(w.a[b.c1]), false, xin, GU, GB, true, nullptr);
@@ -846,7 +850,7 @@ ppo_status ppo_bench_unit_gemm(ppo_net* net, int op, int unit, int frames, const
     if (op == 0)
       gemm_conv_fwd(net->prec, g, X, c.wt(u.w), epi(OUT, u.Cout), kSplitKBytes, c.splitk(), s);
     else if (op == 1)
-      gemm_conv_dgrad(net->prec, g, DY, c.wt(u.w), epi(OUT, u.Cin), kSplitKBytes, c.splitk(), s);
+      gemm_conv_dgrad(net->prec, g, DY, c.wt(u.w), c.at<void>(w.wT), epi(OUT, u.Cin), kSplitKBytes, c.splitk(), s);
     else
       gemm_conv_wgrad(net->prec, g, X, DY, epi(grad + u.w, u.K * u.K * u.Cin), kSplitKBytes, c.splitk(), s);
   }

@@ -117,43 +117,49 @@ struct ConvFwdProb {
   }
 };
 
-// Data gradient: A(m = (b,hi,wi), k = (kh,kw,co)) = dy[b][(hi+p-kh)/s][(wi+p-kw)/s][co]
-// when the division is exact and in range; B(n = ci, k) = w[co][kh][kw][ci]
-// (B is contiguous along n: lanes walk n, 8 strided loads per chunk).
+// Data gradient over one class of input pixels: rows m = (b, hq, wq) are
+// the pixels hi = step*hq + rh, wi = step*wq + rw (step 1: every pixel;
+// step 2: one of the four parity classes of a stride-2 convolution), and k =
+// (tap t of the class, co) with kh = kh0 + step*(t / nkw), kw = kw0 +
+// step*(t % nkw), the only taps for which (hi + pad - kh) / stride is exact.
+// A(m, k) = dy[b][(hi+pad-kh)/s][(wi+pad-kw)/s][co] (0 outside the output);
+// B(n = ci, k) = wt[ci][kh*KW + kw][co] (weights reordered so B rows are
+// contiguous along k).
 template <typename TW>
 struct ConvDgradProb {
   ConvGeo g;
-  FastDiv dCo, dKW, dHW, dW;
+  FastDiv dCo, dNkw, dHqWq, dWq;
   const float* dy;
-  const TW* w;
-  int M, N, K;  // M = B*H*W, N = C, K = KH*KW*Co
+  const TW* wt;
+  int M, N, K;  // M = B*Hq*Wq, N = C, K = nkh*nkw*Co
+  int step, rh, rw, kh0, kw0, nkw, Wq;
   struct RA {
     int off, th, tw, ok;
   };
   struct RB {
-    int n, ok;
+    const TW* p;
+    int ok;
   };
   DEV RA rowA(int m) const {
     RA r{0, 0, 0, m < M};
     if (r.ok) {
-      const int b = dHW.div(m), q = m - b * g.H * g.W;
-      const int hi = dW.div(q), wi = q - hi * g.W;
+      const int b = dHqWq.div(m), q = m - b * (M / g.B);
+      const int hq = dWq.div(q), wq = q - hq * Wq;
       r.off = b * g.Ho * g.Wo * g.Co;
-      r.th = hi + g.pad;
-      r.tw = wi + g.pad;
+      r.th = step * hq + rh + g.pad;
+      r.tw = step * wq + rw + g.pad;
     }
     return r;
   }
-  DEV RB rowB(int n) const { return RB{n, n < N}; }
-  DEV bool src(const RA& r, int kh, int kw, int& pix) const {
+  DEV RB rowB(int n) const { return RB{wt + (size_t)n * g.KH * g.KW * g.Co, n < N}; }
+  // tap t -> (kh, kw) and the source output pixel; false outside the output
+  DEV bool src(const RA& r, int t, int& tap, int& pix) const {
+    const int ih = dNkw.div(t), iw = t - ih * nkw;
+    const int kh = kh0 + step * ih, kw = kw0 + step * iw;
+    tap = kh * g.KW + kw;
     const int th = r.th - kh, tw = r.tw - kw;
     if (th < 0 || tw < 0) return false;
-    int ho = th, wo = tw;
-    if (g.stride == 2) {
-      if ((th | tw) & 1) return false;
-      ho >>= 1;
-      wo >>= 1;
-    }
+    const int ho = g.stride == 2 ? th >> 1 : th, wo = g.stride == 2 ? tw >> 1 : tw;
     if (ho >= g.Ho || wo >= g.Wo) return false;
     pix = ho * g.Wo + wo;
     return true;
@@ -161,10 +167,9 @@ struct ConvDgradProb {
   DEV void a8(const RA& r, int k, float v[8]) const {
     if (!r.ok || k >= K) return zero8(v);
     if ((g.Co & 7) == 0) {
-      const int tap = dCo.div(k), co = k - tap * g.Co;
-      const int kh = dKW.div(tap), kw = tap - kh * g.KW;
-      int pix;
-      if (src(r, kh, kw, pix)) return load8(dy + r.off + (size_t)pix * g.Co + co, v);
+      const int t = dCo.div(k), co = k - t * g.Co;
+      int tap, pix;
+      if (src(r, t, tap, pix)) return load8(dy + r.off + (size_t)pix * g.Co + co, v);
       return zero8(v);
     }
 #pragma unroll
@@ -172,24 +177,33 @@ struct ConvDgradProb {
       const int kk = k + e;
       float val = 0.f;
       if (kk < K) {
-        const int tap = dCo.div(kk), co = kk - tap * g.Co;
-        const int kh = dKW.div(tap), kw = tap - kh * g.KW;
-        int pix;
-        if (src(r, kh, kw, pix)) val = dy[r.off + (size_t)pix * g.Co + co];
+        const int t = dCo.div(kk), co = kk - t * g.Co;
+        int tap, pix;
+        if (src(r, t, tap, pix)) val = dy[r.off + (size_t)pix * g.Co + co];
       }
       v[e] = val;
     }
   }
   DEV void b8(const RB& r, int k, float v[8]) const {
-    if (!r.ok) return zero8(v);
-    const int khw = g.KH * g.KW;
+    if (!r.ok || k >= K) return zero8(v);
+    if ((g.Co & 7) == 0) {
+      const int t = dCo.div(k), co = k - t * g.Co;
+      const int ih = dNkw.div(t), iw = t - ih * nkw;
+      const int tap = (kh0 + step * ih) * g.KW + kw0 + step * iw;
+      const TW* p = r.p + (size_t)tap * g.Co + co;
+      if (aligned16(p)) return load8(p, v);
+#pragma unroll
+      for (int e = 0; e < 8; ++e) v[e] = ldf(p + e);
+      return;
+    }
 #pragma unroll
     for (int e = 0; e < 8; ++e) {
       const int kk = k + e;
       float val = 0.f;
       if (kk < K) {
-        const int tap = dCo.div(kk), co = kk - tap * g.Co;
-        val = ldf(w + ((size_t)co * khw + tap) * g.C + r.n);
+        const int t = dCo.div(kk), co = kk - t * g.Co;
+        const int ih = dNkw.div(t), iw = t - ih * nkw;
+        val = ldf(r.p + (size_t)((kh0 + step * ih) * g.KW + kw0 + step * iw) * g.Co + co);
       }
       v[e] = val;
     }
@@ -292,7 +306,7 @@ struct DenseProb {
 // Is the operand contiguous along rows (so lanes should walk rows)?
 template <class P> struct Layout;
 template <typename TW> struct Layout<ConvFwdProb<TW>> { static constexpr bool A_ROWS = false, B_ROWS = false; };
-template <typename TW> struct Layout<ConvDgradProb<TW>> { static constexpr bool A_ROWS = false, B_ROWS = true; };
+template <typename TW> struct Layout<ConvDgradProb<TW>> { static constexpr bool A_ROWS = false, B_ROWS = false; };
 template <> struct Layout<ConvWgradProb> { static constexpr bool A_ROWS = true, B_ROWS = true; };
 template <typename A_, typename B_, bool TA, bool TB>
 struct Layout<DenseProb<A_, B_, TA, TB>> { static constexpr bool A_ROWS = TA, B_ROWS = TB; };
@@ -491,7 +505,7 @@ __global__ void __launch_bounds__(256) gemm_kernel(Prob p, Epi e, int tiles_n, i
             e.partial[((size_t)blockIdx.y * p.M + m) * p.N + n] = v;
           } else {
             v *= e.alpha;
-            float* cp = e.C + (size_t)m * e.ldc + n;
+            float* cp = e.C + crow(e, m) * e.ldc + n;
             if (e.accumulate) v += *cp;
             if (e.bias) v += e.bias[n];
             if (e.relu) v = fmaxf(v, 0.f);

@@ -3,15 +3,31 @@
 #include "gemm.h"
 #include "kernels.h"
 
+// out = epilogue(sum_z part[z]): a block owns 64 outputs; wavefront w sums the
+// splits z = w (mod 4) with 8 loads in flight, then the 4 partial sums are
+// added in a fixed order (deterministic).
 __global__ void __launch_bounds__(256) splitk_reduce_kernel(const float* __restrict__ part, int splits,
                                                             int M, int N, Epi e) {
+  __shared__ float red[4][64];
   const size_t MN = (size_t)M * N;
-  for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < MN; i += (size_t)gridDim.x * 256) {
-    float v = 0.f;
-    for (int z = 0; z < splits; ++z) v += part[(size_t)z * MN + i];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const size_t i = (size_t)blockIdx.x * 64 + lane;
+  float acc[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+  if (i < MN) {
+    int z = w;
+    for (; z + 28 < splits; z += 32) {
+#pragma unroll
+      for (int q = 0; q < 8; ++q) acc[q] += part[(size_t)(z + 4 * q) * MN + i];
+    }
+    for (; z < splits; z += 4) acc[0] += part[(size_t)z * MN + i];
+  }
+  red[w][lane] = ((acc[0] + acc[1]) + (acc[2] + acc[3])) + ((acc[4] + acc[5]) + (acc[6] + acc[7]));
+  __syncthreads();
+  if (w == 0 && i < MN) {
+    float v = (red[0][lane] + red[1][lane]) + (red[2][lane] + red[3][lane]);
     const int m = (int)(i / N), n = (int)(i - (size_t)m * N);
     v *= e.alpha;
-    float* cp = e.C + (size_t)m * e.ldc + n;
+    float* cp = e.C + crow(e, m) * e.ldc + n;
     if (e.accumulate) v += *cp;
     if (e.bias) v += e.bias[n];
     if (e.relu) v = fmaxf(v, 0.f);
@@ -70,8 +86,8 @@ int launch(const Prob& p, Epi e, int splits, float* partial, hipStream_t s, bool
                      dim3(256), 0, s, p, ek, tiles_n, kps);
   if (splits > 1 && !defer) {
     const size_t MN = (size_t)p.M * p.N;
-    const int nb = (int)std::min<size_t>(2048, (MN + 255) / 256);
-    hipLaunchKernelGGL(splitk_reduce_kernel, dim3(nb), dim3(256), 0, s, partial, splits, p.M, p.N, e);
+    hipLaunchKernelGGL(splitk_reduce_kernel, dim3((unsigned)((MN + 63) / 64)), dim3(256), 0, s, partial, splits,
+                       p.M, p.N, e);
   }
   return splits;
 }
@@ -124,17 +140,76 @@ int gemm_conv_fwd(int prec, const ConvGeo& g, const float* x, const void* w, Epi
   return run<ConvFwdProb<float>, float, false>(p, e, pb, partial, s, 0, defer);
 }
 
-void gemm_conv_dgrad(int prec, const ConvGeo& g, const float* dy, const void* w, Epi e, size_t pb,
-                     float* partial, hipStream_t s) {
-  const int M = g.B * g.H * g.W, N = g.C, K = g.KH * g.KW * g.Co;
-  const FastDiv dCo = fast_div(g.Co), dKW = fast_div(g.KW), dHW = fast_div(g.H * g.W), dW = fast_div(g.W);
-  if (prec == 1) {
-    ConvDgradProb<bf16_t> p{g, dCo, dKW, dHW, dW, dy, (const bf16_t*)w, M, N, K};
-    run_prec(p, e, 1, true, pb, partial, s);
-  } else {
-    ConvDgradProb<float> p{g, dCo, dKW, dHW, dW, dy, (const float*)w, M, N, K};
-    run_prec(p, e, 0, false, pb, partial, s);
+// wt[ci][tap][co] = w[co][tap][ci]
+template <typename T>
+__global__ void __launch_bounds__(256) conv_w_transpose_kernel(const T* __restrict__ w, int Co, int KK, int C,
+                                                                T* __restrict__ wt) {
+  __shared__ T tile[32][33];
+  const int c0 = blockIdx.x * 32, o0 = blockIdx.y * 32, tap = blockIdx.z;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+  for (int y = ty; y < 32; y += 8)
+    if (o0 + y < Co && c0 + tx < C) tile[y][tx] = w[((size_t)(o0 + y) * KK + tap) * C + c0 + tx];
+  __syncthreads();
+  for (int y = ty; y < 32; y += 8)
+    if (c0 + y < C && o0 + tx < Co) wt[((size_t)(c0 + y) * KK + tap) * Co + o0 + tx] = tile[tx][y];
+}
+
+// C rows of one parity class set to zero (a class no tap reaches, e.g. the
+// odd pixels of a 1x1 stride-2 convolution).
+__global__ void __launch_bounds__(256) zero_rows_kernel(Epi e, int M, int N) {
+  const size_t MN = (size_t)M * N;
+  for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < MN; i += (size_t)gridDim.x * 256) {
+    const int m = (int)(i / N), n = (int)(i - (size_t)m * N);
+    e.C[crow(e, m) * e.ldc + n] = 0.f;
   }
+}
+
+void gemm_conv_dgrad(int prec, const ConvGeo& g, const float* dy, const void* w, void* wt, Epi e, size_t pb,
+                     float* partial, hipStream_t s) {
+  const int KK = g.KH * g.KW;
+  const dim3 tg(cdiv(g.C, 32), cdiv(g.Co, 32), KK);
+  if (prec == 1)
+    hipLaunchKernelGGL(conv_w_transpose_kernel<bf16_t>, tg, dim3(256), 0, s, (const bf16_t*)w, g.Co, KK, g.C,
+                       (bf16_t*)wt);
+  else
+    hipLaunchKernelGGL(conv_w_transpose_kernel<float>, tg, dim3(256), 0, s, (const float*)w, g.Co, KK, g.C,
+                       (float*)wt);
+  const int step = g.stride == 2 ? 2 : 1;
+  for (int rh = 0; rh < step; ++rh)
+    for (int rw = 0; rw < step; ++rw) {
+      // taps with (pixel + pad - k) divisible by the stride
+      const int kh0 = (rh + g.pad) % step, kw0 = (rw + g.pad) % step;
+      const int nkh = kh0 < g.KH ? (g.KH - kh0 + step - 1) / step : 0;
+      const int nkw = kw0 < g.KW ? (g.KW - kw0 + step - 1) / step : 0;
+      const int Hq = (g.H - rh + step - 1) / step, Wq = (g.W - rw + step - 1) / step;
+      const int M = g.B * Hq * Wq, N = g.C, K = nkh * nkw * g.Co;
+      Epi ec = e;
+      if (step == 2) {
+        ec.rq = Hq * Wq;
+        ec.rwq = Wq;
+        ec.rs1 = g.H * g.W;
+        ec.rs2 = 2 * g.W;
+        ec.rs3 = 2;
+        ec.r0 = rh * g.W + rw;
+      }
+      if (M <= 0) continue;
+      if (K <= 0) {
+        if (!e.accumulate)
+          hipLaunchKernelGGL(zero_rows_kernel, dim3((unsigned)std::min<size_t>(4096, ((size_t)M * N + 255) / 256)),
+                             dim3(256), 0, s, ec, M, N);
+        continue;
+      }
+      const FastDiv dCo = fast_div(g.Co), dNkw = fast_div(nkw), dHqWq = fast_div(Hq * Wq), dWq = fast_div(Wq);
+      if (prec == 1) {
+        ConvDgradProb<bf16_t> p{g, dCo, dNkw, dHqWq, dWq, dy, (const bf16_t*)wt, M, N, K,
+                                step, rh, rw, kh0, kw0, nkw, Wq};
+        run_prec(p, ec, 1, true, pb, partial, s);
+      } else {
+        ConvDgradProb<float> p{g, dCo, dNkw, dHqWq, dWq, dy, (const float*)wt, M, N, K,
+                               step, rh, rw, kh0, kw0, nkw, Wq};
+        run_prec(p, ec, 0, false, pb, partial, s);
+      }
+    }
 }
 
 void gemm_conv_wgrad(int prec, const ConvGeo& g, const float* x, const float* dy, Epi e, size_t pb,

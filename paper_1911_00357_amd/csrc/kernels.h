@@ -32,6 +32,9 @@ struct ConvGeo {
 };
 
 // GEMM epilogue: C = alpha * acc (+ C if accumulate) (+ bias[n]) (ReLU).
+// Row m of the product is row crow(m) of C: m itself, or (rq > 0) the
+// strided map (m / rq) rs1 + ((m % rq) / rwq) rs2 + (m % rwq) rs3 + r0 used
+// by the stride-2 data gradient's parity classes.
 struct Epi {
   float* C;
   int ldc;
@@ -40,10 +43,17 @@ struct Epi {
   int relu;
   int accumulate;
   float* partial;  // set by the launcher for split-K
+  int rq, rwq, rs1, rs2, rs3, r0;
 };
 
 inline Epi epi(float* C, int ldc, const float* bias = nullptr, int relu = 0, int accumulate = 0) {
-  return Epi{C, ldc, bias, 1.0f, relu, accumulate, nullptr};
+  return Epi{C, ldc, bias, 1.0f, relu, accumulate, nullptr, 0, 1, 0, 0, 0, 0};
+}
+
+__device__ __forceinline__ size_t crow(const Epi& e, int m) {
+  if (e.rq <= 0) return (size_t)m;
+  const int b = m / e.rq, q = m - b * e.rq, h = q / e.rwq, w = q - h * e.rwq;
+  return (size_t)b * e.rs1 + (size_t)h * e.rs2 + (size_t)w * e.rs3 + e.r0;
 }
 
 constexpr int kMaxMbEnvs = 256;
@@ -60,7 +70,9 @@ int gemm_max_splits_for(long M, long N, long K, int prec);
 // launch); returns the split count
 int gemm_conv_fwd(int prec, const ConvGeo& g, const float* x, const void* w, Epi e, size_t pb,
                   float* partial, hipStream_t s, bool defer = false);
-void gemm_conv_dgrad(int prec, const ConvGeo& g, const float* dy, const void* w, Epi e, size_t pb,
+// wt: scratch for the weights reordered to [C][KH*KW][Co] (C*KH*KW*Co elements
+// of the operand type).
+void gemm_conv_dgrad(int prec, const ConvGeo& g, const float* dy, const void* w, void* wt, Epi e, size_t pb,
                      float* partial, hipStream_t s);
 void gemm_conv_wgrad(int prec, const ConvGeo& g, const float* x, const float* dy, Epi e, size_t pb,
                      float* partial, hipStream_t s);
