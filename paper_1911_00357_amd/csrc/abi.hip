@@ -304,6 +304,17 @@ struct Ctx {
   bool keep_u = true;  // store convolution outputs for a backward pass
 };
 
+// GroupNorm of a unit in the one-launch form (a workgroup per image and group,
+// best when frames are few) or the coalesced partial / finalize / apply form
+// (best for large tensors); the element count threshold can be tuned with
+// DDPPO_GN_FUSED_MAX.
+bool gn_one_launch(const Ctx& c, const Unit& u) {
+  const char* e = getenv("DDPPO_GN_FUSED_MAX");
+  const long limit = e ? atol(e) : (long)(4 << 20);
+  const int P = u.Hout * u.Wout, G = c.n->d.gn_groups;
+  return gn_fused_npt(P, u.Cout / G) && (long)c.F * P * u.Cout <= limit;
+}
+
 ConvGeo geo(const Unit& u, int F) {
   return ConvGeo{F, u.Hin, u.Win, u.Cin, u.Hout, u.Wout, u.Cout, u.K, u.K, u.stride, u.pad};
 }
@@ -313,7 +324,7 @@ void unit_fwd(const Ctx& c, int ui, const float* x, const float* res, bool relu,
   const Unit& u = c.n->units[ui];
   const ConvGeo g = geo(u, c.F);
   const int P = u.Hout * u.Wout, G = c.n->d.gn_groups;
-  if (gn_fused_npt(P, u.Cout / G)) {
+  if (gn_one_launch(c, u)) {
     // conv (split-K partials left in place) -> one fused GroupNorm launch
     float* y = c.at(c.w->u[ui]);
     const int splits = gemm_conv_fwd(c.n->prec, g, x, c.wt(u.w), epi(y, u.Cout), kSplitKBytes, c.splitk(), c.s,
@@ -369,7 +380,7 @@ const float* encoder_fwd(const Ctx& c) {
 void gn_bwd(const Ctx& c, int ui, const float* dout, const float* mask_out, bool chw, float* du, float* dres) {
   const Unit& u = c.n->units[ui];
   const int P = u.Hout * u.Wout, G = c.n->d.gn_groups;
-  if (gn_fused_npt(P, u.Cout / G)) {
+  if (gn_one_launch(c, u)) {
     launch_gnb_fused(dout, mask_out, chw ? 1 : 0, c.at(c.w->u[ui]), c.F, P, u.Cout, G, c.at<float2>(c.w->st[ui]),
                      c.pf(u.g), du, dres, c.grad + u.g, c.grad + u.b, c.at<float2>(c.w->gbpart), c.s);
     return;

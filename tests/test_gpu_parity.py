@@ -300,3 +300,13 @@ def test_loss_backward_resnet_paper_shape(P, dtype):
     g, s, g_ref, s_ref, floor = _loss_case(P, C1.net, dtype, 4, 3, [2, 0], [4, 2, 3], seed=21,
                                            same_decisions=True)
     check_loss(C1.net, dtype, g, s, g_ref, s_ref, "resnet", floor)
+
+
+@pytest.mark.parametrize("limit", ["0", "1000000000"], ids=["partial_finalize_apply", "one_launch"])
+def test_loss_backward_both_groupnorm_forms(P, limit, monkeypatch):
+    """Both GroupNorm forms (per image-and-group launch; coalesced partial /
+    finalize / apply) against the oracle on the same case."""
+    monkeypatch.setenv("DDPPO_GN_FUSED_MAX", limit)
+    say(f"loss f32 mini_resnet, GroupNorm form limit {limit}")
+    g, s, g_ref, s_ref, _ = _loss_case(P, MINI_RESNET, "f32", 5, 3, [2, 1, 0], [5, 3, 4], seed=38)
+    check_loss(MINI_RESNET, "f32", g, s, g_ref, s_ref, f"mini_resnet gn limit {limit}")
