@@ -69,7 +69,9 @@ def _update(w, env, parts, lengths):
         w.update(env, parts, lengths)
 
 
-def run_gpu(wl, steps, warmup, seed):
+def run_gpu(wl, steps, warmup, seed, timer=None):
+    """timer: (unit, op) whose GEMM kernel launches are timed with HIP events
+    over the timed region."""
     import torch
     from paper_1911_00357_amd.worker import PPOHyper, Worker
     from synth import rollout as R
@@ -90,6 +92,8 @@ def run_gpu(wl, steps, warmup, seed):
         lengths = None if not wl.ragged else lens
         if i == warmup:
             torch.cuda.synchronize()
+            if timer is not None:
+                w.net.gemm_timer_arm(timer[0], timer[1])
             ev[0].record()
             t_start = time.perf_counter()
         w.collect(env, lengths, graph=GRAPH)
@@ -100,7 +104,11 @@ def run_gpu(wl, steps, warmup, seed):
     torch.cuda.synchronize()
     wall = time.perf_counter() - t_start
     gpu_ms = ev[0].elapsed_time(ev[1])
-    return {"frames": sum(frames), "wall_s": wall, "gpu_ms": gpu_ms, "worker": w}
+    timed = None
+    if timer is not None:
+        timed = w.net.gemm_timer_read()
+        w.net.gemm_timer_arm(-1, 0)
+    return {"frames": sum(frames), "wall_s": wall, "gpu_ms": gpu_ms, "worker": w, "timed": timed}
 
 
 def act_update_split(wl, seed):
@@ -205,12 +213,14 @@ def cpu_baseline(wl, seed):
                       f"{wl.ppo.minibatches} minibatch updates, {frames} frames, {dt:.1f} s"}
 
 
-def roofline(wl, seed, reps=10):
-    """The dominant kernel launch of the learner: every trunk unit's
-    convolution GEMM (forward, data gradient, weight gradient) at the
-    learner's minibatch size, each timed with HIP events on the stream it is
-    launched on; the slowest launch is reported against the MFMA peak of its
-    operand type (algorithmic FLOPs 2*M*N*K per launch)."""
+OPS = ["conv forward", "conv data gradient", "conv weight gradient"]
+
+
+def dominant_gemm(wl, seed, reps=5):
+    """The learner's slowest convolution GEMM launch: every trunk unit's
+    forward, data-gradient and weight-gradient GEMM at the learner's
+    minibatch size, timed with HIP events (selection only).  Returns
+    (unit, op, name, per-launch ms table summary)."""
     import torch
     import paper_1911_00357_amd as P
     from paper_1911_00357_amd._lib import PPO_OP_LEARN
@@ -229,22 +239,36 @@ def roofline(wl, seed, reps=10):
         for op in (0, 1, 2):
             if op == 1 and u == 0:
                 continue              # the first convolution needs no data gradient
-            n.bench_unit_gemm(op, u, F, params, lp, grad, 2)
+            n.bench_unit_gemm(op, u, F, params, lp, grad, 1)
             ev[0].record()
             fl = n.bench_unit_gemm(op, u, F, params, lp, grad, reps)
             ev[1].record()
             torch.cuda.synchronize()
-            rows.append((ev[0].elapsed_time(ev[1]) / reps, fl, name, op))
-    t_ms, fl, name, op = max(rows)
-    peak = PEAK_BF16_TFLOPS if wl.dtype == "bf16" else PEAK_FP32_TFLOPS
-    ach = fl / (t_ms / 1e3) / 1e12
+            rows.append((ev[0].elapsed_time(ev[1]) / reps, fl, name, op, u))
+    t_ms, fl, name, op, u = max(rows)
     tot_t = sum(r[0] for r in rows)
     tot_f = sum(r[1] for r in rows)
+    del n, params, lp, grad
+    torch.cuda.empty_cache()
+    return u, op, name, round(tot_f / (tot_t / 1e3) / 1e12, 3)
+
+
+def roofline_live(wl, sel, timed):
+    """Roofline entry of the dominant GEMM kernel from its launches inside the
+    timed steps (HIP events on the learner's stream around the kernel
+    itself): achieved = summed 2*M*N*K / summed duration."""
+    u, op, name, all_tf = sel
+    launches, ms, fl = timed
+    peak = PEAK_BF16_TFLOPS if wl.dtype == "bf16" else PEAK_FP32_TFLOPS
+    if launches == 0 or ms <= 0:
+        return {"bound": "mfma", "achieved": None, "peak": peak, "unit": "TFLOP/s", "frac": None,
+                "traffic": None, "kernel": f"{OPS[op]} GEMM of {name}"}
+    ach = fl / (ms / 1e3) / 1e12
     return {"bound": "mfma", "achieved": round(ach, 3), "peak": peak, "unit": "TFLOP/s",
             "frac": round(ach / peak, 5), "traffic": None,
-            "kernel": f"{['conv forward', 'conv data gradient', 'conv weight gradient'][op]} GEMM of {name}",
-            "frames": F, "avg_launch_us": round(t_ms * 1e3, 2), "flops_per_launch": fl,
-            "all_conv_gemms_tflops": round(tot_f / (tot_t / 1e3) / 1e12, 3)}
+            "kernel": f"{OPS[op]} GEMM of {name}", "launches": launches,
+            "avg_launch_us": round(ms / launches * 1e3, 2), "flops_per_launch": fl / launches,
+            "all_conv_gemms_tflops_microbench": all_tf}
 
 
 def flops_per_frame(net):
@@ -295,7 +319,9 @@ def main():
         sys.exit(1)
     from synth.configs import WORKLOADS
     wl = WORKLOADS[a.workload]
-    res = run_gpu(wl, a.steps, a.warmup, a.seed)
+    sel = dominant_gemm(wl, a.seed)
+    res = run_gpu(wl, a.steps, a.warmup, a.seed, timer=sel[:2])
+    roof = roofline_live(wl, sel, res["timed"])
     fps = res["frames"] / (res["gpu_ms"] / 1e3)
     ms_step = res["gpu_ms"] / a.steps
     frames_step = res["frames"] / a.steps
@@ -336,8 +362,7 @@ def main():
         out["unpacked_update_frames_per_s"] = round(ufr / (uu / 1e3), 1)
         out["packed_speedup_act"] = round(out["act_frames_per_s"] / out["unpacked_act_frames_per_s"], 3)
         out["packed_speedup_update"] = round(out["update_frames_per_s"] / out["unpacked_update_frames_per_s"], 3)
-    torch.cuda.empty_cache()
-    out["roofline"] = roofline(wl, a.seed)
+    out["roofline"] = roof
     if not a.no_cpu:
         out["cpu_baseline"] = cpu_baseline(wl, a.seed)
     print(json.dumps(out), flush=True)

@@ -284,6 +284,18 @@ ppo_status ppo_bench_unit_gemm(ppo_net* net, int op, int unit, int frames, const
                                const void* params_lp, float* grad, void* ws, size_t ws_bytes, int reps,
                                double* flops, void* stream);
 
+/* Benchmark aid: time the GEMM kernel launches of trunk unit `unit`, op (0
+ * forward, 1 data gradient, 2 weight gradient) inside later library calls on
+ * this net, e.g. ppo_loss_backward.  Events are recorded on the call's stream
+ * around each GEMM kernel itself (a split-K reduction that follows it is not
+ * included), for at most max_launches launches, never inside stream capture.
+ * unit < 0 disarms and frees the events.  Not thread-safe with other calls
+ * on the same net. */
+ppo_status ppo_gemm_timer_arm(ppo_net* net, int unit, int op, int max_launches);
+/* Waits for the recorded launches and returns their count, summed duration
+ * (ms) and summed 2*M*N*K; then starts a new count (still armed). */
+ppo_status ppo_gemm_timer_read(ppo_net* net, int* launches, double* total_ms, double* flops);
+
 /* dst[i] = bfloat16(src[i]) (round to nearest even) for the initial working
  * copy of the parameters; later copies come from ppo_adam_step.  src [n]
  * float32, dst [n] bfloat16, both device. */

@@ -139,6 +139,17 @@ class Net:
               "ppo_bench_unit_gemm")
         return fl.value
 
+    def gemm_timer_arm(self, unit: int, op: int, max_launches: int = 4096):
+        """Time the GEMM kernel launches of one trunk unit and op in later calls
+        (benchmark aid; unit < 0 disarms)."""
+        check(lib().ppo_gemm_timer_arm(self._h, unit, op, max_launches), "ppo_gemm_timer_arm")
+
+    def gemm_timer_read(self):
+        """(launches, summed ms, summed 2*M*N*K) since the last read."""
+        n, ms, fl = C.c_int(), C.c_double(), C.c_double()
+        check(lib().ppo_gemm_timer_read(self._h, C.byref(n), C.byref(ms), C.byref(fl)), "ppo_gemm_timer_read")
+        return n.value, ms.value, fl.value
+
     def last_workspace(self, op: int):
         return self._ws.get((op, "cuda:0")) if self._ws else None
 

@@ -68,6 +68,10 @@ struct ppo_net {
   size_t max_unit = 0;        // largest conv output per frame
   size_t gn_part = 0;         // largest S*C per frame
   int max_G = 0;
+  // GEMM launch timer (benchmark aid, ppo_gemm_timer_arm)
+  mutable int timer_unit = -1, timer_op = -1;
+  mutable std::vector<hipEvent_t> timer_ev;
+  mutable GemmTimer timer{};
 };
 
 namespace {
@@ -315,6 +319,15 @@ bool gn_one_launch(const Ctx& c, const Unit& u) {
   return gn_fused_npt(P, u.Cout / G) && (long)c.F * P * u.Cout <= limit;
 }
 
+// Arms the launch timer for the duration of one unit GEMM call when that
+// (unit, op) was selected with ppo_gemm_timer_arm.
+struct TimerScope {
+  TimerScope(const ppo_net* n, int ui, int op) {
+    if (n->timer_unit == ui && n->timer_op == op && n->timer.cap > 0) g_gemm_timer = &n->timer;
+  }
+  ~TimerScope() { g_gemm_timer = nullptr; }
+};
+
 ConvGeo geo(const Unit& u, int F) {
   return ConvGeo{F, u.Hin, u.Win, u.Cin, u.Hout, u.Wout, u.Cout, u.K, u.K, u.stride, u.pad};
 }
@@ -327,15 +340,21 @@ void unit_fwd(const Ctx& c, int ui, const float* x, const float* res, bool relu,
   if (gn_one_launch(c, u)) {
     // conv (split-K partials left in place) -> one fused GroupNorm launch
     float* y = c.at(c.w->u[ui]);
-    const int splits = gemm_conv_fwd(c.n->prec, g, x, c.wt(u.w), epi(y, u.Cout), kSplitKBytes, c.splitk(), c.s,
-                                     true);
+    int splits;
+    {
+      TimerScope ts(c.n, ui, 0);
+      splits = gemm_conv_fwd(c.n->prec, g, x, c.wt(u.w), epi(y, u.Cout), kSplitKBytes, c.splitk(), c.s, true);
+    }
     const float* src = splits > 1 ? c.splitk() : y;
     launch_gn_fused(src, splits, (size_t)c.F * P * u.Cout, (splits > 1 && c.keep_u) ? y : nullptr, c.F, P,
                     u.Cout, G, kGnEps, c.pf(u.g), c.pf(u.b), res, relu ? 1 : 0, out, chw ? 1 : 0,
                     c.at<float2>(c.w->st[ui]), c.s);
     return;
   }
-  gemm_conv_fwd(c.n->prec, g, x, c.wt(u.w), epi(c.at(c.w->u[ui]), u.Cout), kSplitKBytes, c.splitk(), c.s);
+  {
+    TimerScope ts(c.n, ui, 0);
+    gemm_conv_fwd(c.n->prec, g, x, c.wt(u.w), epi(c.at(c.w->u[ui]), u.Cout), kSplitKBytes, c.splitk(), c.s);
+  }
   launch_gn_forward(c.at(c.w->u[ui]), c.F, u.Hout * u.Wout, u.Cout, c.n->d.gn_groups, kGnEps, c.pf(u.g),
                     c.pf(u.b), res, relu ? 1 : 0, out, chw ? 1 : 0, c.at<float2>(c.w->st[ui]),
                     c.at<float4>(c.w->gpart), u.S, c.s);
@@ -397,11 +416,13 @@ void unit_bwd(const Ctx& c, int ui, const float* dout, const float* mask_out, bo
   const int P = u.Hout * u.Wout;
   gn_bwd(c, ui, dout, mask_out, chw, du, dres);
   const ConvGeo g = geo(u, c.F);
-  const long R = (long)c.F * P, Kw = (long)u.K * u.K * u.Cin;
-  gemm_conv_wgrad(n->prec, g, x, du, epi(c.grad + u.w, (int)Kw), kSplitKBytes, c.splitk(),
-                  c.s);
+  const long Kw = (long)u.K * u.K * u.Cin;
+  {
+    TimerScope ts(n, ui, 2);
+    gemm_conv_wgrad(n->prec, g, x, du, epi(c.grad + u.w, (int)Kw), kSplitKBytes, c.splitk(), c.s);
+  }
   if (dx) {
-    const long M = (long)c.F * u.Hin * u.Win, K = (long)u.K * u.K * u.Cout;
+    TimerScope ts(n, ui, 1);
     gemm_conv_dgrad(n->prec, g, du, c.wt(u.w), c.at<void>(c.w->wT), epi(dx, u.Cin, nullptr, 0, dx_acc ? 1 : 0),
                     kSplitKBytes, c.splitk(), c.s);
   }
@@ -431,14 +452,16 @@ void encoder_bwd(const Ctx& c, const float* dfeat) {
     if (b.ds >= 0) {
       // c1 first (its du must not be overwritten before its data gradient)
       const Unit& u1 = n->units[b.c1];
-      const int P1 = u1.Hout * u1.Wout;
       gn_bwd(c, b.c1, GD, c.at(w.a[b.c1]), false, GU, nullptr);
       const ConvGeo g1 = geo(u1, c.F);
-      const long R1 = (long)c.F * P1, K1 = (long)u1.Cin;
-      gemm_conv_wgrad(n->prec, g1, xin, GU, epi(c.grad + u1.w, (int)K1), kSplitKBytes, c.splitk(), c.s);
+      const long K1 = (long)u1.Cin;
+      {
+        TimerScope ts(n, b.c1, 2);
+        gemm_conv_wgrad(n->prec, g1, xin, GU, epi(c.grad + u1.w, (int)K1), kSplitKBytes, c.splitk(), c.s);
+      }
       // projection shortcut: writes dX, then c1's data gradient accumulates
       unit_bwd(c, b.ds, GR, nullptr, false, xin, GD, GB, false, nullptr);
-      const long M = (long)c.F * u1.Hin * u1.Win;
+      TimerScope ts(n, b.c1, 1);
       gemm_conv_dgrad(n->prec, g1, GU, c.wt(u1.w), c.at<void>(w.wT), epi(GB, u1.Cin, nullptr, 0, 1),
                       kSplitKBytes, c.splitk(), c.s);
     } else {
@@ -484,7 +507,12 @@ ppo_status ppo_net_create(const ppo_net_desc* desc, ppo_net** out) {
   return PPO_OK;
 }
 
-void ppo_net_destroy(ppo_net* net) { delete net; }
+void ppo_net_destroy(ppo_net* net) {
+  if (!net) return;
+  for (hipEvent_t e : net->timer_ev)
+    if (e) (void)hipEventDestroy(e);
+  delete net;
+}
 
 size_t ppo_param_count(const ppo_net* net) { return net ? net->P : 0; }
 
@@ -866,6 +894,46 @@ ppo_status ppo_bench_unit_gemm(ppo_net* net, int op, int unit, int frames, const
       gemm_conv_wgrad(net->prec, g, X, DY, epi(grad + u.w, u.K * u.K * u.Cin), kSplitKBytes, c.splitk(), s);
   }
   return check_launch();
+}
+
+ppo_status ppo_gemm_timer_arm(ppo_net* net, int unit, int op, int max_launches) {
+  if (!net) return fail(PPO_EINVAL, "null argument");
+  for (hipEvent_t e : net->timer_ev)
+    if (e) (void)hipEventDestroy(e);
+  net->timer_ev.clear();
+  net->timer = GemmTimer{};
+  net->timer_unit = net->timer_op = -1;
+  if (unit < 0) return PPO_OK;
+  if (unit >= (int)net->units.size() || op < 0 || op > 2 || max_launches <= 0 || max_launches > (1 << 16))
+    return fail(PPO_EINVAL, "bad unit / op / max_launches");
+  net->timer_ev.resize(2 * (size_t)max_launches);
+  for (hipEvent_t& e : net->timer_ev)
+    if (hipEventCreate(&e) != hipSuccess) {
+      e = nullptr;
+      return fail(PPO_EDEVICE, "hipEventCreate failed");
+    }
+  net->timer = GemmTimer{net->timer_ev.data(), net->timer_ev.data() + max_launches, max_launches, 0, 0.0};
+  net->timer_unit = unit;
+  net->timer_op = op;
+  return PPO_OK;
+}
+
+ppo_status ppo_gemm_timer_read(ppo_net* net, int* launches, double* total_ms, double* flops) {
+  if (!net || !launches || !total_ms || !flops) return fail(PPO_EINVAL, "null argument");
+  double t = 0.0;
+  for (int i = 0; i < net->timer.n; ++i) {
+    float ms = 0.f;
+    if (hipEventSynchronize(net->timer.end[i]) != hipSuccess ||
+        hipEventElapsedTime(&ms, net->timer.start[i], net->timer.end[i]) != hipSuccess)
+      return fail(PPO_EDEVICE, "timer event query failed");
+    t += ms;
+  }
+  *launches = net->timer.n;
+  *total_ms = t;
+  *flops = net->timer.flops;
+  net->timer.n = 0;
+  net->timer.flops = 0.0;
+  return PPO_OK;
 }
 
 ppo_status ppo_workspace_probe(const ppo_net* net, int op, int max_frames, int max_envs, int kind,

@@ -35,9 +35,19 @@ __global__ void __launch_bounds__(256) splitk_reduce_kernel(const float* __restr
   }
 }
 
+thread_local GemmTimer* g_gemm_timer = nullptr;
+
 namespace {
 
 constexpr int BK = 32;
+
+GemmTimer* active_timer(hipStream_t s) {
+  GemmTimer* t = g_gemm_timer;
+  if (!t || t->n >= t->cap) return nullptr;
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(s, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) return nullptr;
+  return t;
+}
 
 enum Tile { T128x128, T128x64, T64x128, T64x64, T128x32, T32x128 };
 
@@ -82,8 +92,15 @@ int launch(const Prob& p, Epi e, int splits, float* partial, hipStream_t s, bool
   splits = std::max(1, cdiv(p.K, kps));
   Epi ek = e;
   ek.partial = splits > 1 ? partial : nullptr;
+  GemmTimer* tm = active_timer(s);
+  if (tm) hipEventRecord(tm->start[tm->n], s);
   hipLaunchKernelGGL((gemm_kernel<Prob, TC, BM, BN, WGM, WGN, SPLIT>), dim3(tiles_m * tiles_n, splits),
                      dim3(256), 0, s, p, ek, tiles_n, kps);
+  if (tm) {
+    hipEventRecord(tm->end[tm->n], s);
+    ++tm->n;
+    tm->flops += 2.0 * p.M * p.N * p.K;
+  }
   if (splits > 1 && !defer) {
     const size_t MN = (size_t)p.M * p.N;
     hipLaunchKernelGGL(splitk_reduce_kernel, dim3((unsigned)((MN + 63) / 64)), dim3(256), 0, s, partial, splits,

@@ -63,6 +63,18 @@ struct MapArgs {
   int len[kMaxMbEnvs];
 };
 
+// Benchmark aid: while g_gemm_timer is set, each GEMM launcher records
+// start[n] / end[n] on its stream around the GEMM kernel itself (not the
+// split-K reduction) and adds the launch's 2*M*N*K to flops, up to cap
+// launches (never while the stream is being captured).
+struct GemmTimer {
+  hipEvent_t* start;
+  hipEvent_t* end;
+  int cap, n;
+  double flops;
+};
+extern thread_local GemmTimer* g_gemm_timer;
+
 // gemm.hip (prec: 0 float32 operands, 1 bfloat16 operands)
 int gemm_max_splits_for(long M, long N, long K, int prec);
 // pb: bytes of `partial` available for split-K partial tiles
