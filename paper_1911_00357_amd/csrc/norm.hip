@@ -540,11 +540,11 @@ __global__ void __launch_bounds__(NT) gnb_fused_kernel(const float* __restrict__
 }
 
 // Elements per thread (1..32) of the fused kernels, 0 when unsupported; the
-// block has 256 threads up to 2048 elements per (image, group), else 1024.
+// block has 256 threads up to 512 elements per (image, group), else 1024.
 int gn_fused_npt(int P, int Cg) {
   const int n = P * Cg;
   if (256 % Cg) return 0;
-  const int nt = n <= 256 * 8 ? 256 : 1024;
+  const int nt = n <= 256 * 2 ? 256 : 1024;
   for (int k = 1; k <= 32; k *= 2)
     if (n <= nt * k) return k;
   return 0;
@@ -572,7 +572,7 @@ int gn_fused_npt(int P, int Cg) {
 void launch_gn_fused(const float* src, int nsplit, size_t zstride, float* u_out, int B, int P, int C, int G,
                      float eps, const float* gamma, const float* beta, const float* res, int relu, float* out,
                      int out_chw, float2* stats, hipStream_t s) {
-  const int npt = gn_fused_npt(P, C / G), nt = (long)P * (C / G) <= 256 * 8 ? 256 : 1024;
+  const int npt = gn_fused_npt(P, C / G), nt = (long)P * (C / G) <= 256 * 2 ? 256 : 1024;
 #define GN_CALL(K, T)                                                                                        \
   hipLaunchKernelGGL((gn_fused_kernel<K, T>), dim3(B * G), dim3(T), 0, s, src, nsplit, zstride, u_out, P, C, \
                      G, eps, gamma, beta, res, relu, out, out_chw, stats)
@@ -583,7 +583,7 @@ void launch_gn_fused(const float* src, int nsplit, size_t zstride, float* u_out,
 void launch_gnb_fused(const float* dout, const float* outm, int chw, const float* y, int B, int P, int C, int G,
                       const float2* stats, const float* gamma, float* dy, float* dres, float* dgamma,
                       float* dbeta, float2* bpart, hipStream_t s) {
-  const int npt = gn_fused_npt(P, C / G), nt = (long)P * (C / G) <= 256 * 8 ? 256 : 1024;
+  const int npt = gn_fused_npt(P, C / G), nt = (long)P * (C / G) <= 256 * 2 ? 256 : 1024;
 #define GNB_CALL(K, T)                                                                                       \
   hipLaunchKernelGGL((gnb_fused_kernel<K, T>), dim3(B * G), dim3(T), 0, s, dout, outm, chw, y, P, C, G, stats, \
                      gamma, dy, dres, bpart)
