@@ -267,6 +267,61 @@ struct ConvWgradProb {
   }
 };
 
+// Weight gradient with channel-vector chunks: a chunk is the 8 consecutive
+// rows m..m+7 (output channels co for A, (kh,kw,ci) for B) at one reduction
+// index r = (b,ho,wo), read as two float4 along the NHWC channel axis and
+// written transposed into the k-contiguous LDS rows.  Needs Co % 8 == 0 and
+// C % 4 == 0 (a B chunk spans one tap when C % 8 == 0, else two taps of 4).
+struct ConvWgradRTProb {
+  ConvGeo g;
+  FastDiv dHoWo, dWo;
+  const float* x;
+  const float* dy;
+  int M, N, K;  // M = Co, N = KH*KW*C, K = B*Ho*Wo
+  struct RA {
+    int co, ok;
+  };
+  struct RB {
+    int kh0, kw0, ci0, kh1, kw1, ci1, nv;  // taps of rows n..n+3 and n+4..n+7; valid rows
+  };
+  DEV RA rowA(int m) const { return RA{m, m < M}; }
+  DEV RB rowB(int n) const {
+    RB r{0, 0, 0, 0, 0, 0, max(0, min(8, N - n))};
+    const int t0 = n / g.C, t1 = (n + 4) / g.C;
+    r.ci0 = n - t0 * g.C;
+    r.kh0 = t0 / g.KW;
+    r.kw0 = t0 - r.kh0 * g.KW;
+    r.ci1 = n + 4 - t1 * g.C;
+    r.kh1 = t1 / g.KW;
+    r.kw1 = t1 - r.kh1 * g.KW;
+    return r;
+  }
+  DEV void a8(const RA& r, int k, float v[8]) const {
+    if (!r.ok || k >= K) return zero8(v);
+    load8(dy + (size_t)k * g.Co + r.co, v);
+  }
+  DEV void b8(const RB& r, int k, float v[8]) const {
+    if (r.nv <= 0 || k >= K) return zero8(v);
+    const int b = dHoWo.div(k), q = k - b * g.Ho * g.Wo;
+    const int ho = dWo.div(q), wo = q - ho * g.Wo;
+    const int hb = ho * g.stride - g.pad, wb = wo * g.stride - g.pad;
+    const float* xb = x + (size_t)b * g.H * g.W * g.C;
+    auto quad = [&](int kh, int kw, int ci, float* o) {
+      const int hi = hb + kh, wi = wb + kw;
+      if ((unsigned)hi < (unsigned)g.H && (unsigned)wi < (unsigned)g.W) {
+        const float4 t = *(const float4*)(xb + ((size_t)hi * g.W + wi) * g.C + ci);
+        o[0] = t.x; o[1] = t.y; o[2] = t.z; o[3] = t.w;
+      } else {
+        o[0] = o[1] = o[2] = o[3] = 0.f;
+      }
+    };
+    quad(r.kh0, r.kw0, r.ci0, v);
+    if (r.nv > 4) quad(r.kh1, r.kw1, r.ci1, v + 4);
+    else v[4] = v[5] = v[6] = v[7] = 0.f;
+    for (int e = r.nv; e < 4; ++e) v[e] = 0.f;
+  }
+};
+
 // Dense: A(m, k) = a[m*lda + k] (or a[k*lda + m] when TA), B(n, k) = b[n*ldb + k]
 // (or b[k*ldb + n] when TB).
 template <typename TAe, typename TBe, bool TA, bool TB>
@@ -303,13 +358,25 @@ struct DenseProb {
   }
 };
 
-// Is the operand contiguous along rows (so lanes should walk rows)?
+// Is the operand contiguous along rows (so lanes should walk rows)?  RT:
+// chunks are 8 rows at one k (vector loads along rows, transposed LDS writes).
 template <class P> struct Layout;
-template <typename TW> struct Layout<ConvFwdProb<TW>> { static constexpr bool A_ROWS = false, B_ROWS = false; };
-template <typename TW> struct Layout<ConvDgradProb<TW>> { static constexpr bool A_ROWS = false, B_ROWS = false; };
-template <> struct Layout<ConvWgradProb> { static constexpr bool A_ROWS = true, B_ROWS = true; };
+template <> struct Layout<ConvWgradRTProb> {
+  static constexpr bool A_ROWS = false, B_ROWS = false, A_RT = true, B_RT = true;
+};
+template <typename TW> struct Layout<ConvFwdProb<TW>> {
+  static constexpr bool A_ROWS = false, B_ROWS = false, A_RT = false, B_RT = false;
+};
+template <typename TW> struct Layout<ConvDgradProb<TW>> {
+  static constexpr bool A_ROWS = false, B_ROWS = false, A_RT = false, B_RT = false;
+};
+template <> struct Layout<ConvWgradProb> {
+  static constexpr bool A_ROWS = true, B_ROWS = true, A_RT = false, B_RT = false;
+};
 template <typename A_, typename B_, bool TA, bool TB>
-struct Layout<DenseProb<A_, B_, TA, TB>> { static constexpr bool A_ROWS = TA, B_ROWS = TB; };
+struct Layout<DenseProb<A_, B_, TA, TB>> {
+  static constexpr bool A_ROWS = TA, B_ROWS = TB, A_RT = false, B_RT = false;
+};
 
 // ------------------------------------------------------------- MFMA
 template <typename TC>
@@ -381,6 +448,26 @@ DEV void put8(bf16_t* d, const float v[8], bf16_t* lo) {
   }
 }
 
+// 8 floats -> one k column of 8 consecutive LDS rows (stride ld elements).
+DEV void put8t(float* d, int ld, const float v[8], float*) {
+#pragma unroll
+  for (int e = 0; e < 8; ++e) d[e * ld] = v[e];
+}
+DEV void put8t(bf16_t* d, int ld, const float v[8], bf16_t* lo) {
+#pragma unroll
+  for (int e = 0; e < 8; e += 2) {
+    const uint32_t h = pk_bf16(v[e], v[e + 1]);
+    d[e * ld] = (bf16_t)(h & 0xffffu);
+    d[(e + 1) * ld] = (bf16_t)(h >> 16);
+    if (lo) {
+      const float a = __uint_as_float(h << 16), b = __uint_as_float(h & 0xffff0000u);
+      const uint32_t l = pk_bf16(v[e] - a, v[e + 1] - b);
+      lo[e * ld] = (bf16_t)(l & 0xffffu);
+      lo[(e + 1) * ld] = (bf16_t)(l >> 16);
+    }
+  }
+}
+
 // ------------------------------------------------------------- kernel
 template <class Prob, typename TC, int BM, int BN, int WGM, int WGN, bool SPLIT>
 __global__ void __launch_bounds__(256) gemm_kernel(Prob p, Epi e, int tiles_n, int k_per_split) {
@@ -394,6 +481,7 @@ __global__ void __launch_bounds__(256) gemm_kernel(Prob p, Epi e, int tiles_n, i
   constexpr int CA = BM * BK / 8, CB = BN * BK / 8;
   constexpr int QA = (CA + 255) / 256, QB = (CB + 255) / 256;
   constexpr bool AR = Layout<Prob>::A_ROWS, BR = Layout<Prob>::B_ROWS;
+  constexpr bool ART = Layout<Prob>::A_RT, BRT = Layout<Prob>::B_RT;
   constexpr int NSPL = SPLIT ? 2 : 1;
   __shared__ __attribute__((aligned(16))) TC sA[NSPL][2][BM * LDK];
   __shared__ __attribute__((aligned(16))) TC sB[2][BN * LDK];
@@ -407,10 +495,11 @@ __global__ void __launch_bounds__(256) gemm_kernel(Prob p, Epi e, int tiles_n, i
 
   // chunk c -> (row, k offset): lanes walk k for k-contiguous operands and
   // rows for row-contiguous ones
-  auto a_row = [&](int c) { return AR ? c % BM : c / (BK / 8); };
-  auto a_kc = [&](int c) { return AR ? (c / BM) * 8 : (c % (BK / 8)) * 8; };
-  auto b_row = [&](int c) { return BR ? c % BN : c / (BK / 8); };
-  auto b_kc = [&](int c) { return BR ? (c / BN) * 8 : (c % (BK / 8)) * 8; };
+  // (RT: chunk c -> first row 8*(c % (rows/8)) of an 8-row group and one k)
+  auto a_row = [&](int c) { return ART ? (c % (BM / 8)) * 8 : AR ? c % BM : c / (BK / 8); };
+  auto a_kc = [&](int c) { return ART ? c / (BM / 8) : AR ? (c / BM) * 8 : (c % (BK / 8)) * 8; };
+  auto b_row = [&](int c) { return BRT ? (c % (BN / 8)) * 8 : BR ? c % BN : c / (BK / 8); };
+  auto b_kc = [&](int c) { return BRT ? c / (BN / 8) : BR ? (c / BN) * 8 : (c % (BK / 8)) * 8; };
 
   typename Prob::RA ra[QA];
   typename Prob::RB rb[QB];
@@ -454,13 +543,21 @@ __global__ void __launch_bounds__(256) gemm_kernel(Prob p, Epi e, int tiles_n, i
       const int c = tid + 256 * q;
       if (c < CA) {
         const int o = a_row(c) * LDK + a_kc(c);
-        put8(&sA[0][buf][o], va[q], SPLIT ? &sA[NSPL - 1][buf][o] : (TC*)nullptr);
+        if constexpr (ART)
+          put8t(&sA[0][buf][o], LDK, va[q], SPLIT ? &sA[NSPL - 1][buf][o] : (TC*)nullptr);
+        else
+          put8(&sA[0][buf][o], va[q], SPLIT ? &sA[NSPL - 1][buf][o] : (TC*)nullptr);
       }
     }
 #pragma unroll
     for (int q = 0; q < QB; ++q) {
       const int c = tid + 256 * q;
-      if (c < CB) put8(&sB[buf][b_row(c) * LDK + b_kc(c)], vb[q], (TC*)nullptr);
+      if (c < CB) {
+        if constexpr (BRT)
+          put8t(&sB[buf][b_row(c) * LDK + b_kc(c)], LDK, vb[q], (TC*)nullptr);
+        else
+          put8(&sB[buf][b_row(c) * LDK + b_kc(c)], vb[q], (TC*)nullptr);
+      }
     }
   };
 

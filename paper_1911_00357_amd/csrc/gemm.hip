@@ -231,8 +231,15 @@ void gemm_conv_dgrad(int prec, const ConvGeo& g, const float* dy, const void* w,
 
 void gemm_conv_wgrad(int prec, const ConvGeo& g, const float* x, const float* dy, Epi e, size_t pb,
                      float* partial, hipStream_t s) {
-  ConvWgradProb p{g, fast_div(g.C), fast_div(g.KW), fast_div(g.Ho * g.Wo), fast_div(g.Wo), x, dy, g.Co,
-                  g.KH * g.KW * g.C, g.B * g.Ho * g.Wo};
+  const int M = g.Co, N = g.KH * g.KW * g.C, K = g.B * g.Ho * g.Wo;
+  // channel-vector chunks pay for their transposed LDS writes only where the
+  // scalar gather is worst: fewer than 8 input channels per tap (the stem)
+  if (g.Co % 8 == 0 && g.C % 8 != 0 && g.C % 4 == 0 && (((uintptr_t)x | (uintptr_t)dy) & 15) == 0) {
+    ConvWgradRTProb p{g, fast_div(g.Ho * g.Wo), fast_div(g.Wo), x, dy, M, N, K};
+    run_prec(p, e, prec, true, pb, partial, s);
+    return;
+  }
+  ConvWgradProb p{g, fast_div(g.C), fast_div(g.KW), fast_div(g.Ho * g.Wo), fast_div(g.Wo), x, dy, M, N, K};
   run_prec(p, e, prec, true, pb, partial, s);
 }
 
