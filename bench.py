@@ -41,6 +41,8 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--eager", action="store_true", help="launch the act loop eagerly (no HIP graph)")
+    ap.add_argument("--pmc-probe", action="store_true",
+                    help="only run a 256 MiB copy and the dominant learner GEMM 3x each (for rocprofv3 --pmc)")
     ap.add_argument("--autograd", choices=["auto", "on", "off"], default="auto",
                     help="take the update's gradient through torch.autograd (auto: for C3)")
     return ap.parse_args()
@@ -253,6 +255,52 @@ def dominant_gemm(wl, seed, reps=5):
     return u, op, name, round(tot_f / (tot_t / 1e3) / 1e12, 3)
 
 
+COPY_BYTES = 256 << 20
+
+
+def pmc_probe(wl, seed, sel):
+    """Calibration copy (COPY_BYTES read + written per launch) and the dominant
+    learner GEMM, three launches each, for HBM byte counters."""
+    import torch
+    import paper_1911_00357_amd as P
+    from synth import rollout as R
+    dev = torch.device("cuda", 0)
+    src = torch.ones(COPY_BYTES // 4, dtype=torch.float32, device=dev)
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    del src, dst
+    n = P.Net(wl.net, wl.dtype)
+    params = torch.tensor(R.init_params(wl.net, seed), device=dev)
+    lp = P.cast_bf16(params) if wl.dtype == "bf16" else None
+    grad = torch.zeros_like(params)
+    F = wl.T * wl.N // wl.ppo.minibatches
+    n.bench_unit_gemm(sel[1], sel[0], F, params, lp, grad, 3)
+    torch.cuda.synchronize()
+    print(json.dumps({"pmc_probe": {"copy_bytes": COPY_BYTES, "kernel": f"{OPS[sel[1]]} GEMM of {sel[2]}",
+                                    "frames": F}}), flush=True)
+
+
+def traffic_bytes(kernel):
+    """Per-launch HBM bytes (fetch + write) of `kernel` from the committed PMC
+    summary, or None when that summary is missing or was taken on other GEMM
+    sources than the ones built now."""
+    import hashlib
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles", "pmc_traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        rec = json.load(f)
+    h = hashlib.sha256()
+    for name in rec.get("sources", []):
+        with open(os.path.join(os.path.dirname(os.path.abspath(__file__)), name), "rb") as f:
+            h.update(f.read())
+    if rec.get("kernel") != kernel or rec.get("sources_sha256") != h.hexdigest():
+        return None
+    return rec["fetch_bytes_per_launch"] + rec["write_bytes_per_launch"]
+
+
 def roofline_live(wl, sel, timed):
     """Roofline entry of the dominant GEMM kernel from its launches inside the
     timed steps (HIP events on the learner's stream around the kernel
@@ -265,7 +313,7 @@ def roofline_live(wl, sel, timed):
                 "traffic": None, "kernel": f"{OPS[op]} GEMM of {name}"}
     ach = fl / (ms / 1e3) / 1e12
     return {"bound": "mfma", "achieved": round(ach, 3), "peak": peak, "unit": "TFLOP/s",
-            "frac": round(ach / peak, 5), "traffic": None,
+            "frac": round(ach / peak, 5), "traffic": traffic_bytes(f"{OPS[op]} GEMM of {name}"),
             "kernel": f"{OPS[op]} GEMM of {name}", "launches": launches,
             "avg_launch_us": round(ms / launches * 1e3, 2), "flops_per_launch": fl / launches,
             "all_conv_gemms_tflops_microbench": all_tf}
@@ -320,6 +368,9 @@ def main():
     from synth.configs import WORKLOADS
     wl = WORKLOADS[a.workload]
     sel = dominant_gemm(wl, a.seed)
+    if a.pmc_probe:
+        pmc_probe(wl, a.seed, sel)
+        return
     res = run_gpu(wl, a.steps, a.warmup, a.seed, timer=sel[:2])
     roof = roofline_live(wl, sel, res["timed"])
     fps = res["frames"] / (res["gpu_ms"] / 1e3)
@@ -346,6 +397,10 @@ def main():
     fpf = flops_per_frame(wl.net)
     upd_flops = 3 * fpf * fr * wl.ppo.epochs
     peak = PEAK_BF16_TFLOPS if wl.dtype == "bf16" else PEAK_FP32_TFLOPS
+    # whole iteration: act forward of every frame (+ the bootstrap step) and E x (forward + backward)
+    step_flops = fpf * ((1 + 3 * wl.ppo.epochs) * frames_step + wl.N)
+    out["step_tflops"] = round(step_flops / (ms_step / 1e3) / 1e12, 3)
+    out["step_mfma_frac"] = round(step_flops / (ms_step / 1e3) / 1e12 / (PEAK_BF16_TFLOPS if wl.dtype == "bf16" else PEAK_FP32_TFLOPS), 5)
     out["update_tflops"] = round(upd_flops / (upd_ms / 1e3) / 1e12, 3)
     out["update_mfma_frac"] = round(upd_flops / (upd_ms / 1e3) / 1e12 / peak, 5)
     if wl.dtype == "bf16" and not a.no_fp32:
