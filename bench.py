@@ -84,6 +84,7 @@ def run_gpu(wl, steps, warmup, seed, timer=None):
     w = Worker(wl.net, wl.dtype, wl.T, wl.N, R.init_params(wl.net, seed), hp, dev)
     its = warmup + steps
     envs = [stage_env(wl, seed, i, dev) for i in range(min(its, 2))]
+    w.net.autotune(1)             # GEMM tiles tuned during the first warm-up iteration
     parts = R.partitions(wl, seed)
     frames = []
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
@@ -92,6 +93,8 @@ def run_gpu(wl, steps, warmup, seed, timer=None):
     for i in range(its):
         env, lens = envs[i % len(envs)]
         lengths = None if not wl.ragged else lens
+        if i == min(1, warmup):
+            w.net.autotune(0)
         if i == warmup:
             torch.cuda.synchronize()
             if timer is not None:
@@ -125,9 +128,11 @@ def act_update_split(wl, seed):
     env, lens = stage_env(wl, seed, 0, dev)
     lengths = None if not wl.ragged else lens
     parts = R.partitions(wl, seed)
+    w.net.autotune(1)
     for _ in range(2):
         w.collect(env, lengths, graph=GRAPH)
         _update(w, env, parts, lengths)
+        w.net.autotune(0)
     e = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
     e[0].record()
     w.collect(env, lengths, graph=GRAPH)
@@ -180,8 +185,10 @@ def unpacked_split(wl, seed):
                 for e in envs:
                     w.net.loss_backward(ro, [int(e)], lens, w.params, w.lp, cfg, loss_scale=scale,
                                         adv_stats=w.adv_stats, grad=w.grad, stats=w.stats)
+    w.net.autotune(1)
     act_unpacked()
     update_unpacked()
+    w.net.autotune(0)
     e = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
     torch.cuda.synchronize()
     e[0].record()
@@ -234,6 +241,7 @@ def dominant_gemm(wl, seed, reps=5):
     grad = torch.zeros_like(params)
     F = wl.T * wl.N // wl.ppo.minibatches
     nunits = n.probe(PPO_OP_LEARN, F, 1, 3)[3][0]
+    n.autotune(1)                 # each problem is tuned on its first (untimed) launch
     rows = []
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
     for u in range(nunits):
@@ -276,6 +284,10 @@ def pmc_probe(wl, seed, sel):
     lp = P.cast_bf16(params) if wl.dtype == "bf16" else None
     grad = torch.zeros_like(params)
     F = wl.T * wl.N // wl.ppo.minibatches
+    n.autotune(1)
+    n.bench_unit_gemm(sel[1], sel[0], F, params, lp, grad, 1)   # tunes the problem as the worker does
+    n.autotune(0)
+    torch.cuda.synchronize()
     n.bench_unit_gemm(sel[1], sel[0], F, params, lp, grad, 3)
     torch.cuda.synchronize()
     print(json.dumps({"pmc_probe": {"copy_bytes": COPY_BYTES, "kernel": f"{OPS[sel[1]]} GEMM of {sel[2]}",
@@ -386,7 +398,7 @@ def main():
                       "minibatches": wl.ppo.minibatches, "frames_per_step": frames_step,
                       "parallelism": "single worker",
                       "gradient": "torch.autograd.Function, activations recomputed" if AUTOGRAD
-                      else "ppo_loss_backward"},
+                      else "ppo_loss_backward", "gemm_tiles": "autotuned in warm-up"},
            "wall_s": round(res["wall_s"], 3)}
     del res
     torch.cuda.empty_cache()

@@ -82,6 +82,7 @@ EXPORTS = {
                                     C.POINTER(c_int), C.POINTER(c_size_t), C.POINTER(c_int)]),
     "ppo_bench_unit_gemm": (c_int, [c_void_p, c_int, c_int, c_int, c_void_p, c_void_p, c_void_p, c_void_p,
                                     c_size_t, c_int, C.POINTER(C.c_double), c_void_p]),
+    "ppo_autotune": (c_int, [c_void_p, c_int, C.POINTER(c_int)]),
     "ppo_gemm_timer_arm": (c_int, [c_void_p, c_int, c_int, c_int]),
     "ppo_gemm_timer_read": (c_int, [c_void_p, C.POINTER(c_int), C.POINTER(C.c_double), C.POINTER(C.c_double)]),
     "ppo_last_error": (C.c_char_p, []),

@@ -139,6 +139,13 @@ class Net:
               "ppo_bench_unit_gemm")
         return fl.value
 
+    def autotune(self, mode: int) -> int:
+        """1: tune GEMM tiles of new problems in later calls (waits on the GPU);
+        0: stop tuning, keep the table; -1: clear it.  Returns table entries."""
+        n = C.c_int()
+        check(lib().ppo_autotune(self._h, mode, C.byref(n)), "ppo_autotune")
+        return n.value
+
     def gemm_timer_arm(self, unit: int, op: int, max_launches: int = 4096):
         """Time the GEMM kernel launches of one trunk unit and op in later calls
         (benchmark aid; unit < 0 disarms)."""

@@ -72,6 +72,13 @@ struct ppo_net {
   mutable int timer_unit = -1, timer_op = -1;
   mutable std::vector<hipEvent_t> timer_ev;
   mutable GemmTimer timer{};
+  mutable GemmTune tune;      // tile / K-split choices (ppo_autotune)
+};
+
+// Makes the net's tile table visible to the GEMM launchers for one call.
+struct TuneScope {
+  explicit TuneScope(const ppo_net* n) { g_gemm_tune = n ? &n->tune : nullptr; }
+  ~TuneScope() { g_gemm_tune = nullptr; }
 };
 
 namespace {
@@ -534,6 +541,7 @@ ppo_status ppo_workspace_size(const ppo_net* net, int op, int max_frames, int ma
 }
 
 ppo_status ppo_act(ppo_net* net, const ppo_act_io* io, void* ws, size_t ws_bytes, void* stream) {
+  TuneScope tsc(net);
   if (!net || !io) return fail(PPO_EINVAL, "null argument");
   const ppo_net_desc& d = net->d;
   const int B = io->batch;
@@ -789,6 +797,7 @@ extern "C" {
 ppo_status ppo_loss_backward(ppo_net* net, const ppo_batch* b, const ppo_loss_cfg* cfg,
                              const float* d_loss_scale, float* grad, float* stats, void* ws,
                              size_t ws_bytes, void* stream) {
+  TuneScope tsc(net);
   if (!net || !b || !cfg || !grad || !stats) return fail(PPO_EINVAL, "null argument");
   if (!b->action || !b->logp_old || !b->adv || !b->ret || (cfg->norm_adv && !cfg->adv_stats))
     return fail(PPO_EINVAL, "null pointer in ppo_batch");
@@ -813,6 +822,7 @@ ppo_status ppo_loss_backward(ppo_net* net, const ppo_batch* b, const ppo_loss_cf
 
 ppo_status ppo_policy_forward(ppo_net* net, const ppo_batch* b, float* logits, float* values, int32_t* frame_src,
                               void* ws, size_t ws_bytes, void* stream) {
+  TuneScope tsc(net);
   if (!net || !b || !logits || !values) return fail(PPO_EINVAL, "null argument");
   Sched S;
   const ppo_status st = schedule(net, b, S);
@@ -832,6 +842,7 @@ ppo_status ppo_policy_forward(ppo_net* net, const ppo_batch* b, float* logits, f
 
 ppo_status ppo_policy_backward(ppo_net* net, const ppo_batch* b, const float* dlogits, const float* dvalues,
                                float* grad, void* ws, size_t ws_bytes, void* stream) {
+  TuneScope tsc(net);
   if (!net || !b || !dlogits || !dvalues || !grad) return fail(PPO_EINVAL, "null argument");
   Sched S;
   const ppo_status st = schedule(net, b, S);
@@ -871,6 +882,7 @@ ppo_status ppo_adam_step(float* master, const float* grad, float* m, float* v, v
 ppo_status ppo_bench_unit_gemm(ppo_net* net, int op, int unit, int frames, const float* params,
                                const void* params_lp, float* grad, void* ws, size_t ws_bytes, int reps,
                                double* flops, void* stream) {
+  TuneScope tsc(net);
   if (!net || !params || !grad || !flops || (net->prec && !params_lp)) return fail(PPO_EINVAL, "null argument");
   if (unit < 0 || unit >= (int)net->units.size() || op < 0 || op > 2 || frames <= 0 || reps <= 0)
     return fail(PPO_EINVAL, "bad unit / op / frames / reps");
@@ -894,6 +906,19 @@ ppo_status ppo_bench_unit_gemm(ppo_net* net, int op, int unit, int frames, const
       gemm_conv_wgrad(net->prec, g, X, DY, epi(grad + u.w, u.K * u.K * u.Cin), kSplitKBytes, c.splitk(), s);
   }
   return check_launch();
+}
+
+ppo_status ppo_autotune(ppo_net* net, int mode, int* entries) {
+  if (!net) return fail(PPO_EINVAL, "null argument");
+  if (mode < -1 || mode > 1) return fail(PPO_EINVAL, "mode must be -1, 0 or 1");
+  if (mode == -1) {
+    net->tune.best.clear();
+    net->tune.tuning = 0;
+  } else {
+    net->tune.tuning = mode;
+  }
+  if (entries) *entries = (int)net->tune.best.size();
+  return PPO_OK;
 }
 
 ppo_status ppo_gemm_timer_arm(ppo_net* net, int unit, int op, int max_launches) {

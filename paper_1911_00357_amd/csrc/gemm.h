@@ -60,6 +60,7 @@ DEV bool aligned16(const void* p) { return (((uintptr_t)p) & 15) == 0; }
 // Forward: A(m = (b,ho,wo), k = (kh,kw,ci)) = x[b][ho*s-p+kh][wo*s-p+kw][ci]; B(n = co, k) = w[co][k].
 template <typename TW>
 struct ConvFwdProb {
+  static constexpr int kKind = 1;
   ConvGeo g;
   FastDiv dC, dKW, dHoWo, dWo;
   const float* x;
@@ -127,6 +128,7 @@ struct ConvFwdProb {
 // contiguous along k).
 template <typename TW>
 struct ConvDgradProb {
+  static constexpr int kKind = 2;
   ConvGeo g;
   FastDiv dCo, dNkw, dHqWq, dWq;
   const float* dy;
@@ -214,6 +216,7 @@ struct ConvDgradProb {
 // r = (b,ho,wo) is the reduction.  Both operands are contiguous along their
 // rows: lanes walk co (A) or n (B); 8 consecutive r per chunk.
 struct ConvWgradProb {
+  static constexpr int kKind = 3;
   ConvGeo g;
   FastDiv dC, dKW, dHoWo, dWo;
   const float* x;
@@ -273,6 +276,7 @@ struct ConvWgradProb {
 // written transposed into the k-contiguous LDS rows.  Needs Co % 8 == 0 and
 // C % 4 == 0 (a B chunk spans one tap when C % 8 == 0, else two taps of 4).
 struct ConvWgradRTProb {
+  static constexpr int kKind = 4;
   ConvGeo g;
   FastDiv dHoWo, dWo;
   const float* x;
@@ -326,6 +330,7 @@ struct ConvWgradRTProb {
 // (or b[k*ldb + n] when TB).
 template <typename TAe, typename TBe, bool TA, bool TB>
 struct DenseProb {
+  static constexpr int kKind = 8 + 4 * (int)(sizeof(TBe) == 2) + 2 * (int)TA + (int)TB;
   const TAe* a;
   const TBe* b;
   int lda, ldb;

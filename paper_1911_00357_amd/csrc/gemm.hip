@@ -36,6 +36,7 @@ __global__ void __launch_bounds__(256) splitk_reduce_kernel(const float* __restr
 }
 
 thread_local GemmTimer* g_gemm_timer = nullptr;
+thread_local GemmTune* g_gemm_tune = nullptr;
 
 namespace {
 
@@ -109,17 +110,8 @@ int launch(const Prob& p, Epi e, int splits, float* partial, hipStream_t s, bool
   return splits;
 }
 
-// Returns the K split used; with defer and a split > 1 the partial tiles are
-// left in `partial` ([splits][M][N]) for the caller to sum.
 template <class Prob, typename TC, bool SPLIT>
-int run(const Prob& p, Epi e, size_t partial_bytes, float* partial, hipStream_t s, int prec, bool defer = false) {
-  if (p.M <= 0 || p.N <= 0) return 1;
-  const Tile t = choose(p.M, p.N, prec);
-  const TileDim d = dim_of(t);
-  const long tiles = (long)cdiv(p.M, d.bm) * cdiv(p.N, d.bn);
-  int splits = p.K > 0 ? splits_for(tiles, p.K) : 1;
-  const long cap = (long)(partial_bytes / (sizeof(float) * (size_t)p.M * p.N));
-  if (splits > cap) splits = (int)std::max<long>(1, cap);
+int launch_tile(Tile t, const Prob& p, Epi e, int splits, float* partial, hipStream_t s, bool defer) {
   switch (t) {
     case T128x128: return launch<Prob, TC, 128, 128, 2, 2, SPLIT>(p, e, splits, partial, s, defer);
     case T128x64: return launch<Prob, TC, 128, 64, 2, 2, SPLIT>(p, e, splits, partial, s, defer);
@@ -128,6 +120,93 @@ int run(const Prob& p, Epi e, size_t partial_bytes, float* partial, hipStream_t 
     case T128x32: return launch<Prob, TC, 128, 32, 4, 1, SPLIT>(p, e, splits, partial, s, defer);
     default: return launch<Prob, TC, 32, 128, 1, 4, SPLIT>(p, e, splits, partial, s, defer);
   }
+}
+
+bool capturing(hipStream_t s) {
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  return hipStreamIsCapturing(s, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone;
+}
+
+// Times every (tile, split) candidate of one problem on stream s (output
+// redirected to scratch, so accumulating epilogues are not disturbed) and
+// returns the fastest; falls back to `dflt` when timing is not possible.
+template <class Prob, typename TC, bool SPLIT>
+std::pair<int, int> tune(const Prob& p, const Epi& e, long cap, float* partial, hipStream_t s,
+                         std::pair<int, int> dflt) {
+  // rows of C written: up to the row of m = M-1 (the row map is monotone in m)
+  size_t rows = (size_t)p.M;
+  if (e.rq > 0) {
+    const int m = p.M - 1, b = m / e.rq, q = m - b * e.rq, h = q / e.rwq, w = q - h * e.rwq;
+    rows = (size_t)b * e.rs1 + (size_t)h * e.rs2 + (size_t)w * e.rs3 + e.r0 + 1;
+  }
+  float* scratch = nullptr;
+  if (hipMalloc(&scratch, rows * (size_t)e.ldc * sizeof(float)) != hipSuccess) {
+    (void)hipGetLastError();
+    return dflt;
+  }
+  Epi et = e;
+  et.C = scratch;
+  et.accumulate = 0;
+  hipEvent_t a = nullptr, b = nullptr;
+  std::pair<int, int> best = dflt;
+  float best_ms = 1e30f;
+  if (hipEventCreate(&a) == hipSuccess && hipEventCreate(&b) == hipSuccess) {
+    const long kmax = std::max<long>(1, (long)cdiv(p.K, BK));
+    for (int ti = 0; ti <= (int)T32x128; ++ti) {
+      const TileDim d = dim_of((Tile)ti);
+      const long tiles = (long)cdiv(p.M, d.bm) * cdiv(p.N, d.bn);
+      const int s0 = p.K > 0 ? splits_for(tiles, p.K) : 1;
+      int cand[6] = {1, s0 / 2, s0, 2 * s0, 4 * s0, 8 * s0};
+      int last = -1;
+      for (int z : cand) {
+        z = (int)std::min<long>({(long)z, cap, kmax, 256L});
+        if (z < 1 || z == last) continue;
+        last = z;
+        launch_tile<Prob, TC, SPLIT>((Tile)ti, p, et, z, partial, s, false);
+        hipEventRecord(a, s);
+        for (int r = 0; r < 3; ++r) launch_tile<Prob, TC, SPLIT>((Tile)ti, p, et, z, partial, s, false);
+        hipEventRecord(b, s);
+        float ms = 0.f;
+        if (hipEventSynchronize(b) != hipSuccess || hipEventElapsedTime(&ms, a, b) != hipSuccess) continue;
+        if (ms < best_ms) {
+          best_ms = ms;
+          best = {ti, z};
+        }
+      }
+    }
+  }
+  if (a) (void)hipEventDestroy(a);
+  if (b) (void)hipEventDestroy(b);
+  (void)hipStreamSynchronize(s);
+  (void)hipFree(scratch);
+  (void)hipGetLastError();
+  return best;
+}
+
+// Returns the K split used; with defer and a split > 1 the partial tiles are
+// left in `partial` ([splits][M][N]) for the caller to sum.
+template <class Prob, typename TC, bool SPLIT>
+int run(const Prob& p, Epi e, size_t partial_bytes, float* partial, hipStream_t s, int prec, bool defer = false) {
+  if (p.M <= 0 || p.N <= 0) return 1;
+  Tile t = choose(p.M, p.N, prec);
+  const TileDim d = dim_of(t);
+  const long tiles = (long)cdiv(p.M, d.bm) * cdiv(p.N, d.bn);
+  int splits = p.K > 0 ? splits_for(tiles, p.K) : 1;
+  const long cap = (long)(partial_bytes / (sizeof(float) * (size_t)p.M * p.N));
+  if (splits > cap) splits = (int)std::max<long>(1, cap);
+  GemmTune* tu = g_gemm_tune;
+  if (tu && !defer) {
+    const std::array<long long, 5> key{Prob::kKind, p.M, p.N, p.K, 2 * prec + (int)SPLIT};
+    auto it = tu->best.find(key);
+    if (it == tu->best.end() && tu->tuning && !capturing(s))
+      it = tu->best.emplace(key, tune<Prob, TC, SPLIT>(p, e, std::max<long>(1, cap), partial, s, {(int)t, splits}))
+               .first;
+    if (it != tu->best.end()) {
+      t = (Tile)it->second.first;
+      splits = (int)std::max<long>(1, std::min<long>(it->second.second, std::max<long>(1, cap)));
+    }
+  }
+  return launch_tile<Prob, TC, SPLIT>(t, p, e, splits, partial, s, defer);
 }
 
 // bfloat16 with the gradient operand split (backward products) or not.

@@ -4,6 +4,9 @@
 #include <stdint.h>
 
 #include <algorithm>
+#include <array>
+#include <map>
+#include <utility>
 
 #include "../../include/ddppo.h"
 
@@ -74,6 +77,17 @@ struct GemmTimer {
   double flops;
 };
 extern thread_local GemmTimer* g_gemm_timer;
+
+// GEMM tile autotuner state of one net: the fastest (tile, K split) per
+// problem (operand kind, M, N, K, precision); while `tuning` is set, a problem
+// not in the table is timed on its stream over every candidate before it runs
+// (never inside stream capture, never for a deferred split whose partial
+// tiles a consumer sums).  g_gemm_tune is set by the library entry points.
+struct GemmTune {
+  std::map<std::array<long long, 5>, std::pair<int, int>> best;
+  int tuning = 0;
+};
+extern thread_local GemmTune* g_gemm_tune;
 
 // gemm.hip (prec: 0 float32 operands, 1 bfloat16 operands)
 int gemm_max_splits_for(long M, long N, long K, int prec);

@@ -310,3 +310,29 @@ def test_loss_backward_both_groupnorm_forms(P, limit, monkeypatch):
     say(f"loss f32 mini_resnet, GroupNorm form limit {limit}")
     g, s, g_ref, s_ref, _ = _loss_case(P, MINI_RESNET, "f32", 5, 3, [2, 1, 0], [5, 3, 4], seed=38)
     check_loss(MINI_RESNET, "f32", g, s, g_ref, s_ref, f"mini_resnet gn limit {limit}")
+
+
+def test_autotuned_loss_backward(P):
+    """The tile autotuner: the tuning call and a later call from the table give
+    the same bits, both within the tolerance of the oracle."""
+    say("autotuned loss backward")
+    net, T, N, envs, lengths = MINI_RESNET, 5, 3, [2, 1, 0], [5, 3, 4]
+    flat = R.init_params(net, 41, random_affine=True)
+    rec = random_record(net, T, N, 42, lengths=lengths)
+    envs = sorted(envs, key=lambda e: -lengths[e])
+    n = P.Net(net, "f32")
+    params = torch.tensor(flat, device=DEV)
+    ro = to_device(rec)
+    n.autotune(1)
+    g1, s1 = n.loss_backward(ro, envs, rec["lengths"], params, None, P.LossCfg(),
+                             loss_scale=torch.tensor([1.0], device=DEV))
+    entries = n.autotune(0)
+    g2, s2 = n.loss_backward(ro, envs, rec["lengths"], params, None, P.LossCfg(),
+                             loss_scale=torch.tensor([1.0], device=DEV))
+    torch.cuda.synchronize()
+    assert entries > 0
+    assert torch.equal(g1, g2) and torch.equal(s1, s2)
+    mb = oracle_minibatch(rec, envs)
+    s_ref, g_ref = ppo.loss_grad(flat.astype(np.float64), net, PPOCfg(), mb)
+    assert rel_err(g2.cpu().numpy(), g_ref) < 1e-4
+    assert n.autotune(-1) == 0
