@@ -13,6 +13,8 @@ Contents
           inverse-CDF sampling; forward over sequences and hand backward
   ppo     GAE, advantage statistics, the clipped PPO loss (Eq. 2) with its
           gradient, Adam, and the worker update loop (Sec. 3-4)
+  preempt the preemption threshold of Sec. 3: rollout length per worker from
+          per-step durations
 Parity status per function is stated in each module's header.
 """
-from . import nn, params, policy, ppo  # noqa: F401
+from . import nn, params, policy, ppo, preempt  # noqa: F401
