@@ -430,25 +430,24 @@ __global__ void __launch_bounds__(NT) gn_fused_kernel(const float* __restrict__ 
   // element j of this thread: pixel p0 + j*pstep, channel c (NT % Cg == 0)
   const int cc = threadIdx.x % Cg, p0 = threadIdx.x / Cg, pstep = NT / Cg, c = g * Cg + cc;
   const size_t base = ((size_t)b * P + p0) * C + c, jstr = (size_t)pstep * C;
+  // the split-K partials, ZB splits per round with every load of a round in
+  // flight together (summed in split order: deterministic)
+  constexpr int ZB = NPT >= 16 ? 1 : NPT >= 8 ? 2 : NPT >= 4 ? 4 : 8;
   float x[NPT];
 #pragma unroll
-  for (int j = 0; j < NPT; ++j) x[j] = p0 + j * pstep < P ? src[base + j * jstr] : 0.f;
-  // remaining split-K partials: NPT x 4 loads in flight per round
-  int z = 1;
-  for (; z + 4 <= nsplit; z += 4) {
-    float y[4][NPT];
+  for (int j = 0; j < NPT; ++j) x[j] = 0.f;
+  for (int z0 = 0; z0 < nsplit; z0 += ZB) {
+    float y[ZB][NPT];
 #pragma unroll
-    for (int q = 0; q < 4; ++q)
+    for (int q = 0; q < ZB; ++q)
 #pragma unroll
       for (int j = 0; j < NPT; ++j)
-        y[q][j] = p0 + j * pstep < P ? src[(size_t)(z + q) * zstride + base + j * jstr] : 0.f;
+        y[q][j] = (z0 + q < nsplit && p0 + j * pstep < P) ? src[(size_t)(z0 + q) * zstride + base + j * jstr] : 0.f;
 #pragma unroll
-    for (int j = 0; j < NPT; ++j) x[j] += (y[0][j] + y[1][j]) + (y[2][j] + y[3][j]);
+    for (int q = 0; q < ZB; ++q)
+#pragma unroll
+      for (int j = 0; j < NPT; ++j) x[j] += y[q][j];
   }
-  for (; z < nsplit; ++z)
-#pragma unroll
-    for (int j = 0; j < NPT; ++j)
-      if (p0 + j * pstep < P) x[j] += src[(size_t)z * zstride + base + j * jstr];
   float s = 0.f;
 #pragma unroll
   for (int j = 0; j < NPT; ++j) {
