@@ -317,11 +317,11 @@ struct Ctx {
 
 // GroupNorm of a unit in the one-launch form (a workgroup per image and group,
 // best when frames are few) or the coalesced partial / finalize / apply form
-// (best for large tensors); the element count threshold can be tuned with
-// DDPPO_GN_FUSED_MAX.
-bool gn_one_launch(const Ctx& c, const Unit& u) {
-  const char* e = getenv("DDPPO_GN_FUSED_MAX");
-  const long limit = e ? atol(e) : (long)(4 << 20);
+// (best for large tensors); the element count thresholds (4 M forward, 1 M
+// backward, measured) can be tuned with DDPPO_GN_FUSED_MAX / DDPPO_GNB_FUSED_MAX.
+bool gn_one_launch(const Ctx& c, const Unit& u, bool bwd = false) {
+  const char* e = getenv(bwd ? "DDPPO_GNB_FUSED_MAX" : "DDPPO_GN_FUSED_MAX");
+  const long limit = e ? atol(e) : (long)(bwd ? 1 << 20 : 4 << 20);
   const int P = u.Hout * u.Wout, G = c.n->d.gn_groups;
   return gn_fused_npt(P, u.Cout / G) && (long)c.F * P * u.Cout <= limit;
 }
@@ -406,7 +406,7 @@ const float* encoder_fwd(const Ctx& c) {
 void gn_bwd(const Ctx& c, int ui, const float* dout, const float* mask_out, bool chw, float* du, float* dres) {
   const Unit& u = c.n->units[ui];
   const int P = u.Hout * u.Wout, G = c.n->d.gn_groups;
-  if (gn_one_launch(c, u)) {
+  if (gn_one_launch(c, u, true)) {
     launch_gnb_fused(dout, mask_out, chw ? 1 : 0, c.at(c.w->u[ui]), c.F, P, u.Cout, G, c.at<float2>(c.w->st[ui]),
                      c.pf(u.g), du, dres, c.grad + u.g, c.grad + u.b, c.at<float2>(c.w->gbpart), c.s);
     return;

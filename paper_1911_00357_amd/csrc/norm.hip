@@ -14,23 +14,26 @@
 // first pixel.
 __global__ void __launch_bounds__(256) gn_partial_kernel(const float* __restrict__ y, int P, int C,
                                                          int S, float4* __restrict__ part) {
-  __shared__ float s1[256], s2[256];
+  // lanes take channel quads (float4 loads), the rest of the block walks pixels
+  __shared__ float4 s1[256], s2[256];
   const int b = blockIdx.y, s = blockIdx.x, tid = threadIdx.x;
   const int chunk = (P + S - 1) / S;
   const int p0 = s * chunk, p1 = min(P, p0 + chunk);
   const float* yb = y + (size_t)b * P * C;
-  const int CT = C < 256 ? C : 256;  // channels handled per pass
-  const int PR = 256 / CT;           // pixel lanes
-  const int c0 = tid % CT, pr = tid / CT;
-  for (int cb = 0; cb < C; cb += CT) {
-    const int c = cb + c0;
-    float a = 0.f, q = 0.f, K = 0.f;
+  const int C4 = C >> 2;
+  const int QT = C4 < 256 ? C4 : 256;  // channel quads per pass
+  const int PR = 256 / QT;             // pixel lanes
+  const int q0 = tid % QT, pr = tid / QT;
+  for (int qb = 0; qb < C4; qb += QT) {
+    const int c = 4 * (qb + q0);
+    float4 a = make_float4(0.f, 0.f, 0.f, 0.f), q = a, K = a;
     if (p0 < p1 && pr < PR) {
-      K = yb[(size_t)p0 * C + c];
+      K = *(const float4*)(yb + (size_t)p0 * C + c);
       for (int p = p0 + pr; p < p1; p += PR) {
-        const float d = yb[(size_t)p * C + c] - K;
-        a += d;
-        q += d * d;
+        const float4 v = *(const float4*)(yb + (size_t)p * C + c);
+        const float4 d = make_float4(v.x - K.x, v.y - K.y, v.z - K.z, v.w - K.w);
+        a.x += d.x; a.y += d.y; a.z += d.z; a.w += d.w;
+        q.x += d.x * d.x; q.y += d.y * d.y; q.z += d.z * d.z; q.w += d.w * d.w;
       }
     }
     s1[tid] = a;
@@ -38,10 +41,16 @@ __global__ void __launch_bounds__(256) gn_partial_kernel(const float* __restrict
     __syncthreads();
     if (pr == 0) {
       for (int r = 1; r < PR; ++r) {
-        a += s1[r * CT + c0];
-        q += s2[r * CT + c0];
+        const float4 u = s1[r * QT + q0], w = s2[r * QT + q0];
+        a.x += u.x; a.y += u.y; a.z += u.z; a.w += u.w;
+        q.x += w.x; q.y += w.y; q.z += w.z; q.w += w.w;
       }
-      part[((size_t)b * S + s) * C + c] = make_float4(a, q, K, (float)max(0, p1 - p0));
+      const float n = (float)max(0, p1 - p0);
+      float4* o = part + ((size_t)b * S + s) * C + c;
+      o[0] = make_float4(a.x, q.x, K.x, n);
+      o[1] = make_float4(a.y, q.y, K.y, n);
+      o[2] = make_float4(a.z, q.z, K.z, n);
+      o[3] = make_float4(a.w, q.w, K.w, n);
     }
     __syncthreads();
   }
@@ -91,30 +100,29 @@ __global__ void __launch_bounds__(256) gn_apply_kernel(const float* __restrict__
                                                        const float* __restrict__ beta,
                                                        const float* __restrict__ res, int relu,
                                                        float* __restrict__ out, int out_chw) {
-  const size_t n4 = (size_t)B * P * C / 4;
-  const int Cg = C / G;
-  for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n4; i += (size_t)gridDim.x * 256) {
-    const size_t e = i * 4;
-    const int c = (int)(e % C);
-    const size_t bp = e / C;
-    const int b = (int)(bp / P), p = (int)(bp % P);
+  const int C4 = C >> 2, Cg = C / G;
+  const int rows = B * P, n4 = rows * C4;
+  for (int i = blockIdx.x * 256 + threadIdx.x; i < n4; i += gridDim.x * 256) {
+    const int row = i / C4, c = 4 * (i - row * C4);
+    const int b = row / P, p = row - b * P;
+    const size_t e = (size_t)row * C + c;
     const float4 v = *(const float4*)(y + e);
-    float r[4] = {v.x, v.y, v.z, v.w};
+    const float r[4] = {v.x, v.y, v.z, v.w};
     float4 rr = make_float4(0.f, 0.f, 0.f, 0.f);
     if (res) rr = *(const float4*)(res + e);
     const float ra[4] = {rr.x, rr.y, rr.z, rr.w};
+    float o[4];
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
       const float2 st = stats[b * G + (c + j) / Cg];
-      float o = (r[j] - st.x) * st.y * gamma[c + j] + beta[c + j] + ra[j];
-      if (relu) o = fmaxf(o, 0.f);
-      r[j] = o;
+      o[j] = (r[j] - st.x) * st.y * gamma[c + j] + beta[c + j] + ra[j];
+      if (relu) o[j] = fmaxf(o[j], 0.f);
     }
     if (!out_chw) {
-      *(float4*)(out + e) = make_float4(r[0], r[1], r[2], r[3]);
+      *(float4*)(out + e) = make_float4(o[0], o[1], o[2], o[3]);
     } else {
 #pragma unroll
-      for (int j = 0; j < 4; ++j) out[((size_t)b * C + c + j) * P + p] = r[j];
+      for (int j = 0; j < 4; ++j) out[((size_t)b * C + c + j) * P + p] = o[j];
     }
   }
 }
@@ -143,37 +151,62 @@ __global__ void __launch_bounds__(256) gnb_partial_kernel(const float* __restric
                                                           const float* __restrict__ y, int P, int C,
                                                           int G, int S, const float2* __restrict__ stats,
                                                           float2* __restrict__ bpart) {
-  __shared__ float s1[256], s2[256];
+  __shared__ float4 s1[256], s2[256];
   const int b = blockIdx.y, s = blockIdx.x, tid = threadIdx.x;
   const int chunk = (P + S - 1) / S;
   const int p0 = s * chunk, p1 = min(P, p0 + chunk);
-  const int CT = C < 256 ? C : 256;
-  const int PR = 256 / CT;
-  const int c0 = tid % CT, pr = tid / CT;
+  const int C4 = C >> 2;
+  const int QT = C4 < 256 ? C4 : 256;
+  const int PR = 256 / QT;
+  const int q0 = tid % QT, pr = tid / QT;
   const int Cg = C / G;
-  for (int cb = 0; cb < C; cb += CT) {
-    const int c = cb + c0;
-    float a = 0.f, q = 0.f;
+  for (int qb = 0; qb < C4; qb += QT) {
+    const int c = 4 * (qb + q0);
+    float a[4] = {0.f, 0.f, 0.f, 0.f}, q[4] = {0.f, 0.f, 0.f, 0.f};
     if (pr < PR) {
-      const float2 st = stats[b * G + c / Cg];
+      float2 st[4];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) st[j] = stats[b * G + (c + j) / Cg];
       for (int p = p0 + pr; p < p1; p += PR) {
-        const size_t io = io_index(b, p, c, P, C, chw);
-        float dz = dout[io];
-        if (out && !(out[io] > 0.f)) dz = 0.f;
-        const float xh = (y[((size_t)b * P + p) * C + c] - st.x) * st.y;
-        a += dz;
-        q += dz * xh;
+        const size_t e = ((size_t)b * P + p) * C + c;
+        float dz[4], om[4] = {1.f, 1.f, 1.f, 1.f};
+        if (!chw) {
+          const float4 d = *(const float4*)(dout + e);
+          dz[0] = d.x; dz[1] = d.y; dz[2] = d.z; dz[3] = d.w;
+          if (out) {
+            const float4 m = *(const float4*)(out + e);
+            om[0] = m.x; om[1] = m.y; om[2] = m.z; om[3] = m.w;
+          }
+        } else {
+#pragma unroll
+          for (int j = 0; j < 4; ++j) {
+            const size_t io = ((size_t)b * C + c + j) * P + p;
+            dz[j] = dout[io];
+            if (out) om[j] = out[io];
+          }
+        }
+        const float4 yv = *(const float4*)(y + e);
+        const float yy[4] = {yv.x, yv.y, yv.z, yv.w};
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const float z = om[j] > 0.f ? dz[j] : 0.f;
+          a[j] += z;
+          q[j] += z * (yy[j] - st[j].x) * st[j].y;
+        }
       }
     }
-    s1[tid] = a;
-    s2[tid] = q;
+    s1[tid] = make_float4(a[0], a[1], a[2], a[3]);
+    s2[tid] = make_float4(q[0], q[1], q[2], q[3]);
     __syncthreads();
     if (pr == 0) {
       for (int r = 1; r < PR; ++r) {
-        a += s1[r * CT + c0];
-        q += s2[r * CT + c0];
+        const float4 u = s1[r * QT + q0], w = s2[r * QT + q0];
+        a[0] += u.x; a[1] += u.y; a[2] += u.z; a[3] += u.w;
+        q[0] += w.x; q[1] += w.y; q[2] += w.z; q[3] += w.w;
       }
-      bpart[((size_t)b * S + s) * C + c] = make_float2(a, q);
+      float2* o = bpart + ((size_t)b * S + s) * C + c;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) o[j] = make_float2(a[j], q[j]);
     }
     __syncthreads();
   }
@@ -230,20 +263,41 @@ __global__ void __launch_bounds__(256) gnb_apply_kernel(const float* __restrict_
                                                         const float2* __restrict__ coef,
                                                         const float* __restrict__ gamma,
                                                         float* __restrict__ dy, float* __restrict__ dres) {
-  const size_t n = (size_t)B * P * C;
-  const int Cg = C / G;
-  for (size_t e = (size_t)blockIdx.x * 256 + threadIdx.x; e < n; e += (size_t)gridDim.x * 256) {
-    const int c = (int)(e % C);
-    const size_t bp = e / C;
-    const int b = (int)(bp / P), p = (int)(bp % P);
-    const size_t io = chw ? ((size_t)b * C + c) * P + p : e;
-    float dz = dout[io];
-    if (out && !(out[io] > 0.f)) dz = 0.f;
-    const int bg = b * G + c / Cg;
-    const float2 st = stats[bg], cf = coef[bg];
-    const float xh = (y[e] - st.x) * st.y;
-    dy[e] = st.y * (dz * gamma[c] - cf.x - xh * cf.y);
-    if (dres) dres[e] = dz;
+  const int C4 = C >> 2, Cg = C / G;
+  const int rows = B * P, n4 = rows * C4;
+  for (int i = blockIdx.x * 256 + threadIdx.x; i < n4; i += gridDim.x * 256) {
+    const int row = i / C4, c = 4 * (i - row * C4);
+    const int b = row / P, p = row - b * P;
+    const size_t e = (size_t)row * C + c;
+    float dz[4], om[4] = {1.f, 1.f, 1.f, 1.f};
+    if (!chw) {
+      const float4 d = *(const float4*)(dout + e);
+      dz[0] = d.x; dz[1] = d.y; dz[2] = d.z; dz[3] = d.w;
+      if (out) {
+        const float4 m = *(const float4*)(out + e);
+        om[0] = m.x; om[1] = m.y; om[2] = m.z; om[3] = m.w;
+      }
+    } else {
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const size_t io = ((size_t)b * C + c + j) * P + p;
+        dz[j] = dout[io];
+        if (out) om[j] = out[io];
+      }
+    }
+    const float4 yv = *(const float4*)(y + e);
+    const float yy[4] = {yv.x, yv.y, yv.z, yv.w};
+    float o[4], zz[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int bg = b * G + (c + j) / Cg;
+      const float2 st = stats[bg], cf = coef[bg];
+      const float z = om[j] > 0.f ? dz[j] : 0.f;
+      zz[j] = z;
+      o[j] = st.y * (z * gamma[c + j] - cf.x - (yy[j] - st.x) * st.y * cf.y);
+    }
+    *(float4*)(dy + e) = make_float4(o[0], o[1], o[2], o[3]);
+    if (dres) *(float4*)(dres + e) = make_float4(zz[0], zz[1], zz[2], zz[3]);
   }
 }
 
@@ -257,7 +311,7 @@ void launch_gn_backward(const float* dout, const float* out, int chw, const floa
                      P, gamma, coef);
   hipLaunchKernelGGL(gnb_affine_kernel, dim3(cdiv(C, 4)), dim3(256), 0, s, bpart, B, S, C, dgamma,
                      dbeta);
-  const size_t n = (size_t)B * P * C;
+  const size_t n = (size_t)B * P * C / 4;
   const int nb = (int)std::min<size_t>(8192, (n + 255) / 256);
   hipLaunchKernelGGL(gnb_apply_kernel, dim3(nb), dim3(256), 0, s, dout, out, chw, y, B, P, C, G, stats,
                      coef, gamma, dy, dres);
