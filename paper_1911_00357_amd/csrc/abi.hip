@@ -568,9 +568,33 @@ ppo_status ppo_act(ppo_net* net, const ppo_act_io* io, void* ws, size_t ws_bytes
   gemm_dense(net->prec, false, false, feat, net->flat, c.wt(net->fc_w), net->prec == 1, net->flat, B,
              d.vis_hidden, net->flat, epi(zh, ld0, c.pf(net->fc_b), 1),
              false, kSplitKBytes, c.splitk(), s);
-  launch_embed_fwd(io->goal, io->prev_action, io->mask, nullptr, B, d.goal_mode == PPO_GOAL_POLAR,
-                   d.goal_dim, d.goal_mode == PPO_GOAL_POLAR ? c.pf(net->goal_w) : nullptr,
-                   d.goal_mode == PPO_GOAL_POLAR ? c.pf(net->goal_b) : nullptr, std::max(0, d.prev_act_dim),
+  const bool polar = d.goal_mode == PPO_GOAL_POLAR;
+  bool fused = L <= 2;
+  for (int l = 0; l < L; ++l) fused = fused && act_layer_supported(l == 0 ? net->din0 : H, H, B);
+  if (fused) {
+    // goal / embedding inputs and every layer's masked state in one launch (all
+    // of h_in, c_in read before any output is written), then one launch per
+    // layer; the masked copies use the layer-0 gate slab (4 B H floats)
+    float* hm = c.at(w.g[0]);
+    float* cm = hm + (size_t)L * B * H;
+    launch_act_core_prep(io->goal, io->prev_action, io->mask, B, polar, d.goal_dim,
+                         polar ? c.pf(net->goal_w) : nullptr, polar ? c.pf(net->goal_b) : nullptr,
+                         std::max(0, d.prev_act_dim), d.prev_act_dim > 0 ? c.pf(net->emb) : nullptr, zh, ld0,
+                         d.vis_hidden, io->h_in, io->c_in, L, SR, H, hm, cm, s);
+    for (int l = 0; l < L; ++l) {
+      const int din = l == 0 ? net->din0 : H;
+      const float* X = l == 0 ? zh : io->h_out + (size_t)(l - 1) * SR * H;
+      launch_lstm_act_layer(net->prec, X, l == 0 ? ld0 : H, din, hm + (size_t)l * B * H, cm + (size_t)l * B * H,
+                            c.wt(net->lstm_w[l]), din + H, c.pf(net->lstm_b[l]), B, H,
+                            io->h_out + (size_t)l * SR * H, io->c_out + (size_t)l * SR * H, s);
+    }
+    launch_act_head(io->h_out + (size_t)(L - 1) * SR * H, B, H, A, c.pf(net->head_w), c.pf(net->head_b),
+                    io->u, io->action, io->logp, io->value, io->logits, s);
+    return check_launch();
+  }
+  launch_embed_fwd(io->goal, io->prev_action, io->mask, nullptr, B, polar,
+                   d.goal_dim, polar ? c.pf(net->goal_w) : nullptr,
+                   polar ? c.pf(net->goal_b) : nullptr, std::max(0, d.prev_act_dim),
                    d.prev_act_dim > 0 ? c.pf(net->emb) : nullptr, zh, ld0, d.vis_hidden, s);
   // masked recurrent state of every layer, read before any output is written
   std::vector<float*> zl(L), cpl(L);

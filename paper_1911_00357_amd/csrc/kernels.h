@@ -163,6 +163,17 @@ int launch_lstm_seq_bwd(int prec, const MapArgs& m, int TB, int H, const void* W
                         const float* CP, const float* Cs, const float* dH, int ldd, float* dG, const float* mskf,
                         unsigned* sync, hipStream_t s);
 
+// lstm_act.hip: the act step's goal / embedding inputs and masked state
+// (one launch), then one launch per LSTM layer (see the file header)
+void launch_act_core_prep(const float* goal, const int32_t* prev_a, const float* mask, int B, int polar,
+                          int goal_dim, const float* gw, const float* gb, int E, const float* emb, float* Z, int ldz,
+                          int zoff, const float* h_in, const float* c_in, int L, int SR, int H, float* hm, float* cm,
+                          hipStream_t s);
+bool act_layer_supported(int din, int H, int B);
+void launch_lstm_act_layer(int prec, const float* X, int ldx, int din, const float* HM, const float* CM,
+                           const void* W, int ldw, const float* bias, int B, int H, float* h_out, float* c_out,
+                           hipStream_t s);
+
 // head.hip
 void launch_act_head(const float* htop, int rows, int H, int A, const float* W, const float* b,
                      const float* u, int32_t* action, float* logp, float* value, float* logits,
