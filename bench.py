@@ -185,10 +185,8 @@ def unpacked_split(wl, seed):
                 for e in envs:
                     w.net.loss_backward(ro, [int(e)], lens, w.params, w.lp, cfg, loss_scale=scale,
                                         adv_stats=w.adv_stats, grad=w.grad, stats=w.stats)
-    w.net.autotune(1)
-    act_unpacked()
-    update_unpacked()
-    w.net.autotune(0)
+    act_unpacked()                # warm-up (tiles: the heuristic choice; every env has its own
+    update_unpacked()             # frame count, so tuning each one is not part of this comparison)
     e = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
     torch.cuda.synchronize()
     e[0].record()
@@ -201,11 +199,12 @@ def unpacked_split(wl, seed):
 
 
 def cpu_baseline(wl, seed):
-    """The FP64 oracle on a bounded sample of the same workload: an 8-step
-    rollout of all N envs (9 act steps) and the update over its frames."""
+    """The FP64 oracle on a bounded sample of the same workload: a 16-step
+    rollout of all N envs (17 act steps) and the update over its frames
+    (about 10-20 s of host time for the paper-shaped worker)."""
     import oracle
     from synth import rollout as R
-    small = wl.with_(T=8)
+    small = wl.with_(T=16)
     flat = R.init_params(wl.net, seed)
     inp = R.gen_rollout(small, seed, 0)
     inp["lengths"] = np.full(small.N, small.T, np.int32)
@@ -218,7 +217,7 @@ def cpu_baseline(wl, seed):
     threads = int(os.environ.get("OPENBLAS_NUM_THREADS", os.environ.get("OMP_NUM_THREADS", os.cpu_count())))
     return {"value": frames / dt, "unit": "frames/s", "cores": min(threads, os.cpu_count()),
             "kind": "oracle",
-            "sample": f"T=8 rollout of N={small.N} envs (9 act steps) + {wl.ppo.epochs}x"
+            "sample": f"T={small.T} rollout of N={small.N} envs ({small.T + 1} act steps) + {wl.ppo.epochs}x"
                       f"{wl.ppo.minibatches} minibatch updates, {frames} frames, {dt:.1f} s"}
 
 
@@ -364,6 +363,10 @@ def flops_per_frame(net):
     return f
 
 
+def progress(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
 def main():
     a = parse()
     global GRAPH, AUTOGRAD
@@ -379,10 +382,12 @@ def main():
         sys.exit(1)
     from synth.configs import WORKLOADS
     wl = WORKLOADS[a.workload]
+    progress(f"workload {a.workload}: selecting the dominant learner GEMM")
     sel = dominant_gemm(wl, a.seed)
     if a.pmc_probe:
         pmc_probe(wl, a.seed, sel)
         return
+    progress("timed run")
     res = run_gpu(wl, a.steps, a.warmup, a.seed, timer=sel[:2])
     roof = roofline_live(wl, sel, res["timed"])
     fps = res["frames"] / (res["gpu_ms"] / 1e3)
@@ -402,6 +407,7 @@ def main():
            "wall_s": round(res["wall_s"], 3)}
     del res
     torch.cuda.empty_cache()
+    progress("act / update split")
     act_ms, upd_ms, fr = act_update_split(wl, a.seed)
     out["act_ms"], out["update_ms"] = round(act_ms, 3), round(upd_ms, 3)
     out["act_frames_per_s"] = round((fr + wl.N) / (act_ms / 1e3), 1)
@@ -417,6 +423,7 @@ def main():
     out["update_mfma_frac"] = round(upd_flops / (upd_ms / 1e3) / 1e12 / peak, 5)
     if wl.dtype == "bf16" and not a.no_fp32:
         torch.cuda.empty_cache()
+        progress("float32 form")
         wl32 = wl.with_(dtype="f32")
         r32 = run_gpu(wl32, a.steps, 1, a.seed)
         out["fp32_value"] = round(r32["frames"] / (r32["gpu_ms"] / 1e3), 2)
@@ -424,13 +431,16 @@ def main():
         del r32
     if wl.ragged:
         torch.cuda.empty_cache()
+        progress("unpacked per-env launches")
         ua, uu, ufr = unpacked_split(wl, a.seed)
         out["unpacked_act_frames_per_s"] = round((ufr + wl.N) / (ua / 1e3), 1)
         out["unpacked_update_frames_per_s"] = round(ufr / (uu / 1e3), 1)
         out["packed_speedup_act"] = round(out["act_frames_per_s"] / out["unpacked_act_frames_per_s"], 3)
         out["packed_speedup_update"] = round(out["update_frames_per_s"] / out["unpacked_update_frames_per_s"], 3)
+        out["unpacked_gemm_tiles"] = "heuristic"
     out["roofline"] = roof
     if not a.no_cpu:
+        progress("oracle CPU baseline")
         out["cpu_baseline"] = cpu_baseline(wl, a.seed)
     print(json.dumps(out), flush=True)
 

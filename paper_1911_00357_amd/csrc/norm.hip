@@ -212,30 +212,49 @@ __global__ void __launch_bounds__(256) gnb_partial_kernel(const float* __restric
   }
 }
 
-// coef[b*G+g] = {sum_c gamma_c sum dz / n, sum_c gamma_c sum dz xhat / n}
-__global__ void __launch_bounds__(256) gnb_coef_kernel(const float2* __restrict__ bpart, int B, int S,
-                                                       int C, int G, int P,
-                                                       const float* __restrict__ gamma,
-                                                       float2* __restrict__ coef) {
+// Two reductions of the chunk partials in one launch (one wavefront per item):
+//   items [0, B G):    coef[b*G+g] = {sum_c gamma_c sum dz / n, sum_c gamma_c sum dz xhat / n}
+//   items [B G, +C):   dgamma[c] = sum_{b,s} sum dz xhat, dbeta[c] = sum_{b,s} sum dz
+__global__ void __launch_bounds__(256) gnb_coef_affine_kernel(const float2* __restrict__ bpart, int B, int S,
+                                                              int C, int G, int P,
+                                                              const float* __restrict__ gamma,
+                                                              float2* __restrict__ coef, float* __restrict__ dgamma,
+                                                              float* __restrict__ dbeta) {
   const int wid = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
-  if (wid >= B * G) return;
-  const int b = wid / G, g = wid % G, Cg = C / G;
+  if (wid < B * G) {
+    const int b = wid / G, g = wid % G, Cg = C / G;
+    double a = 0.0, q = 0.0;
+    for (int i = lane; i < S * Cg; i += 64) {
+      const int s = i / Cg, c = g * Cg + i % Cg;
+      const float2 v = bpart[((size_t)b * S + s) * C + c];
+      a += (double)gamma[c] * v.x;
+      q += (double)gamma[c] * v.y;
+    }
+    a = wave_sum(a);
+    q = wave_sum(q);
+    if (lane == 0) {
+      const double n = (double)P * Cg;
+      coef[wid] = make_float2((float)(a / n), (float)(q / n));
+    }
+    return;
+  }
+  const int c = wid - B * G;
+  if (c >= C) return;
   double a = 0.0, q = 0.0;
-  for (int i = lane; i < S * Cg; i += 64) {
-    const int s = i / Cg, c = g * Cg + i % Cg;
-    const float2 v = bpart[((size_t)b * S + s) * C + c];
-    a += (double)gamma[c] * v.x;
-    q += (double)gamma[c] * v.y;
+  for (int i = lane; i < B * S; i += 64) {
+    const float2 v = bpart[(size_t)i * C + c];
+    a += v.x;
+    q += v.y;
   }
   a = wave_sum(a);
   q = wave_sum(q);
   if (lane == 0) {
-    const double n = (double)P * Cg;
-    coef[wid] = make_float2((float)(a / n), (float)(q / n));
+    dgamma[c] = (float)q;
+    dbeta[c] = (float)a;
   }
 }
 
-// dgamma[c] = sum_{b,s} sum dz xhat, dbeta[c] = sum_{b,s} sum dz (one wavefront per channel)
+// dgamma / dbeta only (the one-launch backward's per-image partials, S = 1).
 __global__ void __launch_bounds__(256) gnb_affine_kernel(const float2* __restrict__ bpart, int B, int S,
                                                          int C, float* __restrict__ dgamma,
                                                          float* __restrict__ dbeta) {
@@ -307,10 +326,8 @@ void launch_gn_backward(const float* dout, const float* out, int chw, const floa
                         hipStream_t s) {
   hipLaunchKernelGGL(gnb_partial_kernel, dim3(S, B), dim3(256), 0, s, dout, out, chw, y, P, C, G, S,
                      stats, bpart);
-  hipLaunchKernelGGL(gnb_coef_kernel, dim3(cdiv((long)B * G, 4)), dim3(256), 0, s, bpart, B, S, C, G,
-                     P, gamma, coef);
-  hipLaunchKernelGGL(gnb_affine_kernel, dim3(cdiv(C, 4)), dim3(256), 0, s, bpart, B, S, C, dgamma,
-                     dbeta);
+  hipLaunchKernelGGL(gnb_coef_affine_kernel, dim3(cdiv((long)B * G + C, 4)), dim3(256), 0, s, bpart, B, S, C,
+                     G, P, gamma, coef, dgamma, dbeta);
   const size_t n = (size_t)B * P * C / 4;
   const int nb = (int)std::min<size_t>(8192, (n + 255) / 256);
   hipLaunchKernelGGL(gnb_apply_kernel, dim3(nb), dim3(256), 0, s, dout, out, chw, y, B, P, C, G, stats,
