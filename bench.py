@@ -103,6 +103,9 @@ def run_gpu(wl, steps, warmup, seed, timer=None):
             t_start = time.perf_counter()
         w.collect(env, lengths, graph=GRAPH)
         _update(w, env, parts, lengths)
+        if i < warmup:
+            torch.cuda.synchronize()
+            progress(f"warm-up iteration {i + 1}/{warmup} done")
         if i >= warmup:
             frames.append(int(lens.sum()))
     ev[1].record()

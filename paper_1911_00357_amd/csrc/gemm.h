@@ -96,6 +96,24 @@ struct ConvFwdProb {
         return load8(x + r.off + ((size_t)hi * g.W + wi) * g.C + ci, v);
       return zero8(v);
     }
+    if ((g.C & 3) == 0) {
+      // two 4-channel quads (one or two taps), each one float4 load
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int kk = k + 4 * h;
+        float* o = v + 4 * h;
+        o[0] = o[1] = o[2] = o[3] = 0.f;
+        if (kk >= K) continue;
+        const int tap = dC.div(kk), ci = kk - tap * g.C;
+        const int kh = dKW.div(tap), kw = tap - kh * g.KW;
+        const int hi = r.h0 + kh, wi = r.w0 + kw;
+        if ((unsigned)hi < (unsigned)g.H && (unsigned)wi < (unsigned)g.W) {
+          const float4 t = *(const float4*)(x + r.off + ((size_t)hi * g.W + wi) * g.C + ci);
+          o[0] = t.x; o[1] = t.y; o[2] = t.z; o[3] = t.w;
+        }
+      }
+      return;
+    }
 #pragma unroll
     for (int e = 0; e < 8; ++e) {
       const int kk = k + e;

@@ -164,7 +164,7 @@ std::pair<int, int> tune(const Prob& p, const Epi& e, long cap, float* partial, 
         last = z;
         launch_tile<Prob, TC, SPLIT>((Tile)ti, p, et, z, partial, s, false);
         hipEventRecord(a, s);
-        for (int r = 0; r < 3; ++r) launch_tile<Prob, TC, SPLIT>((Tile)ti, p, et, z, partial, s, false);
+        for (int r = 0; r < 2; ++r) launch_tile<Prob, TC, SPLIT>((Tile)ti, p, et, z, partial, s, false);
         hipEventRecord(b, s);
         float ms = 0.f;
         if (hipEventSynchronize(b) != hipSuccess || hipEventElapsedTime(&ms, a, b) != hipSuccess) continue;
