@@ -223,7 +223,7 @@ struct WsLayout {
   std::vector<size_t> g, c, cp, hp, hout;  // per layer
   size_t h0g, c0g;                 // gathered start state [L][nb][H]
   size_t zh;                       // act: [B][max(din0, H) + H]
-  size_t fstat, dout, dh0, dh1, dG, dhp, dcp, dvis, whT;
+  size_t fstat, dout, dh0, dh1, dG, dG2, dhp, dcp, dvis, whT;
   size_t sync;                     // persistent recurrence barrier words
   size_t wT;                       // one unit's weights reordered for its data gradient
   size_t total;
@@ -280,6 +280,7 @@ WsLayout plan(const ppo_net* n, int F, int nb, bool learn) {
     w.dh0 = A.take((size_t)F * wmax * f4);
     w.dh1 = A.take((size_t)F * wmax * f4);
     w.dG = A.take((size_t)F * 4 * H * f4);
+    w.dG2 = A.take(L == 2 ? (size_t)F * 4 * H * f4 : 0);  // layer 0's dG in the two-layer recurrence
     w.dhp = A.take((size_t)std::max(nb, 1) * H * f4);
     w.dcp = A.take((size_t)std::max(nb, 1) * H * f4);
     w.dvis = A.take((size_t)F * d.vis_hidden * f4);
@@ -712,6 +713,20 @@ const float* learner_fwd(const Ctx& c, const ppo_batch* b, const Sched& S) {
   launch_embed_fwd(b->goal, b->prev_action, b->mask, src, F, polar, d.goal_dim,
                    polar ? c.pf(net->goal_w) : nullptr, polar ? c.pf(net->goal_b) : nullptr, E,
                    E ? c.pf(net->emb) : nullptr, Z, D0, d.vis_hidden, s);
+  if (L == 2) {
+    // both layers in one pipelined launch: only layer 0's input projection runs as a product
+    const size_t w0 = net->lstm_w[0], w1 = net->lstm_w[1];
+    gemm_dense(net->prec, false, false, Z, D0, c.wt(w0), net->prec == 1, D0 + H, F, 4 * H, D0,
+               epi(c.at(w.g[0]), 4 * H, c.pf(net->lstm_b[0])), false, kSplitKBytes, c.splitk(), s);
+    for (int l = 0; l < 2; ++l)
+      launch_mask_state(c.at(w.h0g) + (size_t)l * nb * H, c.at(w.c0g) + (size_t)l * nb * H, mskf, act[0], H,
+                        c.at(w.hp[l]), H, c.at(w.cp[l]), s);
+    if (launch_lstm_seq2_fwd(net->prec, S.m, TB, H, c.wt(w0 + D0), D0 + H,
+                             c.wt(w1), c.pf(net->lstm_b[1]), c.at(w.g[0]), c.at(w.hp[0]), c.at(w.cp[0]),
+                             c.at(w.c[0]), c.at(w.hout[0]), c.at(w.g[1]), c.at(w.hp[1]), c.at(w.cp[1]),
+                             c.at(w.c[1]), c.at(w.hout[1]), mskf, c.at<unsigned>(w.sync), s) == 0)
+      return feat;
+  }
   for (int l = 0; l < L; ++l) {
     const int din = l == 0 ? D0 : H;
     const float* X = l == 0 ? Z : c.at(w.hout[l - 1]);
@@ -767,7 +782,32 @@ void learner_bwd(const Ctx& c, const ppo_batch* b, const Sched& S, const float* 
              epi(grad + net->head_w, H), true, kSplitKBytes, c.splitk(), s);
   launch_colsum(dout, F, A + 1, A + 1, grad + net->head_b, s);
   float* dHn = c.at(w.dh1);
-  for (int l = L - 1; l >= 0; --l) {
+  int l_top = L - 1;
+  if (L == 2) {
+    // both layers in one pipelined launch; layer 0's input gradient is formed in-kernel
+    const size_t w0 = net->lstm_w[0], w1 = net->lstm_w[1];
+    float *dG0 = c.at(w.dG2), *dG1 = c.at(w.dG);
+    if (launch_lstm_seq2_bwd(net->prec, S.m, TB, H, c.wt(w0 + D0), D0 + H, c.wt(w1), c.at(w.g[0]), c.at(w.cp[0]),
+                             c.at(w.c[0]), c.at(w.g[1]), c.at(w.cp[1]), c.at(w.c[1]), dH, dG0, dG1, mskf,
+                             c.at<unsigned>(w.sync), s) == 0) {
+      const float* H0 = c.at(w.hout[0]);
+      gemm_dense(net->prec, true, true, dG1, 4 * H, H0, false, H, 4 * H, H, F, epi(grad + w1, 2 * H), true,
+                 kSplitKBytes, c.splitk(), s);
+      gemm_dense(net->prec, true, true, dG1, 4 * H, c.at(w.hp[1]), false, H, 4 * H, H, F,
+                 epi(grad + w1 + H, 2 * H), true, kSplitKBytes, c.splitk(), s);
+      launch_colsum(dG1, F, 4 * H, 4 * H, grad + net->lstm_b[1], s);
+      gemm_dense(net->prec, true, true, dG0, 4 * H, Z, false, D0, 4 * H, D0, F, epi(grad + w0, D0 + H), true,
+                 kSplitKBytes, c.splitk(), s);
+      gemm_dense(net->prec, true, true, dG0, 4 * H, c.at(w.hp[0]), false, H, 4 * H, H, F,
+                 epi(grad + w0 + D0, D0 + H), true, kSplitKBytes, c.splitk(), s);
+      launch_colsum(dG0, F, 4 * H, 4 * H, grad + net->lstm_b[0], s);
+      gemm_dense(net->prec, false, true, dG0, 4 * H, c.wt(w0), net->prec == 1, D0 + H, F, D0, 4 * H,
+                 epi(dHn, D0), true, kSplitKBytes, c.splitk(), s);
+      std::swap(dH, dHn);
+      l_top = -1;
+    }
+  }
+  for (int l = l_top; l >= 0; --l) {
     const int din = l == 0 ? D0 : H;
     const float* X = l == 0 ? Z : c.at(w.hout[l - 1]);
     const size_t wl = net->lstm_w[l];

@@ -163,6 +163,22 @@ int launch_lstm_seq_bwd(int prec, const MapArgs& m, int TB, int H, const void* W
                         const float* CP, const float* Cs, const float* dH, int ldd, float* dG, const float* mskf,
                         unsigned* sync, hipStream_t s);
 
+// Both layers of a 2-layer LSTM in one cooperative launch per direction,
+// pipelined one step apart (T + 1 barriers).  Forward: G0 holds x W_ih0^T + b0
+// on entry; layer 1's input projection (W1 = [W_ih1 | W_hh1], [4H][2H]) and
+// bias b1 are applied in-kernel; HP/CP rows of step 0 of both layers are set
+// by the caller.  Backward: dHtop is the gradient at layer 1's output; writes
+// dG1 and dG0 (layer 0's input gradient dG1 W_ih1 is formed in-kernel).
+// Return 0 when launched, nonzero when not (nothing launched).
+int launch_lstm_seq2_fwd(int prec, const MapArgs& m, int TB, int H, const void* Whh0, int ldw0, const void* W1,
+                         const float* b1, float* G0, float* HP0, float* CP0, float* Cs0, float* Ho0, float* G1,
+                         float* HP1, float* CP1, float* Cs1, float* Ho1, const float* mskf, unsigned* sync,
+                         hipStream_t s);
+int launch_lstm_seq2_bwd(int prec, const MapArgs& m, int TB, int H, const void* Whh0, int ldw0, const void* W1,
+                         const float* G0, const float* CP0, const float* Cs0, const float* G1, const float* CP1,
+                         const float* Cs1, const float* dHtop, float* dG0, float* dG1, const float* mskf,
+                         unsigned* sync, hipStream_t s);
+
 // lstm_act.hip: the act step's goal / embedding inputs and masked state
 // (one launch), then one launch per LSTM layer (see the file header)
 void launch_act_core_prep(const float* goal, const int32_t* prev_a, const float* mask, int B, int polar,
