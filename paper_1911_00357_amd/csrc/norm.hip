@@ -474,6 +474,23 @@ void launch_relu_grad(const float* dy, const float* y, size_t n, float* dx, hipS
 // apply.  The input is the convolution output, or the sum of its split-K
 // partial tiles (src + z*zstride), in which case the summed output can also
 // be stored (u_out) for the backward.
+// Two block sums in one reduction (double within each wavefront).
+template <int NT>
+DEV float2 block_sum2(float v0, float v1, float2* red) {
+  const double d0 = wave_sum((double)v0), d1 = wave_sum((double)v1);
+  const int w = threadIdx.x >> 6;
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) red[w] = make_float2((float)d0, (float)d1);
+  __syncthreads();
+  float2 t = make_float2(0.f, 0.f);
+#pragma unroll
+  for (int i = 0; i < NT / 64; ++i) {
+    t.x += red[i].x;
+    t.y += red[i].y;
+  }
+  return t;
+}
+
 template <int NT = 256>
 DEV float block_sum(float v, float* red) {
   double d = wave_sum((double)v);
@@ -557,7 +574,7 @@ __global__ void __launch_bounds__(NT) gnb_fused_kernel(const float* __restrict__
                                                         const float2* __restrict__ stats,
                                                         const float* __restrict__ gamma, float* __restrict__ dy,
                                                         float* __restrict__ dres, float2* __restrict__ bpart) {
-  __shared__ float red[NT / 64];
+  __shared__ float2 red2[NT / 64];
   __shared__ float2 cred[NT];
   const int b = blockIdx.x / G, g = blockIdx.x - b * G;
   const int Cg = C / G, n = P * Cg;
@@ -587,8 +604,8 @@ __global__ void __launch_bounds__(NT) gnb_fused_kernel(const float* __restrict__
     cz += dz[j];
     czx += dz[j] * xh[j];
   }
-  const float m1 = block_sum<NT>(s1, red) / n;
-  const float m2 = block_sum<NT>(s2, red) / n;
+  const float2 sm = block_sum2<NT>(s1, s2, red2);
+  const float m1 = sm.x / n, m2 = sm.y / n;
 #pragma unroll
   for (int j = 0; j < NPT; ++j) {
     if (p0 + j * pstep < P) {
