@@ -12,6 +12,8 @@ DEV void head_dots(const float* __restrict__ h, const float* __restrict__ W, con
   float acc[kMaxA];
 #pragma unroll
   for (int k = 0; k < kMaxA; ++k) acc[k] = 0.f;
+  // unrolled so that several rows' loads are in flight together
+#pragma unroll 8
   for (int j = lane; j < H; j += 64) {
     const float hv = h[j];
 #pragma unroll

@@ -521,6 +521,12 @@ __global__ void __launch_bounds__(NT) gn_fused_kernel(const float* __restrict__ 
   // the split-K partials, ZB splits per round with every load of a round in
   // flight together (summed in split order: deterministic)
   constexpr int ZB = NPT >= 16 ? 1 : NPT >= 8 ? 2 : NPT >= 4 ? 4 : 8;
+  // the affine parameters and the residual are loaded up front, so their
+  // latency overlaps the input loads and the reductions
+  const float gm = gamma[c], be = beta[c];
+  float rv[NPT];
+#pragma unroll
+  for (int j = 0; j < NPT; ++j) rv[j] = (res && p0 + j * pstep < P) ? res[base + j * jstr] : 0.f;
   float x[NPT];
 #pragma unroll
   for (int j = 0; j < NPT; ++j) x[j] = 0.f;
@@ -550,14 +556,13 @@ __global__ void __launch_bounds__(NT) gn_fused_kernel(const float* __restrict__ 
   const float var = block_sum<NT>(q, red) / n;
   const float rstd = 1.0f / sqrtf(var + eps);
   if (threadIdx.x == 0) stats[blockIdx.x] = make_float2(mean, rstd);
-  const float ga = gamma[c] * rstd, be = beta[c];
+  const float ga = gm * rstd;
 #pragma unroll
   for (int j = 0; j < NPT; ++j) {
     const int p = p0 + j * pstep;
     if (p < P) {
       const size_t idx = base + j * jstr;
-      float o = (x[j] - mean) * ga + be;
-      if (res) o += res[idx];
+      float o = (x[j] - mean) * ga + be + rv[j];
       if (relu) o = fmaxf(o, 0.f);
       out[out_chw ? ((size_t)b * C + c) * P + p : idx] = o;
     }
