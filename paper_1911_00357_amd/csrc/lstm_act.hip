@@ -80,32 +80,50 @@ __global__ void __launch_bounds__(256) lstm_act_layer_kernel(const float* __rest
       w[i] = k < K ? ldf(wr + k) : 0.f;
     }
   }
-  for (int r = 0; r < B; ++r) {
+  // pointwise operands of this thread's first item, loaded before the products
+  const int it0 = threadIdx.x, r0 = it0 / U, u0 = it0 - r0 * U, j0p = j0 + u0;
+  float pb[4] = {0.f, 0.f, 0.f, 0.f}, pc = 0.f;
+  if (it0 < B * U) {
+#pragma unroll
+    for (int qq = 0; qq < 4; ++qq) pb[qq] = bias[qq * H + j0p];
+    pc = CM[(size_t)r0 * H + j0p];
+  }
+  // every load unconditional (k >= K reads a valid element that meets a zero
+  // weight), so all of them are in flight together; row r + 1 is loaded while
+  // row r is reduced
+  auto load_row = [&](int r, float (&v)[KMAX]) {
     const float* xr = X + (size_t)r * ldx;
     const float* hr = HM + (size_t)r * H;
-    // every load unconditional (k >= K reads a valid element that meets a zero
-    // weight), so all of them are in flight before the first product
-    float xv[KMAX];
 #pragma unroll
     for (int i = 0; i < KMAX; ++i) {
       const int k = s + TPC * i;
       const float* p = k < din ? xr + k : hr + min(k - din, H - 1);
-      xv[i] = *p;
+      v[i] = *p;
     }
+  };
+  float xv[KMAX], xn[KMAX];
+  load_row(0, xv);
+  for (int r = 0; r < B; ++r) {
+    load_row(min(r + 1, B - 1), xn);
     float acc = 0.f;
 #pragma unroll
     for (int i = 0; i < KMAX; ++i) acc = fmaf(op_round(xv[i], BF), w[i], acc);
 #pragma unroll
     for (int o = TPC / 2; o > 0; o >>= 1) acc += __shfl_xor(acc, o, kWave);
     if (s == 0) gates[r * 4 * U + col] = acc;
+#pragma unroll
+    for (int i = 0; i < KMAX; ++i) xv[i] = xn[i];
   }
   __syncthreads();
   for (int it = threadIdx.x; it < B * U; it += 256) {
     const int r = it / U, u = it - r * U, j = j0 + u;
     const float* gr = gates + r * 4 * U + u;
-    const float ig = sigm(gr[0] + bias[j]), fg = sigm(gr[U] + bias[H + j]);
-    const float gg = tanhf(gr[2 * U] + bias[2 * H + j]), og = sigm(gr[3 * U] + bias[3 * H + j]);
-    const float c2 = fg * CM[(size_t)r * H + j] + ig * gg;
+    const bool first = it == it0;
+    const float b0 = first ? pb[0] : bias[j], b1 = first ? pb[1] : bias[H + j];
+    const float b2 = first ? pb[2] : bias[2 * H + j], b3 = first ? pb[3] : bias[3 * H + j];
+    const float ig = sigm(gr[0] + b0), fg = sigm(gr[U] + b1);
+    const float gg = tanhf(gr[2 * U] + b2), og = sigm(gr[3 * U] + b3);
+    const float c2 = fg * (first ? pc : CM[(size_t)r * H + j]) + ig * gg;
     c_out[(size_t)r * H + j] = c2;
     h_out[(size_t)r * H + j] = og * tanhf(c2);
   }

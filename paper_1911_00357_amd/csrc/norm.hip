@@ -520,7 +520,7 @@ __global__ void __launch_bounds__(NT) gn_fused_kernel(const float* __restrict__ 
   const size_t base = ((size_t)b * P + p0) * C + c, jstr = (size_t)pstep * C;
   // the split-K partials, ZB splits per round with every load of a round in
   // flight together (summed in split order: deterministic)
-  constexpr int ZB = NPT >= 16 ? 1 : NPT >= 8 ? 2 : NPT >= 4 ? 4 : 8;
+  constexpr int ZB = NPT >= 16 ? 1 : 16 / NPT;
   // the affine parameters and the residual are loaded up front, so their
   // latency overlaps the input loads and the reductions
   const float gm = gamma[c], be = beta[c];
