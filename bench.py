@@ -265,6 +265,24 @@ def dominant_gemm(wl, seed, reps=5):
     return u, op, name, round(tot_f / (tot_t / 1e3) / 1e12, 3)
 
 
+def committed_gemm(wl):
+    """(unit, op, name, None) of the roofline kernel named in the committed
+    bench line of this workload (profiles/bench_<workload>.json)."""
+    import paper_1911_00357_amd as P
+    from paper_1911_00357_amd._lib import PPO_OP_LEARN
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles", f"bench_{wl.name}.json")
+    with open(path) as f:
+        label = json.load(f)["roofline"]["kernel"]
+    op = next(i for i, s in enumerate(OPS) if label.startswith(s + " GEMM of "))
+    name = label[len(OPS[op] + " GEMM of "):]
+    n = P.Net(wl.net, wl.dtype)
+    F = wl.T * wl.N // wl.ppo.minibatches
+    for u in range(n.probe(PPO_OP_LEARN, F, 1, 3)[3][0]):
+        if n.probe(PPO_OP_LEARN, F, 1, 0, u)[0] == name:
+            return u, op, name, None
+    raise SystemExit(f"unit {name} not found")
+
+
 COPY_BYTES = 256 << 20
 
 
@@ -385,11 +403,12 @@ def main():
         sys.exit(1)
     from synth.configs import WORKLOADS
     wl = WORKLOADS[a.workload]
+    if a.pmc_probe:
+        # the kernel the committed bench line names (counter runs distort the timing-based selection)
+        pmc_probe(wl, a.seed, committed_gemm(wl))
+        return
     progress(f"workload {a.workload}: selecting the dominant learner GEMM")
     sel = dominant_gemm(wl, a.seed)
-    if a.pmc_probe:
-        pmc_probe(wl, a.seed, sel)
-        return
     progress("timed run")
     res = run_gpu(wl, a.steps, a.warmup, a.seed, timer=sel[:2])
     roof = roofline_live(wl, sel, res["timed"])
