@@ -314,10 +314,10 @@ def pmc_probe(wl, seed, sel):
                                     "frames": F}}), flush=True)
 
 
-def traffic_bytes(kernel):
+def traffic_bytes(kernel, workload):
     """Per-launch HBM bytes (fetch + write) of `kernel` from the committed PMC
-    summary, or None when that summary is missing or was taken on other GEMM
-    sources than the ones built now."""
+    summary, or None when that summary is missing, was taken on another
+    workload or on other GEMM sources than the ones built now."""
     import hashlib
     path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles", "pmc_traffic.json")
     if not os.path.exists(path):
@@ -328,7 +328,7 @@ def traffic_bytes(kernel):
     for name in rec.get("sources", []):
         with open(os.path.join(os.path.dirname(os.path.abspath(__file__)), name), "rb") as f:
             h.update(f.read())
-    if rec.get("kernel") != kernel or rec.get("sources_sha256") != h.hexdigest():
+    if rec.get("kernel") != kernel or rec.get("workload") != workload or rec.get("sources_sha256") != h.hexdigest():
         return None
     return rec["fetch_bytes_per_launch"] + rec["write_bytes_per_launch"]
 
@@ -345,7 +345,7 @@ def roofline_live(wl, sel, timed):
                 "traffic": None, "kernel": f"{OPS[op]} GEMM of {name}"}
     ach = fl / (ms / 1e3) / 1e12
     return {"bound": "mfma", "achieved": round(ach, 3), "peak": peak, "unit": "TFLOP/s",
-            "frac": round(ach / peak, 5), "traffic": traffic_bytes(f"{OPS[op]} GEMM of {name}"),
+            "frac": round(ach / peak, 5), "traffic": traffic_bytes(f"{OPS[op]} GEMM of {name}", wl.name),
             "kernel": f"{OPS[op]} GEMM of {name}", "launches": launches,
             "avg_launch_us": round(ms / launches * 1e3, 2), "flops_per_launch": fl / launches,
             "all_conv_gemms_tflops_microbench": all_tf}
