@@ -36,10 +36,12 @@ namespace {
 
 constexpr int kSpinLimit = 1 << 21;  // polls of about 1 us each
 constexpr int kDeviceScope = 16;     // buffer-load cache policy bit for device (agent) scope coherence
-constexpr int kRowsF = 16;           // exchanged rows staged per round: forward, one layer
-constexpr int kRowsB = 4;            // backward, one layer (rows of 4H)
-constexpr int kRowsF2 = 8;           // forward, two layers (three row sets)
-constexpr int kRowsB2 = 4;           // backward, two layers (two row sets of 4H)
+// exchanged rows staged per round (32 KB of forward rows, 32 KB of backward
+// rows for one layer; 48 / 64 KB for two layers): 16 / 4 / 8 / 4 rows at H = 512
+constexpr int rows_f(int H) { return 8192 / H; }   // forward, one layer
+constexpr int rows_b(int H) { return 2048 / H; }   // backward, one layer (rows of 4H)
+constexpr int rows_f2(int H) { return 4096 / H; }  // forward, two layers (three row sets)
+constexpr int rows_b2(int H) { return 2048 / H; }  // backward, two layers (two row sets of 4H)
 
 struct SeqArgs {
   const void* W;  // layer weights [4H][ldw]; W_hh at column offset 0 of this pointer
@@ -164,6 +166,7 @@ __global__ void __launch_bounds__(256) lstm_seq_fwd_kernel(SeqArgs a) {
   constexpr int TPC = 64 / U;
   constexpr int H = TPC * KPT;
   constexpr bool BF = sizeof(TW) == 2;
+  constexpr int kRowsF = rows_f(H);
   int* off = (int*)lds;                      // [TB + 1]
   float* gates = lds + ((a.TB + 4) & ~3);    // [nb][4U]
   float* cst = gates + kMaxMbEnvs * 4 * U;   // [nb][U] masked c_{t-1}
@@ -252,6 +255,7 @@ __global__ void __launch_bounds__(256) lstm_seq_bwd_kernel(SeqArgs a) {
   constexpr int TPB = 256 / U;
   constexpr int WPU = TPB / 64;  // wavefronts per unit (>= 1)
   constexpr int H4 = TPB * KPT, H = H4 / 4;
+  constexpr int kRowsB = rows_b(H);
   int* off = (int*)lds;                          // [TB + 1]
   float* red = lds + ((a.TB + 4) & ~3);          // [4 waves][nb]
   float* dcs = red + 4 * kMaxMbEnvs;             // [nb][U] dc carry
@@ -358,6 +362,7 @@ __global__ void __launch_bounds__(256) lstm_seq2_fwd_kernel(Seq2Args a) {
   constexpr int TPC = 64 / U;
   constexpr int H = TPC * KPT;
   constexpr bool BF = sizeof(TW) == 2;
+  constexpr int kRowsF2 = rows_f2(H);
   int* off = (int*)lds;                        // [TB + 1]
   float* g0 = lds + ((a.TB + 4) & ~3);         // [nb][4U] gates of layer 0
   float* g1 = g0 + kMaxMbEnvs * 4 * U;         // [nb][4U] gates of layer 1
@@ -492,6 +497,7 @@ __global__ void __launch_bounds__(256) lstm_seq2_bwd_kernel(Seq2Args a) {
   constexpr int TPB = 256 / U;
   constexpr int WPU = TPB / 64;
   constexpr int H4 = TPB * KPT, H = H4 / 4;
+  constexpr int kRowsB2 = rows_b2(H);
   int* off = (int*)lds;                        // [TB + 1]
   float* r1 = lds + ((a.TB + 4) & ~3);         // [4 waves][nb]: dG1_{t+1} W_hh1 (layer 1 carry)
   float* rx = r1 + 4 * kMaxMbEnvs;             // [4 waves][nb]: dG1_{t0} W_ih1 (layer 0 input gradient)
@@ -609,10 +615,12 @@ __global__ void zero_sync_kernel(unsigned* p, int n) {
 }
 
 // Units per block: the smallest U (1, 2, 4) with H U a multiple of 256 and
-// at most 256 blocks; 0 when no such U keeps KPT = H U / 64 within 32.
+// at most 256 blocks; 0 when no such U keeps KPT = H U / 64 within 64
+// (H = 1024: U = 4, KPT = 64) or H outside [64, 1024].
 int pick_units(int H) {
+  if (H < 64 || H > 1024) return 0;
   for (int U = 1; U <= 4; U *= 2)
-    if ((H * U) % 256 == 0 && H / U <= 256 && H * U / 64 <= 32) return U;
+    if ((H * U) % 256 == 0 && H / U <= 256 && H * U / 64 <= 64) return U;
   return 0;
 }
 
@@ -628,7 +636,7 @@ const void* pick_kernel(int prec, bool bwd, int U, int KPT) {
   if (U == U_ && KPT == K_) return seq_kernel<U_, K_>(prec, bwd);
   SEQ_CASE(1, 4) SEQ_CASE(1, 8) SEQ_CASE(1, 16) SEQ_CASE(1, 32)
   SEQ_CASE(2, 4) SEQ_CASE(2, 8) SEQ_CASE(2, 16) SEQ_CASE(2, 32)
-  SEQ_CASE(4, 4) SEQ_CASE(4, 8) SEQ_CASE(4, 16) SEQ_CASE(4, 32)
+  SEQ_CASE(4, 4) SEQ_CASE(4, 8) SEQ_CASE(4, 16) SEQ_CASE(4, 32) SEQ_CASE(4, 64)
 #undef SEQ_CASE
   return nullptr;
 }
@@ -641,7 +649,7 @@ int launch_seq(int prec, bool bwd, const MapArgs& m, int TB, int H, const void* 
   const int KPT = H * U / 64;
   const void* k = pick_kernel(prec, bwd, U, KPT);
   if (!k) return 1;
-  const size_t stg = bwd ? (size_t)kRowsB * 4 * H : (size_t)kRowsF * H;
+  const size_t stg = bwd ? (size_t)rows_b(H) * 4 * H : (size_t)rows_f(H) * H;
   const size_t shmem =
       (size_t)(((TB + 4) & ~3) + (bwd ? 4 : 4 * U) * kMaxMbEnvs + kMaxMbEnvs * U + stg) * sizeof(float);
   if ((long)m.F * 4 * H * 4 >= 0x7fffffffL) return 1;  // exchange offsets are 32-bit
@@ -703,7 +711,7 @@ const void* pick_kernel2(int prec, bool bwd, int U, int KPT) {
   if (U == U_ && KPT == K_) return seq2_kernel<U_, K_>(prec, bwd);
   SEQ2_CASE(1, 4) SEQ2_CASE(1, 8) SEQ2_CASE(1, 16) SEQ2_CASE(1, 32)
   SEQ2_CASE(2, 4) SEQ2_CASE(2, 8) SEQ2_CASE(2, 16) SEQ2_CASE(2, 32)
-  SEQ2_CASE(4, 4) SEQ2_CASE(4, 8) SEQ2_CASE(4, 16) SEQ2_CASE(4, 32)
+  SEQ2_CASE(4, 4) SEQ2_CASE(4, 8) SEQ2_CASE(4, 16) SEQ2_CASE(4, 32) SEQ2_CASE(4, 64)
 #undef SEQ2_CASE
   return nullptr;
 }
@@ -715,8 +723,8 @@ int launch_seq2(int prec, bool bwd, const MapArgs& m, int TB, Seq2Args& a, hipSt
   const int KPT = H * U / 64;
   const void* k = pick_kernel2(prec, bwd, U, KPT);
   if (!k) return 1;
-  const size_t nf = bwd ? (size_t)3 * 4 * kMaxMbEnvs + 2 * kMaxMbEnvs * U + 2 * kRowsB2 * 4 * H
-                        : (size_t)2 * kMaxMbEnvs * 4 * U + 2 * kMaxMbEnvs * U + 3 * kRowsF2 * H;
+  const size_t nf = bwd ? (size_t)3 * 4 * kMaxMbEnvs + 2 * kMaxMbEnvs * U + 2 * rows_b2(H) * 4 * H
+                        : (size_t)2 * kMaxMbEnvs * 4 * U + 2 * kMaxMbEnvs * U + 3 * rows_f2(H) * H;
   const size_t shmem = (((TB + 4) & ~3) + nf) * sizeof(float);
   if ((long)m.F * 4 * H * 4 >= 0x7fffffffL) return 1;  // exchange offsets are 32-bit
   const int nblk = H / U;

@@ -17,6 +17,9 @@ RESNET_64 = NetDesc(in_hw=64)
 RESNET_SMALLCORE = NetDesc(in_hw=64, vis_hidden=16, goal_dim=8, prev_act_dim=8, hidden=16)
 TINY_BIGCORE = NetDesc(in_hw=32, avgpool=False, trunk="tiny", gn_groups=8, vis_hidden=512,
                        goal_mode="polar", goal_dim=32, prev_act_dim=32, lstm_layers=2, hidden=512)
+# the 1024-unit LSTM variant of the paper's larger agents (tiny trunk)
+TINY_CORE1024 = NetDesc(in_hw=32, avgpool=False, trunk="tiny", gn_groups=8, vis_hidden=512,
+                        goal_mode="polar", goal_dim=32, prev_act_dim=32, lstm_layers=2, hidden=1024)
 
 
 def wl(net, T=4, N=3, dtype="f32", ragged=False, **ppo):

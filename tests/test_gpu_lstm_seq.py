@@ -12,7 +12,7 @@ from oracle import ppo
 from synth import rollout as R
 from synth.configs import TINY_NET, NetDesc, PPOCfg
 from tests.gpu_util import DEV, oracle_minibatch, random_record, rel_err, to_device
-from tests.nets import TINY_BIGCORE
+from tests.nets import TINY_BIGCORE, TINY_CORE1024
 from tests.test_gpu_parity import say
 
 pytestmark = pytest.mark.gpu
@@ -56,6 +56,7 @@ CASES = [
     ("bigcore_equal", TINY_BIGCORE, 8, 3, [0, 1, 2], None),
     ("tiny", TINY_NET, 16, 4, [0, 1, 2, 3], [16, 1, 11, 5]),
     ("tiny_2l64", TINY_2L64, 10, 6, [5, 0, 3, 1, 2], [10, 2, 7, 1, 10, 4]),
+    ("core1024", TINY_CORE1024, 6, 3, [2, 0, 1], [6, 2, 5]),
 ]
 TWO_LAYER = [c for c in CASES if c[1].lstm_layers == 2]
 
@@ -94,11 +95,13 @@ def test_seq2_matches_per_layer_and_step(P, name, net, T, N, envs, lengths, dtyp
         assert abs(s2[0] - s_ref[0]) <= tol * max(abs(s_ref[0]), 1e-6)
 
 
+@pytest.mark.parametrize("core", ["512", "1024"])
 @pytest.mark.parametrize("mode", ["seq2", "seq"])
 @pytest.mark.parametrize("dtype,tol", [("f32", 1e-4), ("bf16", 2e-2)])
-def test_seq_bigcore_vs_oracle(P, dtype, tol, mode):
-    say(f"lstm {mode} vs oracle bigcore {dtype}")
-    net, T, N, envs, lengths = TINY_BIGCORE, 7, 4, [3, 1, 0], [7, 6, 2, 5]
+def test_seq_bigcore_vs_oracle(P, dtype, tol, mode, core):
+    say(f"lstm {mode} vs oracle core {core} {dtype}")
+    net = TINY_BIGCORE if core == "512" else TINY_CORE1024
+    T, N, envs, lengths = 7, 4, [3, 1, 0], [7, 6, 2, 5]
     flat, rec, envs, g, s = _run(P, net, dtype, T, N, envs, lengths, 21, mode)
     mb = oracle_minibatch(rec, envs)
     s_ref, g_ref = ppo.loss_grad(flat.astype(np.float64), net, PPOCfg(), mb)

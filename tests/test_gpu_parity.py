@@ -12,7 +12,7 @@ from oracle import params as OP, policy, ppo
 from synth import rollout as R
 from synth.configs import C0, C1, PPOCfg
 from tests.gpu_util import DEV, oracle_minibatch, per_tensor_errors, random_record, rel_err, to_device
-from tests.nets import MINI_RESNET, RESNET_64, RESNET_SMALLCORE, TINY_BIGCORE, TINY_NET, TINY_PLUS
+from tests.nets import MINI_RESNET, RESNET_64, RESNET_SMALLCORE, TINY_BIGCORE, TINY_CORE1024, TINY_NET, TINY_PLUS
 
 pytestmark = pytest.mark.gpu
 TOL = {"f32": 1e-4, "bf16": 2e-2}
@@ -132,6 +132,8 @@ def _act_case(P, net, dtype, B, seed, state_rows=0):
                                               ("mini_resnet", MINI_RESNET, "f32", 4),
                                               ("resnet_smallcore", RESNET_SMALLCORE, "f32", 2),
                                               ("tiny_bigcore", TINY_BIGCORE, "f32", 4),
+                                              ("tiny_core1024", TINY_CORE1024, "f32", 3),
+                                              ("tiny_core1024", TINY_CORE1024, "bf16", 3),
                                               ("resnet64", RESNET_64, "f32", 2),
                                               ("tiny+", TINY_PLUS, "bf16", 3),
                                               ("mini_resnet", MINI_RESNET, "bf16", 4)])
