@@ -394,7 +394,7 @@ def main():
     GRAPH = not a.eager
     AUTOGRAD = a.autograd == "on" or (a.autograd == "auto" and a.workload == "C3")
     if a.gpus != 1:
-        print(json.dumps({"error": "this build measures one GPU; the gradient all-reduce of a "
+        print(json.dumps({"error": "this benchmark measures one GPU; the gradient all-reduce of a "
                                    "multi-GPU worker group is not implemented", "n_gpus": a.gpus}))
         sys.exit(2)
     import torch

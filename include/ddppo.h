@@ -259,7 +259,7 @@ ppo_status ppo_adam_step(float* master, const float* grad, float* m, float* v, v
 
 /* Test introspection of a workspace laid out for (op, max_frames, max_envs):
  * where a call leaves the forward activations that decided each ReLU and
- * max pool, so a checker can take the same decisions.  Frames are in the
+ * max pool, so a reference implementation can take the same decisions.  Frames are in the
  * call's packed order (time-major; envs sorted by length, longest first,
  * ties in the given order).
  *   kind 0: normalised output of trunk unit `index` (conv + GroupNorm [+ residual]
