@@ -12,16 +12,28 @@ DEV void head_dots(const float* __restrict__ h, const float* __restrict__ W, con
   float acc[kMaxA];
 #pragma unroll
   for (int k = 0; k < kMaxA; ++k) acc[k] = 0.f;
-  // unrolled so that several rows' loads are in flight together
-#pragma unroll 8
+  // branch-free loads (rows k >= A1 re-read row A1-1 and are discarded), so
+  // the loads of an iteration, and of the unrolled iterations, are in flight together
+#pragma unroll 4
   for (int j = lane; j < H; j += 64) {
     const float hv = h[j];
 #pragma unroll
-    for (int k = 0; k < kMaxA; ++k)
-      if (k < A1) acc[k] += W[(size_t)k * H + j] * hv;
+    for (int k = 0; k < kMaxA; ++k) acc[k] += W[(size_t)min(k, A1 - 1) * H + j] * hv;
   }
 #pragma unroll
   for (int k = 0; k < kMaxA; ++k) out[k] = (k < A1) ? wave_sum(acc[k]) + b[k] : 0.f;
+}
+
+// One wavefront per row: dh[j] = sum_{k < A1} d[k] W[k][j] (d[k] = 0 for k >= A1).
+DEV void head_dh(const float d[kMaxA], const float* __restrict__ W, int H, int A1, float* __restrict__ dh) {
+  const int lane = threadIdx.x & 63;
+#pragma unroll 4
+  for (int j = lane; j < H; j += 64) {
+    float v = 0.f;
+#pragma unroll
+    for (int k = 0; k < kMaxA; ++k) v += d[k] * W[(size_t)min(k, A1 - 1) * H + j];
+    dh[j] = v;
+  }
 }
 
 // Act head: logits, value, log-softmax, inverse-CDF sample.
@@ -128,11 +140,7 @@ __global__ void __launch_bounds__(256) loss_head_kernel(
     fs[5] = ratio;
     for (int k = 0; k <= A; ++k) dout[(size_t)f * (A + 1) + k] = d[k];
   }
-  for (int j = lane; j < H; j += 64) {
-    float v = 0.f;
-    for (int k = 0; k <= A; ++k) v += d[k] * W[(size_t)k * H + j];
-    dh[(size_t)f * H + j] = v;
-  }
+  head_dh(d, W, H, A + 1, dh + (size_t)f * H);
 }
 
 // stats[8] = {loss, pg, vf, ent, clip_frac, approx_kl, ratio_min, ratio_max}
@@ -394,15 +402,13 @@ __global__ void __launch_bounds__(256) head_bwd_kernel(const float* __restrict__
   const int f = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
   if (f >= F) return;
   float d[kMaxA];
+#pragma unroll
+  for (int k = 0; k < kMaxA; ++k) d[k] = 0.f;
   for (int k = 0; k < A; ++k) d[k] = dlogits[(size_t)f * A + k];
   d[A] = dvalues[f];
   if (lane == 0)
     for (int k = 0; k <= A; ++k) dout[(size_t)f * (A + 1) + k] = d[k];
-  for (int j = lane; j < H; j += 64) {
-    float v = 0.f;
-    for (int k = 0; k <= A; ++k) v += d[k] * W[(size_t)k * H + j];
-    dh[(size_t)f * H + j] = v;
-  }
+  head_dh(d, W, H, A + 1, dh + (size_t)f * H);
 }
 
 __global__ void __launch_bounds__(256) copy_i32_kernel(const int32_t* __restrict__ s, int n, int32_t* __restrict__ d) {

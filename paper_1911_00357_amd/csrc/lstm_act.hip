@@ -74,10 +74,13 @@ __global__ void __launch_bounds__(256) lstm_act_layer_kernel(const float* __rest
   float w[KMAX];
   {
     const TW* wr = W + (size_t)(q * H + j0 + uc) * ldw;
+    // unconditional loads (k >= K re-reads element K-1, then zeroed): a load
+    // inside a branch would wait for its own result before the next is issued
 #pragma unroll
     for (int i = 0; i < KMAX; ++i) {
       const int k = s + TPC * i;
-      w[i] = k < K ? ldf(wr + k) : 0.f;
+      const float t = ldf(wr + min(k, K - 1));
+      w[i] = k < K ? t : 0.f;
     }
   }
   // pointwise operands of this thread's first item, loaded before the products

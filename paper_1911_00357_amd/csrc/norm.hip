@@ -349,21 +349,24 @@ __global__ void __launch_bounds__(256) maxpool_fwd_kernel(const float* __restric
     r /= Wo;
     const int ho = (int)(r % Ho);
     const int b = (int)(r / Ho);
+    // all nine window loads first (outside taps read a clamped in-bounds
+    // element and are skipped), then the first maximum in window order
+    float v[9];
+    bool ok[9];
+#pragma unroll
+    for (int t = 0; t < 9; ++t) {
+      const int hi = 2 * ho - 1 + t / 3, wi = 2 * wo - 1 + t % 3;
+      ok[t] = hi >= 0 && hi < H && wi >= 0 && wi < W;
+      v[t] = x[(((size_t)b * H + min(max(hi, 0), H - 1)) * W + min(max(wi, 0), W - 1)) * C + c];
+    }
     float best = -INFINITY;
     int bi = 0;
-    for (int kh = 0; kh < 3; ++kh) {
-      const int hi = 2 * ho - 1 + kh;
-      if (hi < 0 || hi >= H) continue;
-      for (int kw = 0; kw < 3; ++kw) {
-        const int wi = 2 * wo - 1 + kw;
-        if (wi < 0 || wi >= W) continue;
-        const float v = x[(((size_t)b * H + hi) * W + wi) * C + c];
-        if (v > best) {
-          best = v;
-          bi = kh * 3 + kw;
-        }
+#pragma unroll
+    for (int t = 0; t < 9; ++t)
+      if (ok[t] && v[t] > best) {
+        best = v[t];
+        bi = t;
       }
-    }
     y[e] = best;
     arg[e] = (uint8_t)bi;
   }
