@@ -128,8 +128,9 @@ bool capturing(hipStream_t s) {
 }
 
 // Times every (tile, split) candidate of one problem on stream s (output
-// redirected to scratch, so accumulating epilogues are not disturbed) and
-// returns the fastest; falls back to `dflt` when timing is not possible.
+// redirected to scratch, so accumulating epilogues are not disturbed; 2
+// launches, 16 when those take under 0.2 ms) and returns the fastest; falls
+// back to `dflt` when timing is not possible.
 template <class Prob, typename TC, bool SPLIT>
 std::pair<int, int> tune(const Prob& p, const Epi& e, long cap, float* partial, hipStream_t s,
                          std::pair<int, int> dflt) {
@@ -168,6 +169,13 @@ std::pair<int, int> tune(const Prob& p, const Epi& e, long cap, float* partial, 
         hipEventRecord(b, s);
         float ms = 0.f;
         if (hipEventSynchronize(b) != hipSuccess || hipEventElapsedTime(&ms, a, b) != hipSuccess) continue;
+        if (ms < 0.2f) {  // short launches: 16 more for a steadier figure (per 2 launches)
+          hipEventRecord(a, s);
+          for (int r = 0; r < 16; ++r) launch_tile<Prob, TC, SPLIT>((Tile)ti, p, et, z, partial, s, false);
+          hipEventRecord(b, s);
+          if (hipEventSynchronize(b) != hipSuccess || hipEventElapsedTime(&ms, a, b) != hipSuccess) continue;
+          ms /= 8.f;
+        }
         if (ms < best_ms) {
           best_ms = ms;
           best = {ti, z};
@@ -195,8 +203,10 @@ int run(const Prob& p, Epi e, size_t partial_bytes, float* partial, hipStream_t 
   const long cap = (long)(partial_bytes / (sizeof(float) * (size_t)p.M * p.N));
   if (splits > cap) splits = (int)std::max<long>(1, cap);
   GemmTune* tu = g_gemm_tune;
-  if (tu && !defer) {
-    const std::array<long long, 5> key{Prob::kKind, p.M, p.N, p.K, 2 * prec + (int)SPLIT};
+  if (tu) {
+    // a deferred product (its partial tiles summed by the consumer) is tuned
+    // on its own key, timed with the ordered reduction as the consumer's stand-in
+    const std::array<long long, 5> key{Prob::kKind, p.M, p.N, p.K, 2 * prec + (int)SPLIT + 4 * (int)defer};
     auto it = tu->best.find(key);
     if (it == tu->best.end() && tu->tuning && !capturing(s))
       it = tu->best.emplace(key, tune<Prob, TC, SPLIT>(p, e, std::max<long>(1, cap), partial, s, {(int)t, splits}))

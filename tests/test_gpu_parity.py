@@ -338,3 +338,42 @@ def test_autotuned_loss_backward(P):
     s_ref, g_ref = ppo.loss_grad(flat.astype(np.float64), net, PPOCfg(), mb)
     assert rel_err(g2.cpu().numpy(), g_ref) < 1e-4
     assert n.autotune(-1) == 0
+
+
+@pytest.mark.parametrize("dtype", ["f32", "bf16"])
+def test_autotuned_act(P, dtype):
+    """Act calls whose convolutions leave split-K partials for the GroupNorm
+    take tuned tiles too: the tuning call and a later call from the table give
+    the same bits, within the tolerance of the oracle."""
+    say(f"autotuned act {dtype}")
+    net, B = C1.net, 4
+    flat = R.init_params(net, 23, random_affine=True)
+    g = np.random.default_rng(24)
+    obs = g.random((B, net.in_ch, net.in_hw, net.in_hw), dtype=np.float32)
+    if dtype == "bf16":
+        obs = R.round_bf16(obs)
+    goal = g.standard_normal((B, 2)).astype(np.float32)
+    prev = g.integers(0, net.num_actions, B).astype(np.int32)
+    mask = np.ones(B, np.float32)
+    h = (0.5 * g.standard_normal((net.lstm_layers, B, net.hidden))).astype(np.float32)
+    c = (0.5 * g.standard_normal((net.lstm_layers, B, net.hidden))).astype(np.float32)
+    u = g.random(B).astype(np.float32)
+    n = P.Net(net, dtype)
+    params = torch.tensor(flat, device=DEV)
+    lp = P.cast_bf16(params) if dtype == "bf16" else None
+    td = lambda a: torch.tensor(a, device=DEV)
+    o = td(obs).to(torch.bfloat16) if dtype == "bf16" else td(obs)
+    n.autotune(1)
+    out1 = n.act(o, td(goal), td(prev), td(mask), td(h), td(c), td(u), params, lp, want_logits=True)
+    entries = n.autotune(0)
+    out2 = n.act(o, td(goal), td(prev), td(mask), td(h), td(c), td(u), params, lp, want_logits=True)
+    torch.cuda.synchronize()
+    assert entries > 0
+    for k in ("logits", "value", "h", "c", "action"):
+        assert torch.equal(out1[k], out2[k]), k
+    ref = policy.act(OP.unpack(net, flat), net, obs, goal, prev, mask, h, c, u)
+    ref["u"] = u
+    tol = TOL[dtype]
+    assert rel_err(out2["logits"].cpu().numpy(), ref["logits"]) < tol
+    assert rel_err(out2["h"].cpu().numpy(), ref["h"]) < tol
+    assert_actions_agree(out2["action"].cpu().numpy(), ref, tol)
