@@ -65,6 +65,7 @@ __global__ void __launch_bounds__(256) gn_finalize_kernel(const float4* __restri
   const int b = wid / G, g = wid % G, Cg = C / G;
   const int nparts = S * Cg;
   double sn = 0.0, sx = 0.0;
+#pragma unroll 4
   for (int i = lane; i < nparts; i += 64) {
     const int s = i / Cg, c = g * Cg + i % Cg;
     const float4 v = part[((size_t)b * S + s) * C + c];
@@ -75,6 +76,7 @@ __global__ void __launch_bounds__(256) gn_finalize_kernel(const float4* __restri
   sx = wave_sum(sx);
   const double mean = sn > 0 ? sx / sn : 0.0;
   double m2 = 0.0;
+#pragma unroll 4
   for (int i = lane; i < nparts; i += 64) {
     const int s = i / Cg, c = g * Cg + i % Cg;
     const float4 v = part[((size_t)b * S + s) * C + c];
@@ -224,6 +226,7 @@ __global__ void __launch_bounds__(256) gnb_coef_affine_kernel(const float2* __re
   if (wid < B * G) {
     const int b = wid / G, g = wid % G, Cg = C / G;
     double a = 0.0, q = 0.0;
+#pragma unroll 4
     for (int i = lane; i < S * Cg; i += 64) {
       const int s = i / Cg, c = g * Cg + i % Cg;
       const float2 v = bpart[((size_t)b * S + s) * C + c];
@@ -241,6 +244,7 @@ __global__ void __launch_bounds__(256) gnb_coef_affine_kernel(const float2* __re
   const int c = wid - B * G;
   if (c >= C) return;
   double a = 0.0, q = 0.0;
+#pragma unroll 4
   for (int i = lane; i < B * S; i += 64) {
     const float2 v = bpart[(size_t)i * C + c];
     a += v.x;
@@ -261,6 +265,7 @@ __global__ void __launch_bounds__(256) gnb_affine_kernel(const float2* __restric
   const int c = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
   if (c >= C) return;
   double a = 0.0, q = 0.0;
+#pragma unroll 4
   for (int i = lane; i < B * S; i += 64) {
     const float2 v = bpart[(size_t)i * C + c];
     a += v.x;
