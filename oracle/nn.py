@@ -7,7 +7,8 @@ only library primitives used are numpy's array slicing and tensordot
 Pins (tests/test_oracle_nn.py): each forward against torch CPU float64
 library routines (conv2d, group_norm, max_pool2d, avg_pool2d, the LSTM cell
 equations of torch.nn.LSTMCell, log_softmax); each backward against central
-finite differences and torch autograd.
+finite differences and torch autograd; round_bf16 against torch's float32 to
+bfloat16 conversion and against brute force over the representable values.
 """
 from __future__ import annotations
 
@@ -15,6 +16,17 @@ import numpy as np
 from numpy.lib.stride_tricks import sliding_window_view
 
 GN_EPS = 1e-5
+
+
+# ------------------------------------------------------------ quantisation
+def round_bf16(x):
+    """Nearest bfloat16 value of each element (8 significant bits, ties to
+    even), returned as float64.  Rounds the float64 value directly (no
+    float32 step).  bfloat16 shares float32's exponent range; the values
+    quantised here are far from its limits."""
+    x = np.asarray(x, np.float64)
+    m, e = np.frexp(x)                    # x = m 2^e, 0.5 <= |m| < 1
+    return np.ldexp(np.round(m * 256.0), e - 8)   # np.round: half to even
 
 
 # ---------------------------------------------------------------- convolution
@@ -98,7 +110,8 @@ def max_pool3s2(x, winner=None):
     """3x3 window, stride 2, padding 1 (padding never wins).  Returns the
     output and, per output, the flat input index of the first maximum in
     row-major window order.  `winner` ([B,C,Ho,Wo] window index kh*3+kw)
-    imposes the choice instead (a decision taken elsewhere)."""
+    imposes the choice instead (a decision taken elsewhere).  The cache also
+    keeps the window index of every output."""
     B, C, H, W = x.shape
     Ho, Wo = conv_out(H, 3, 2, 1), conv_out(W, 3, 2, 1)
     xp = np.pad(x, ((0, 0), (0, 0), (1, 1), (1, 1)), constant_values=-np.inf)
@@ -108,11 +121,11 @@ def max_pool3s2(x, winner=None):
     kh, kw = k // 3, k % 3
     ii = 2 * np.arange(Ho)[:, None] + kh - 1    # input row of the winner
     jj = 2 * np.arange(Wo)[None, :] + kw - 1
-    return y, (ii * W + jj, x.shape)
+    return y, (ii * W + jj, x.shape, k)
 
 
 def max_pool3s2_backward(cache, dy):
-    idx, shape = cache
+    idx, shape = cache[:2]
     B, C, H, W = shape
     dx = np.zeros((B * C, H * W))
     flat_idx = idx.reshape(B * C, -1)

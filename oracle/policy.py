@@ -23,7 +23,27 @@ against torch autograd and central finite differences (tests/test_oracle_policy.
 Discrete decisions (each ReLU's on/off pattern, each max-pool winner) can be
 imposed through a `decide` dict, so that a comparison against an
 implementation in another precision takes the same decisions; without it
-they are taken here in float64.
+they are taken here in float64.  A `record` dict receives every ReLU's
+pre-activation and output and the max-pool input, from which `decisions`
+forms the decide dict of a free run (imposing it reproduces that run bit for
+bit; tests/test_oracle_decisions.py).
+
+Precision form (quant="bf16"): the arithmetic stays float64, but every
+operand of a matrix product -- the input and weight of each convolution, of
+the visual FC and of each LSTM layer ([x, m h] and [W_ih | W_hh]) -- is first
+rounded to the nearest bfloat16 value, the mixed-precision reading of the
+design notes (GroupNorm, residual, pooling, the LSTM cell state and
+pointwise math, the goal FC, the embedding and the policy/value head stay
+unrounded).  Gradients pass the rounding unchanged (straight through): the
+weight gradient of a product is taken against its rounded input and the
+input gradient against its rounded weight.  Pinned against an independent
+torch float64 model with the same rounding and straight-through autograd.
+Rounding an activation to bfloat16 is itself a decision made by floating
+point (which of two neighbouring codes), so in this form each activation
+operand's codes can be imposed too: decide['q:' + key] holds the codes of the
+operand named key (a convolution's input by the convolution's name, 'fc',
+'lstm<l>.x', 'lstm<l>.h'), and record['q:' + key] receives the value the
+oracle rounded.
 """
 from __future__ import annotations
 
@@ -32,26 +52,71 @@ import numpy as np
 from . import nn
 
 
+# ------------------------------------------------------- precision form
+QUANT_WEIGHTS = ("fc.w",)   # plus every convolution and LSTM layer weight
+
+
+def quantizer(quant):
+    """Operand rounding of the precision form: identity, or bfloat16."""
+    if quant is None:
+        return lambda a: a
+    if quant == "bf16":
+        return nn.round_bf16
+    raise ValueError(quant)
+
+
+def quantize_params(net, P, quant):
+    """The parameter dict with every matrix-product weight rounded."""
+    if quant is None:
+        return P
+    q = quantizer(quant)
+    out = dict(P)
+    for k, v in P.items():
+        if k.startswith("lstm") and k.endswith(".w") or k in QUANT_WEIGHTS or \
+                (v.ndim == 4):            # convolutions (out, in, kh, kw)
+            out[k] = q(v)
+    return out
+
+
 # ------------------------------------------------------------------ encoder
 def prep_obs(net, obs):
     x = np.asarray(obs, dtype=np.float64)
     return nn.avg_pool2(x) if net.avgpool else x
 
 
-def _relu(y, key, decide):
+def _relu(y, key, decide, record=None, outputs=True):
     """ReLU with its on/off pattern taken here (y > 0) or imposed."""
     m = (y > 0) if (decide is None or key not in decide) else np.asarray(decide[key], bool)
-    return np.where(m, y, 0.0), m
+    a = np.where(m, y, 0.0)
+    if record is not None:
+        record.setdefault(key, []).append(y)
+        if outputs:
+            record.setdefault(key + ":out", []).append(a)
+    return a, m
 
 
-def _conv_gn(P, net, name, x, s, p, relu, tape, decide=None):
-    u = nn.conv2d(x, P[name], s, p)
+def _operand(x, key, q, decide, record):
+    """A product operand of the precision form: x rounded by q, or the codes
+    imposed as decide[key]; record[key] receives x (the value before
+    rounding).  q None (exact arithmetic): x unchanged."""
+    if q is None:
+        return x
+    if record is not None:
+        record.setdefault(key, []).append(x)
+    if decide is not None and key in decide:
+        return np.asarray(decide[key], np.float64)
+    return q(x)
+
+
+def _conv_gn(P, net, name, x, s, p, relu, tape, decide=None, q=None, record=None, outputs=True):
+    xq = _operand(x, "q:" + name, q, decide, record)
+    u = nn.conv2d(xq, P[name], s, p)
     y, gc = nn.group_norm(u, P[name + ".gn.g"], P[name + ".gn.b"], net.gn_groups)
     m = None
     if relu:
-        y, m = _relu(y, name, decide)
+        y, m = _relu(y, name, decide, record, outputs)
     if tape is not None:
-        tape[name] = (x, s, p, gc, m)
+        tape[name] = (xq, s, p, gc, m)
     return y
 
 
@@ -76,28 +141,36 @@ def _blocks(net):
     return out
 
 
-def encoder_forward(P, net, x, tape=None, decide=None):
+def encoder_forward(P, net, x, tape=None, decide=None, quant=None, record=None, record_outputs=True):
     """x: [F, C, h, w] after the optional pooling -> features [F, flat_dim]
     in channel, row, column order.  decide: optional imposed decisions keyed
     by unit name (ReLU masks, NCHW), 'sS.bJ.out' (block output ReLU) and
-    'maxpool' (winner index)."""
+    'maxpool' (winner index).  P must already be quantize_params(.., quant).
+    record: optional dict of lists receiving each ReLU's pre-activation
+    (key) and output (key + ':out', unless record_outputs is False) and the
+    max-pool input ('maxpool')."""
+    q = None if quant is None else quantizer(quant)
+    cg = lambda name, a, s, p, relu: _conv_gn(P, net, name, a, s, p, relu, tape, decide, q, record,
+                                              record_outputs)
     if net.trunk == "tiny":
-        a = _conv_gn(P, net, "conv1", x, 2, 1, True, tape, decide)
-        a = _conv_gn(P, net, "conv2", a, 2, 1, True, tape, decide)
+        a = cg("conv1", x, 2, 1, True)
+        a = cg("conv2", a, 2, 1, True)
         return a.reshape(a.shape[0], -1)
-    a = _conv_gn(P, net, "stem", x, 2, 3, True, tape, decide)
+    a = cg("stem", x, 2, 3, True)
+    if record is not None:
+        record.setdefault("maxpool", []).append(a)
     a, mc = nn.max_pool3s2(a, None if decide is None else decide.get("maxpool"))
     if tape is not None:
         tape["maxpool"] = mc
     for pre, st, proj in _blocks(net):
-        y = _conv_gn(P, net, pre + "c1", a, 1, 0, True, tape, decide)
-        y = _conv_gn(P, net, pre + "c2", y, st, 1, True, tape, decide)
-        y = _conv_gn(P, net, pre + "c3", y, 1, 0, False, tape, decide)
-        sc = _conv_gn(P, net, pre + "ds", a, st, 0, False, tape, decide) if proj else a
-        a, m = _relu(y + sc, pre + "out", decide)
+        y = cg(pre + "c1", a, 1, 0, True)
+        y = cg(pre + "c2", y, st, 1, True)
+        y = cg(pre + "c3", y, 1, 0, False)
+        sc = cg(pre + "ds", a, st, 0, False) if proj else a
+        a, m = _relu(y + sc, pre + "out", decide, record, record_outputs)
         if tape is not None:
             tape[pre + "out"] = m
-    a = _conv_gn(P, net, "compress", a, 1, 1, True, tape, decide)
+    a = cg("compress", a, 1, 1, True)
     return a.reshape(a.shape[0], -1)
 
 
@@ -128,25 +201,46 @@ def _slice(decide, s, e):
     return None if decide is None else {k: v[s:e] for k, v in decide.items()}
 
 
-def encode(P, net, obs, chunk=64, decide=None):
+def encode(P, net, obs, chunk=64, decide=None, quant=None, record=None, record_outputs=True):
     """Features of many frames, processed in chunks of frames to bound the
-    im2col memory (frames are independent)."""
+    im2col memory (frames are independent).  record: as for encoder_forward,
+    with the chunks' arrays concatenated along frames at the end."""
     F = obs.shape[0]
     out = np.zeros((F, net.flat_dim))
+    rec = None if record is None else {}
     for s in range(0, F, chunk):
         out[s:s + chunk] = encoder_forward(P, net, prep_obs(net, obs[s:s + chunk]),
-                                           decide=_slice(decide, s, s + chunk))
+                                           decide=_slice(decide, s, s + chunk), quant=quant, record=rec,
+                                           record_outputs=record_outputs)
+    if record is not None:
+        for k, v in rec.items():
+            record[k] = np.concatenate(v, axis=0)
     return out
 
 
-def encode_backward(P, net, obs, dfeat, grads, chunk=64, decide=None):
+def encode_backward(P, net, obs, dfeat, grads, chunk=64, decide=None, quant=None):
     """Recompute each chunk's forward with a tape, then run its backward;
     the chunk gradients are summed."""
     F = obs.shape[0]
     for s in range(0, F, chunk):
         tape = {}
-        encoder_forward(P, net, prep_obs(net, obs[s:s + chunk]), tape, _slice(decide, s, s + chunk))
+        encoder_forward(P, net, prep_obs(net, obs[s:s + chunk]), tape, _slice(decide, s, s + chunk), quant)
         encoder_backward(P, net, tape, dfeat[s:s + chunk], grads)
+
+
+def decisions(net, record, vis_pre=None):
+    """The decide dict of the run that filled `record` (encode's record of
+    the encoder over frames; vis_pre [T,B,vis_hidden] the visual-FC
+    pre-activations of the core): every ReLU's on/off pattern and every
+    max-pool window's first maximum."""
+    dec = {k: v > 0 for k, v in record.items()
+           if k != "maxpool" and not k.endswith(":out") and not k.startswith("q:")}
+    dec.update({k: nn.round_bf16(v) for k, v in record.items() if k.startswith("q:")})
+    if "maxpool" in record:
+        dec["maxpool"] = nn.max_pool3s2(record["maxpool"])[1][2]
+    if vis_pre is not None:
+        dec["vis"] = vis_pre > 0
+    return dec
 
 
 # ------------------------------------------------------------- policy core
@@ -156,15 +250,26 @@ def polar(goal):
     return np.stack([d, np.cos(th), np.sin(th)], axis=-1)
 
 
-def core_forward(P, net, feat, goal, prev_a, masks, h0, c0, keep=False, vis_mask=None):
+def core_forward(P, net, feat, goal, prev_a, masks, h0, c0, keep=False, vis_mask=None, quant=None,
+                 vis_pre=None, codes=None, qrec=None):
     """Run the policy over a sequence.
 
     feat [T,B,flat], goal [T,B,2], prev_a [T,B] (action taken at t-1),
     masks [T,B] (0 at an episode start), h0/c0 [L,B,H].
-    vis_mask [T,B,vis_hidden] optionally imposes the visual-FC ReLU pattern.
+    vis_mask [T,B,vis_hidden] optionally imposes the visual-FC ReLU pattern;
+    vis_pre (array [T,B,vis_hidden]) receives its pre-activations.
+    P must already be quantize_params(.., quant).  codes: optional imposed
+    operand codes 'q:fc' [T,B,flat], 'q:lstm<l>.x', 'q:lstm<l>.h' [T,B,.];
+    qrec (dict) receives the values rounded, as lists over t.
     Returns logits [T,B,A], values [T,B], final (h, c), and a tape."""
     T, B = feat.shape[:2]
     L, A = net.lstm_layers, net.num_actions
+    q = None if quant is None else quantizer(quant)
+
+    def op(x, key, t):
+        dec = None if codes is None or key not in codes else {key: codes[key][t]}
+        return _operand(x, key, q, dec, qrec)
+
     h = [np.asarray(h0[l], np.float64).copy() for l in range(L)]
     c = [np.asarray(c0[l], np.float64).copy() for l in range(L)]
     logits = np.zeros((T, B, A))
@@ -172,8 +277,11 @@ def core_forward(P, net, feat, goal, prev_a, masks, h0, c0, keep=False, vis_mask
     tape = [] if keep else None
     for t in range(T):
         m = np.asarray(masks[t], np.float64)[:, None]
-        vis, vmask = _relu(nn.linear(feat[t], P["fc.w"], P["fc.b"]), t,
-                           None if vis_mask is None else {t: vis_mask[t]})
+        ft = op(np.asarray(feat[t], np.float64), "q:fc", t)
+        pre = nn.linear(ft, P["fc.w"], P["fc.b"])
+        if vis_pre is not None:
+            vis_pre[t] = pre
+        vis, vmask = _relu(pre, t, None if vis_mask is None else {t: vis_mask[t]})
         parts = [vis]
         g3 = None
         if net.goal_mode == "polar":
@@ -188,7 +296,7 @@ def core_forward(P, net, feat, goal, prev_a, masks, h0, c0, keep=False, vis_mask
         x = np.concatenate(parts, axis=1)
         cells = []
         for l in range(L):
-            h[l], c[l], cc = nn.lstm_cell(x, m * h[l], m * c[l],
+            h[l], c[l], cc = nn.lstm_cell(op(x, "q:lstm%d.x" % l, t), op(m * h[l], "q:lstm%d.h" % l, t), m * c[l],
                                           P["lstm%d.w" % l], P["lstm%d.b" % l])
             cells.append(cc)
             x = h[l]
@@ -196,7 +304,7 @@ def core_forward(P, net, feat, goal, prev_a, masks, h0, c0, keep=False, vis_mask
         logits[t] = out[:, :A]
         values[t] = out[:, A]
         if keep:
-            tape.append((feat[t], vmask, g3, idx, m, cells, x))
+            tape.append((ft, vmask, g3, idx, m, cells, x))
     return logits, values, (np.stack(h), np.stack(c)), tape
 
 
@@ -263,13 +371,14 @@ def sample(logp, u):
     return a.astype(np.int32)
 
 
-def act(P, net, obs, goal, prev_a, mask, h, c, u):
+def act(P, net, obs, goal, prev_a, mask, h, c, u, quant=None):
     """One batched act step for B envs: returns action, logp(action), value,
-    logits, h', c'."""
-    feat = encoder_forward(P, net, prep_obs(net, obs))
+    logits, h', c'.  quant: the precision form (module header)."""
+    P = quantize_params(net, P, quant)
+    feat = encoder_forward(P, net, prep_obs(net, obs), quant=quant)
     logits, values, (h2, c2), _ = core_forward(
         P, net, feat[None], np.asarray(goal)[None], np.asarray(prev_a)[None],
-        np.asarray(mask)[None], h, c)
+        np.asarray(mask)[None], h, c, quant=quant)
     lp = nn.log_softmax(logits[0])
     a = sample(lp, u)
     return {"action": a, "logp": lp[np.arange(len(a)), a], "value": values[0],

@@ -34,11 +34,12 @@ STAT_NAMES = ("loss", "pg", "vf", "ent", "clip_frac", "approx_kl", "ratio_min", 
 
 
 # ------------------------------------------------------------------ rollout
-def rollout(flat, net, inp, h0, c0, prev_a0=None, mask0=None, forced_actions=None):
+def rollout(flat, net, inp, h0, c0, prev_a0=None, mask0=None, forced_actions=None, quant=None):
     """Collect one rollout with T+1 act steps.  inp holds obs, goal, done, u,
     lengths.  Env n is active at act step t when t <= T_n; the step t = T_n
     only provides the bootstrap value.  If forced_actions [T+1,N] is given,
-    those actions (not the sampled ones) feed the previous-action input."""
+    those actions (not the sampled ones) feed the previous-action input.
+    quant: the precision form of policy (None: exact float64)."""
     P = params.unpack(net, flat)
     obs, goal, done, u, lens = inp["obs"], inp["goal"], inp["done"], inp["u"], inp["lengths"]
     T1, N = u.shape
@@ -57,7 +58,7 @@ def rollout(flat, net, inp, h0, c0, prev_a0=None, mask0=None, forced_actions=Non
         if t > 0:
             m = 1.0 - done[t - 1].astype(np.float64)
         o = policy.act(P, net, obs[t, act_ix], goal[t, act_ix], prev[act_ix], m[act_ix],
-                       h[:, act_ix], c[:, act_ix], u[t, act_ix])
+                       h[:, act_ix], c[:, act_ix], u[t, act_ix], quant=quant)
         rec["mask"][t] = m
         rec["prev_action"][t] = prev
         for k in ("logp", "value", "action", "logits"):
@@ -113,15 +114,24 @@ def minibatch_inputs(net, inp, rec, adv, ret, envs):
     }
 
 
-def loss_grad(flat, net, ppo, mb, with_grad=True, adv_norm=None, decide=None):
+def loss_grad(flat, net, ppo, mb, with_grad=True, adv_norm=None, decide=None, quant=None, record=None,
+              record_outputs=True):
     """PPO loss of one minibatch and (optionally) its flat gradient.
 
     L = -sum_n w_n sum_t min(r A, clip(r, 1-eps, 1+eps) A)
         + c_v sum_n w_n sum_t 1/2 (V - R)^2 - c_e sum_n w_n sum_t H(pi),
     w_n = 1 / (|B| T_n).  adv_norm = (mean, var) applies (A - mean)/(std + 1e-5).
     decide: optional imposed ReLU / max-pool decisions (policy.encoder_forward),
-    per valid frame in time-major order, plus 'vis' [T_B, B, vis_hidden]."""
-    P = params.unpack(net, flat)
+    per valid frame in time-major order, plus 'vis' [T_B, B, vis_hidden].
+    quant: the precision form of policy (None: exact float64).
+    record: optional dict receiving the encoder's pre-activations, outputs
+    and max-pool inputs per valid frame (policy.encode) and 'vis' [T_B, B,
+    vis_hidden] (visual-FC pre-activations; invalid frames 0), and in the
+    bfloat16 form the values each operand rounded ('q:' keys; the core's
+    time-major); record_outputs False leaves out the ReLU outputs (key +
+    ':out');
+    policy.decisions(net, record, record['vis']) is then this run's decide."""
+    P = policy.quantize_params(net, params.unpack(net, flat), quant)
     lens = mb["lens"]
     TB, B = mb["action"].shape
     A_ = net.num_actions
@@ -130,11 +140,23 @@ def loss_grad(flat, net, ppo, mb, with_grad=True, adv_norm=None, decide=None):
     # encoder over valid frames only
     tt, jj = np.nonzero(valid)
     feat = np.zeros((TB, B, net.flat_dim))
-    enc_decide = None if decide is None else {k: v for k, v in decide.items() if k != "vis"}
-    feat[tt, jj] = policy.encode(P, net, mb["obs"][tt, jj], decide=enc_decide)
+    core_keys = lambda k: k == "vis" or k.startswith("q:fc") or k.startswith("q:lstm")
+    enc_decide = None if decide is None else {k: v for k, v in decide.items() if not core_keys(k)}
+    codes = None if decide is None else {k: v for k, v in decide.items() if k.startswith("q:") and core_keys(k)}
+    enc_rec = None if record is None else {}
+    feat[tt, jj] = policy.encode(P, net, mb["obs"][tt, jj], decide=enc_decide, quant=quant, record=enc_rec,
+                                 record_outputs=record_outputs)
+    vis_pre = None if record is None else np.zeros((TB, B, net.vis_hidden))
+    qrec = None if record is None else {}
     logits, values, _, tape = policy.core_forward(
         P, net, feat, mb["goal"], mb["prev_action"], mb["mask"], mb["h0"], mb["c0"], keep=with_grad,
-        vis_mask=None if decide is None else decide.get("vis"))
+        vis_mask=None if decide is None else decide.get("vis"), quant=quant, vis_pre=vis_pre, codes=codes,
+        qrec=qrec)
+    if record is not None:
+        record.update(enc_rec)
+        record["vis"] = np.where(valid[..., None], vis_pre, 0.0)
+        for k, v in qrec.items():     # time-major [T_B, B, .]; invalid frames 0
+            record[k] = np.where(valid[..., None], np.stack(v), 0.0)
     lp = nn.log_softmax(logits)
     p = np.exp(lp)
     a = mb["action"]
@@ -165,7 +187,7 @@ def loss_grad(flat, net, ppo, mb, with_grad=True, adv_norm=None, decide=None):
     dvalues = ppo.value_coef * w * (values - mb["ret"])
     grads = {}
     dfeat = policy.core_backward(P, net, tape, dlogits, dvalues, grads)
-    policy.encode_backward(P, net, mb["obs"][tt, jj], dfeat[tt, jj], grads, decide=enc_decide)
+    policy.encode_backward(P, net, mb["obs"][tt, jj], dfeat[tt, jj], grads, decide=enc_decide, quant=quant)
     return stats, params.pack(net, grads)
 
 

@@ -16,6 +16,21 @@ from synth.layout import tensor_list
 GN_EPS = 1e-5
 
 
+def _bf16(x):
+    """Nearest bfloat16 value (ties to even) of a float64 tensor, float64."""
+    m, e = torch.frexp(x)
+    return torch.ldexp(torch.round(m * 256.0), (e - 8).to(x.dtype))
+
+
+def quantizer(quant):
+    """Operand rounding of the precision form with a straight-through
+    gradient (the rounding counts as the identity for autograd)."""
+    if quant is None:
+        return lambda x: x
+    assert quant == "bf16"
+    return lambda x: x + (_bf16(x.detach()) - x.detach())
+
+
 def unpack(net, flat, requires_grad=True):
     flat_t = torch.tensor(np.asarray(flat, np.float64), requires_grad=requires_grad)
     P = {}
@@ -28,51 +43,55 @@ def unpack(net, flat, requires_grad=True):
     return flat_t, P
 
 
-def _cgn(P, net, x, conv, gn, s, p, relu):
-    y = F.conv2d(x, P[conv], stride=s, padding=p)
+def _cgn(P, net, x, conv, gn, s, p, relu, q=lambda a: a):
+    y = F.conv2d(q(x), q(P[conv]), stride=s, padding=p)
     y = F.group_norm(y, net.gn_groups, P[gn + ".g"], P[gn + ".b"], eps=GN_EPS)
     return F.relu(y) if relu else y
 
 
-def encoder(P, net, obs):
+def encoder(P, net, obs, quant=None):
+    q = quantizer(quant)
+    cgn = lambda x, conv, gn, s, p, relu: _cgn(P, net, x, conv, gn, s, p, relu, q)
     x = obs
     if net.avgpool:
         x = F.avg_pool2d(x, 2)
     if net.trunk == "tiny":
-        x = _cgn(P, net, x, "enc.conv1", "enc.gn1", 2, 1, True)
-        x = _cgn(P, net, x, "enc.conv2", "enc.gn2", 2, 1, True)
+        x = cgn(x, "enc.conv1", "enc.gn1", 2, 1, True)
+        x = cgn(x, "enc.conv2", "enc.gn2", 2, 1, True)
         return x.flatten(1)
-    x = _cgn(P, net, x, "enc.stem", "enc.stem.gn", 2, 3, True)
+    x = cgn(x, "enc.stem", "enc.stem.gn", 2, 3, True)
     x = F.max_pool2d(x, 3, 2, 1)
     for s, nb in enumerate(net.blocks):
         for j in range(nb):
             p = f"enc.s{s}.b{j}"
             st = 2 if (j == 0 and s > 0) else 1
-            y = _cgn(P, net, x, p + ".c1", p + ".gn1", 1, 0, True)
-            y = _cgn(P, net, y, p + ".c2", p + ".gn2", st, 1, True)
-            y = _cgn(P, net, y, p + ".c3", p + ".gn3", 1, 0, False)
-            sc = _cgn(P, net, x, p + ".ds", p + ".ds.gn", st, 0, False) if j == 0 else x
+            y = cgn(x, p + ".c1", p + ".gn1", 1, 0, True)
+            y = cgn(y, p + ".c2", p + ".gn2", st, 1, True)
+            y = cgn(y, p + ".c3", p + ".gn3", 1, 0, False)
+            sc = cgn(x, p + ".ds", p + ".ds.gn", st, 0, False) if j == 0 else x
             x = F.relu(y + sc)
-    x = _cgn(P, net, x, "enc.compress", "enc.compress.gn", 1, 1, True)
+    x = cgn(x, "enc.compress", "enc.compress.gn", 1, 1, True)
     return x.flatten(1)
 
 
-def policy_seq(P, net, obs, goal, prev_a, masks, h0, c0):
-    """obs [T,B,C,H,W] -> logits [T,B,A], values [T,B]."""
+def policy_seq(P, net, obs, goal, prev_a, masks, h0, c0, quant=None):
+    """obs [T,B,C,H,W] -> logits [T,B,A], values [T,B].  quant: the
+    precision form (every conv, visual-FC and LSTM operand rounded)."""
+    q = quantizer(quant)
     T, B = obs.shape[:2]
-    feat = encoder(P, net, obs.reshape(T * B, *obs.shape[2:])).reshape(T, B, -1)
+    feat = encoder(P, net, obs.reshape(T * B, *obs.shape[2:]), quant).reshape(T, B, -1)
     H = net.hidden
     cells = []
     for l in range(net.lstm_layers):
         w = P[f"lstm{l}.w"]
         din = w.shape[1] - H
-        cells.append((w[:, :din], w[:, din:], P[f"lstm{l}.b"]))
+        cells.append((q(w[:, :din]), q(w[:, din:]), P[f"lstm{l}.b"]))
     h = [h0[l] for l in range(net.lstm_layers)]
     c = [c0[l] for l in range(net.lstm_layers)]
     logits, values = [], []
     for t in range(T):
         m = masks[t][:, None]
-        v = F.relu(F.linear(feat[t], P["fc.w"], P["fc.b"]))
+        v = F.relu(F.linear(q(feat[t]), q(P["fc.w"]), P["fc.b"]))
         parts = [v]
         if net.goal_mode == "polar":
             d, th = goal[t][:, 0], goal[t][:, 1]
@@ -86,7 +105,7 @@ def policy_seq(P, net, obs, goal, prev_a, masks, h0, c0):
         x = torch.cat(parts, 1)
         for l, (wih, whh, b) in enumerate(cells):
             # torch's fused LSTM cell (gate order i, f, g, o)
-            h[l], c[l] = torch._VF.lstm_cell(x, (m * h[l], m * c[l]), wih, whh, b,
+            h[l], c[l] = torch._VF.lstm_cell(q(x), (q(m * h[l]), m * c[l]), wih, whh, b,
                                              torch.zeros_like(b))
             x = h[l]
         o = F.linear(x, P["head.w"], P["head.b"])
@@ -95,7 +114,7 @@ def policy_seq(P, net, obs, goal, prev_a, masks, h0, c0):
     return torch.stack(logits), torch.stack(values)
 
 
-def ppo_loss(net, ppo, flat, mb):
+def ppo_loss(net, ppo, flat, mb, quant=None):
     """Loss of one minibatch dict (as made by oracle.ppo.minibatch_inputs),
     its gradient by autograd, and the logits/values."""
     flat_t, P = unpack(net, flat)
@@ -106,7 +125,7 @@ def ppo_loss(net, ppo, flat, mb):
     w = valid / (B * lens[None, :])
     logits, values = policy_seq(P, net, tt(mb["obs"]), tt(mb["goal"]),
                                 tt(mb["prev_action"], torch.int64), tt(mb["mask"]),
-                                tt(mb["h0"]), tt(mb["c0"]))
+                                tt(mb["h0"]), tt(mb["c0"]), quant)
     lp = F.log_softmax(logits, -1)
     lpa = lp.gather(2, tt(mb["action"], torch.int64)[..., None])[..., 0]
     adv = tt(mb["adv"])
