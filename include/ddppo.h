@@ -11,8 +11,11 @@
  * Conventions for every call:
  *   - Pointers named d_* or documented as "device" are device memory owned
  *     by the caller; "host" pointers are read before the call returns.  The
- *     library allocates no device memory: scratch space is the caller's
- *     workspace (size from ppo_workspace_size).
+ *     compute calls allocate no device memory: scratch space is the caller's
+ *     workspace (size from ppo_workspace_size).  The exceptions are
+ *     benchmark and tuning aids, each documented below: a GEMM problem timed
+ *     by the tile autotuner (ppo_autotune mode 1) allocates and frees a
+ *     scratch output, and ppo_gemm_timer_arm creates HIP events.
  *   - All work is enqueued on `stream` (a hipStream_t passed as void*;
  *     NULL = the null stream) and is asynchronous.  Shape, pointer and
  *     workspace errors are detected on the host before any launch and
@@ -67,7 +70,7 @@ typedef enum {
 enum { PPO_F32 = 0, PPO_BF16 = 1 };
 enum { PPO_TRUNK_TINY = 0, PPO_TRUNK_RESNET = 1 };
 enum { PPO_GOAL_RAW = 0, PPO_GOAL_POLAR = 1 };
-enum { PPO_OP_ACT = 0, PPO_OP_LEARN = 1 };
+enum { PPO_OP_ACT = 0, PPO_OP_LEARN = 1, PPO_OP_LOSS = 2 };
 
 /* Network shape (appendix "Agent Design"; Sec. 4 "Agent"). */
 typedef struct ppo_net_desc {
@@ -95,7 +98,10 @@ typedef struct ppo_net ppo_net;
 /* Validate a description and build the host-side plan.  No device memory is
  * allocated.  Errors: PPO_EINVAL (null), PPO_ESHAPE (sizes that do not
  * divide: e.g. widths not multiples of gn_groups, a trunk that does not
- * reduce in_hw to an integer map), PPO_EUNSUPPORTED (device is not gfx950). */
+ * reduce in_hw to an integer map), PPO_EUNSUPPORTED (the current HIP device
+ * is not a gfx950), PPO_EDEVICE (the device cannot be queried).  With no
+ * HIP device visible the plan is still built (sizes and offsets can be
+ * read); compute calls then fail with PPO_EDEVICE. */
 ppo_status ppo_net_create(const ppo_net_desc* desc, ppo_net** out);
 void ppo_net_destroy(ppo_net* net);
 
@@ -108,9 +114,11 @@ ppo_status ppo_param_tensor(const ppo_net* net, int i, const char** name, size_t
                             size_t* count);
 
 /* Workspace bytes for one call of ppo_act (op = PPO_OP_ACT, max_frames = the
- * largest act batch) or ppo_loss_backward (op = PPO_OP_LEARN, max_frames =
- * the largest number of valid frames of one minibatch, max_envs its env
- * count).  The workspace must be 256-byte aligned device memory. */
+ * largest act batch), ppo_loss_backward / ppo_policy_forward /
+ * ppo_policy_backward (op = PPO_OP_LEARN, max_frames = the largest number of
+ * valid frames of one minibatch, max_envs its env count) or ppo_loss_head
+ * (op = PPO_OP_LOSS, same sizes; a few bytes per frame).  The workspace must
+ * be 256-byte aligned device memory. */
 ppo_status ppo_workspace_size(const ppo_net* net, int op, int max_frames, int max_envs,
                               size_t* bytes);
 
@@ -223,16 +231,33 @@ ppo_status ppo_policy_backward(ppo_net* net, const ppo_batch* b, const float* dl
                                const float* dvalues, float* grad, void* ws, size_t ws_bytes,
                                void* stream);
 
+/* ppo_loss_head -- the objective of ppo_loss_backward (Eq. 2 with the value
+ * and entropy terms, weights w_n = 1/(|B| T_n) of Sec. 3, optional advantage
+ * normalisation) evaluated on given policy outputs: logits [F][A] and values
+ * [F] (device float32) of the minibatch's valid frames in the order of
+ * ppo_policy_forward.  Writes stats [8] (as ppo_loss_backward), loss_out
+ * [1] = S*L (device float32, or NULL) and the gradient of S*L with respect
+ * to the outputs: dlogits [F][A], dvalues [F] (device float32; S =
+ * *d_loss_scale for PPO_BF16 nets, 1 for PPO_F32).
+ * Reads the minibatch's env_ids, lengths, mask, action, logp_old, adv and
+ * ret fields only.  Workspace: ppo_workspace_size(op = PPO_OP_LOSS).  With
+ * ppo_policy_forward / ppo_policy_backward it splits ppo_loss_backward in
+ * three (a caller's autograd graph in between). */
+ppo_status ppo_loss_head(ppo_net* net, const ppo_batch* b, const ppo_loss_cfg* cfg, const float* d_loss_scale,
+                         const float* logits, const float* values, float* dlogits, float* dvalues, float* stats,
+                         float* loss_out, void* ws, size_t ws_bytes, void* stream);
+
 /* ---------------------------------------------------------------------------
  * ppo_adam_step -- ParamUpdate of Eq. 3-4 (Adam, Kingma & Ba, with bias
  * correction; the paper's optimiser, Sec. 4 "Training").  Device state:
  *   scaler->scale S: gradients arrive multiplied by S and are unscaled here;
  *   if any unscaled gradient is not finite the step is skipped (params, m, v,
- *   step unchanged), S halves and skipped increments; otherwise step += 1,
+ *   step unchanged), S halves (only when growth_interval > 0) and skipped
+ *   increments; otherwise step += 1,
  *     m = b1 m + (1-b1) g, v = b2 v + (1-b2) g^2,
  *     theta -= lr (m / (1-b1^step)) / (sqrt(v / (1-b2^step)) + eps),
  *   and after `growth_interval` consecutive good steps S doubles (dynamic
- *   loss scaling; growth_interval 0 keeps S fixed).
+ *   loss scaling; growth_interval 0 keeps S fixed, also on a skipped step).
  * master, m, v [P] float32 in place; grad [P] float32 (read only); lp_copy
  * [P] bfloat16 rewritten from the new master (NULL to skip).  ws: at least
  * ppo_adam_workspace_size(P) bytes of device scratch.
@@ -258,8 +283,9 @@ ppo_status ppo_adam_step(float* master, const float* grad, float* m, float* v, v
                          size_t ws_bytes, void* stream);
 
 /* Test introspection of a workspace laid out for (op, max_frames, max_envs):
- * where a call leaves the forward activations that decided each ReLU and
- * max pool, so a reference implementation can take the same decisions.  Frames are in the
+ * where a call leaves the forward activations that decided each ReLU, max
+ * pool and bfloat16 operand rounding, so a reference implementation can take
+ * the same decisions.  Frames are in the
  * call's packed order (time-major; envs sorted by length, longest first,
  * ties in the given order).
  *   kind 0: normalised output of trunk unit `index` (conv + GroupNorm [+ residual]
@@ -270,6 +296,15 @@ ppo_status ppo_adam_step(float* master, const float* grad, float* m, float* v, v
  *   kind 2: LSTM layer-0 input rows float32 [F][din0], columns < vis_hidden
  *           being the post-ReLU visual FC output; dims = {din0, vis_hidden, 0, 0}
  *   kind 3: dims[0] = number of trunk units
+ *   kind 5: max-pool output float32 [F][h][w][C]; dims = {h, w, C, 0}
+ *   kind 6: LSTM layer `index`'s masked previous state m_t h_{t-1}, float32
+ *           [F][H] (the recurrent operand of the gate products); dims = {H, ..}
+ *   kind 7: LSTM layer `index`'s output h_t, float32 [F][H]; dims = {H, ..}
+ *   kind 4 (op PPO_OP_LEARN): the learner's recurrence status, one uint32;
+ *           nonzero after a call means a device-wide barrier of the persistent
+ *           LSTM launches gave up waiting (bounded wait) and the call's
+ *           outputs were poisoned with NaN; cleared at the start of every
+ *           learner call; dims = {1, 0, 0, 0}
  * Returns PPO_EINVAL for an index or kind that does not exist. */
 ppo_status ppo_workspace_probe(const ppo_net* net, int op, int max_frames, int max_envs, int kind,
                                int index, const char** name, int* relu, size_t* offset, int dims[4]);

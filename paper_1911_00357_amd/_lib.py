@@ -14,7 +14,7 @@ PPO_OK, PPO_EINVAL, PPO_ESHAPE, PPO_EUNSUPPORTED, PPO_EWORKSPACE, PPO_EDEVICE = 
 PPO_F32, PPO_BF16 = 0, 1
 PPO_TRUNK_TINY, PPO_TRUNK_RESNET = 0, 1
 PPO_GOAL_RAW, PPO_GOAL_POLAR = 0, 1
-PPO_OP_ACT, PPO_OP_LEARN = 0, 1
+PPO_OP_ACT, PPO_OP_LEARN, PPO_OP_LOSS = 0, 1, 2
 
 STATUS_NAMES = {0: "PPO_OK", -1: "PPO_EINVAL", -2: "PPO_ESHAPE", -3: "PPO_EUNSUPPORTED",
                 -4: "PPO_EWORKSPACE", -5: "PPO_EDEVICE"}
@@ -74,6 +74,8 @@ EXPORTS = {
                                    c_size_t, c_void_p]),
     "ppo_policy_backward": (c_int, [c_void_p, C.POINTER(Batch), c_void_p, c_void_p, c_void_p, c_void_p,
                                     c_size_t, c_void_p]),
+    "ppo_loss_head": (c_int, [c_void_p, C.POINTER(Batch), C.POINTER(LossCfg), c_void_p, c_void_p, c_void_p,
+                              c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_size_t, c_void_p]),
     "ppo_adam_workspace_size": (c_size_t, [c_size_t]),
     "ppo_adam_step": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_size_t,
                               C.POINTER(AdamCfg), c_void_p, c_void_p, c_size_t, c_void_p]),

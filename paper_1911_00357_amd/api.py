@@ -84,6 +84,7 @@ class Net:
         self.P = int(lib().ppo_param_count(h))
         self.L, self.H, self.A = spec.lstm_layers, spec.hidden, spec.num_actions
         self._ws = {}
+        self._last_learn = None   # (frames, envs) of the last learner call
 
     def __del__(self):
         h = getattr(self, "_h", None)
@@ -157,6 +158,15 @@ class Net:
         check(lib().ppo_gemm_timer_read(self._h, C.byref(n), C.byref(ms), C.byref(fl)), "ppo_gemm_timer_read")
         return n.value, ms.value, fl.value
 
+    def recurrence_failed(self) -> bool:
+        """True if a persistent LSTM launch of the last learner call gave up
+        at a barrier (its outputs are then NaN); synchronises the stream."""
+        ws = self.last_workspace(L.PPO_OP_LEARN)
+        if ws is None or self._last_learn is None:
+            return False
+        off = self.probe(L.PPO_OP_LEARN, *self._last_learn, 4)[2]
+        return bool(ws[off:off + 4].view(torch.int32).item())
+
     def last_workspace(self, op: int):
         return self._ws.get((op, "cuda:0")) if self._ws else None
 
@@ -209,23 +219,27 @@ class Net:
         return out
 
     # -------------------------------------------------------------- learner
-    def _batch(self, ro, env_ids, lengths, params, params_lp, learner=True):
-        obs = ro["obs"]
-        T1, N = obs.shape[0], obs.shape[1]
+    def _batch(self, ro, env_ids, lengths, params, params_lp, learner=True, inputs=True):
+        """The ppo_batch of a minibatch.  learner: the loss fields (actions,
+        old log-probs, advantages, returns); inputs: the policy inputs."""
+        T1, N = ro["mask"].shape[0], ro["mask"].shape[1]
         T = T1 - 1
-        _need(obs, torch.bfloat16 if self.bf16 else torch.float32, "obs")
-        fields = [("goal", torch.float32, T1 * N * 2), ("mask", torch.float32, T1 * N),
-                  ("h0", torch.float32, self.L * N * self.H), ("c0", torch.float32, self.L * N * self.H)]
+        fields = [("mask", torch.float32, T1 * N)]
+        if inputs:
+            _need(ro["obs"], torch.bfloat16 if self.bf16 else torch.float32, "obs")
+            fields += [("goal", torch.float32, T1 * N * 2), ("h0", torch.float32, self.L * N * self.H),
+                       ("c0", torch.float32, self.L * N * self.H)]
         if learner:
             fields += [("action", torch.int32, T1 * N), ("logp", torch.float32, T1 * N),
                        ("adv", torch.float32, T * N), ("ret", torch.float32, T * N)]
         for k, dt, n in fields:
             _need(ro[k], dt, k, n)
-        if self.spec.prev_act_dim:
-            _need(ro["prev_action"], torch.int32, "prev_action", T1 * N)
-        _need(params, torch.float32, "params", self.P)
-        if self.bf16:
-            _need(params_lp, torch.bfloat16, "params_lp", self.P)
+        if inputs:
+            if self.spec.prev_act_dim:
+                _need(ro["prev_action"], torch.int32, "prev_action", T1 * N)
+            _need(params, torch.float32, "params", self.P)
+            if self.bf16:
+                _need(params_lp, torch.bfloat16, "params_lp", self.P)
         env = (C.c_int32 * len(env_ids))(*[int(e) for e in env_ids])
         lens = None
         F = T * len(env_ids)
@@ -236,14 +250,15 @@ class Net:
         b.T, b.N, b.nb = T, N, len(env_ids)
         b.env_ids = C.cast(env, L.P_i32)
         b.lengths = C.cast(lens, L.P_i32) if lens is not None else None
-        b.obs, b.goal, b.prev_action, b.mask = (_ptr(obs), _ptr(ro["goal"]),
-                                                _ptr(ro.get("prev_action")), _ptr(ro["mask"]))
+        b.mask = _ptr(ro["mask"])
+        if inputs:
+            b.obs, b.goal, b.prev_action = _ptr(ro["obs"]), _ptr(ro["goal"]), _ptr(ro.get("prev_action"))
+            b.h0, b.c0 = _ptr(ro["h0"]), _ptr(ro["c0"])
+            b.params, b.params_lp = _ptr(params), _ptr(params_lp)
         if learner:
             b.action, b.logp_old, b.adv, b.ret = (_ptr(ro["action"]), _ptr(ro["logp"]),
                                                   _ptr(ro["adv"]), _ptr(ro["ret"]))
-        b.h0, b.c0 = _ptr(ro["h0"]), _ptr(ro["c0"])
-        b.params, b.params_lp = _ptr(params), _ptr(params_lp)
-        return b, (env, lens), F, obs.device
+        return b, (env, lens), F, ro["mask"].device
 
     def loss_backward(self, ro: dict, env_ids, lengths, params, params_lp=None, cfg: LossCfg = None,
                       loss_scale=None, adv_stats=None, grad=None, stats=None):
@@ -261,6 +276,7 @@ class Net:
         if stats is None:
             stats = torch.empty(8, dtype=torch.float32, device=dev)
         ws = self.workspace(L.PPO_OP_LEARN, F, len(env_ids), dev)
+        self._last_learn = (F, len(env_ids))
         check(lib().ppo_loss_backward(self._h, C.byref(b), C.byref(c), _ptr(loss_scale), _ptr(grad),
                                       _ptr(stats), _ptr(ws), ws.numel(), _stream(dev)),
               "ppo_loss_backward")
@@ -274,9 +290,37 @@ class Net:
         values = torch.empty(F, dtype=torch.float32, device=dev)
         src = torch.empty(F, dtype=torch.int32, device=dev)
         ws = self.workspace(L.PPO_OP_LEARN, F, len(env_ids), dev)
+        self._last_learn = (F, len(env_ids))
         check(lib().ppo_policy_forward(self._h, C.byref(b), _ptr(logits), _ptr(values), _ptr(src), _ptr(ws),
                                        ws.numel(), _stream(dev)), "ppo_policy_forward")
         return logits, values, src
+
+    def loss_head(self, ro, env_ids, lengths, logits, values, cfg: LossCfg = None, loss_scale=None,
+                  adv_stats=None, dlogits=None, dvalues=None, stats=None, loss_out=None):
+        """The PPO objective on given policy outputs (frames in policy_forward's
+        order): (dlogits [F, A], dvalues [F], stats [8], loss_out (one element)); the
+        gradients and loss_out are of S*L (S = *loss_scale for bfloat16 nets)."""
+        cfg = cfg or LossCfg()
+        b, keep, F, dev = self._batch(ro, env_ids, lengths, None, None, learner=True, inputs=False)
+        _need(logits, torch.float32, "logits", F * self.A)
+        _need(values, torch.float32, "values", F)
+        c = L.LossCfg()
+        c.clip, c.value_coef, c.entropy_coef = cfg.clip, cfg.value_coef, cfg.entropy_coef
+        c.norm_adv = int(cfg.norm_adv)
+        c.adv_stats = _ptr(adv_stats)
+        if dlogits is None:
+            dlogits = torch.empty(F, self.A, dtype=torch.float32, device=dev)
+        if dvalues is None:
+            dvalues = torch.empty(F, dtype=torch.float32, device=dev)
+        if stats is None:
+            stats = torch.empty(8, dtype=torch.float32, device=dev)
+        if loss_out is None:
+            loss_out = torch.empty((), dtype=torch.float32, device=dev)
+        ws = self.workspace(L.PPO_OP_LOSS, F, len(env_ids), dev)
+        check(lib().ppo_loss_head(self._h, C.byref(b), C.byref(c), _ptr(loss_scale), _ptr(logits), _ptr(values),
+                                  _ptr(dlogits), _ptr(dvalues), _ptr(stats), _ptr(loss_out), _ptr(ws), ws.numel(),
+                                  _stream(dev)), "ppo_loss_head")
+        return dlogits, dvalues, stats, loss_out
 
     def policy_backward(self, ro, env_ids, lengths, params, params_lp, dlogits, dvalues, grad=None):
         b, keep, F, dev = self._batch(ro, env_ids, lengths, params, params_lp, learner=False)
@@ -285,6 +329,7 @@ class Net:
         if grad is None:
             grad = torch.empty(self.P, dtype=torch.float32, device=dev)
         ws = self.workspace(L.PPO_OP_LEARN, F, len(env_ids), dev)
+        self._last_learn = (F, len(env_ids))
         check(lib().ppo_policy_backward(self._h, C.byref(b), _ptr(dlogits), _ptr(dvalues), _ptr(grad),
                                         _ptr(ws), ws.numel(), _stream(dev)), "ppo_policy_backward")
         return grad

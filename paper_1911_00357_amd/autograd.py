@@ -1,11 +1,17 @@
-"""The policy as a torch.autograd.Function over the flat parameter vector.
+"""The learner as torch.autograd.Functions over the flat parameter vector.
 
-forward runs ppo_policy_forward (logits and values of every frame of a
-minibatch of whole env sequences); backward runs ppo_policy_backward, which
-recomputes the encoder and LSTM activations and applies the hand-written
-backward to the incoming d(logits), d(values).  Any loss written in torch on
-the outputs (for instance the clipped surrogate of Eq. 2) can then be
-differentiated with respect to the parameters.
+PolicyFunction: forward runs ppo_policy_forward (logits and values of every
+frame of a minibatch of whole env sequences); backward runs
+ppo_policy_backward, which recomputes the encoder and LSTM activations and
+applies the hand-written backward to the incoming d(logits), d(values).
+
+PPOLossFunction: the PPO objective (Eq. 2 with the value and entropy terms,
+the per-env weights 1/(|B| T_n) of Sec. 3, the loss scale) on the policy
+outputs, by ppo_loss_head: forward returns S*L and the loss statistics,
+backward the library's d(S*L)/d(logits, values), times the incoming
+gradient of the loss (the chain rule; 1 for a loss differentiated directly).
+Together they split ppo_loss_backward in three with torch's autograd graph
+in between; torch computes no part of the method.
 """
 from __future__ import annotations
 
@@ -30,23 +36,31 @@ class PolicyFunction(torch.autograd.Function):
         return grad, None, None, None, None, None
 
 
+class PPOLossFunction(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, logits, values, net, ro, env_ids, lengths, cfg, loss_scale, adv_stats):
+        dl, dv, stats, loss = net.loss_head(ro, env_ids, lengths, logits.detach().contiguous(),
+                                            values.detach().contiguous(), cfg, loss_scale, adv_stats)
+        ctx.save_for_backward(dl, dv)
+        ctx.mark_non_differentiable(stats)
+        return loss, stats
+
+    @staticmethod
+    def backward(ctx, g_loss, _g_stats):
+        dl, dv = ctx.saved_tensors
+        return g_loss * dl, g_loss * dv, None, None, None, None, None, None, None
+
+
 def policy(params, net, ro, env_ids, lengths=None, params_lp=None):
     """(logits [F, A], values [F], frame_src [F]) with autograd support on params."""
     return PolicyFunction.apply(params, net, ro, list(env_ids), lengths, params_lp)
 
 
-def ppo_loss(logits, values, src, ro, lengths_w, clip=0.2, value_coef=0.5, entropy_coef=0.01):
-    """The clipped PPO loss of Eq. 2 (+ value and entropy terms) written in
-    torch on the policy outputs; lengths_w [F] holds each frame's weight
-    1/(|B| T_n).  Used to exercise the autograd path."""
-    idx = src.long()
-    a = ro["action"].reshape(-1)[idx].long()
-    lp = torch.log_softmax(logits, -1)
-    lpa = lp.gather(1, a[:, None])[:, 0]
-    adv = ro["adv"].reshape(-1)[idx]
-    ratio = torch.exp(lpa - ro["logp"].reshape(-1)[idx])
-    surr = torch.min(ratio * adv, torch.clamp(ratio, 1 - clip, 1 + clip) * adv)
-    ent = -(lp.exp() * lp).sum(-1)
-    ret = ro["ret"].reshape(-1)[idx]
-    return (-(lengths_w * surr).sum() + value_coef * (lengths_w * 0.5 * (values - ret) ** 2).sum()
-            - entropy_coef * (lengths_w * ent).sum())
+def ppo_loss(logits, values, net, ro, env_ids, lengths=None, cfg=None, loss_scale=None, adv_stats=None):
+    """(S*L (0-dim), stats [8]) of the minibatch whose policy outputs are given
+    (frames in policy()'s order), differentiable in logits and values.
+    cfg: api.LossCfg (clip, coefficients, norm_adv); loss_scale: device
+    float [1] (bfloat16 nets); adv_stats: device double [2] when norm_adv."""
+    from .api import LossCfg
+    return PPOLossFunction.apply(logits, values, net, ro, list(env_ids), lengths, cfg or LossCfg(), loss_scale,
+                                 adv_stats)

@@ -500,9 +500,30 @@ extern "C" {
 
 const char* ppo_last_error(void) { return g_err.c_str(); }
 
+// The kernels are built for gfx950 only: a visible current device of another
+// architecture is refused.  With no device visible the host-side plan is
+// still built (sizes, tensor offsets); compute calls then fail at launch.
+ppo_status check_device() {
+  int count = 0;
+  if (hipGetDeviceCount(&count) != hipSuccess || count == 0) {
+    (void)hipGetLastError();
+    return PPO_OK;
+  }
+  int dev = 0;
+  hipDeviceProp_t prop;
+  if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess)
+    return fail(PPO_EDEVICE, "cannot query the current HIP device");
+  if (strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+    return fail(PPO_EUNSUPPORTED, "device %d is %s; the library's kernels are built for gfx950", dev,
+                prop.gcnArchName);
+  return PPO_OK;
+}
+
 ppo_status ppo_net_create(const ppo_net_desc* desc, ppo_net** out) {
   if (!desc || !out) return fail(PPO_EINVAL, "null argument");
   *out = nullptr;
+  const ppo_status dv = check_device();
+  if (dv != PPO_OK) return dv;
   ppo_net* n = new (std::nothrow) ppo_net();
   if (!n) return fail(PPO_EINVAL, "out of host memory");
   n->d = *desc;
@@ -532,10 +553,30 @@ ppo_status ppo_param_tensor(const ppo_net* net, int i, const char** name, size_t
   return PPO_OK;
 }
 
+// Workspace of ppo_loss_head: the frame map and the per-frame loss terms.
+struct LossWs {
+  size_t src, wf, mskf, envrow, fstat, total;
+};
+LossWs plan_loss(int F, int nb) {
+  Arena A;
+  LossWs w{};
+  w.src = A.take((size_t)F * 4);
+  w.wf = A.take((size_t)F * 4);
+  w.mskf = A.take((size_t)F * 4);
+  w.envrow = A.take((size_t)std::max(nb, 1) * 4);
+  w.fstat = A.take((size_t)F * 8 * sizeof(float));
+  w.total = A.off;
+  return w;
+}
+
 ppo_status ppo_workspace_size(const ppo_net* net, int op, int max_frames, int max_envs, size_t* bytes) {
   if (!net || !bytes) return fail(PPO_EINVAL, "null argument");
-  if (max_frames <= 0 || (op == PPO_OP_LEARN && (max_envs <= 0 || max_envs > kMaxMbEnvs)))
+  if (max_frames <= 0 || (op != PPO_OP_ACT && (max_envs <= 0 || max_envs > kMaxMbEnvs)))
     return fail(PPO_ESHAPE, "bad max_frames / max_envs");
+  if (op == PPO_OP_LOSS) {
+    *bytes = plan_loss(max_frames, max_envs).total;
+    return PPO_OK;
+  }
   if (op != PPO_OP_ACT && op != PPO_OP_LEARN) return fail(PPO_EINVAL, "unknown op");
   *bytes = plan(net, max_frames, max_envs, op == PPO_OP_LEARN).total;
   return PPO_OK;
@@ -645,10 +686,13 @@ struct Sched {
   std::vector<int> act, off;
 };
 
-ppo_status schedule(const ppo_net* net, const ppo_batch* b, Sched& S) {
+// Packing of a minibatch (envs longest first, frames time-major).  inputs:
+// also require the policy inputs (frames, goal, state, parameters).
+ppo_status schedule(const ppo_net* net, const ppo_batch* b, Sched& S, bool inputs = true) {
   const ppo_net_desc& d = net->d;
-  if (!b->env_ids || !b->obs || !b->goal || !b->mask || !b->h0 || !b->c0 || !b->params ||
-      (net->prec && !b->params_lp) || (d.prev_act_dim > 0 && !b->prev_action))
+  if (!b->env_ids || !b->mask ||
+      (inputs && (!b->obs || !b->goal || !b->h0 || !b->c0 || !b->params || (net->prec && !b->params_lp) ||
+                  (d.prev_act_dim > 0 && !b->prev_action))))
     return fail(PPO_EINVAL, "null pointer in ppo_batch");
   if (b->T <= 0 || b->N <= 0 || b->nb <= 0 || b->nb > b->N || b->nb > kMaxMbEnvs)
     return fail(PPO_ESHAPE, "bad T / N / nb");
@@ -699,6 +743,7 @@ const float* learner_fwd(const Ctx& c, const ppo_batch* b, const Sched& S) {
   const float* mskf = c.at(w.mskf);
   const int32_t* envrow = c.at<int32_t>(w.envrow);
   launch_frame_map(S.m, b->mask, c.at<int32_t>(w.src), c.at(w.wf), c.at(w.mskf), c.at<int32_t>(w.envrow), s);
+  launch_lstm_clear_error(c.at<unsigned>(w.sync), s);
   launch_gather_state(b->h0, L, b->N, nb, H, envrow, c.at(w.h0g), s);
   launch_gather_state(b->c0, L, b->N, nb, H, envrow, c.at(w.c0g), s);
 
@@ -778,8 +823,9 @@ void learner_bwd(const Ctx& c, const ppo_batch* b, const Sched& S, const float* 
   const float* Htop = c.at(w.hout[L - 1]);
   float* dout = c.at(w.dout);
   float* dH = c.at(w.dh0);
-  gemm_dense(net->prec, true, true, dout, A + 1, Htop, false, H, A + 1, H, F,
-             epi(grad + net->head_w, H), true, kSplitKBytes, c.splitk(), s);
+  // the head is float32 in both precisions (forward and its weight gradient)
+  gemm_dense(0, true, true, dout, A + 1, Htop, false, H, A + 1, H, F,
+             epi(grad + net->head_w, H), false, kSplitKBytes, c.splitk(), s);
   launch_colsum(dout, F, A + 1, A + 1, grad + net->head_b, s);
   float* dHn = c.at(w.dh1);
   int l_top = L - 1;
@@ -924,6 +970,30 @@ ppo_status ppo_policy_backward(ppo_net* net, const ppo_batch* b, const float* dl
   return check_launch();
 }
 
+ppo_status ppo_loss_head(ppo_net* net, const ppo_batch* b, const ppo_loss_cfg* cfg, const float* d_loss_scale,
+                         const float* logits, const float* values, float* dlogits, float* dvalues, float* stats,
+                         float* loss_out, void* ws, size_t ws_bytes, void* stream) {
+  if (!net || !b || !cfg || !logits || !values || !dlogits || !dvalues || !stats)
+    return fail(PPO_EINVAL, "null argument");
+  if (!b->action || !b->logp_old || !b->adv || !b->ret || (cfg->norm_adv && !cfg->adv_stats))
+    return fail(PPO_EINVAL, "null pointer in ppo_batch");
+  Sched S;
+  const ppo_status st = schedule(net, b, S, false);
+  if (st != PPO_OK) return st;
+  const LossWs w = plan_loss(S.F, b->nb);
+  if (!ws || ws_bytes < w.total) return fail(PPO_EWORKSPACE, "workspace needs %zu bytes", w.total);
+  if (!al256(ws)) return fail(PPO_EWORKSPACE, "workspace must be 256-byte aligned");
+  hipStream_t s = strm(stream);
+  char* base = (char*)ws;
+  launch_frame_map(S.m, b->mask, (int32_t*)(base + w.src), (float*)(base + w.wf), (float*)(base + w.mskf),
+                   (int32_t*)(base + w.envrow), s);
+  launch_loss_terms(logits, values, S.F, net->d.num_actions, (const int32_t*)(base + w.src), b->action,
+                    b->logp_old, b->adv, b->ret, (const float*)(base + w.wf), cfg->clip, cfg->value_coef,
+                    cfg->entropy_coef, cfg->norm_adv, cfg->adv_stats, net->prec ? d_loss_scale : nullptr,
+                    (float*)(base + w.fstat), dlogits, dvalues, stats, loss_out, s);
+  return check_launch();
+}
+
 size_t ppo_adam_workspace_size(size_t P) {
   (void)P;
   return adam_ws_bytes();
@@ -1062,6 +1132,26 @@ ppo_status ppo_workspace_probe(const ppo_net* net, int op, int max_frames, int m
   }
   if (kind == 3) {
     dims[0] = (int)net->units.size();
+    return PPO_OK;
+  }
+  if (kind == 5) {
+    if (net->d.trunk != PPO_TRUNK_RESNET) return fail(PPO_EINVAL, "no max pool in this trunk");
+    *offset = w.pool;
+    dims[0] = net->pool_h;
+    dims[1] = net->pool_w;
+    dims[2] = net->d.base_width;
+    return PPO_OK;
+  }
+  if (kind == 6 || kind == 7) {
+    if (index < 0 || index >= net->d.lstm_layers) return fail(PPO_EINVAL, "layer index out of range");
+    *offset = kind == 6 ? w.hp[index] : w.hout[index];
+    dims[0] = net->d.hidden;
+    return PPO_OK;
+  }
+  if (kind == 4) {
+    if (op != PPO_OP_LEARN) return fail(PPO_EINVAL, "the recurrence status is in learner workspaces");
+    *offset = w.sync + lstm_error_word_offset();
+    dims[0] = 1;
     return PPO_OK;
   }
   return fail(PPO_EINVAL, "unknown probe kind");

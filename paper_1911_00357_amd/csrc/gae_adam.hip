@@ -143,7 +143,7 @@ __global__ void __launch_bounds__(256) adam_finalize_kernel(const int* __restric
     c.inv_scale = 1.0f / sc->scale;
     c.skip = bad;
     if (bad) {
-      sc->scale = sc->scale * 0.5f;
+      if (growth > 0) sc->scale = sc->scale * 0.5f;  // a static scale (growth 0) stays fixed
       sc->good_steps = 0;
       sc->skipped += 1;
       sc->found_inf = 1;
@@ -152,8 +152,9 @@ __global__ void __launch_bounds__(256) adam_finalize_kernel(const int* __restric
       const int k = sc->step + 1;
       sc->step = k;
       sc->found_inf = 0;
-      c.c1 = (float)(1.0 / (1.0 - pow((double)b1, (double)k)));
-      c.c2 = (float)(1.0 / (1.0 - pow((double)b2, (double)k)));
+      // 1 / (1 - b^k) = -1 / expm1(k log1p(b - 1)); b - 1 is exact in float for b in [0.5, 1)
+      c.c1 = -1.0f / expm1f((float)k * log1pf(b1 - 1.0f));
+      c.c2 = -1.0f / expm1f((float)k * log1pf(b2 - 1.0f));
       if (growth > 0) {
         sc->good_steps += 1;
         if (sc->good_steps >= growth) {

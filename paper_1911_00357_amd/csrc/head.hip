@@ -79,11 +79,60 @@ void launch_act_head(const float* htop, int rows, int H, int A, const float* W, 
                      action, logp, value, logits);
 }
 
-// Learner head + PPO loss (Eq. 2 with ratio r = exp(logp - logp_old); value
-// term 1/2 (V - R)^2; entropy bonus), per frame f with weight w_f:
-//   fstat[f] = {w(-min(rA, clip(r)A)), w 1/2 (V-R)^2, w H, w [|r-1| > eps], w (lp_old - lp), r}
-//   dout[f]  = S * dL/d(logits, value)
-//   dh[f]    = dout[f] W      (gradient into the top LSTM output)
+// PPO loss terms of one frame (Eq. 2 with ratio r = exp(logp - logp_old);
+// value term 1/2 (V - R)^2; entropy bonus) with frame weight w, from its
+// logits o[0..A) and value o[A]:
+//   fs[0..6) = {w(-min(rA, clip(r)A)), w 1/2 (V-R)^2, w H, w [|r-1| > eps], w (lp_old - lp), r}
+//   d[0..A]  = S * dL/d(logits, value)
+DEV void ppo_frame_terms(const float o[kMaxA], int A, int a, float At, float lp_old, float R, float w,
+                         float clip, float vcoef, float ecoef, float S, float d[kMaxA], float fs[6]) {
+  float mx = o[0];
+  for (int k = 1; k < A; ++k) mx = fmaxf(mx, o[k]);
+  float se = 0.f;
+  for (int k = 0; k < A; ++k) se += expf(o[k] - mx);
+  const float lse = mx + logf(se);
+  const float lpa = o[a] - lse;
+  const float ratio = expf(lpa - lp_old);
+  const float s1 = ratio * At;
+  const float s2 = fminf(fmaxf(ratio, 1.f - clip), 1.f + clip) * At;
+  const float surr = fminf(s1, s2);
+  float ent = 0.f;
+  float p[kMaxA], lp[kMaxA];
+  for (int k = 0; k < A; ++k) {
+    lp[k] = o[k] - lse;
+    p[k] = expf(lp[k]);
+    ent -= p[k] * lp[k];
+  }
+  const float V = o[A];
+  // d/dlogp(a): the unclipped branch (taken at ties) carries r A
+  const float dlpa = (s1 <= s2) ? -w * At * ratio : 0.f;
+#pragma unroll
+  for (int k = 0; k < kMaxA; ++k) d[k] = 0.f;
+  for (int k = 0; k < A; ++k) {
+    const float onehot = (k == a) ? 1.f : 0.f;
+    d[k] = S * (dlpa * (onehot - p[k]) + ecoef * w * p[k] * (lp[k] + ent));
+  }
+  d[A] = S * vcoef * w * (V - R);
+  fs[0] = -w * surr;
+  fs[1] = w * 0.5f * (V - R) * (V - R);
+  fs[2] = w * ent;
+  fs[3] = (fabsf(ratio - 1.f) > clip) ? w : 0.f;
+  fs[4] = w * (lp_old - lpa);
+  fs[5] = ratio;
+}
+
+// the advantage of a frame, normalised with the float64 statistics of ppo_gae
+// (read once, then float32 arithmetic) when norm_adv is set
+DEV float frame_adv(const float* adv, int sidx, int norm_adv, const double* adv_stats) {
+  const float At = adv[sidx];
+  if (!norm_adv) return At;
+  const float mean = (float)adv_stats[0], sd = sqrtf((float)adv_stats[1]);
+  return (At - mean) / (sd + 1e-5f);
+}
+
+// Learner head + PPO loss, one wavefront per frame f:
+//   fstat[f] = ppo_frame_terms' fs; dout[f] = its d; dh[f] = dout[f] W (gradient
+//   into the top LSTM output)
 __global__ void __launch_bounds__(256) loss_head_kernel(
     const float* __restrict__ htop, int F, int H, int A, const float* __restrict__ W,
     const float* __restrict__ bias, const int32_t* __restrict__ src, const int32_t* __restrict__ actions,
@@ -96,60 +145,52 @@ __global__ void __launch_bounds__(256) loss_head_kernel(
   float o[kMaxA];
   head_dots(htop + (size_t)f * H, W, bias, H, A + 1, o);
   const int sidx = src[f];
-  const float w = wf[f];
-  const float S = loss_scale ? *loss_scale : 1.f;
-  float d[kMaxA];
-#pragma unroll
-  for (int k = 0; k < kMaxA; ++k) d[k] = 0.f;
+  float d[kMaxA], fs[6];
   // every lane computes the (scalar) loss terms; lane 0 stores them
-  float mx = o[0];
-  for (int k = 1; k < A; ++k) mx = fmaxf(mx, o[k]);
-  float se = 0.f;
-  for (int k = 0; k < A; ++k) se += expf(o[k] - mx);
-  const float lse = mx + logf(se);
-  const int a = actions[sidx];
-  const float lpa = o[a] - lse;
-  float At = adv[sidx];
-  if (norm_adv) At = (float)(((double)At - adv_stats[0]) / (sqrt(adv_stats[1]) + 1e-5));
-  const float ratio = expf(lpa - logp_old[sidx]);
-  const float s1 = ratio * At;
-  const float s2 = fminf(fmaxf(ratio, 1.f - clip), 1.f + clip) * At;
-  const float surr = fminf(s1, s2);
-  float ent = 0.f;
-  float p[kMaxA], lp[kMaxA];
-  for (int k = 0; k < A; ++k) {
-    lp[k] = o[k] - lse;
-    p[k] = expf(lp[k]);
-    ent -= p[k] * lp[k];
-  }
-  const float V = o[A], R = ret[sidx];
-  // d/dlogp(a): the unclipped branch (taken at ties) carries r A
-  const float dlpa = (s1 <= s2) ? -w * At * ratio : 0.f;
-  for (int k = 0; k < A; ++k) {
-    const float onehot = (k == a) ? 1.f : 0.f;
-    d[k] = S * (dlpa * (onehot - p[k]) + ecoef * w * p[k] * (lp[k] + ent));
-  }
-  d[A] = S * vcoef * w * (V - R);
+  ppo_frame_terms(o, A, actions[sidx], frame_adv(adv, sidx, norm_adv, adv_stats), logp_old[sidx], ret[sidx],
+                  wf[f], clip, vcoef, ecoef, loss_scale ? *loss_scale : 1.f, d, fs);
   if (lane == 0) {
-    float* fs = fstat + (size_t)f * 8;
-    fs[0] = -w * surr;
-    fs[1] = w * 0.5f * (V - R) * (V - R);
-    fs[2] = w * ent;
-    fs[3] = (fabsf(ratio - 1.f) > clip) ? w : 0.f;
-    fs[4] = w * (logp_old[sidx] - lpa);
-    fs[5] = ratio;
+    for (int k = 0; k < 6; ++k) fstat[(size_t)f * 8 + k] = fs[k];
     for (int k = 0; k <= A; ++k) dout[(size_t)f * (A + 1) + k] = d[k];
   }
   head_dh(d, W, H, A + 1, dh + (size_t)f * H);
 }
 
+// PPO loss on given policy outputs, one thread per frame: logits [F][A],
+// values [F] in, fstat as above, dlogits [F][A] and dvalues [F] out.
+__global__ void __launch_bounds__(256) loss_terms_kernel(
+    const float* __restrict__ logits, const float* __restrict__ values, int F, int A,
+    const int32_t* __restrict__ src, const int32_t* __restrict__ actions, const float* __restrict__ logp_old,
+    const float* __restrict__ adv, const float* __restrict__ ret, const float* __restrict__ wf, float clip,
+    float vcoef, float ecoef, int norm_adv, const double* __restrict__ adv_stats,
+    const float* __restrict__ loss_scale, float* __restrict__ fstat, float* __restrict__ dlogits,
+    float* __restrict__ dvalues) {
+  const int f = blockIdx.x * 256 + threadIdx.x;
+  if (f >= F) return;
+  float o[kMaxA];
+#pragma unroll
+  for (int k = 0; k < kMaxA; ++k) o[k] = 0.f;
+  for (int k = 0; k < A; ++k) o[k] = logits[(size_t)f * A + k];
+  o[A] = values[f];
+  const int sidx = src[f];
+  float d[kMaxA], fs[6];
+  ppo_frame_terms(o, A, actions[sidx], frame_adv(adv, sidx, norm_adv, adv_stats), logp_old[sidx], ret[sidx],
+                  wf[f], clip, vcoef, ecoef, loss_scale ? *loss_scale : 1.f, d, fs);
+  for (int k = 0; k < 6; ++k) fstat[(size_t)f * 8 + k] = fs[k];
+  for (int k = 0; k < A; ++k) dlogits[(size_t)f * A + k] = d[k];
+  dvalues[f] = d[A];
+}
+
 // stats[8] = {loss, pg, vf, ent, clip_frac, approx_kl, ratio_min, ratio_max}
+// loss_out (or NULL): S * stats[0], S = *loss_scale (1 when NULL).
 __global__ void __launch_bounds__(256) loss_stats_kernel(const float* __restrict__ fstat, int F,
                                                          float vcoef, float ecoef,
-                                                         float* __restrict__ stats) {
-  __shared__ double red[5][4];
+                                                         float* __restrict__ stats,
+                                                         const float* __restrict__ loss_scale,
+                                                         float* __restrict__ loss_out) {
+  __shared__ float red[5][4];
   __shared__ float rmn[4], rmx[4];
-  double acc[5] = {0, 0, 0, 0, 0};
+  float acc[5] = {0.f, 0.f, 0.f, 0.f, 0.f};
   float mn = INFINITY, mx = -INFINITY;
   for (int f = threadIdx.x; f < F; f += 256) {
     const float* fs = fstat + (size_t)f * 8;
@@ -170,14 +211,12 @@ __global__ void __launch_bounds__(256) loss_stats_kernel(const float* __restrict
   }
   __syncthreads();
   if (threadIdx.x == 0) {
-    double t[5];
-    for (int k = 0; k < 5; ++k) t[k] = red[k][0] + red[k][1] + red[k][2] + red[k][3];
-    stats[0] = (float)(t[0] + vcoef * t[1] - ecoef * t[2]);
-    stats[1] = (float)t[0];
-    stats[2] = (float)t[1];
-    stats[3] = (float)t[2];
-    stats[4] = (float)t[3];
-    stats[5] = (float)t[4];
+    float t[5];
+    for (int k = 0; k < 5; ++k) t[k] = (red[k][0] + red[k][1]) + (red[k][2] + red[k][3]);
+    const float loss = t[0] + vcoef * t[1] - ecoef * t[2];
+    stats[0] = loss;
+    for (int k = 0; k < 5; ++k) stats[1 + k] = t[k];
+    if (loss_out) *loss_out = loss * (loss_scale ? *loss_scale : 1.f);
     stats[6] = fminf(fminf(rmn[0], rmn[1]), fminf(rmn[2], rmn[3]));
     stats[7] = fmaxf(fmaxf(rmx[0], rmx[1]), fmaxf(rmx[2], rmx[3]));
   }
@@ -191,7 +230,20 @@ void launch_loss_head(const float* htop, int F, int H, int A, const float* W, co
   hipLaunchKernelGGL(loss_head_kernel, dim3(cdiv(F, 4)), dim3(256), 0, s, htop, F, H, A, W, b, src,
                      actions, logp_old, adv, ret, wf, clip, vcoef, ecoef, norm_adv, adv_stats, loss_scale,
                      fstat, dout, dh);
-  hipLaunchKernelGGL(loss_stats_kernel, dim3(1), dim3(256), 0, s, fstat, F, vcoef, ecoef, stats);
+  hipLaunchKernelGGL(loss_stats_kernel, dim3(1), dim3(256), 0, s, fstat, F, vcoef, ecoef, stats, nullptr,
+                     nullptr);
+}
+
+void launch_loss_terms(const float* logits, const float* values, int F, int A, const int32_t* src,
+                       const int32_t* actions, const float* logp_old, const float* adv, const float* ret,
+                       const float* wf, float clip, float vcoef, float ecoef, int norm_adv,
+                       const double* adv_stats, const float* loss_scale, float* fstat, float* dlogits,
+                       float* dvalues, float* stats, float* loss_out, hipStream_t s) {
+  hipLaunchKernelGGL(loss_terms_kernel, dim3(cdiv(F, 256)), dim3(256), 0, s, logits, values, F, A, src, actions,
+                     logp_old, adv, ret, wf, clip, vcoef, ecoef, norm_adv, adv_stats, loss_scale, fstat, dlogits,
+                     dvalues);
+  hipLaunchKernelGGL(loss_stats_kernel, dim3(1), dim3(256), 0, s, fstat, F, vcoef, ecoef, stats, loss_scale,
+                     loss_out);
 }
 
 // --------------------------------------------------------- LSTM input parts
@@ -251,7 +303,7 @@ __global__ void __launch_bounds__(256) embed_bwd_kernel(const float* __restrict_
   const int ngoal = polar ? goal_dim * 4 : 0;
   const int nemb = A1 * E;
   if (wid >= ngoal + nemb) return;
-  double acc = 0.0;
+  float acc = 0.f;
   if (wid < ngoal) {
     const int k = wid / 4, i = wid % 4;  // i < 3: weight column, i = 3: bias
     for (int f = lane; f < F; f += 64) {
@@ -262,12 +314,12 @@ __global__ void __launch_bounds__(256) embed_bwd_kernel(const float* __restrict_
         const float d = goal[(size_t)si * 2], th = goal[(size_t)si * 2 + 1];
         x = (i == 0) ? d : (i == 1 ? cosf(th) : sinf(th));
       }
-      acc += (double)g * x;
+      acc = fmaf(g, x, acc);
     }
     acc = wave_sum(acc);
     if (lane == 0) {
-      if (i < 3) dgw[k * 3 + i] = (float)acc;
-      else dgb[k] = (float)acc;
+      if (i < 3) dgw[k * 3 + i] = acc;
+      else dgb[k] = acc;
     }
   } else {
     const int q = wid - ngoal, a = q / E, j = q % E;
@@ -277,7 +329,7 @@ __global__ void __launch_bounds__(256) embed_bwd_kernel(const float* __restrict_
       if (idx == a) acc += dZ[(size_t)f * ldz + zoff + goal_dim + j];
     }
     acc = wave_sum(acc);
-    if (lane == 0) demb[(size_t)a * E + j] = (float)acc;
+    if (lane == 0) demb[(size_t)a * E + j] = acc;
   }
 }
 

@@ -156,6 +156,11 @@ void launch_transpose_whh(int prec, const void* W, int ldw, int H, void* WT, hip
 // does not allow it (nothing launched; the caller runs the per-step kernels).
 // sync: kLstmSyncBytes of device memory owned by the call.
 constexpr size_t kLstmSyncBytes = 257 * 256;
+// The sticky error word of the persistent launches (uint32 at this byte
+// offset of the sync area): nonzero once a barrier wait gave up and the
+// launch poisoned its outputs with NaN.  Cleared by launch_lstm_clear_error.
+size_t lstm_error_word_offset();
+void launch_lstm_clear_error(unsigned* sync, hipStream_t s);
 int launch_lstm_seq_fwd(int prec, const MapArgs& m, int TB, int H, const void* Whh, int ldw, float* G, float* HP,
                         float* CP, float* Cs, float* Ho, int ldh, const float* mskf, unsigned* sync,
                         hipStream_t s);
@@ -199,6 +204,11 @@ void launch_loss_head(const float* htop, int F, int H, int A, const float* W, co
                       const float* ret, const float* wf, float clip, float vcoef, float ecoef,
                       int norm_adv, const double* adv_stats, const float* loss_scale, float* fstat,
                       float* dout, float* dh, float* stats, hipStream_t s);
+void launch_loss_terms(const float* logits, const float* values, int F, int A, const int32_t* src,
+                       const int32_t* actions, const float* logp_old, const float* adv, const float* ret,
+                       const float* wf, float clip, float vcoef, float ecoef, int norm_adv,
+                       const double* adv_stats, const float* loss_scale, float* fstat, float* dlogits,
+                       float* dvalues, float* stats, float* loss_out, hipStream_t s);
 void launch_embed_fwd(const float* goal, const int32_t* prev_a, const float* mask, const int32_t* src,
                       int F, int polar, int goal_dim, const float* gw, const float* gb, int E,
                       const float* emb, float* Z, int ldz, int zoff, hipStream_t s);

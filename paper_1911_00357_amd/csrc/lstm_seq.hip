@@ -57,7 +57,7 @@ struct SeqArgs {
   int ldd;
   float* dG;        // [F][4H] gate pre-activation gradients (backward)
   const float* mskf;  // [F] m_t per packed row
-  unsigned* sync;     // [blocks] flag words at a 64-word stride, then the error word; zero at launch
+  unsigned* sync;     // [blocks] flag words at a 64-word stride (zeroed at launch); error word at kErrWord
   int len[kMaxMbEnvs];
 };
 
@@ -120,6 +120,10 @@ DEV float ldot(const float* row, int s, const float (&w)[KPT]) {
 }
 
 constexpr int kFlagStride = 64;  // words: one 256-byte line per block
+// The error word sits on the line after the largest grid's flags (at most 256
+// blocks, pick_units); launches clear only their flags, so a failure stays
+// visible until the next learner call clears it (launch_lstm_clear_error).
+constexpr int kErrWord = kFlagStride * 256;
 
 // Barrier `gen` (1, 2, ...) of the launch; `broken` is uniform in the block.
 DEV void grid_sync(unsigned* flags, unsigned gen, int& broken) {
@@ -136,7 +140,7 @@ DEV void grid_sync(unsigned* flags, unsigned gen, int& broken) {
     if (spins > kSpinLimit) {
       broken = 1;
       if (threadIdx.x == 0)
-        __hip_atomic_store(flags + kFlagStride * gridDim.x, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(flags + kErrWord, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       return;
     }
     __builtin_amdgcn_s_sleep(1);
@@ -679,7 +683,7 @@ int launch_seq(int prec, bool bwd, const MapArgs& m, int TB, int H, const void* 
   a.mskf = mskf;
   a.sync = sync;
   for (int j = 0; j < m.nb; ++j) a.len[j] = m.len[j];
-  const int nsync = kFlagStride * (nblk + 1);
+  const int nsync = kFlagStride * nblk;  // the flags; the error word is kept
   hipLaunchKernelGGL(zero_sync_kernel, dim3(cdiv(nsync, 256)), dim3(256), 0, s, sync, nsync);
   void* args[] = {&a};
   if (hipLaunchCooperativeKernel(k, dim3(nblk), dim3(256), args, (unsigned)shmem, s) != hipSuccess) {
@@ -738,7 +742,7 @@ int launch_seq2(int prec, bool bwd, const MapArgs& m, int TB, Seq2Args& a, hipSt
   a.TB = TB;
   a.nb = m.nb;
   for (int j = 0; j < m.nb; ++j) a.len[j] = m.len[j];
-  const int nsync = kFlagStride * (nblk + 1);
+  const int nsync = kFlagStride * nblk;  // the flags; the error word is kept
   hipLaunchKernelGGL(zero_sync_kernel, dim3(cdiv(nsync, 256)), dim3(256), 0, s, a.sync, nsync);
   void* args[] = {&a};
   if (hipLaunchCooperativeKernel(k, dim3(nblk), dim3(256), args, (unsigned)shmem, s) != hipSuccess) {
@@ -749,6 +753,12 @@ int launch_seq2(int prec, bool bwd, const MapArgs& m, int TB, Seq2Args& a, hipSt
 }
 
 }  // namespace
+
+void launch_lstm_clear_error(unsigned* sync, hipStream_t s) {
+  hipLaunchKernelGGL(zero_sync_kernel, dim3(1), dim3(64), 0, s, sync + kErrWord, 1);
+}
+
+size_t lstm_error_word_offset() { return (size_t)kErrWord * sizeof(unsigned); }
 
 int launch_lstm_seq_fwd(int prec, const MapArgs& m, int TB, int H, const void* Whh, int ldw, float* G, float* HP,
                         float* CP, float* Cs, float* Ho, int ldh, const float* mskf, unsigned* sync,

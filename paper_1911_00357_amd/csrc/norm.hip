@@ -4,8 +4,9 @@
 // Activations are [B][P][C] (NHWC, P = H*W pixels).  GroupNorm statistics are
 // gathered in two steps: every workgroup reduces one chunk of pixels of one
 // image for all channels into per-channel shifted sums, then one wavefront
-// per (image, group) merges the chunk results in float64 with the exact
-// parallel-variance formula.
+// per (image, group) merges the chunk results with the exact
+// parallel-variance formula (each chunk's centred second moment plus n_i
+// (mean_i - mean)^2), all in float32.
 #include "common.h"
 #include "kernels.h"
 
@@ -64,33 +65,33 @@ __global__ void __launch_bounds__(256) gn_finalize_kernel(const float4* __restri
   if (wid >= B * G) return;
   const int b = wid / G, g = wid % G, Cg = C / G;
   const int nparts = S * Cg;
-  double sn = 0.0, sx = 0.0;
+  float sn = 0.f, sx = 0.f;
 #pragma unroll 4
   for (int i = lane; i < nparts; i += 64) {
     const int s = i / Cg, c = g * Cg + i % Cg;
     const float4 v = part[((size_t)b * S + s) * C + c];
-    sn += (double)v.w;
-    sx += (double)v.w * (double)v.z + (double)v.x;  // n K + sum(y - K)
+    sn += v.w;
+    sx += fmaf(v.w, v.z, v.x);  // n K + sum(y - K)
   }
   sn = wave_sum(sn);
   sx = wave_sum(sx);
-  const double mean = sn > 0 ? sx / sn : 0.0;
-  double m2 = 0.0;
+  const float mean = sn > 0.f ? sx / sn : 0.f;
+  float m2 = 0.f;
 #pragma unroll 4
   for (int i = lane; i < nparts; i += 64) {
     const int s = i / Cg, c = g * Cg + i % Cg;
     const float4 v = part[((size_t)b * S + s) * C + c];
-    if (v.w > 0) {
-      const double n = v.w, mi = (double)v.z + (double)v.x / n;
-      const double m2i = (double)v.y - (double)v.x * (double)v.x / n;
-      const double d = mi - mean;
-      m2 += m2i + n * d * d;
+    if (v.w > 0.f) {
+      const float n = v.w, a = v.x / n;  // chunk mean - K
+      const float m2i = fmaxf(v.y - v.x * a, 0.f);
+      const float d = (v.z - mean) + a;
+      m2 += fmaf(n * d, d, m2i);
     }
   }
   m2 = wave_sum(m2);
   if (lane == 0) {
-    const double var = sn > 0 ? fmax(m2 / sn, 0.0) : 0.0;
-    stats[wid] = make_float2((float)mean, (float)(1.0 / sqrt(var + (double)eps)));
+    const float var = sn > 0.f ? fmaxf(m2 / sn, 0.f) : 0.f;
+    stats[wid] = make_float2(mean, 1.0f / sqrtf(var + eps));
   }
 }
 
@@ -225,25 +226,25 @@ __global__ void __launch_bounds__(256) gnb_coef_affine_kernel(const float2* __re
   const int wid = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
   if (wid < B * G) {
     const int b = wid / G, g = wid % G, Cg = C / G;
-    double a = 0.0, q = 0.0;
+    float a = 0.f, q = 0.f;
 #pragma unroll 4
     for (int i = lane; i < S * Cg; i += 64) {
       const int s = i / Cg, c = g * Cg + i % Cg;
       const float2 v = bpart[((size_t)b * S + s) * C + c];
-      a += (double)gamma[c] * v.x;
-      q += (double)gamma[c] * v.y;
+      a = fmaf(gamma[c], v.x, a);
+      q = fmaf(gamma[c], v.y, q);
     }
     a = wave_sum(a);
     q = wave_sum(q);
     if (lane == 0) {
-      const double n = (double)P * Cg;
-      coef[wid] = make_float2((float)(a / n), (float)(q / n));
+      const float n = (float)P * (float)Cg;
+      coef[wid] = make_float2(a / n, q / n);
     }
     return;
   }
   const int c = wid - B * G;
   if (c >= C) return;
-  double a = 0.0, q = 0.0;
+  float a = 0.f, q = 0.f;
 #pragma unroll 4
   for (int i = lane; i < B * S; i += 64) {
     const float2 v = bpart[(size_t)i * C + c];
@@ -253,8 +254,8 @@ __global__ void __launch_bounds__(256) gnb_coef_affine_kernel(const float2* __re
   a = wave_sum(a);
   q = wave_sum(q);
   if (lane == 0) {
-    dgamma[c] = (float)q;
-    dbeta[c] = (float)a;
+    dgamma[c] = q;
+    dbeta[c] = a;
   }
 }
 
@@ -264,7 +265,7 @@ __global__ void __launch_bounds__(256) gnb_affine_kernel(const float2* __restric
                                                          float* __restrict__ dbeta) {
   const int c = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
   if (c >= C) return;
-  double a = 0.0, q = 0.0;
+  float a = 0.f, q = 0.f;
 #pragma unroll 4
   for (int i = lane; i < B * S; i += 64) {
     const float2 v = bpart[(size_t)i * C + c];
@@ -274,8 +275,8 @@ __global__ void __launch_bounds__(256) gnb_affine_kernel(const float2* __restric
   a = wave_sum(a);
   q = wave_sum(q);
   if (lane == 0) {
-    dgamma[c] = (float)q;
-    dbeta[c] = (float)a;
+    dgamma[c] = q;
+    dbeta[c] = a;
   }
 }
 
@@ -482,13 +483,13 @@ void launch_relu_grad(const float* dy, const float* y, size_t n, float* dx, hipS
 // apply.  The input is the convolution output, or the sum of its split-K
 // partial tiles (src + z*zstride), in which case the summed output can also
 // be stored (u_out) for the backward.
-// Two block sums in one reduction (double within each wavefront).
+// Two block sums in one reduction.
 template <int NT>
 DEV float2 block_sum2(float v0, float v1, float2* red) {
-  const double d0 = wave_sum((double)v0), d1 = wave_sum((double)v1);
+  const float d0 = wave_sum(v0), d1 = wave_sum(v1);
   const int w = threadIdx.x >> 6;
   __syncthreads();
-  if ((threadIdx.x & 63) == 0) red[w] = make_float2((float)d0, (float)d1);
+  if ((threadIdx.x & 63) == 0) red[w] = make_float2(d0, d1);
   __syncthreads();
   float2 t = make_float2(0.f, 0.f);
 #pragma unroll
@@ -501,10 +502,10 @@ DEV float2 block_sum2(float v0, float v1, float2* red) {
 
 template <int NT = 256>
 DEV float block_sum(float v, float* red) {
-  double d = wave_sum((double)v);
+  const float d = wave_sum(v);
   const int w = threadIdx.x >> 6;
   __syncthreads();
-  if ((threadIdx.x & 63) == 0) red[w] = (float)d;
+  if ((threadIdx.x & 63) == 0) red[w] = d;
   __syncthreads();
   float t = 0.f;
 #pragma unroll

@@ -143,26 +143,23 @@ class Worker:
         return adv, ret
 
     def update_autograd(self, env, partitions, lengths=None):
-        """The same update with the gradient taken through torch.autograd:
-        the policy is a torch.autograd.Function whose backward recomputes the
-        encoder and LSTM activations, and the PPO loss is written in torch on
-        its outputs."""
+        """The same update with the gradient taken through torch.autograd: the
+        policy is a torch.autograd.Function whose backward recomputes the
+        encoder and LSTM activations, and the PPO objective another whose
+        forward and backward are ppo_loss_head (weights, loss scale and
+        advantage normalisation applied in the library)."""
         from .autograd import policy, ppo_loss
         adv, ret = self.advantages(env, lengths)
         ro = self.rollout_view(env, adv, ret)
-        lens_h = np.full(self.N, self.T) if lengths is None else np.asarray(lengths)
-        lens = torch.as_tensor(lens_h, dtype=torch.float32, device=self.dev)
+        cfg = LossCfg(self.hp.clip, self.hp.value_coef, self.hp.entropy_coef, self.hp.norm_adv)
         theta = self.params.detach().requires_grad_(True)   # shares storage with the master weights
         scale = self.adam.scale_tensor() if self.bf16 else None
         for ep in partitions:
             for envs in ep:
-                envs = sorted((int(e) for e in envs), key=lambda e: -lens_h[e])
-                logits, values, src = policy(theta, self.net, ro, envs, lengths, self.lp)
-                wts = 1.0 / (len(envs) * lens[src.long() % self.N])
-                loss = ppo_loss(logits, values, src, ro, wts, self.hp.clip, self.hp.value_coef,
-                                self.hp.entropy_coef)
-                if scale is not None:
-                    loss = loss * scale[0]
+                envs = [int(e) for e in envs]
+                logits, values, _ = policy(theta, self.net, ro, envs, lengths, self.lp)
+                loss, self.stats = ppo_loss(logits, values, self.net, ro, envs, lengths, cfg, scale,
+                                            self.adv_stats)
                 (g,) = torch.autograd.grad(loss, theta)
                 self.adam.step(self.params, g, self.lp)
         return adv, ret

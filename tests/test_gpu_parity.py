@@ -11,7 +11,8 @@ import oracle
 from oracle import params as OP, policy, ppo
 from synth import rollout as R
 from synth.configs import C0, C1, PPOCfg
-from tests.gpu_util import DEV, oracle_minibatch, per_tensor_errors, random_record, rel_err, to_device
+from tests.gpu_util import (DEV, assert_close, errs, flip_summary, oracle_minibatch, random_record, rel_err,
+                            tensor_errors, to_device, validate_decisions)
 from tests.nets import MINI_RESNET, RESNET_64, RESNET_SMALLCORE, TINY_BIGCORE, TINY_CORE1024, TINY_NET, TINY_PLUS
 
 pytestmark = pytest.mark.gpu
@@ -40,8 +41,8 @@ def test_gae_parity(P, T, N, ragged, seed):
                      0.99, 0.95, stats=stats)
     A, Rt = ppo.gae(rew, val, done, lens, 0.99, 0.95)
     torch.cuda.synchronize()
-    assert rel_err(adv.cpu().numpy(), A) < 1e-5
-    assert rel_err(ret.cpu().numpy(), Rt) < 1e-5
+    assert_close("advantages", adv.cpu().numpy(), A, 1e-5)
+    assert_close("returns", ret.cpu().numpy(), Rt, 1e-5)
     mu, var = ppo.adv_stats(A, lens)
     s = stats.cpu().numpy()
     assert abs(s[0] - mu) < 1e-6 * max(1, abs(mu)) and abs(s[1] - var) < 1e-5 * var
@@ -56,7 +57,7 @@ def test_gae_closed_form_lambda0(P):
     adv, _ = P.gae(torch.tensor(rew, device=DEV), torch.tensor(val, device=DEV),
                    torch.tensor(done, device=DEV), None, 0.9, 0.0)
     td = rew.astype(np.float64) + 0.9 * (1 - done) * val[1:] - val[:-1]
-    assert rel_err(adv.cpu().numpy(), td) < 1e-6
+    assert_close("advantages", adv.cpu().numpy(), td, 1e-6)
 
 
 # ---------------------------------------------------------------- Adam
@@ -76,7 +77,7 @@ def test_adam_parity(P):
         tho, m, v = ppo.adam(before, gr.astype(np.float64), m, v, k, 2.5e-4)
         got = master.cpu().numpy().astype(np.float64)
         # float32 storage of theta bounds the agreement of the update
-        assert rel_err(got - before, tho - before) < 1e-4
+        assert_close("update", got - before, tho - before, 1e-4)
     st = opt.state()
     assert st["step"] == 3 and st["skipped"] == 0
     assert torch.equal(lp, master.to(torch.bfloat16))
@@ -98,6 +99,26 @@ def test_adam_skips_non_finite_and_halves_scale(P):
     opt.step(master, g)
     opt.step(master, g)
     assert opt.state()["scale"] == 1024.0 and opt.state()["step"] == 3
+
+
+def test_adam_static_scale_kept_on_skip(P):
+    """A float32 net's scale (1, no growth) stays 1 when a non-finite gradient
+    skips a step, so later gradients are not rescaled."""
+    n = 1000
+    master = torch.randn(n, device=DEV)
+    opt = P.Adam(n, DEV, lr=1e-3, loss_scale=1.0, growth_interval=0)
+    g = torch.randn(n, device=DEV)
+    g[3] = float("nan")
+    th0 = master.clone()
+    opt.step(master, g)
+    st = opt.state()
+    assert torch.equal(master, th0) and st["skipped"] == 1 and st["scale"] == 1.0 and st["step"] == 0
+    g[3] = 0.0
+    opt.step(master, g)
+    tho, _, _ = ppo.adam(th0.cpu().numpy().astype(np.float64), g.cpu().numpy().astype(np.float64),
+                         np.zeros(n), np.zeros(n), 1, 1e-3)
+    assert opt.state()["scale"] == 1.0 and opt.state()["step"] == 1
+    assert_close("update", master.cpu().numpy() - th0.cpu().numpy(), tho - th0.cpu().numpy(), 1e-4)
 
 
 # ---------------------------------------------------------------- act
@@ -124,7 +145,34 @@ def _act_case(P, net, dtype, B, seed, state_rows=0):
     torch.cuda.synchronize()
     ref = policy.act(OP.unpack(net, flat), net, obs, goal, prev, mask, h[:, :B], c[:, :B], u)
     ref["u"] = u
+    if dtype == "bf16":
+        ref["form"] = policy.act(OP.unpack(net, flat), net, obs, goal, prev, mask, h[:, :B], c[:, :B], u,
+                                 quant="bf16")
+        ref["form"]["u"] = u
     return out, ref
+
+
+def check_act(out, ref, dtype, B, tag):
+    """Logits, value, h, c (and float32 log-probs) within the tolerance of the
+    float64 oracle (relative L2 and element-wise); float32 actions identical,
+    bfloat16 actions identical or flipped only where u lies within the
+    tolerance of a CDF step.  For bfloat16 the error of the oracle's own
+    bfloat16 precision form is printed beside the GPU's (a forward pass is
+    continuous: no decision is imposed)."""
+    tol = TOL[dtype]
+    g = lambda k: out[k].cpu().numpy()[:, :B] if k in ("h", "c") else out[k].cpu().numpy()
+    line = []
+    for k in ("logits", "value", "h", "c"):
+        l2, mx = assert_close(k, g(k), ref[k], tol)
+        line.append(f"{k} {l2:.1e}/{mx:.1e}")
+        if dtype == "bf16":
+            line[-1] += " (form %.1e/%.1e)" % errs(ref["form"][k], ref[k])
+    say(f"  {tag}: " + "; ".join(line))
+    if dtype == "f32":
+        np.testing.assert_array_equal(g("action"), ref["action"])
+        assert_close("logp", g("logp"), ref["logp"], tol)
+    else:
+        assert_actions_agree(g("action"), ref, tol)
 
 
 @pytest.mark.parametrize("name,net,dtype,B", [("tiny", TINY_NET, "f32", 2), ("tiny", TINY_NET, "f32", 5),
@@ -140,14 +188,7 @@ def _act_case(P, net, dtype, B, seed, state_rows=0):
 def test_act_parity_small(P, name, net, dtype, B):
     say(f"act {name} {dtype} B={B}")
     out, ref = _act_case(P, net, dtype, B, seed=B)
-    tol = TOL[dtype]
-    assert rel_err(out["logits"].cpu().numpy(), ref["logits"]) < tol
-    assert rel_err(out["value"].cpu().numpy(), ref["value"]) < tol
-    assert rel_err(out["h"].cpu().numpy(), ref["h"]) < tol
-    assert rel_err(out["c"].cpu().numpy(), ref["c"]) < tol
-    if dtype == "f32":
-        np.testing.assert_array_equal(out["action"].cpu().numpy(), ref["action"])
-        assert rel_err(out["logp"].cpu().numpy(), ref["logp"]) < tol
+    check_act(out, ref, dtype, B, name)
 
 
 @pytest.mark.parametrize("dtype", ["f32", "bf16"])
@@ -155,11 +196,7 @@ def test_act_parity_resnet_paper_shape(P, dtype):
     """The paper's encoder at 256x256 frames, batch 4 (one act step of a worker)."""
     say(f"act resnet {dtype}")
     out, ref = _act_case(P, C1.net, dtype, 4, seed=11, state_rows=6)
-    tol = TOL[dtype]
-    assert rel_err(out["logits"].cpu().numpy(), ref["logits"]) < tol
-    assert rel_err(out["value"].cpu().numpy(), ref["value"]) < tol
-    assert rel_err(out["h"].cpu().numpy()[:, :4], ref["h"]) < tol
-    assert_actions_agree(out["action"].cpu().numpy(), ref, tol)
+    check_act(out, ref, dtype, 4, "resnet")
 
 
 def assert_actions_agree(a, ref, tol):
@@ -175,40 +212,116 @@ def assert_actions_agree(a, ref, tol):
 
 
 # ---------------------------------------------------------- loss backward
-def gpu_decisions(n, net, F, nb, mb):
+def _ws_f32(ws, off, n):
+    return ws[off:off + n * 4].view(torch.float32).cpu().numpy()
+
+
+def gpu_decisions(n, net, F, nb, mb, codes=False):
     """The ReLU patterns and max-pool winners the GPU used in its last
-    ppo_loss_backward, in the oracle's layout (frames time-major)."""
+    learner call, in the oracle's layout (frames time-major); with codes,
+    also the bfloat16 codes of every activation operand it rounded (each
+    convolution's input by the convolution's name, the visual FC's input, each
+    LSTM layer's input and masked previous state), as decide's 'q:' keys."""
+    from oracle.nn import round_bf16
     from paper_1911_00357_amd._lib import PPO_OP_LEARN
     ws = n.last_workspace(PPO_OP_LEARN)
     dec = {}
     nunits = n.probe(PPO_OP_LEARN, F, nb, 3)[3][0]
+    outs = {}
     for i in range(nunits):
         name, relu, off, (ho, wo, C, chw) = n.probe(PPO_OP_LEARN, F, nb, 0, i)
-        if not relu:
+        if not relu and not codes:
             continue
-        a = ws[off:off + F * ho * wo * C * 4].view(torch.float32).cpu().numpy()
+        a = _ws_f32(ws, off, F * ho * wo * C)
         a = a.reshape(F, C, ho, wo) if chw else a.reshape(F, ho, wo, C).transpose(0, 3, 1, 2)
         key = name[len("enc."):]
-        if key.endswith(".c3"):
-            key = key[:-2] + "out"
-        dec[key] = a > 0
+        if relu:
+            dec[key[:-2] + "out" if key.endswith(".c3") else key] = a > 0
+        if codes:
+            outs[key] = round_bf16(a)
     if net.trunk == "resnet":
         _, _, off, (h, w, C, _) = n.probe(PPO_OP_LEARN, F, nb, 1)
         dec["maxpool"] = ws[off:off + F * h * w * C].cpu().numpy().reshape(F, h, w, C).transpose(0, 3, 1, 2)
-    _, _, off, (d0, vis, _, _) = n.probe(PPO_OP_LEARN, F, nb, 2)
-    z = ws[off:off + F * d0 * 4].view(torch.float32).cpu().numpy().reshape(F, d0)
     TB, B = mb["action"].shape
     valid = np.arange(TB)[:, None] < mb["lens"][None, :]
     tt, jj = np.nonzero(valid)
-    vm = np.zeros((TB, B, vis), bool)
-    vm[tt, jj] = z[:, :vis] > 0
-    dec["vis"] = vm
+
+    def tm(rows):                       # packed frame rows -> [T_B, B, .] (invalid frames 0)
+        o = np.zeros((TB, B) + rows.shape[1:], rows.dtype)
+        o[tt, jj] = rows
+        return o
+
+    _, _, off, (d0, vis, _, _) = n.probe(PPO_OP_LEARN, F, nb, 2)
+    z = _ws_f32(ws, off, F * d0).reshape(F, d0)
+    dec["vis"] = tm(z[:, :vis] > 0)
+    if codes:
+        if net.trunk == "resnet":
+            _, _, off, (h, w, C, _) = n.probe(PPO_OP_LEARN, F, nb, 5)
+            prev = round_bf16(_ws_f32(ws, off, F * h * w * C).reshape(F, h, w, C).transpose(0, 3, 1, 2))
+            for s_ in range(4):
+                for j in range(net.blocks[s_]):
+                    pre = "s%d.b%d." % (s_, j)
+                    dec["q:" + pre + "c1"] = prev
+                    if j == 0:
+                        dec["q:" + pre + "ds"] = prev
+                    dec["q:" + pre + "c2"] = outs[pre + "c1"]
+                    dec["q:" + pre + "c3"] = outs[pre + "c2"]
+                    prev = outs[pre + "c3"]
+            dec["q:compress"] = prev
+            last = outs["compress"]
+        else:
+            dec["q:conv2"] = outs["conv1"]
+            last = outs["conv2"]
+        dec["q:fc"] = tm(last.reshape(F, -1))
+        dec["q:lstm0.x"] = tm(round_bf16(z))
+        H = net.hidden
+        for l in range(net.lstm_layers):
+            off = n.probe(PPO_OP_LEARN, F, nb, 6, l)[2]
+            dec["q:lstm%d.h" % l] = tm(round_bf16(_ws_f32(ws, off, F * H).reshape(F, H)))
+            if l + 1 < net.lstm_layers:
+                off = n.probe(PPO_OP_LEARN, F, nb, 7, l)[2]
+                dec["q:lstm%d.x" % (l + 1)] = tm(round_bf16(_ws_f32(ws, off, F * H).reshape(F, H)))
     return dec
 
 
-def _loss_case(P, net, dtype, T, N, envs, lengths, seed, norm_adv=False, same_decisions=False):
+FLIP_TOL = {"f32": 1e-3, "bf16": 1e-3}     # near-kink margin of a flipped decision (x rms)
+QTOL = 1e-4      # an imposed bfloat16 code: the rounding of a value within QTOL x rms of the oracle's
+AT_RISK = 1e-2   # bfloat16 tensors whose precision-form error (own rounding) reaches this are reported
+
+
+class LossCase:
+    """GPU loss/gradient of one minibatch (g, s) and its oracle references,
+    with the GPU's ReLU / max-pool decisions imposed when `flips` is set:
+    `exact` (float64); for bfloat16 also `own` (the precision form with its
+    own roundings: the form's cost) and `form` (the precision form with the
+    GPU's bfloat16 operand codes imposed too: what the kernels must match)."""
+
+
+def oracle_refs(c, net, dtype, flat, mb, dec, mu_var=None, coded=None):
+    """Fill c's oracle references (see LossCase); dec: the GPU's decisions,
+    coded: the same plus operand codes (bfloat16)."""
+    flat64 = flat.astype(np.float64)
+    cfg = PPOCfg()
+    r = {} if dec is not None else None
+    if dtype == "f32":
+        c.s_exact, c.g_exact = ppo.loss_grad(flat64, net, cfg, mb, adv_norm=mu_var, decide=dec, record=r,
+                                             record_outputs=False)
+        if dec is not None:
+            c.flips = validate_decisions(dec, r, mb["lens"], FLIP_TOL[dtype])
+        return c
+    c.s_form, c.g_form = ppo.loss_grad(flat64, net, cfg, mb, adv_norm=mu_var, decide=coded, quant="bf16",
+                                       record=r, record_outputs=False)
+    if coded is not None:
+        c.flips = validate_decisions(coded, r, mb["lens"], FLIP_TOL[dtype], QTOL)
+    del r
+    c.s_own, c.g_own = ppo.loss_grad(flat64, net, cfg, mb, adv_norm=mu_var, decide=dec, quant="bf16")
+    c.s_exact, c.g_exact = ppo.loss_grad(flat64, net, cfg, mb, adv_norm=mu_var, decide=dec)
+    return c
+
+
+def _loss_case(P, net, dtype, T, N, envs, lengths, seed, norm_adv=False, same_decisions=False, rec=None):
     flat = R.init_params(net, seed, random_affine=True)
-    rec = random_record(net, T, N, seed + 1, lengths=lengths, bf16=dtype == "bf16")
+    rec = rec or random_record(net, T, N, seed + 1, lengths=lengths, bf16=dtype == "bf16")
     if lengths is not None:   # longest first (the library's packing order)
         envs = sorted(envs, key=lambda e: -lengths[e])
     n = P.Net(net, dtype)
@@ -225,41 +338,73 @@ def _loss_case(P, net, dtype, T, N, envs, lengths, seed, norm_adv=False, same_de
                                   loss_scale=torch.tensor([1.0], device=DEV), adv_stats=adv_stats)
     torch.cuda.synchronize()
     mb = oracle_minibatch(rec, envs)
-    dec = None
+    c = LossCase()
+    c.g, c.s = grad.cpu().numpy(), stats.cpu().numpy()
+    c.flips = None
+    dec = coded = None
     if same_decisions:
         F = int(mb["lens"].sum())
-        dec = gpu_decisions(n, net, F, len(envs), mb)
-    s_ref, g_ref = ppo.loss_grad(flat.astype(np.float64), net, PPOCfg(), mb, adv_norm=mu_var, decide=dec)
-    floor = None
-    if dtype == "bf16" and same_decisions:
-        # the exact gradient at the bfloat16-rounded weights, same decisions: how far
-        # rounding the working copy alone moves each tensor's gradient
-        _, g_w = ppo.loss_grad(R.round_bf16(flat).astype(np.float64), net, PPOCfg(), mb, adv_norm=mu_var,
-                               decide=dec)
-        floor = per_tensor_errors(net, g_w, g_ref)
-    return grad.cpu().numpy(), stats.cpu().numpy(), g_ref, s_ref, floor
+        if dtype == "bf16":
+            coded = gpu_decisions(n, net, F, len(envs), mb, codes=True)
+            dec = {k: v for k, v in coded.items() if not k.startswith("q:")}
+        else:
+            dec = gpu_decisions(n, net, F, len(envs), mb)
+    del n, ro
+    torch.cuda.empty_cache()
+    return oracle_refs(c, net, dtype, flat, mb, dec, mu_var, coded)
 
 
-def check_loss(net, dtype, g, s, g_ref, s_ref, tag, floor=None):
-    """Loss terms and the whole gradient within the tolerance; each parameter
-    tensor's gradient within the tolerance, or (bfloat16) within 4x the change
-    that rounding the weights to bfloat16 alone causes in the exact gradient
-    (cancellation-heavy tensors such as deep GroupNorm scales).  The kernels
-    round both operands of every product (weights and activations) and the
-    floor measures the weight rounding only: about twice the floor is the
-    expected error, and the bound leaves a factor 2 over that."""
-    tol = TOL[dtype]
-    errs = per_tensor_errors(net, g, g_ref)
-    order = sorted(errs, key=errs.get, reverse=True)
-    say(f"  {tag}: global grad err {rel_err(g, g_ref):.2e}; worst tensors: " +
-        ", ".join(f"{k}={errs[k]:.1e}" + (f"(floor {floor[k]:.1e})" if floor else "") for k in order[:5]) +
-        f"; loss {s[0]:.6f} vs {s_ref[0]:.6f}")
+def _loss_rel(s, s_ref):
+    """Loss terms' errors: total relative to |L_pg| + c_v |L_v| + c_e |L_H|,
+    each term relative to itself."""
     denom = abs(s_ref[1]) + 0.5 * abs(s_ref[2]) + 0.01 * abs(s_ref[3])
-    assert abs(s[0] - s_ref[0]) / denom < tol
-    for k in (1, 2, 3):
-        assert abs(s[k] - s_ref[k]) <= tol * max(abs(s_ref[k]), 1e-6)
-    assert rel_err(g, g_ref) < tol
-    bad = {k: v for k, v in errs.items() if v >= tol and (floor is None or v >= 4 * floor[k])}
+    return [abs(s[0] - s_ref[0]) / denom] + [abs(s[k] - s_ref[k]) / max(abs(s_ref[k]), 1e-6) for k in (1, 2, 3)]
+
+
+def check_loss(net, dtype, c, tag):
+    """float32: every loss term, the whole gradient and each parameter
+    tensor's gradient (relative L2 and element-wise) within 1e-4 of the
+    float64 oracle.
+
+    bfloat16: (i) against the bfloat16 precision form with the GPU's
+    decisions and operand codes imposed (so both sides multiply the same
+    operands): loss terms within 1e-4, the whole gradient within 1e-3 and each
+    tensor within 5e-3 (relative L2 and element-wise) -- the kernels' gradient
+    operands carry 16 significant bits (hi + lo), 2^7 times float32's
+    rounding, and the float32 path's worst tensors sit near 3e-5;
+    (ii) against the float64 oracle (the GPU's decisions imposed): loss terms
+    and the whole gradient within 2e-2, and each tensor within 2e-2 except
+    tensors on which the form with its own roundings already reaches 1e-2
+    (its error there is one draw of the rounding noise, the GPU's another);
+    those are listed with both errors."""
+    tol = TOL[dtype]
+    er = tensor_errors(net, c.g, c.g_exact)
+    order = sorted(er, key=lambda k: -er[k][0])
+    say(f"  {tag}: grad err {rel_err(c.g, c.g_exact):.2e}; worst tensors (L2, elem): " +
+        ", ".join(f"{k}=({er[k][0]:.1e},{er[k][1]:.1e})" for k in order[:4]) +
+        f"; loss {c.s[0]:.6f} vs {c.s_exact[0]:.6f}" +
+        (f"; {flip_summary(c.flips)}" if c.flips is not None else ""))
+    at_risk = {}
+    if dtype == "bf16":
+        eq = tensor_errors(net, c.g, c.g_form)
+        worst = sorted(eq, key=lambda k: -max(eq[k]))[:4]
+        say(f"  {tag}: vs bf16 form with the GPU's codes: grad {rel_err(c.g, c.g_form):.2e}, loss "
+            f"{max(_loss_rel(c.s, c.s_form)):.1e}; worst tensors " +
+            ", ".join(f"{k}=({eq[k][0]:.1e},{eq[k][1]:.1e})" for k in worst))
+        assert max(_loss_rel(c.s, c.s_form)) < 1e-4
+        assert rel_err(c.g, c.g_form) < 1e-3
+        bad = {k: eq[k] for k in eq if max(eq[k]) >= 5e-3}
+        assert not bad, f"GPU vs bf16 form (L2, elem): {bad}"
+        eo = tensor_errors(net, c.g_own, c.g_exact)
+        at_risk = {k: eo[k] for k in eo if max(eo[k]) >= AT_RISK}
+        over = {k: er[k] for k in at_risk if max(er[k]) >= tol}
+        say(f"  {tag}: bf16 form (own roundings) vs exact: grad {rel_err(c.g_own, c.g_exact):.2e}; "
+            f"{len(at_risk)} tensors at risk (form error >= {AT_RISK:.0e}), {len(over)} of them over {tol:.0e} on "
+            f"the GPU" + ("".join(f"; {k}: form ({eo[k][0]:.1e},{eo[k][1]:.1e}), GPU ({er[k][0]:.1e},"
+                                  f"{er[k][1]:.1e})" for k in over)))
+    assert max(_loss_rel(c.s, c.s_exact)) < tol
+    assert_close("gradient", c.g, c.g_exact, tol)
+    bad = {k: er[k] for k in er if max(er[k]) >= tol and k not in at_risk}
     assert not bad, bad
 
 
@@ -271,13 +416,14 @@ def check_loss(net, dtype, g, s, g_ref, s_ref, tag, floor=None):
 ])
 def test_loss_backward_parity_f32(P, name, net, T, N, envs, lengths):
     say(f"loss f32 {name}")
-    g, s, g_ref, s_ref, _ = _loss_case(P, net, "f32", T, N, envs, lengths, seed=T * 7 + N)
-    check_loss(net, "f32", g, s, g_ref, s_ref, name)
+    c = _loss_case(P, net, "f32", T, N, envs, lengths, seed=T * 7 + N, same_decisions=True)
+    check_loss(net, "f32", c, name)
 
 
 def test_loss_backward_norm_adv(P):
-    g, s, g_ref, s_ref, _ = _loss_case(P, TINY_PLUS, "f32", 5, 3, [0, 1, 2], None, seed=3, norm_adv=True)
-    assert rel_err(g, g_ref) < 1e-4 and abs(s[1] - s_ref[1]) < 1e-4 * abs(s_ref[1])
+    say("loss f32 tiny+ norm_adv")
+    c = _loss_case(P, TINY_PLUS, "f32", 5, 3, [0, 1, 2], None, seed=3, norm_adv=True, same_decisions=True)
+    check_loss(TINY_PLUS, "f32", c, "tiny+ norm_adv")
 
 
 @pytest.mark.parametrize("name,net,T,N,envs,lengths", [
@@ -286,32 +432,53 @@ def test_loss_backward_norm_adv(P):
 ])
 def test_loss_backward_parity_bf16(P, name, net, T, N, envs, lengths):
     """bfloat16 operands move activations across ReLU kinks; the oracle takes
-    the GPU's ReLU / max-pool decisions."""
+    the GPU's ReLU / max-pool decisions, each checked to sit at a near-kink."""
     say(f"loss bf16 {name}")
-    g, s, g_ref, s_ref, floor = _loss_case(P, net, "bf16", T, N, envs, lengths, seed=T * 3 + N,
-                                           same_decisions=True)
-    check_loss(net, "bf16", g, s, g_ref, s_ref, name, floor)
+    c = _loss_case(P, net, "bf16", T, N, envs, lengths, seed=T * 3 + N, same_decisions=True)
+    check_loss(net, "bf16", c, name)
 
 
+# GroupNorm form limits (elements per tensor below which one launch per
+# (image, group) is used): "0" forces the coalesced partial / finalize /
+# apply kernels of learner-size tensors, a large value the one-launch form
+GN_FORMS = {"partial": {"DDPPO_GN_FUSED_MAX": "0", "DDPPO_GNB_FUSED_MAX": "0"},
+            "one_launch": {"DDPPO_GN_FUSED_MAX": "1000000000", "DDPPO_GNB_FUSED_MAX": "1000000000"},
+            "default": {}}
+
+
+@pytest.mark.parametrize("form", ["default", "partial"])
 @pytest.mark.parametrize("dtype", ["f32", "bf16"])
-def test_loss_backward_resnet_paper_shape(P, dtype):
-    """The paper's network at 256x256 frames: 2 envs x (4, 3) steps.  The
-    oracle takes the GPU's ReLU / max-pool decisions (a decision made by
-    floating point is taken in the kernel's precision on both sides)."""
-    say(f"loss resnet paper shape {dtype}")
-    g, s, g_ref, s_ref, floor = _loss_case(P, C1.net, dtype, 4, 3, [2, 0], [4, 2, 3], seed=21,
-                                           same_decisions=True)
-    check_loss(C1.net, dtype, g, s, g_ref, s_ref, "resnet", floor)
+def test_loss_backward_resnet_paper_shape(P, dtype, form, monkeypatch):
+    """The paper's network at 256x256 frames: 2 envs x (4, 3) steps, in the
+    default GroupNorm choice and with the learner-size GroupNorm kernels
+    (forward and backward partial forms at full width) forced.  The oracle
+    takes the GPU's ReLU / max-pool decisions (a decision made by floating
+    point is taken in the kernel's precision on both sides)."""
+    for k, v in GN_FORMS[form].items():
+        monkeypatch.setenv(k, v)
+    say(f"loss resnet paper shape {dtype}, GroupNorm {form}")
+    c = _loss_case(P, C1.net, dtype, 4, 3, [2, 0], [4, 2, 3], seed=21, same_decisions=True)
+    check_loss(C1.net, dtype, c, f"resnet {form}")
 
 
-@pytest.mark.parametrize("limit", ["0", "1000000000"], ids=["partial_finalize_apply", "one_launch"])
-def test_loss_backward_both_groupnorm_forms(P, limit, monkeypatch):
+@pytest.mark.parametrize("form", ["partial", "one_launch"])
+def test_loss_backward_both_groupnorm_forms(P, form, monkeypatch):
     """Both GroupNorm forms (per image-and-group launch; coalesced partial /
-    finalize / apply) against the oracle on the same case."""
-    monkeypatch.setenv("DDPPO_GN_FUSED_MAX", limit)
-    say(f"loss f32 mini_resnet, GroupNorm form limit {limit}")
-    g, s, g_ref, s_ref, _ = _loss_case(P, MINI_RESNET, "f32", 5, 3, [2, 1, 0], [5, 3, 4], seed=38)
-    check_loss(MINI_RESNET, "f32", g, s, g_ref, s_ref, f"mini_resnet gn limit {limit}")
+    finalize / apply, forward and backward) against the oracle on the same case."""
+    for k, v in GN_FORMS[form].items():
+        monkeypatch.setenv(k, v)
+    say(f"loss f32 mini_resnet, GroupNorm {form}")
+    c = _loss_case(P, MINI_RESNET, "f32", 5, 3, [2, 1, 0], [5, 3, 4], seed=38, same_decisions=True)
+    check_loss(MINI_RESNET, "f32", c, f"mini_resnet gn {form}")
+
+
+def test_loss_backward_worker_minibatch_f32(P):
+    """One minibatch at the paper worker's learner size: 2 envs x T=128 at
+    256x256 (256 frames), the tile / split choices and the 128-step
+    recurrence the benchmark runs; every frame checked through the oracle."""
+    say("loss f32 resnet, 2 envs x T=128 (256 frames)")
+    c = _loss_case(P, C1.net, "f32", 128, 2, [1, 0], None, seed=51, same_decisions=True)
+    check_loss(C1.net, "f32", c, "resnet 256 frames")
 
 
 def test_autotuned_loss_backward(P):
@@ -336,7 +503,8 @@ def test_autotuned_loss_backward(P):
     assert torch.equal(g1, g2) and torch.equal(s1, s2)
     mb = oracle_minibatch(rec, envs)
     s_ref, g_ref = ppo.loss_grad(flat.astype(np.float64), net, PPOCfg(), mb)
-    assert rel_err(g2.cpu().numpy(), g_ref) < 1e-4
+    assert_close("gradient", g2.cpu().numpy(), g_ref, 1e-4)
+    assert max(_loss_rel(s2.cpu().numpy(), s_ref)) < 1e-4
     assert n.autotune(-1) == 0
 
 
@@ -373,7 +541,7 @@ def test_autotuned_act(P, dtype):
         assert torch.equal(out1[k], out2[k]), k
     ref = policy.act(OP.unpack(net, flat), net, obs, goal, prev, mask, h, c, u)
     ref["u"] = u
-    tol = TOL[dtype]
-    assert rel_err(out2["logits"].cpu().numpy(), ref["logits"]) < tol
-    assert rel_err(out2["h"].cpu().numpy(), ref["h"]) < tol
-    assert_actions_agree(out2["action"].cpu().numpy(), ref, tol)
+    if dtype == "bf16":
+        ref["form"] = policy.act(OP.unpack(net, flat), net, obs, goal, prev, mask, h, c, u, quant="bf16")
+        ref["form"]["u"] = u
+    check_act(out2, ref, dtype, B, "autotuned")
