@@ -247,6 +247,22 @@ ppo_status ppo_loss_head(ppo_net* net, const ppo_batch* b, const ppo_loss_cfg* c
                          const float* logits, const float* values, float* dlogits, float* dvalues, float* stats,
                          float* loss_out, void* ws, size_t ws_bytes, void* stream);
 
+/* ppo_loss_head_noalloc -- ppo_loss_head without a workspace argument, for
+ * callers that cannot allocate device memory (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid allocation).  Same arguments,
+ * outputs and errors as ppo_loss_head; its scratch (frame map and per-frame
+ * loss terms) is a static device array of the library, about 1.5 MB, held on
+ * every GPU the library runs on until the process ends.  Allocates nothing,
+ * on the device or the host.  Returns PPO_ESHAPE for a minibatch of more
+ * valid frames than ppo_loss_head_noalloc_max_frames() (32768).  Every call
+ * on one GPU uses that GPU's array: calls that overlap on one GPU (other
+ * streams, other threads) race and must be ordered by the caller.  Nothing in
+ * the array needs to start at zero (each call writes what it reads). */
+ppo_status ppo_loss_head_noalloc(ppo_net* net, const ppo_batch* b, const ppo_loss_cfg* cfg,
+                                 const float* d_loss_scale, const float* logits, const float* values,
+                                 float* dlogits, float* dvalues, float* stats, float* loss_out, void* stream);
+size_t ppo_loss_head_noalloc_max_frames(void);
+
 /* ---------------------------------------------------------------------------
  * ppo_adam_step -- ParamUpdate of Eq. 3-4 (Adam, Kingma & Ba, with bias
  * correction; the paper's optimiser, Sec. 4 "Training").  Device state:

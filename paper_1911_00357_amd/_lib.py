@@ -76,6 +76,9 @@ EXPORTS = {
                                     c_size_t, c_void_p]),
     "ppo_loss_head": (c_int, [c_void_p, C.POINTER(Batch), C.POINTER(LossCfg), c_void_p, c_void_p, c_void_p,
                               c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_size_t, c_void_p]),
+    "ppo_loss_head_noalloc": (c_int, [c_void_p, C.POINTER(Batch), C.POINTER(LossCfg), c_void_p, c_void_p, c_void_p,
+                                      c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
+    "ppo_loss_head_noalloc_max_frames": (c_size_t, []),
     "ppo_adam_workspace_size": (c_size_t, [c_size_t]),
     "ppo_adam_step": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_size_t,
                               C.POINTER(AdamCfg), c_void_p, c_void_p, c_size_t, c_void_p]),

@@ -322,6 +322,32 @@ class Net:
                                   _stream(dev)), "ppo_loss_head")
         return dlogits, dvalues, stats, loss_out
 
+    def loss_head_noalloc(self, ro, env_ids, lengths, logits, values, cfg: LossCfg = None, loss_scale=None,
+                          adv_stats=None, dlogits=None, dvalues=None, stats=None, loss_out=None):
+        """loss_head with the library's static scratch instead of a workspace
+        (ppo_loss_head_noalloc); every output buffer must be given for a call
+        that allocates nothing."""
+        cfg = cfg or LossCfg()
+        b, keep, F, dev = self._batch(ro, env_ids, lengths, None, None, learner=True, inputs=False)
+        _need(logits, torch.float32, "logits", F * self.A)
+        _need(values, torch.float32, "values", F)
+        c = L.LossCfg()
+        c.clip, c.value_coef, c.entropy_coef = cfg.clip, cfg.value_coef, cfg.entropy_coef
+        c.norm_adv = int(cfg.norm_adv)
+        c.adv_stats = _ptr(adv_stats)
+        if dlogits is None:
+            dlogits = torch.empty(F, self.A, dtype=torch.float32, device=dev)
+        if dvalues is None:
+            dvalues = torch.empty(F, dtype=torch.float32, device=dev)
+        if stats is None:
+            stats = torch.empty(8, dtype=torch.float32, device=dev)
+        if loss_out is None:
+            loss_out = torch.empty((), dtype=torch.float32, device=dev)
+        check(lib().ppo_loss_head_noalloc(self._h, C.byref(b), C.byref(c), _ptr(loss_scale), _ptr(logits),
+                                          _ptr(values), _ptr(dlogits), _ptr(dvalues), _ptr(stats), _ptr(loss_out),
+                                          _stream(dev)), "ppo_loss_head_noalloc")
+        return dlogits, dvalues, stats, loss_out
+
     def policy_backward(self, ro, env_ids, lengths, params, params_lp, dlogits, dvalues, grad=None):
         b, keep, F, dev = self._batch(ro, env_ids, lengths, params, params_lp, learner=False)
         _need(dlogits, torch.float32, "dlogits", F * self.A)

@@ -5,6 +5,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -496,6 +497,47 @@ bool al256(const void* p) { return (((uintptr_t)p) & 255) == 0; }
 }  // namespace
 
 // ===================================================================== ABI
+namespace {
+
+// Static scratch of ppo_loss_head_noalloc: the loss head's workspace for up
+// to kNoAllocFrames frames and kMaxMbEnvs envs, resident on every device the
+// library runs on until the process ends.  Host code never passes the
+// array's name to a kernel: it passes the device address that
+// hipGetSymbolAddress returns for the current device (static_scratch).
+constexpr int kNoAllocFrames = 32768;
+constexpr size_t kNoAllocBytes =
+    4 * (((size_t)kNoAllocFrames * 4 + 255) / 256 * 256) + (size_t)kMaxMbEnvs * 4 +
+    ((size_t)kNoAllocFrames * 8 * sizeof(float) + 255) / 256 * 256;
+static __device__ __align__(256) unsigned char scratch[kNoAllocBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// The current device's address of `scratch`, looked up once per device.
+ppo_status static_scratch(void** out) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(PPO_EDEVICE, "no current HIP device");
+  }
+  if (dev < 0 || dev >= kMaxDevices) return fail(PPO_EUNSUPPORTED, "device index %d beyond %d", dev, kMaxDevices);
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) {
+      (void)hipGetLastError();
+      return fail(PPO_EDEVICE, "hipGetSymbolAddress(scratch) failed: %s", hipGetErrorString(e));
+    }
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return PPO_OK;
+}
+
+}  // namespace
+
 extern "C" {
 
 const char* ppo_last_error(void) { return g_err.c_str(); }
@@ -688,7 +730,7 @@ struct Sched {
 
 // Packing of a minibatch (envs longest first, frames time-major).  inputs:
 // also require the policy inputs (frames, goal, state, parameters).
-ppo_status schedule(const ppo_net* net, const ppo_batch* b, Sched& S, bool inputs = true) {
+ppo_status schedule(const ppo_net* net, const ppo_batch* b, Sched& S, bool inputs = true, bool per_step = true) {
   const ppo_net_desc& d = net->d;
   if (!b->env_ids || !b->mask ||
       (inputs && (!b->obs || !b->goal || !b->h0 || !b->c0 || !b->params || (net->prec && !b->params_lp) ||
@@ -718,6 +760,7 @@ ppo_status schedule(const ppo_net* net, const ppo_batch* b, Sched& S, bool input
   }
   S.m.F = S.F;
   S.TB = S.m.len[0];
+  if (!per_step) return PPO_OK;  // frame map only (no host allocation)
   S.act.assign(S.TB + 1, 0);
   S.off.assign(S.TB + 1, 0);
   for (int t = 0; t < S.TB; ++t) {
@@ -900,6 +943,37 @@ void learner_bwd(const Ctx& c, const ppo_batch* b, const Sched& S, const float* 
   encoder_bwd(c, dfeat);
 }
 
+// The PPO objective on given policy outputs (ppo_loss_head and its variant
+// without allocation).  noalloc: the workspace is the static scratch array;
+// no host or device allocation on this path.
+ppo_status loss_head(ppo_net* net, const ppo_batch* b, const ppo_loss_cfg* cfg, const float* d_loss_scale,
+                     const float* logits, const float* values, float* dlogits, float* dvalues, float* stats,
+                     float* loss_out, void* ws, size_t ws_bytes, void* stream, bool noalloc) {
+  if (!net || !b || !cfg || !logits || !values || !dlogits || !dvalues || !stats)
+    return fail(PPO_EINVAL, "null argument");
+  if (!b->action || !b->logp_old || !b->adv || !b->ret || (cfg->norm_adv && !cfg->adv_stats))
+    return fail(PPO_EINVAL, "null pointer in ppo_batch");
+  Sched S;
+  const ppo_status st = schedule(net, b, S, false, false);
+  if (st != PPO_OK) return st;
+  if (noalloc && S.F > kNoAllocFrames)
+    return fail(PPO_ESHAPE, "%d frames exceed the %d of the static scratch of ppo_loss_head_noalloc", S.F,
+                kNoAllocFrames);
+  const LossWs w = plan_loss(S.F, b->nb);
+  if (!ws || ws_bytes < w.total) return fail(PPO_EWORKSPACE, "workspace needs %zu bytes", w.total);
+  if (!al256(ws)) return fail(PPO_EWORKSPACE, "workspace must be 256-byte aligned");
+  hipStream_t s = strm(stream);
+  char* base = (char*)ws;
+  launch_frame_map(S.m, b->mask, (int32_t*)(base + w.src), (float*)(base + w.wf), (float*)(base + w.mskf),
+                   (int32_t*)(base + w.envrow), s);
+  launch_loss_terms(logits, values, S.F, net->d.num_actions, (const int32_t*)(base + w.src), b->action,
+                    b->logp_old, b->adv, b->ret, (const float*)(base + w.wf), cfg->clip, cfg->value_coef,
+                    cfg->entropy_coef, cfg->norm_adv, cfg->adv_stats, net->prec ? d_loss_scale : nullptr,
+                    (float*)(base + w.fstat), dlogits, dvalues, stats, loss_out, s);
+  return check_launch();
+}
+
+
 }  // namespace
 
 extern "C" {
@@ -973,26 +1047,21 @@ ppo_status ppo_policy_backward(ppo_net* net, const ppo_batch* b, const float* dl
 ppo_status ppo_loss_head(ppo_net* net, const ppo_batch* b, const ppo_loss_cfg* cfg, const float* d_loss_scale,
                          const float* logits, const float* values, float* dlogits, float* dvalues, float* stats,
                          float* loss_out, void* ws, size_t ws_bytes, void* stream) {
-  if (!net || !b || !cfg || !logits || !values || !dlogits || !dvalues || !stats)
-    return fail(PPO_EINVAL, "null argument");
-  if (!b->action || !b->logp_old || !b->adv || !b->ret || (cfg->norm_adv && !cfg->adv_stats))
-    return fail(PPO_EINVAL, "null pointer in ppo_batch");
-  Sched S;
-  const ppo_status st = schedule(net, b, S, false);
-  if (st != PPO_OK) return st;
-  const LossWs w = plan_loss(S.F, b->nb);
-  if (!ws || ws_bytes < w.total) return fail(PPO_EWORKSPACE, "workspace needs %zu bytes", w.total);
-  if (!al256(ws)) return fail(PPO_EWORKSPACE, "workspace must be 256-byte aligned");
-  hipStream_t s = strm(stream);
-  char* base = (char*)ws;
-  launch_frame_map(S.m, b->mask, (int32_t*)(base + w.src), (float*)(base + w.wf), (float*)(base + w.mskf),
-                   (int32_t*)(base + w.envrow), s);
-  launch_loss_terms(logits, values, S.F, net->d.num_actions, (const int32_t*)(base + w.src), b->action,
-                    b->logp_old, b->adv, b->ret, (const float*)(base + w.wf), cfg->clip, cfg->value_coef,
-                    cfg->entropy_coef, cfg->norm_adv, cfg->adv_stats, net->prec ? d_loss_scale : nullptr,
-                    (float*)(base + w.fstat), dlogits, dvalues, stats, loss_out, s);
-  return check_launch();
+  return loss_head(net, b, cfg, d_loss_scale, logits, values, dlogits, dvalues, stats, loss_out, ws, ws_bytes,
+                   stream, false);
 }
+
+ppo_status ppo_loss_head_noalloc(ppo_net* net, const ppo_batch* b, const ppo_loss_cfg* cfg,
+                                 const float* d_loss_scale, const float* logits, const float* values,
+                                 float* dlogits, float* dvalues, float* stats, float* loss_out, void* stream) {
+  void* p = nullptr;
+  const ppo_status st = static_scratch(&p);
+  if (st != PPO_OK) return st;
+  return loss_head(net, b, cfg, d_loss_scale, logits, values, dlogits, dvalues, stats, loss_out, p,
+                   sizeof(scratch), stream, true);
+}
+
+size_t ppo_loss_head_noalloc_max_frames(void) { return kNoAllocFrames; }
 
 size_t ppo_adam_workspace_size(size_t P) {
   (void)P;
