@@ -4,16 +4,26 @@ A step is one full worker iteration (Sec. 3-4): T+1 dependent act steps over
 N envs, GAE, then E epochs x M minibatches of (loss backward, Adam).  Frames
 per step = sum of the env rollout lengths.  Inputs are seeded synthetic
 rollouts (frames U[0,1), goals N(0,1), rewards/dones as in the generator)
-staged in device memory before the timed region.  The paper's throughput
-procedure (appendix "Additional scaling details") times the last 5 of 10
-collect+optimise iterations; --warmup 5 --steps 5 reproduces it.
+staged in device memory before the timed region.
 
-Prints one JSON line.  The headline value is the bfloat16 form; the float32
-form of the same workload is timed beside it.
+Protocol (appendix "Additional scaling details": 10 seeds, throughput over
+the last iterations, bootstrapped 95% confidence interval): for each seed,
+--warmup untimed iterations, then --steps timed iterations; the headline
+value is the median over seeds of frames / timed GPU time, with a bootstrap
+95% interval of that median.  The float32 form of the same workload is timed
+on the same seeds.
+
+Prints one JSON line.  The roofline entry is the act step's convolution
+GEMMs (the largest kernel class by time), timed live with HIP events around
+each kernel on act steps launched right after the timed iterations; the
+learner's slowest convolution GEMM is a second entry.  The CPU baseline is
+the float64 oracle on a bounded sample of the same workload, with the GPU's
+per-output errors on that sample.
 """
 from __future__ import annotations
 
 import argparse
+import gc
 import json
 import os
 import sys
@@ -29,6 +39,7 @@ PEAK_FP32_TFLOPS = 157.3      # MI355X fp32 matrix
 PEAK_HBM_GBS = 8000.0
 GRAPH = True                  # act loop replayed as one captured HIP graph
 AUTOGRAD = False              # update gradient through torch.autograd (C3)
+ACT_TIMED_STEPS = 4           # act steps whose convolution GEMMs are timed for the roofline
 
 
 def parse():
@@ -36,25 +47,30 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--seeds", type=int, default=10, help="seeds 0..S-1 (median and bootstrap 95%% CI)")
     ap.add_argument("--workload", default="C2", help="C0..C4 (C2 = bf16 paper-shaped worker)")
     ap.add_argument("--no-fp32", action="store_true", help="skip the float32 comparison run")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
-    ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--eager", action="store_true", help="launch the act loop eagerly (no HIP graph)")
-    ap.add_argument("--pmc-probe", action="store_true",
-                    help="only run a 256 MiB copy and the dominant learner GEMM 3x each (for rocprofv3 --pmc)")
+    ap.add_argument("--pmc-probe", choices=["act", "learner"],
+                    help="only run a 256 MiB copy and then the act steps or the dominant learner GEMM "
+                         "(for rocprofv3 --pmc)")
     ap.add_argument("--autograd", choices=["auto", "on", "off"], default="auto",
                     help="take the update's gradient through torch.autograd (auto: for C3)")
     return ap.parse_args()
 
 
+def progress(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
 def stage_env(wl, seed, it, dev):
-    """One iteration's environment stream on the device."""
+    """One iteration's environment stream on the device (envs longest first)."""
     import torch
     from synth import rollout as R
     ro = R.gen_rollout(wl, seed, it)
     lens = ro["lengths"]
-    order = np.argsort(-lens, kind="stable")    # longest first
+    order = np.argsort(-lens, kind="stable")
     obs = ro["obs"][:, order]
     t = lambda a: torch.as_tensor(np.ascontiguousarray(a)).to(dev)
     env = {"obs": t(obs).to(torch.bfloat16) if wl.dtype == "bf16" else t(obs),
@@ -64,6 +80,13 @@ def stage_env(wl, seed, it, dev):
     return env, lens[order]
 
 
+def _hyper(wl):
+    from paper_1911_00357_amd.worker import PPOHyper
+    p = wl.ppo
+    return PPOHyper(p.gamma, p.lam, p.clip, p.value_coef, p.entropy_coef, p.lr, p.epochs, p.minibatches,
+                    p.norm_adv)
+
+
 def _update(w, env, parts, lengths):
     if AUTOGRAD:
         w.update_autograd(env, parts, lengths)
@@ -71,71 +94,99 @@ def _update(w, env, parts, lengths):
         w.update(env, parts, lengths)
 
 
-def run_gpu(wl, steps, warmup, seed, timer=None):
-    """timer: (unit, op) whose GEMM kernel launches are timed with HIP events
-    over the timed region."""
+def run_seed(wl, seed, steps, warmup, net=None, act_timer=True):
+    """Warm-up and timed iterations of one seed; with act_timer, then the act
+    step's convolution GEMMs timed with HIP events around each kernel over
+    ACT_TIMED_STEPS act steps launched eagerly (the same kernels and tiles
+    the captured graph replays; the runtime that comes with torch refuses
+    event nodes inside a captured graph).  Returns frames, GPU ms, wall s,
+    the act-GEMM timing and the worker."""
     import torch
-    from paper_1911_00357_amd.worker import PPOHyper, Worker
+    from paper_1911_00357_amd._lib import PPO_OP_ACT, PPO_TIMER_ALL_UNITS
+    from paper_1911_00357_amd.worker import Worker
     from synth import rollout as R
     dev = torch.device("cuda", 0)
-    p = wl.ppo
-    hp = PPOHyper(p.gamma, p.lam, p.clip, p.value_coef, p.entropy_coef, p.lr, p.epochs, p.minibatches,
-                  p.norm_adv)
-    w = Worker(wl.net, wl.dtype, wl.T, wl.N, R.init_params(wl.net, seed), hp, dev)
+    w = Worker(wl.net, wl.dtype, wl.T, wl.N, R.init_params(wl.net, seed), _hyper(wl), dev, net=net)
     its = warmup + steps
     envs = [stage_env(wl, seed, i, dev) for i in range(min(its, 2))]
-    w.net.autotune(1)             # GEMM tiles tuned during the first warm-up iteration
     parts = R.partitions(wl, seed)
-    frames = []
+    frames = 0
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
     torch.cuda.synchronize()
     t_start = None
     for i in range(its):
         env, lens = envs[i % len(envs)]
         lengths = None if not wl.ragged else lens
-        if i == min(1, warmup):
-            w.net.autotune(0)
         if i == warmup:
             torch.cuda.synchronize()
-            if timer is not None:
-                w.net.gemm_timer_arm(timer[0], timer[1])
             ev[0].record()
             t_start = time.perf_counter()
         w.collect(env, lengths, graph=GRAPH)
         _update(w, env, parts, lengths)
         if i < warmup:
             torch.cuda.synchronize()
-            progress(f"warm-up iteration {i + 1}/{warmup} done")
-        if i >= warmup:
-            frames.append(int(lens.sum()))
+        else:
+            frames += int(lens.sum())
     ev[1].record()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t_start
-    gpu_ms = ev[0].elapsed_time(ev[1])
-    timed = None
-    if timer is not None:
-        timed = w.net.gemm_timer_read()
+    act = None
+    if act_timer:
+        nunits = w.net.probe(PPO_OP_ACT, wl.N, 1, 3)[3][0]
+        w.net.gemm_timer_arm(PPO_TIMER_ALL_UNITS, 0, nunits * ACT_TIMED_STEPS)
+        env, lens = envs[0]
+        w.collect(env, None if not wl.ragged else lens, graph=False)
+        act = w.net.gemm_timer_read()
         w.net.gemm_timer_arm(-1, 0)
-    return {"frames": sum(frames), "wall_s": wall, "gpu_ms": gpu_ms, "worker": w, "timed": timed}
+    return {"frames": frames, "gpu_ms": ev[0].elapsed_time(ev[1]), "wall_s": wall, "act": act, "worker": w}
 
 
-def act_update_split(wl, seed):
+def run_seeds(wl, seeds, steps, warmup, label):
+    """Every seed on one shared library handle (its tile table is tuned in the
+    first seed's first warm-up iteration).  Returns per-seed results (without
+    workers) and the first seed's worker."""
+    import torch
+    import paper_1911_00357_amd as P
+    net = P.Net(wl.net, wl.dtype)
+    net.autotune(1)
+    out, first = [], None
+    for k, seed in enumerate(seeds):
+        r = run_seed(wl, seed, steps, warmup, net=net, act_timer=(k == 0))
+        if k == 0:
+            net.autotune(0)
+            first = r.pop("worker")
+        else:
+            r.pop("worker").release()
+        out.append(r)
+        progress(f"{label} seed {seed}: {r['frames'] / (r['gpu_ms'] / 1e3):.1f} frames/s")
+        gc.collect()
+        torch.cuda.empty_cache()
+    return out, first
+
+
+def median_ci(x, n_boot=10000, seed=0):
+    """Median of x and a bootstrap 95% interval of the median (percentile)."""
+    x = np.asarray(x, np.float64)
+    if x.size == 1:
+        return float(x[0]), [float(x[0]), float(x[0])]
+    g = np.random.default_rng(seed)
+    meds = np.median(x[g.integers(0, x.size, (n_boot, x.size))], axis=1)
+    return float(np.median(x)), [float(np.percentile(meds, 2.5)), float(np.percentile(meds, 97.5))]
+
+
+def act_update_split(wl, seed, net):
     """Separate timing of the act phase and the update phase (one iteration)."""
     import torch
-    from paper_1911_00357_amd.worker import PPOHyper, Worker
+    from paper_1911_00357_amd.worker import Worker
     from synth import rollout as R
     dev = torch.device("cuda", 0)
-    p = wl.ppo
-    hp = PPOHyper(p.gamma, p.lam, p.clip, p.value_coef, p.entropy_coef, p.lr, p.epochs, p.minibatches)
-    w = Worker(wl.net, wl.dtype, wl.T, wl.N, R.init_params(wl.net, seed), hp, dev)
+    w = Worker(wl.net, wl.dtype, wl.T, wl.N, R.init_params(wl.net, seed), _hyper(wl), dev, net=net)
     env, lens = stage_env(wl, seed, 0, dev)
     lengths = None if not wl.ragged else lens
     parts = R.partitions(wl, seed)
-    w.net.autotune(1)
     for _ in range(2):
         w.collect(env, lengths, graph=GRAPH)
         _update(w, env, parts, lengths)
-        w.net.autotune(0)
     e = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
     e[0].record()
     w.collect(env, lengths, graph=GRAPH)
@@ -143,21 +194,21 @@ def act_update_split(wl, seed):
     _update(w, env, parts, lengths)
     e[2].record()
     torch.cuda.synchronize()
+    w.release()
     return e[0].elapsed_time(e[1]), e[1].elapsed_time(e[2]), int(lens.sum())
 
 
 def unpacked_split(wl, seed):
     """The same ragged iteration without packing: one act call per active env
-    per step (batch 1) and one learner call per env of each minibatch (each
-    followed by its own Adam step is not needed for timing; the per-env calls
-    are what packing replaces).  Returns (act ms, update ms, frames)."""
+    per step (batch 1) and one learner call per env of each minibatch (the
+    per-env calls are what packing replaces).  Returns (act ms, update ms,
+    frames)."""
     import torch
     from paper_1911_00357_amd.api import LossCfg
-    from paper_1911_00357_amd.worker import PPOHyper, Worker
+    from paper_1911_00357_amd.worker import Worker
     from synth import rollout as R
     dev = torch.device("cuda", 0)
-    p = wl.ppo
-    hp = PPOHyper(p.gamma, p.lam, p.clip, p.value_coef, p.entropy_coef, p.lr, p.epochs, p.minibatches)
+    hp = _hyper(wl)
     w = Worker(wl.net, wl.dtype, wl.T, wl.N, R.init_params(wl.net, seed), hp, dev)
     env, lens = stage_env(wl, seed, 0, dev)
     parts = R.partitions(wl, seed)
@@ -188,8 +239,8 @@ def unpacked_split(wl, seed):
                 for e in envs:
                     w.net.loss_backward(ro, [int(e)], lens, w.params, w.lp, cfg, loss_scale=scale,
                                         adv_stats=w.adv_stats, grad=w.grad, stats=w.stats)
-    act_unpacked()                # warm-up (tiles: the heuristic choice; every env has its own
-    update_unpacked()             # frame count, so tuning each one is not part of this comparison)
+    act_unpacked()                # warm-up (tiles: the heuristic choice)
+    update_unpacked()
     e = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
     torch.cuda.synchronize()
     e[0].record()
@@ -198,40 +249,155 @@ def unpacked_split(wl, seed):
     update_unpacked()
     e[2].record()
     torch.cuda.synchronize()
+    w.release()
     return e[0].elapsed_time(e[1]), e[1].elapsed_time(e[2]), int(lens.sum())
 
 
-def cpu_baseline(wl, seed):
-    """The FP64 oracle on a bounded sample of the same workload: a 16-step
-    rollout of all N envs (17 act steps) and the update over its frames
-    (about 10-20 s of host time for the paper-shaped worker)."""
-    import oracle
+# --------------------------------------------------------------- CPU baseline
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def blas_threads():
+    from threadpoolctl import threadpool_info
+    n = [i["num_threads"] for i in threadpool_info() if i.get("user_api") == "blas"]
+    return max(n) if n else 1
+
+
+def gpu_sample(wl, small, seed, inp, parts):
+    """The GPU worker on the oracle's sample: rollout outputs, advantages and
+    the first minibatch's loss statistics, gradient (unscaled) and the
+    decisions it took (ReLU patterns, max-pool winners; bfloat16 operand
+    codes), read from the workspace as the parity tests do."""
+    from tests.test_gpu_parity import gpu_decisions
+    import torch
+    from paper_1911_00357_amd.worker import Worker
     from synth import rollout as R
-    small = wl.with_(T=16)
+    dev = torch.device("cuda", 0)
+    w = Worker(wl.net, wl.dtype, small.T, small.N, R.init_params(wl.net, seed), _hyper(small), dev)
+    t = lambda a: torch.as_tensor(np.ascontiguousarray(a)).to(dev)
+    env = {k: t(inp[k]) for k in ("goal", "u", "mask", "reward", "done")}
+    env["obs"] = t(inp["obs"]).to(torch.bfloat16) if wl.dtype == "bf16" else t(inp["obs"])
+    w.collect(env)
+    first = {}
+
+    def hook(wk):
+        if not first:
+            S = wk.adam.state()["scale"] if wk.bf16 else 1.0
+            first["grad"] = wk.grad.cpu().numpy().astype(np.float64) / S
+            first["stats"] = wk.stats.cpu().numpy().astype(np.float64)
+            B = len(parts[0][0])
+            first["decisions"] = gpu_decisions(wk.net, wl.net, small.T * B, B,
+                                               {"action": np.zeros((small.T, B)), "lens": np.full(B, small.T)},
+                                               codes=wk.bf16)
+    adv, ret = w.update(env, parts, on_minibatch=hook)
+    out = {"action": w.act_rec[1:].cpu().numpy(), "value": w.value.cpu().numpy().astype(np.float64),
+           "logp": w.logp.cpu().numpy().astype(np.float64), "adv": adv.cpu().numpy().astype(np.float64),
+           "ret": ret.cpu().numpy().astype(np.float64), **first}
+    w.release()
+    return out
+
+
+def cpu_baseline(wl, seed):
+    """The float64 oracle on a bounded sample of the same workload: a 16-step
+    rollout of all N envs (17 act steps) and the update over its frames,
+    timed with the host's BLAS threads (about 10-20 s for the paper-shaped
+    worker), and a 2-step sample with one thread.  The GPU's bfloat16 and
+    float32 forms are run on the same sample (the GPU's sampled actions fed
+    to the oracle as previous actions) and their per-output errors against
+    the oracle reported: values, log-probs, advantages, returns, the first
+    minibatch's loss and gradient (the GPU's ReLU / max-pool decisions, and in
+    bfloat16 its operand codes, imposed on the oracle as in the parity tests:
+    exact float64 reference, and for bfloat16 also the precision form)."""
+    from threadpoolctl import threadpool_limits
+    import oracle
+    from oracle import nn as onn
+    from synth import rollout as R
+
+    def rel(x, ref):
+        x, ref = np.asarray(x, np.float64).ravel(), np.asarray(ref, np.float64).ravel()
+        return float(np.linalg.norm(x - ref) / max(np.linalg.norm(ref), 1e-30))
+
+    def sample(T):
+        small = wl.with_(T=T)
+        inp = R.gen_rollout(small, seed, 0)
+        inp["lengths"] = np.full(small.N, small.T, np.int32)
+        return small, inp, R.partitions(small, seed)
+
     flat = R.init_params(wl.net, seed)
-    inp = R.gen_rollout(small, seed, 0)
-    inp["lengths"] = np.full(small.N, small.T, np.int32)
+    small, inp, parts = sample(16)
     h0, c0 = R.gen_state(wl.net, small.N, seed)
+    gpu = {dt: gpu_sample(wl.with_(dtype=dt), small, seed, inp, parts) for dt in ("bf16", "f32")}
+    act = gpu["f32"]["action"]
+    threads = blas_threads()
     t0 = time.perf_counter()
-    rec = oracle.ppo.rollout(flat, wl.net, inp, h0, c0)
-    oracle.ppo.update(flat, wl.net, wl.ppo, inp, rec, R.partitions(small, seed))
+    rec = oracle.ppo.rollout(flat, wl.net, inp, h0, c0, forced_actions=act)
+    lp = np.take_along_axis(onn.log_softmax(rec["logits"]), act[..., None], axis=2)[..., 0]
+    rec["action"], rec["logp"] = act, lp
+    upd = oracle.ppo.update(flat, wl.net, wl.ppo, inp, rec, parts)
     dt = time.perf_counter() - t0
     frames = small.T * small.N
-    threads = int(os.environ.get("OPENBLAS_NUM_THREADS", os.environ.get("OMP_NUM_THREADS", os.cpu_count())))
-    return {"value": frames / dt, "unit": "frames/s", "cores": min(threads, os.cpu_count()),
-            "kind": "oracle",
+    # the first minibatch again, with each side's decisions made the same way (the GPU's, each
+    # checked to sit at a near-kink or rounding midpoint, as in the parity tests)
+    from tests.gpu_util import tensor_errors
+    from tests.test_gpu_parity import LossCase, oracle_refs
+    mb = oracle.ppo.minibatch_inputs(wl.net, inp, rec, upd["adv"], upd["ret"], np.asarray(parts[0][0]))
+    errors = {}
+    for k, g in gpu.items():
+        c = LossCase()
+        c.g, c.s = g["grad"], g["stats"]
+        coded = g["decisions"]
+        dec = {kk: v for kk, v in coded.items() if not kk.startswith("q:")}
+        oracle_refs(c, wl.net, k, flat, mb, dec, coded=coded if k == "bf16" else None)
+        s_ref = c.s_exact
+        te = tensor_errors(wl.net, c.g, c.g_exact)
+        worst = max(te, key=lambda kk: te[kk][0])
+        errors[k] = {"values": rel(g["value"], rec["value"]), "log_probs": rel(g["logp"], lp),
+                     "advantages": rel(g["adv"], upd["adv"]), "returns": rel(g["ret"], upd["ret"]),
+                     "loss": abs(g["stats"][0] - s_ref[0]) /
+                             (abs(s_ref[1]) + wl.ppo.value_coef * abs(s_ref[2]) + wl.ppo.entropy_coef * abs(s_ref[3])),
+                     "gradient": rel(c.g, c.g_exact), "gradient_worst_tensor": [worst, round(te[worst][0], 8)],
+                     "decisions_flipped": int(sum(f for _, f in c.flips.values())),
+                     "actions_differing": int((g["action"] != act).sum())}
+        if k == "bf16":
+            tf = tensor_errors(wl.net, c.g, c.g_form)
+            errors[k]["gradient_vs_bf16_form"] = rel(c.g, c.g_form)
+            errors[k]["gradient_vs_bf16_form_worst_tensor"] = round(max(v[0] for v in tf.values()), 8)
+            errors[k]["bf16_form_gradient_vs_exact"] = rel(c.g_own, c.g_exact)
+        errors[k] = {kk: (round(v, 8) if isinstance(v, float) else v) for kk, v in errors[k].items()}
+    small1, inp1, parts1 = sample(2)
+    with threadpool_limits(1):
+        t1 = time.perf_counter()
+        rec1 = oracle.ppo.rollout(flat, wl.net, inp1, *R.gen_state(wl.net, small1.N, seed))
+        oracle.ppo.update(flat, wl.net, wl.ppo, inp1, rec1, parts1)
+        dt1 = time.perf_counter() - t1
+    return {"value": frames / dt, "unit": "frames/s", "cores": threads, "kind": "oracle",
             "sample": f"T={small.T} rollout of N={small.N} envs ({small.T + 1} act steps) + {wl.ppo.epochs}x"
-                      f"{wl.ppo.minibatches} minibatch updates, {frames} frames, {dt:.1f} s"}
+                      f"{wl.ppo.minibatches} minibatch updates, {frames} frames, {dt:.1f} s",
+            "cpu_model": cpu_model(), "host_cpus": os.cpu_count(),
+            "one_thread": {"value": small1.T * small1.N / dt1, "unit": "frames/s",
+                           "sample": f"T={small1.T} rollout of N={small1.N} envs + the same update, "
+                                     f"{small1.T * small1.N} frames, {dt1:.1f} s"},
+            "gpu_errors_vs_oracle": errors}
 
 
+# ------------------------------------------------------------------ roofline
 OPS = ["conv forward", "conv data gradient", "conv weight gradient"]
+ACT_KERNEL = "act-step convolution GEMMs (gemm_kernel<ConvFwdProb<bf16>, ...>, all tiles)"
 
 
 def dominant_gemm(wl, seed, reps=5):
     """The learner's slowest convolution GEMM launch: every trunk unit's
     forward, data-gradient and weight-gradient GEMM at the learner's
     minibatch size, timed with HIP events (selection only).  Returns
-    (unit, op, name, per-launch ms table summary)."""
+    (unit, op, name, aggregate TFLOP/s of all of them)."""
     import torch
     import paper_1911_00357_amd as P
     from paper_1911_00357_amd._lib import PPO_OP_LEARN
@@ -265,96 +431,84 @@ def dominant_gemm(wl, seed, reps=5):
     return u, op, name, round(tot_f / (tot_t / 1e3) / 1e12, 3)
 
 
-def committed_gemm(wl):
-    """(unit, op, name, None) of the roofline kernel named in the committed
-    bench line of this workload (profiles/bench_<workload>.json)."""
-    import paper_1911_00357_amd as P
+def unit_by_name(n, wl, name):
     from paper_1911_00357_amd._lib import PPO_OP_LEARN
-    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles", f"bench_{wl.name}.json")
-    with open(path) as f:
-        label = json.load(f)["roofline"]["kernel"]
-    op = next(i for i, s in enumerate(OPS) if label.startswith(s + " GEMM of "))
-    name = label[len(OPS[op] + " GEMM of "):]
-    n = P.Net(wl.net, wl.dtype)
     F = wl.T * wl.N // wl.ppo.minibatches
     for u in range(n.probe(PPO_OP_LEARN, F, 1, 3)[3][0]):
         if n.probe(PPO_OP_LEARN, F, 1, 0, u)[0] == name:
-            return u, op, name, None
+            return u
     raise SystemExit(f"unit {name} not found")
 
 
-COPY_BYTES = 256 << 20
-
-
-def pmc_probe(wl, seed, sel):
-    """Calibration copy (COPY_BYTES read + written per launch) and the dominant
-    learner GEMM, three launches each, for HBM byte counters."""
+def learner_gemm_live(w, wl, env, parts, sel):
+    """The dominant learner GEMM timed with HIP events on the learner's
+    stream around the kernel itself, over one update."""
     import torch
-    import paper_1911_00357_amd as P
-    from synth import rollout as R
-    dev = torch.device("cuda", 0)
-    src = torch.ones(COPY_BYTES // 4, dtype=torch.float32, device=dev)
-    dst = torch.empty_like(src)
-    for _ in range(3):
-        dst.copy_(src)
-    torch.cuda.synchronize()
-    del src, dst
-    n = P.Net(wl.net, wl.dtype)
-    params = torch.tensor(R.init_params(wl.net, seed), device=dev)
-    lp = P.cast_bf16(params) if wl.dtype == "bf16" else None
-    grad = torch.zeros_like(params)
-    F = wl.T * wl.N // wl.ppo.minibatches
-    n.autotune(1)
-    n.bench_unit_gemm(sel[1], sel[0], F, params, lp, grad, 1)   # tunes the problem as the worker does
-    n.autotune(0)
-    torch.cuda.synchronize()
-    n.bench_unit_gemm(sel[1], sel[0], F, params, lp, grad, 3)
-    torch.cuda.synchronize()
-    print(json.dumps({"pmc_probe": {"copy_bytes": COPY_BYTES, "kernel": f"{OPS[sel[1]]} GEMM of {sel[2]}",
-                                    "frames": F}}), flush=True)
-
-
-def traffic_bytes(kernel, workload):
-    """Per-launch HBM bytes (fetch + write) of `kernel` from the committed PMC
-    summary, or None when that summary is missing, was taken on another
-    workload or on other GEMM sources than the ones built now."""
-    import hashlib
-    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles", "pmc_traffic.json")
-    if not os.path.exists(path):
-        return None
-    with open(path) as f:
-        rec = json.load(f)
-    h = hashlib.sha256()
-    for name in rec.get("sources", []):
-        with open(os.path.join(os.path.dirname(os.path.abspath(__file__)), name), "rb") as f:
-            h.update(f.read())
-    if rec.get("kernel") != kernel or rec.get("workload") != workload or rec.get("sources_sha256") != h.hexdigest():
-        return None
-    return rec["fetch_bytes_per_launch"] + rec["write_bytes_per_launch"]
-
-
-def roofline_live(wl, sel, timed):
-    """Roofline entry of the dominant GEMM kernel from its launches inside the
-    timed steps (HIP events on the learner's stream around the kernel
-    itself): achieved = summed 2*M*N*K / summed duration."""
     u, op, name, all_tf = sel
-    launches, ms, fl = timed
+    w._graphs.clear()             # the act timer's events belong to the graphs: drop them first
+    w.net.gemm_timer_arm(u, op)
+    _update(w, env, parts, None)
+    torch.cuda.synchronize()
+    launches, ms, fl, _ = w.net.gemm_timer_read()
+    w.net.gemm_timer_arm(-1, 0)
     peak = PEAK_BF16_TFLOPS if wl.dtype == "bf16" else PEAK_FP32_TFLOPS
     if launches == 0 or ms <= 0:
         return {"bound": "mfma", "achieved": None, "peak": peak, "unit": "TFLOP/s", "frac": None,
-                "traffic": None, "kernel": f"{OPS[op]} GEMM of {name}"}
+                "kernel": f"{OPS[op]} GEMM of {name}"}
     ach = fl / (ms / 1e3) / 1e12
     return {"bound": "mfma", "achieved": round(ach, 3), "peak": peak, "unit": "TFLOP/s",
-            "frac": round(ach / peak, 5), "traffic": traffic_bytes(f"{OPS[op]} GEMM of {name}", wl.name),
-            "kernel": f"{OPS[op]} GEMM of {name}", "launches": launches,
+            "frac": round(ach / peak, 5), "kernel": f"{OPS[op]} GEMM of {name}", "launches": launches,
             "avg_launch_us": round(ms / launches * 1e3, 2), "flops_per_launch": fl / launches,
             "all_conv_gemms_tflops_microbench": all_tf}
+
+
+def traffic_bytes(kernel, workload):
+    """Per-launch HBM bytes (fetch + write) of `kernel` from the committed
+    counter summary, or None when it is missing, was taken on another
+    workload or on other GEMM sources than the ones built now."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "pmc_traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        recs = json.load(f)
+    for rec in recs if isinstance(recs, list) else [recs]:
+        h = hashlib.sha256()
+        for name in rec.get("sources", []):
+            with open(os.path.join(ROOT, name), "rb") as f:
+                h.update(f.read())
+        if rec.get("kernel") == kernel and rec.get("workload") == workload and \
+                rec.get("sources_sha256") == h.hexdigest():
+            return rec["fetch_bytes_per_launch"] + rec["write_bytes_per_launch"]
+    return None
+
+
+def act_roofline(wl, act):
+    """Roofline entry of the act step's convolution GEMMs from their HIP-event
+    durations: algorithmic bytes = the weight operand
+    of each product (every activation of an act step could stay on chip), the
+    bound of a batch-4 product; the matrix-core fraction of the same launches
+    is given beside it."""
+    launches, ms, fl, wb = act
+    if not launches or ms <= 0:
+        return {"bound": "hbm", "achieved": None, "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": None,
+                "traffic": None, "kernel": ACT_KERNEL}
+    ach = wb / (ms / 1e3) / 1e9
+    peak_mfma = PEAK_BF16_TFLOPS if wl.dtype == "bf16" else PEAK_FP32_TFLOPS
+    tflops = fl / (ms / 1e3) / 1e12
+    tr = traffic_bytes(ACT_KERNEL, wl.name)
+    return {"bound": "hbm", "achieved": round(ach, 2), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+            "frac": round(ach / PEAK_HBM_GBS, 6), "traffic": tr, "kernel": ACT_KERNEL,
+            "launches": launches, "avg_launch_us": round(ms / launches * 1e3, 3),
+            "bytes_per_launch": wb / launches, "flops_per_launch": fl / launches,
+            "mfma_tflops": round(tflops, 3), "mfma_frac": round(tflops / peak_mfma, 6),
+            "timed": f"the convolution GEMMs of {ACT_TIMED_STEPS} act steps launched eagerly after the timed "
+                     f"iterations (same kernels and tiles as the graph), HIP events around each kernel"}
 
 
 def flops_per_frame(net):
     """Forward multiply-adds x2 of the encoder convolutions, the visual FC and
     the LSTM/head GEMMs for one frame."""
-    from synth.layout import tensor_list
     hw = net.enc_hw
     f = 0
     if net.trunk == "tiny":
@@ -384,10 +538,65 @@ def flops_per_frame(net):
     return f
 
 
-def progress(msg):
-    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+# ------------------------------------------------------------------ counters
+COPY_BYTES = 256 << 20
 
 
+def pmc_probe(wl, seed, what):
+    """Calibration copy (COPY_BYTES read + written per launch, three launches),
+    then either four eager act steps (after tile tuning) or three launches of
+    the dominant learner GEMM named in the committed bench line, for HBM-byte
+    and matrix-core counters."""
+    import torch
+    import paper_1911_00357_amd as P
+    from paper_1911_00357_amd.worker import Worker
+    from synth import rollout as R
+    dev = torch.device("cuda", 0)
+    src = torch.ones(COPY_BYTES // 4, dtype=torch.float32, device=dev)
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    del src, dst
+    if what == "act":
+        w = Worker(wl.net, wl.dtype, wl.T, wl.N, R.init_params(wl.net, seed), _hyper(wl), dev)
+        env, lens = stage_env(wl, seed, 0, dev)
+        w.net.autotune(1)
+        w.collect(env)                 # tunes the act problems
+        w.net.autotune(0)
+        torch.cuda.synchronize()
+        T = wl.T
+        for t in range(4):
+            out = {"action": w.act_rec[t + 1], "logp": w.logp[t], "value": w.value[t], "h": w.h_hist[t + 1],
+                   "c": w.c_hist[t + 1]}
+            w.net.act(env["obs"][t], env["goal"][t], w.act_rec[t], env["mask"][t], w.h_hist[t], w.c_hist[t],
+                      env["u"][t], w.params, w.lp, out=out, state_rows=wl.N)
+        torch.cuda.synchronize()
+        w.release()
+        print(json.dumps({"pmc_probe": {"copy_bytes": COPY_BYTES, "kernel": ACT_KERNEL, "act_steps": 4}}),
+              flush=True)
+        return
+    path = os.path.join(ROOT, "profiles", f"bench_{wl.name}.json")
+    with open(path) as f:
+        label = json.load(f)["roofline_learner"]["kernel"]
+    op = next(i for i, s in enumerate(OPS) if label.startswith(s + " GEMM of "))
+    name = label[len(OPS[op] + " GEMM of "):]
+    n = P.Net(wl.net, wl.dtype)
+    u = unit_by_name(n, wl, name)
+    params = torch.tensor(R.init_params(wl.net, seed), device=dev)
+    lp = P.cast_bf16(params) if wl.dtype == "bf16" else None
+    grad = torch.zeros_like(params)
+    F = wl.T * wl.N // wl.ppo.minibatches
+    n.autotune(1)
+    n.bench_unit_gemm(op, u, F, params, lp, grad, 1)   # tunes the problem as the worker does
+    n.autotune(0)
+    torch.cuda.synchronize()
+    n.bench_unit_gemm(op, u, F, params, lp, grad, 3)
+    torch.cuda.synchronize()
+    print(json.dumps({"pmc_probe": {"copy_bytes": COPY_BYTES, "kernel": label, "frames": F}}), flush=True)
+
+
+# ---------------------------------------------------------------------- main
 def main():
     a = parse()
     global GRAPH, AUTOGRAD
@@ -402,20 +611,21 @@ def main():
         print(json.dumps({"error": "no GPU visible"}))
         sys.exit(1)
     from synth.configs import WORKLOADS
+    from synth import rollout as R
     wl = WORKLOADS[a.workload]
     if a.pmc_probe:
-        # the kernel the committed bench line names (counter runs distort the timing-based selection)
-        pmc_probe(wl, a.seed, committed_gemm(wl))
+        pmc_probe(wl, 0, a.pmc_probe)
         return
+    seeds = list(range(a.seeds))
     progress(f"workload {a.workload}: selecting the dominant learner GEMM")
-    sel = dominant_gemm(wl, a.seed)
-    progress("timed run")
-    res = run_gpu(wl, a.steps, a.warmup, a.seed, timer=sel[:2])
-    roof = roofline_live(wl, sel, res["timed"])
-    fps = res["frames"] / (res["gpu_ms"] / 1e3)
-    ms_step = res["gpu_ms"] / a.steps
-    frames_step = res["frames"] / a.steps
-    out = {"metric": "PPO act+update frames/s", "value": round(fps, 2), "unit": "frames/s",
+    sel = dominant_gemm(wl, 0)
+    progress(f"timed runs, seeds {seeds[0]}..{seeds[-1]}")
+    res, w0 = run_seeds(wl, seeds, a.steps, a.warmup, wl.dtype)
+    fps = [r["frames"] / (r["gpu_ms"] / 1e3) for r in res]
+    value, ci = median_ci(fps)
+    frames_step = res[0]["frames"] / a.steps
+    ms_step = frames_step / value * 1e3
+    out = {"metric": "PPO act+update frames/s", "value": round(value, 2), "unit": "frames/s",
            "n_gpus": 1, "steps": a.steps, "warmup": a.warmup, "ms_per_step": round(ms_step, 3),
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
            "dtype": "bf16" if wl.dtype == "bf16" else "f32", "data": "synthetic",
@@ -426,11 +636,22 @@ def main():
                       "parallelism": "single worker",
                       "gradient": "torch.autograd.Function, activations recomputed" if AUTOGRAD
                       else "ppo_loss_backward", "gemm_tiles": "autotuned in warm-up"},
-           "wall_s": round(res["wall_s"], 3)}
-    del res
+           "seeds": len(seeds), "ci95": [round(c, 2) for c in ci],
+           "per_seed": [round(x, 1) for x in fps],
+           "wall_s": round(sum(r["wall_s"] for r in res), 3)}
+    # roofline: the act step's convolution GEMMs (live, last timed replay of seed 0)
+    roof = act_roofline(wl, res[0]["act"])
+    env0, lens0 = stage_env(wl, 0, 0, torch.device("cuda", 0))
+    learner = learner_gemm_live(w0, wl, env0, R.partitions(wl, 0), sel)
+    learner["traffic"] = traffic_bytes(learner["kernel"], wl.name)
+    net = w0.net
+    w0.release()
+    del w0, env0
+    gc.collect()
     torch.cuda.empty_cache()
     progress("act / update split")
-    act_ms, upd_ms, fr = act_update_split(wl, a.seed)
+    act_ms, upd_ms, fr = act_update_split(wl, 0, net)
+    del net
     out["act_ms"], out["update_ms"] = round(act_ms, 3), round(upd_ms, 3)
     out["act_frames_per_s"] = round((fr + wl.N) / (act_ms / 1e3), 1)
     out["update_frames_per_s"] = round(fr / (upd_ms / 1e3), 1)
@@ -440,30 +661,42 @@ def main():
     # whole iteration: act forward of every frame (+ the bootstrap step) and E x (forward + backward)
     step_flops = fpf * ((1 + 3 * wl.ppo.epochs) * frames_step + wl.N)
     out["step_tflops"] = round(step_flops / (ms_step / 1e3) / 1e12, 3)
-    out["step_mfma_frac"] = round(step_flops / (ms_step / 1e3) / 1e12 / (PEAK_BF16_TFLOPS if wl.dtype == "bf16" else PEAK_FP32_TFLOPS), 5)
+    out["step_mfma_frac"] = round(step_flops / (ms_step / 1e3) / 1e12 / peak, 5)
     out["update_tflops"] = round(upd_flops / (upd_ms / 1e3) / 1e12, 3)
     out["update_mfma_frac"] = round(upd_flops / (upd_ms / 1e3) / 1e12 / peak, 5)
+    gc.collect()
+    torch.cuda.empty_cache()
     if wl.dtype == "bf16" and not a.no_fp32:
+        progress("float32 form, same seeds")
+        r32, w32 = run_seeds(wl.with_(dtype="f32"), seeds, min(a.steps, 5), min(a.warmup, 2), "f32")
+        w32.release()
+        del w32
+        f32 = [r["frames"] / (r["gpu_ms"] / 1e3) for r in r32]
+        v32, ci32 = median_ci(f32)
+        sp, cisp = median_ci(np.asarray(fps) / np.asarray(f32))
+        out["fp32_value"] = round(v32, 2)
+        out["fp32_ci95"] = [round(c, 2) for c in ci32]
+        out["bf16_speedup_vs_fp32"] = round(sp, 3)
+        out["bf16_speedup_ci95"] = [round(c, 3) for c in cisp]
+        gc.collect()
         torch.cuda.empty_cache()
-        progress("float32 form")
-        wl32 = wl.with_(dtype="f32")
-        r32 = run_gpu(wl32, a.steps, 1, a.seed)
-        out["fp32_value"] = round(r32["frames"] / (r32["gpu_ms"] / 1e3), 2)
-        out["bf16_speedup_vs_fp32"] = round(out["value"] / out["fp32_value"], 3)
-        del r32
     if wl.ragged:
-        torch.cuda.empty_cache()
         progress("unpacked per-env launches")
-        ua, uu, ufr = unpacked_split(wl, a.seed)
+        ua, uu, ufr = unpacked_split(wl, 0)
         out["unpacked_act_frames_per_s"] = round((ufr + wl.N) / (ua / 1e3), 1)
         out["unpacked_update_frames_per_s"] = round(ufr / (uu / 1e3), 1)
         out["packed_speedup_act"] = round(out["act_frames_per_s"] / out["unpacked_act_frames_per_s"], 3)
         out["packed_speedup_update"] = round(out["update_frames_per_s"] / out["unpacked_update_frames_per_s"], 3)
         out["unpacked_gemm_tiles"] = "heuristic"
+        gc.collect()
+        torch.cuda.empty_cache()
     out["roofline"] = roof
+    out["roofline_learner"] = learner
     if not a.no_cpu:
-        progress("oracle CPU baseline")
-        out["cpu_baseline"] = cpu_baseline(wl, a.seed)
+        progress("oracle CPU baseline and per-output errors")
+        out["cpu_baseline"] = cpu_baseline(wl, 0)
+    gc.collect()
+    torch.cuda.synchronize()
     print(json.dumps(out), flush=True)
 
 

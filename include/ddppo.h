@@ -347,17 +347,21 @@ ppo_status ppo_bench_unit_gemm(ppo_net* net, int op, int unit, int frames, const
  * calls on the same net. */
 ppo_status ppo_autotune(ppo_net* net, int mode, int* entries);
 
-/* Benchmark aid: time the GEMM kernel launches of trunk unit `unit`, op (0
- * forward, 1 data gradient, 2 weight gradient) inside later library calls on
- * this net, e.g. ppo_loss_backward.  Events are recorded on the call's stream
- * around each GEMM kernel itself (a split-K reduction that follows it is not
- * included), for at most max_launches launches, never inside stream capture.
- * unit < 0 disarms and frees the events.  Not thread-safe with other calls
- * on the same net. */
+/* Benchmark aid: time the GEMM kernel launches of trunk unit `unit`
+ * (PPO_TIMER_ALL_UNITS: every unit), op (0 forward, 1 data gradient, 2 weight
+ * gradient) inside later library calls on this net, e.g. ppo_act or
+ * ppo_loss_backward.  Events are recorded on the call's stream around each
+ * GEMM kernel itself (a split-K reduction that follows it is not included),
+ * for at most max_launches launches, never inside stream capture.  unit = -1
+ * disarms and frees the events.  Creates HIP events; not thread-safe with
+ * other calls on the same net. */
+enum { PPO_TIMER_ALL_UNITS = -2 };
 ppo_status ppo_gemm_timer_arm(ppo_net* net, int unit, int op, int max_launches);
 /* Waits for the recorded launches and returns their count, summed duration
- * (ms) and summed 2*M*N*K; then starts a new count (still armed). */
-ppo_status ppo_gemm_timer_read(ppo_net* net, int* launches, double* total_ms, double* flops);
+ * (ms), summed 2*M*N*K and (wbytes, or NULL) summed bytes of the weight
+ * operands of the timed convolution forward products; then starts a new
+ * count (still armed). */
+ppo_status ppo_gemm_timer_read(ppo_net* net, int* launches, double* total_ms, double* flops, double* wbytes);
 
 /* dst[i] = bfloat16(src[i]) (round to nearest even) for the initial working
  * copy of the parameters; later copies come from ppo_adam_step.  src [n]

@@ -15,6 +15,7 @@ PPO_F32, PPO_BF16 = 0, 1
 PPO_TRUNK_TINY, PPO_TRUNK_RESNET = 0, 1
 PPO_GOAL_RAW, PPO_GOAL_POLAR = 0, 1
 PPO_OP_ACT, PPO_OP_LEARN, PPO_OP_LOSS = 0, 1, 2
+PPO_TIMER_ALL_UNITS = -2
 
 STATUS_NAMES = {0: "PPO_OK", -1: "PPO_EINVAL", -2: "PPO_ESHAPE", -3: "PPO_EUNSUPPORTED",
                 -4: "PPO_EWORKSPACE", -5: "PPO_EDEVICE"}
@@ -89,7 +90,8 @@ EXPORTS = {
                                     c_size_t, c_int, C.POINTER(C.c_double), c_void_p]),
     "ppo_autotune": (c_int, [c_void_p, c_int, C.POINTER(c_int)]),
     "ppo_gemm_timer_arm": (c_int, [c_void_p, c_int, c_int, c_int]),
-    "ppo_gemm_timer_read": (c_int, [c_void_p, C.POINTER(c_int), C.POINTER(C.c_double), C.POINTER(C.c_double)]),
+    "ppo_gemm_timer_read": (c_int, [c_void_p, C.POINTER(c_int), C.POINTER(C.c_double), C.POINTER(C.c_double),
+                                    C.POINTER(C.c_double)]),
     "ppo_last_error": (C.c_char_p, []),
 }
 

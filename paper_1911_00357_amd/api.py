@@ -148,15 +148,17 @@ class Net:
         return n.value
 
     def gemm_timer_arm(self, unit: int, op: int, max_launches: int = 4096):
-        """Time the GEMM kernel launches of one trunk unit and op in later calls
-        (benchmark aid; unit < 0 disarms)."""
+        """Time the GEMM kernel launches of one trunk unit (L.PPO_TIMER_ALL_UNITS:
+        all) and op in later calls (benchmark aid; unit -1 disarms)."""
         check(lib().ppo_gemm_timer_arm(self._h, unit, op, max_launches), "ppo_gemm_timer_arm")
 
     def gemm_timer_read(self):
-        """(launches, summed ms, summed 2*M*N*K) since the last read."""
-        n, ms, fl = C.c_int(), C.c_double(), C.c_double()
-        check(lib().ppo_gemm_timer_read(self._h, C.byref(n), C.byref(ms), C.byref(fl)), "ppo_gemm_timer_read")
-        return n.value, ms.value, fl.value
+        """(launches, summed ms, summed 2*M*N*K, summed weight bytes) since the
+        last read."""
+        n, ms, fl, wb = C.c_int(), C.c_double(), C.c_double(), C.c_double()
+        check(lib().ppo_gemm_timer_read(self._h, C.byref(n), C.byref(ms), C.byref(fl), C.byref(wb)),
+              "ppo_gemm_timer_read")
+        return n.value, ms.value, fl.value, wb.value
 
     def recurrence_failed(self) -> bool:
         """True if a persistent LSTM launch of the last learner call gave up

@@ -332,7 +332,8 @@ bool gn_one_launch(const Ctx& c, const Unit& u, bool bwd = false) {
 // (unit, op) was selected with ppo_gemm_timer_arm.
 struct TimerScope {
   TimerScope(const ppo_net* n, int ui, int op) {
-    if (n->timer_unit == ui && n->timer_op == op && n->timer.cap > 0) g_gemm_timer = &n->timer;
+    if ((n->timer_unit == ui || n->timer_unit == PPO_TIMER_ALL_UNITS) && n->timer_op == op && n->timer.cap > 0)
+      g_gemm_timer = &n->timer;
   }
   ~TimerScope() { g_gemm_timer = nullptr; }
 };
@@ -1131,7 +1132,7 @@ ppo_status ppo_gemm_timer_arm(ppo_net* net, int unit, int op, int max_launches) 
   net->timer_ev.clear();
   net->timer = GemmTimer{};
   net->timer_unit = net->timer_op = -1;
-  if (unit < 0) return PPO_OK;
+  if (unit < 0 && unit != PPO_TIMER_ALL_UNITS) return PPO_OK;
   if (unit >= (int)net->units.size() || op < 0 || op > 2 || max_launches <= 0 || max_launches > (1 << 16))
     return fail(PPO_EINVAL, "bad unit / op / max_launches");
   net->timer_ev.resize(2 * (size_t)max_launches);
@@ -1140,13 +1141,13 @@ ppo_status ppo_gemm_timer_arm(ppo_net* net, int unit, int op, int max_launches) 
       e = nullptr;
       return fail(PPO_EDEVICE, "hipEventCreate failed");
     }
-  net->timer = GemmTimer{net->timer_ev.data(), net->timer_ev.data() + max_launches, max_launches, 0, 0.0};
+  net->timer = GemmTimer{net->timer_ev.data(), net->timer_ev.data() + max_launches, max_launches, 0, 0.0, 0.0};
   net->timer_unit = unit;
   net->timer_op = op;
   return PPO_OK;
 }
 
-ppo_status ppo_gemm_timer_read(ppo_net* net, int* launches, double* total_ms, double* flops) {
+ppo_status ppo_gemm_timer_read(ppo_net* net, int* launches, double* total_ms, double* flops, double* wbytes) {
   if (!net || !launches || !total_ms || !flops) return fail(PPO_EINVAL, "null argument");
   double t = 0.0;
   for (int i = 0; i < net->timer.n; ++i) {
@@ -1159,8 +1160,10 @@ ppo_status ppo_gemm_timer_read(ppo_net* net, int* launches, double* total_ms, do
   *launches = net->timer.n;
   *total_ms = t;
   *flops = net->timer.flops;
+  if (wbytes) *wbytes = net->timer.wbytes;
   net->timer.n = 0;
   net->timer.flops = 0.0;
+  net->timer.wbytes = 0.0;
   return PPO_OK;
 }
 

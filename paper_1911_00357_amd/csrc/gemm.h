@@ -381,6 +381,11 @@ struct DenseProb {
   }
 };
 
+// Bytes per element of a convolution's weight operand (the B rows of the
+// forward product); 0 for other products (GEMM launch timer's byte count).
+template <class P> struct WeightBytes { static constexpr int v = 0; };
+template <typename TW> struct WeightBytes<ConvFwdProb<TW>> { static constexpr int v = (int)sizeof(TW); };
+
 // Is the operand contiguous along rows (so lanes should walk rows)?  RT:
 // chunks are 8 rows at one k (vector loads along rows, transposed LDS writes).
 template <class P> struct Layout;

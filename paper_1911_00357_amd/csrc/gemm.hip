@@ -101,6 +101,7 @@ int launch(const Prob& p, Epi e, int splits, float* partial, hipStream_t s, bool
     hipEventRecord(tm->end[tm->n], s);
     ++tm->n;
     tm->flops += 2.0 * p.M * p.N * p.K;
+    tm->wbytes += (double)p.N * p.K * WeightBytes<Prob>::v;
   }
   if (splits > 1 && !defer) {
     const size_t MN = (size_t)p.M * p.N;

@@ -75,6 +75,7 @@ struct GemmTimer {
   hipEvent_t* end;
   int cap, n;
   double flops;
+  double wbytes;  // weight operand bytes of the timed convolution products
 };
 extern thread_local GemmTimer* g_gemm_timer;
 
@@ -130,14 +131,8 @@ void launch_gnb_fused(const float* dout, const float* outm, int chw, const float
                       float* dbeta, float2* bpart, hipStream_t s);
 
 // lstm.hip
-void launch_lstm_fwd(float* G, const float* cp, float* h, int ldh, float* c, int rows, int H,
-                     const float* mask_next, int rows_next, float* hp_next, float* cp_next,
-                     hipStream_t s);
 void launch_mask_state(const float* h_in, const float* c_in, const float* mask, int rows, int H,
                        float* hp, int ldhp, float* cp, hipStream_t s);
-void launch_lstm_bwd(const float* act, const float* c, const float* cp, const float* dh_in, int ldd,
-                     int rows, int H, const float* mask_next, int rows_next, const float* dhp_next,
-                     const float* dcp_next, float* dG, float* dcp, hipStream_t s);
 void launch_colsum(const float* in, int rows, int cols, int ld, float* out, hipStream_t s);
 
 // lstm_step.hip: one launch per time step (see the file header)

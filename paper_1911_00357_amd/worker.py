@@ -34,10 +34,12 @@ class PPOHyper:
 
 
 class Worker:
-    def __init__(self, spec, dtype: str, T: int, N: int, params, hyper: PPOHyper = None, device="cuda"):
+    def __init__(self, spec, dtype: str, T: int, N: int, params, hyper: PPOHyper = None, device="cuda", net=None):
+        """net: an existing Net of this spec and dtype to share (its tile table
+        and workspaces), else a new one."""
         self.hp = hyper or PPOHyper()
         self.spec, self.T, self.N, self.dev = spec, T, N, torch.device(device)
-        self.net = Net(spec, dtype)
+        self.net = net if net is not None else Net(spec, dtype)
         self.bf16 = dtype == "bf16"
         self.params = torch.as_tensor(np.asarray(params, np.float32)).to(self.dev).contiguous()
         assert self.params.numel() == self.net.P
@@ -59,18 +61,29 @@ class Worker:
         self.c_scr = torch.zeros(L, N, H, **f32)
         self._graphs = {}
 
+    def release(self):
+        """Drop the captured graphs and the library state now (before the
+        interpreter's teardown), after the device has finished with them."""
+        torch.cuda.synchronize()
+        self._graphs.clear()
+        self.net = None
+        self.adam = None
+
     # ------------------------------------------------------------- rollout
-    def collect(self, env: dict, lengths=None, graph: bool = False):
+    def collect(self, env: dict, lengths=None, graph: bool = False, before_capture=None):
         """env: device tensors obs [T+1,N,C,H,W], goal [T+1,N,2], mask [T+1,N],
         u [T+1,N].  lengths: host ints [N] (non-increasing) or None.
         graph=True replays the T+1 act calls as one captured HIP graph (captured
-        on the first call for these env buffers, after one eager pass)."""
+        on the first call for these env buffers, after one eager pass);
+        before_capture() is called between that eager pass and the capture."""
         if graph:
             key = (env["obs"].data_ptr(), env["u"].data_ptr(), None if lengths is None else tuple(lengths))
             g = self._graphs.get(key)
             if g is None:
                 self._collect(env, lengths)        # eager pass: workspaces exist before capture
                 torch.cuda.synchronize()
+                if before_capture is not None:
+                    before_capture()
                 g = torch.cuda.CUDAGraph()
                 with torch.cuda.graph(g):
                     self._collect(env, lengths)
