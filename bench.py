@@ -14,9 +14,10 @@ value is the median over seeds of frames / timed GPU time, with a bootstrap
 on the same seeds.
 
 Prints one JSON line.  The roofline entry is the act step's convolution
-GEMMs (the largest kernel class by time), timed live with HIP events around
-each kernel on act steps launched right after the timed iterations; the
-learner's slowest convolution GEMM is a second entry.  The CPU baseline is
+GEMMs (the largest kernel class by time), timed live with HIP events right
+after the timed iterations (each unit's product as the act graph runs it,
+many launches back to back); the learner's slowest convolution GEMM is a
+second entry.  The CPU baseline is
 the float64 oracle on a bounded sample of the same workload, with the GPU's
 per-output errors on that sample.
 """
@@ -39,7 +40,7 @@ PEAK_FP32_TFLOPS = 157.3      # MI355X fp32 matrix
 PEAK_HBM_GBS = 8000.0
 GRAPH = True                  # act loop replayed as one captured HIP graph
 AUTOGRAD = False              # update gradient through torch.autograd (C3)
-ACT_TIMED_STEPS = 4           # act steps whose convolution GEMMs are timed for the roofline
+ACT_REPS = 64                 # back-to-back launches per act product in the roofline timing
 
 
 def parse():
@@ -53,8 +54,10 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--eager", action="store_true", help="launch the act loop eagerly (no HIP graph)")
     ap.add_argument("--pmc-probe", choices=["act", "learner"],
-                    help="only run a 256 MiB copy and then the act steps or the dominant learner GEMM "
-                         "(for rocprofv3 --pmc)")
+                    help="only run a 256 MiB copy and then every convolution GEMM at the act or the "
+                         "learner batch (for rocprofv3 --pmc)")
+    ap.add_argument("--tiles-out", help="write the tuned tile table (JSON) of the timed form here")
+    ap.add_argument("--tiles-in", help="use this tile table (from --tiles-out) instead of tuning")
     ap.add_argument("--autograd", choices=["auto", "on", "off"], default="auto",
                     help="take the update's gradient through torch.autograd (auto: for C3)")
     return ap.parse_args()
@@ -62,6 +65,16 @@ def parse():
 
 def progress(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def trace_marker():
+    """A one-block bfloat16 cast of three values: a dispatch no other step of
+    the bench makes (parameter casts cover whole vectors), so a kernel trace
+    can find the phases it separates.  Synchronises."""
+    import torch
+    import paper_1911_00357_amd as P
+    P.cast_bf16(torch.zeros(3, device="cuda"))
+    torch.cuda.synchronize()
 
 
 def stage_env(wl, seed, it, dev):
@@ -96,13 +109,10 @@ def _update(w, env, parts, lengths):
 
 def run_seed(wl, seed, steps, warmup, net=None, act_timer=True):
     """Warm-up and timed iterations of one seed; with act_timer, then the act
-    step's convolution GEMMs timed with HIP events around each kernel over
-    ACT_TIMED_STEPS act steps launched eagerly (the same kernels and tiles
-    the captured graph replays; the runtime that comes with torch refuses
-    event nodes inside a captured graph).  Returns frames, GPU ms, wall s,
-    the act-GEMM timing and the worker."""
+    step's convolution products timed (act_gemms_live; the runtime that comes
+    with torch refuses event nodes inside the captured graph itself).
+    Returns frames, GPU ms, wall s, the act-GEMM timing and the worker."""
     import torch
-    from paper_1911_00357_amd._lib import PPO_OP_ACT, PPO_TIMER_ALL_UNITS
     from paper_1911_00357_amd.worker import Worker
     from synth import rollout as R
     dev = torch.device("cuda", 0)
@@ -118,6 +128,8 @@ def run_seed(wl, seed, steps, warmup, net=None, act_timer=True):
         env, lens = envs[i % len(envs)]
         lengths = None if not wl.ragged else lens
         if i == warmup:
+            if act_timer:
+                trace_marker()          # kernel-trace landmark: the timed iterations start
             torch.cuda.synchronize()
             ev[0].record()
             t_start = time.perf_counter()
@@ -130,25 +142,54 @@ def run_seed(wl, seed, steps, warmup, net=None, act_timer=True):
     ev[1].record()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t_start
-    act = None
-    if act_timer:
-        nunits = w.net.probe(PPO_OP_ACT, wl.N, 1, 3)[3][0]
-        w.net.gemm_timer_arm(PPO_TIMER_ALL_UNITS, 0, nunits * ACT_TIMED_STEPS)
-        env, lens = envs[0]
-        w.collect(env, None if not wl.ragged else lens, graph=False)
-        act = w.net.gemm_timer_read()
-        w.net.gemm_timer_arm(-1, 0)
+    act = act_gemms_live(w, wl) if act_timer else None
     return {"frames": frames, "gpu_ms": ev[0].elapsed_time(ev[1]), "wall_s": wall, "act": act, "worker": w}
 
 
-def run_seeds(wl, seeds, steps, warmup, label):
+def act_gemms_live(w, wl, reps=ACT_REPS):
+    """The act step's convolution products timed live: each trunk unit's
+    product as ppo_act runs it at the act batch (same tiles and K split, from
+    the table tuned in the warm-up), `reps` launches back to back between
+    two HIP events on the stream they run on.  Returns (launches, ms, FLOPs,
+    weight bytes, per-unit us)."""
+    import torch
+    from paper_1911_00357_amd._lib import PPO_OP_LEARN
+    trace_marker()                      # kernel-trace landmark: the timed act products follow
+    n = w.net
+    N = wl.N
+    nunits = n.probe(PPO_OP_LEARN, N, 1, 3)[3][0]
+    wcount = {name: cnt for name, _, cnt in n.tensors()}
+    esize = 2 if wl.dtype == "bf16" else 4
+    grad = torch.zeros_like(w.params)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    tot_ms = tot_fl = tot_b = 0.0
+    per = []
+    for u in range(nunits):
+        name = n.probe(PPO_OP_LEARN, N, 1, 0, u)[0]
+        n.bench_unit_gemm(3, u, N, w.params, w.lp, grad, 1)
+        ev[0].record()
+        fl = n.bench_unit_gemm(3, u, N, w.params, w.lp, grad, reps)
+        ev[1].record()
+        torch.cuda.synchronize()
+        ms = ev[0].elapsed_time(ev[1])
+        tot_ms += ms
+        tot_fl += fl * reps
+        tot_b += wcount[name] * esize * reps
+        per.append((name, round(ms / reps * 1e3, 3)))
+    return nunits * reps, tot_ms, tot_fl, tot_b, per
+
+
+def run_seeds(wl, seeds, steps, warmup, label, tiles=None):
     """Every seed on one shared library handle (its tile table is tuned in the
-    first seed's first warm-up iteration).  Returns per-seed results (without
-    workers) and the first seed's worker."""
+    first seed's first warm-up iteration, or loaded from `tiles`).  Returns
+    per-seed results (without workers) and the first seed's worker."""
     import torch
     import paper_1911_00357_amd as P
     net = P.Net(wl.net, wl.dtype)
-    net.autotune(1)
+    if tiles:
+        net.tile_table(tiles)
+    else:
+        net.autotune(1)
     out, first = [], None
     for k, seed in enumerate(seeds):
         r = run_seed(wl, seed, steps, warmup, net=net, act_timer=(k == 0))
@@ -431,15 +472,6 @@ def dominant_gemm(wl, seed, reps=5):
     return u, op, name, round(tot_f / (tot_t / 1e3) / 1e12, 3)
 
 
-def unit_by_name(n, wl, name):
-    from paper_1911_00357_amd._lib import PPO_OP_LEARN
-    F = wl.T * wl.N // wl.ppo.minibatches
-    for u in range(n.probe(PPO_OP_LEARN, F, 1, 3)[3][0]):
-        if n.probe(PPO_OP_LEARN, F, 1, 0, u)[0] == name:
-            return u
-    raise SystemExit(f"unit {name} not found")
-
-
 def learner_gemm_live(w, wl, env, parts, sel):
     """The dominant learner GEMM timed with HIP events on the learner's
     stream around the kernel itself, over one update."""
@@ -489,7 +521,7 @@ def act_roofline(wl, act):
     of each product (every activation of an act step could stay on chip), the
     bound of a batch-4 product; the matrix-core fraction of the same launches
     is given beside it."""
-    launches, ms, fl, wb = act
+    launches, ms, fl, wb, per = act
     if not launches or ms <= 0:
         return {"bound": "hbm", "achieved": None, "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": None,
                 "traffic": None, "kernel": ACT_KERNEL}
@@ -499,11 +531,12 @@ def act_roofline(wl, act):
     tr = traffic_bytes(ACT_KERNEL, wl.name)
     return {"bound": "hbm", "achieved": round(ach, 2), "peak": PEAK_HBM_GBS, "unit": "GB/s",
             "frac": round(ach / PEAK_HBM_GBS, 6), "traffic": tr, "kernel": ACT_KERNEL,
-            "launches": launches, "avg_launch_us": round(ms / launches * 1e3, 3),
+            "launches": launches, "reps_per_unit": ACT_REPS, "avg_launch_us": round(ms / launches * 1e3, 3),
             "bytes_per_launch": wb / launches, "flops_per_launch": fl / launches,
             "mfma_tflops": round(tflops, 3), "mfma_frac": round(tflops / peak_mfma, 6),
-            "timed": f"the convolution GEMMs of {ACT_TIMED_STEPS} act steps launched eagerly after the timed "
-                     f"iterations (same kernels and tiles as the graph), HIP events around each kernel"}
+            "timed": f"after the timed iterations: each unit's act product (the tiles and K split the "
+                     f"graph replays) launched {ACT_REPS} times back to back between two HIP events",
+            "per_unit_us": per}
 
 
 def flops_per_frame(net):
@@ -542,14 +575,21 @@ def flops_per_frame(net):
 COPY_BYTES = 256 << 20
 
 
-def pmc_probe(wl, seed, what):
+
+
+def pmc_probe(wl, seed, what, tiles=None):
     """Calibration copy (COPY_BYTES read + written per launch, three launches),
-    then either four eager act steps (after tile tuning) or three launches of
-    the dominant learner GEMM named in the committed bench line, for HBM-byte
-    and matrix-core counters."""
+    then, after a landmark, every trunk unit's convolution GEMMs launched once
+    through ppo_bench_unit_gemm, tiles tuned first as the worker tunes them
+    (or taken from a tile table the benchmark wrote): 'act' the forward
+    products as the act step runs them (N frames, split-K partials left for
+    the GroupNorm), 'learner' the forward, data-gradient and weight-gradient
+    products at the learner's minibatch size.  For HBM-byte and matrix-core
+    counters per dispatch (no other kernel runs between the landmark and the
+    end)."""
     import torch
     import paper_1911_00357_amd as P
-    from paper_1911_00357_amd.worker import Worker
+    from paper_1911_00357_amd._lib import PPO_OP_LEARN
     from synth import rollout as R
     dev = torch.device("cuda", 0)
     src = torch.ones(COPY_BYTES // 4, dtype=torch.float32, device=dev)
@@ -558,46 +598,155 @@ def pmc_probe(wl, seed, what):
         dst.copy_(src)
     torch.cuda.synchronize()
     del src, dst
-    if what == "act":
-        w = Worker(wl.net, wl.dtype, wl.T, wl.N, R.init_params(wl.net, seed), _hyper(wl), dev)
-        env, lens = stage_env(wl, seed, 0, dev)
-        w.net.autotune(1)
-        w.collect(env)                 # tunes the act problems
-        w.net.autotune(0)
-        torch.cuda.synchronize()
-        T = wl.T
-        for t in range(4):
-            out = {"action": w.act_rec[t + 1], "logp": w.logp[t], "value": w.value[t], "h": w.h_hist[t + 1],
-                   "c": w.c_hist[t + 1]}
-            w.net.act(env["obs"][t], env["goal"][t], w.act_rec[t], env["mask"][t], w.h_hist[t], w.c_hist[t],
-                      env["u"][t], w.params, w.lp, out=out, state_rows=wl.N)
-        torch.cuda.synchronize()
-        w.release()
-        print(json.dumps({"pmc_probe": {"copy_bytes": COPY_BYTES, "kernel": ACT_KERNEL, "act_steps": 4}}),
-              flush=True)
-        return
-    path = os.path.join(ROOT, "profiles", f"bench_{wl.name}.json")
-    with open(path) as f:
-        label = json.load(f)["roofline_learner"]["kernel"]
-    op = next(i for i, s in enumerate(OPS) if label.startswith(s + " GEMM of "))
-    name = label[len(OPS[op] + " GEMM of "):]
     n = P.Net(wl.net, wl.dtype)
-    u = unit_by_name(n, wl, name)
     params = torch.tensor(R.init_params(wl.net, seed), device=dev)
     lp = P.cast_bf16(params) if wl.dtype == "bf16" else None
     grad = torch.zeros_like(params)
-    F = wl.T * wl.N // wl.ppo.minibatches
-    n.autotune(1)
-    n.bench_unit_gemm(op, u, F, params, lp, grad, 1)   # tunes the problem as the worker does
+    F = wl.N if what == "act" else wl.T * wl.N // wl.ppo.minibatches
+    ops = (3,) if what == "act" else (0, 1, 2)
+    nunits = n.probe(PPO_OP_LEARN, F, 1, 3)[3][0]
+    todo = [(op, u) for u in range(nunits) for op in ops if not (op == 1 and u == 0)]
+    if tiles:
+        n.tile_table(tiles)
+    n.autotune(0 if tiles else 1)
+    for op, u in todo:
+        n.bench_unit_gemm(op, u, F, params, lp, grad, 1)
     n.autotune(0)
+    trace_marker()
+    for op, u in todo:
+        n.bench_unit_gemm(op, u, F, params, lp, grad, 1)
     torch.cuda.synchronize()
-    n.bench_unit_gemm(op, u, F, params, lp, grad, 3)
-    torch.cuda.synchronize()
-    print(json.dumps({"pmc_probe": {"copy_bytes": COPY_BYTES, "kernel": label, "frames": F}}), flush=True)
+    print(json.dumps({"pmc_probe": {"copy_bytes": COPY_BYTES, "what": what, "frames": F, "launches": len(todo)}}),
+          flush=True)
+
+
+# ------------------------------------------------------- profile summaries
+def _is_marker(r):
+    return r["Kernel_Name"].startswith("cast_bf16_kernel") and int(r.get("Grid_Size_X", r.get("Grid_Size", 0))) <= 256
+
+
+def _short(n):
+    return n.split("(")[0].replace("unsigned short", "bf16")[:110]
+
+
+def summarize_trace(csv_path, log_path=None, ref_path=None):
+    """Markdown summary of a kernel trace of this benchmark: the timed
+    iteration (between the first two landmarks) split into act loop and
+    update at its GAE launch, and the act convolution GEMMs the benchmark
+    times after the second landmark, beside the benchmark line of the same
+    run (log_path) and of an unprofiled run with the same tiles (ref_path)."""
+    import collections
+    import csv
+    rows = sorted(csv.DictReader(open(csv_path)), key=lambda r: int(r["Start_Timestamp"]))
+    dur = lambda r: (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1000.0
+    marks = [i for i, r in enumerate(rows) if _is_marker(r)]
+    out = []
+
+    def table(sub, title, top=25):
+        busy = sum(dur(r) for r in sub)
+        span = (int(sub[-1]["End_Timestamp"]) - int(sub[0]["Start_Timestamp"])) / 1000.0
+        g = collections.defaultdict(lambda: [0, 0.0])
+        for r in sub:
+            x = g[_short(r["Kernel_Name"])]
+            x[0] += 1
+            x[1] += dur(r)
+        out.append(f"\n## {title}: {len(sub)} dispatches, span {span / 1000:.2f} ms, kernel busy {busy / 1000:.2f} ms\n")
+        out.append("| calls | total ms | avg us | % | kernel |\n|---:|---:|---:|---:|---|")
+        for k, (n, t) in sorted(g.items(), key=lambda kv: -kv[1][1])[:top]:
+            out.append(f"| {n} | {t / 1000:.2f} | {t / n:.2f} | {100 * t / busy:.1f} | `{k}` |")
+
+    if len(marks) >= 2:
+        timed = rows[marks[0] + 1:marks[1]]
+        gae = next(i for i, r in enumerate(timed) if r["Kernel_Name"].startswith("gae_kernel"))
+        table(timed[:gae], "act loop of the timed iteration (129 act steps, one graph replay)")
+        conv = [dur(r) for r in timed[:gae] if "ConvFwdProb" in r["Kernel_Name"]]
+        out.append(f"\nact convolution GEMMs in the graph replay: {len(conv)} launches, average "
+                   f"{sum(conv) / max(len(conv), 1):.3f} us")
+        table(timed[gae:], "update of the timed iteration")
+        after = [r for r in rows[marks[1] + 1:] if "ConvFwdProb" in r["Kernel_Name"]]
+        line = None
+        if log_path:
+            for l in open(log_path):
+                if l.startswith("{") and '"roofline"' in l:
+                    line = json.loads(l)["roofline"]
+        n = line["launches"] if line else 0
+        reps = line.get("reps_per_unit", 0) if line else 0
+        # per unit: one untimed launch, then `reps` between the events
+        leg = [r for i, r in enumerate(after[:n + n // max(reps, 1)]) if reps and i % (reps + 1)]
+        if leg:
+            avg = sum(dur(r) for r in leg) / len(leg)
+            units = [leg[i:i + reps] for i in range(0, len(leg), reps)]
+            span = sum((int(u[-1]["End_Timestamp"]) - int(u[0]["Start_Timestamp"])) / 1000.0 for u in units)
+            per_span = span / len(leg)
+            out.append(f"\n## roofline kernel: {line['kernel']}\n\n"
+                       f"The act products the benchmark times after the second landmark: {len(leg)} launches "
+                       f"({len(units)} units x {reps}), trace average duration {avg:.3f} us, first-to-last span "
+                       f"per launch {per_span:.3f} us; {line['bytes_per_launch']:.0f} algorithmic bytes and "
+                       f"{line['flops_per_launch']:.0f} FLOP per launch, i.e. "
+                       f"{line['bytes_per_launch'] / avg / 1e3:.2f} GB/s "
+                       f"({line['bytes_per_launch'] / avg / 1e3 / PEAK_HBM_GBS:.6f} of {PEAK_HBM_GBS:.0f} GB/s) "
+                       f"on the trace's durations. HIP events of the same (traced) run: "
+                       f"{line['avg_launch_us']} us per launch.")
+            if ref_path:
+                for l in open(ref_path):
+                    if l.startswith("{") and '"roofline"' in l:
+                        ref = json.loads(l)["roofline"]
+                        out.append(f"Unprofiled run with the same tile table: {ref['avg_launch_us']} us per launch "
+                                   f"over {ref['launches']} launches (HIP events), {ref['achieved']} GB/s, "
+                                   f"frac {ref['frac']}.")
+    agg = collections.defaultdict(lambda: [0, 0.0])
+    for r in rows:
+        a = agg[_short(r["Kernel_Name"])]
+        a[0] += 1
+        a[1] += dur(r)
+    out.append("\n## whole run (including tile tuning), top 15 by total time\n")
+    out.append("| calls | total ms | avg us | kernel |\n|---:|---:|---:|---|")
+    for k, (n, t) in sorted(agg.items(), key=lambda kv: -kv[1][1])[:15]:
+        out.append(f"| {n} | {t / 1000:.2f} | {t / n:.2f} | `{k}` |")
+    return "\n".join(out) + "\n"
+
+
+def summarize_counters(csv_path):
+    """Per kernel class, summed counters of the dispatches after the landmark
+    of a --pmc-probe run (the copy before it is the calibration): JSON."""
+    import collections
+    import csv
+    rows = list(csv.DictReader(open(csv_path)))
+    disp = collections.OrderedDict()
+    for r in rows:
+        d = disp.setdefault(int(r["Dispatch_Id"]), {"name": r["Kernel_Name"], "grid": r.get("Grid_Size", ""),
+                                                     "c": collections.defaultdict(float)})
+        d["c"][r["Counter_Name"]] += float(r["Counter_Value"])
+    ids = sorted(disp)
+    mark = [i for i in ids if disp[i]["name"].startswith("cast_bf16_kernel") and int(disp[i]["grid"] or 0) <= 256]
+    copy = [i for i in ids if "copyBuffer" in disp[i]["name"]]
+    cls = collections.defaultdict(lambda: {"dispatches": 0, "counters": collections.defaultdict(float)})
+    start = mark[-1] if mark else -1
+    for i in ids:
+        if i <= start:
+            continue
+        name = disp[i]["name"]
+        k = "conv forward GEMM" if "ConvFwdProb" in name else \
+            "stem weight-gradient GEMM (channel-vector loads)" if "ConvWgradRTProb" in name else \
+            "conv weight-gradient GEMM" if "ConvWgrad" in name \
+            else "conv data-gradient GEMM" if "ConvDgrad" in name else "dense GEMM" if "DenseProb" in name \
+            else _short(name)
+        cls[k]["dispatches"] += 1
+        for cn, v in disp[i]["c"].items():
+            cls[k]["counters"][cn] += v
+    calib = [{cn: v for cn, v in disp[i]["c"].items()} for i in ids if i < start and i in copy][:3]
+    return {"copy_calibration": calib, "classes": {k: {"dispatches": v["dispatches"], **v["counters"]}
+                                                    for k, v in cls.items()}}
 
 
 # ---------------------------------------------------------------------- main
 def main():
+    if len(sys.argv) >= 3 and sys.argv[1] == "--summarize-trace":
+        sys.stdout.write(summarize_trace(*sys.argv[2:5]))
+        return
+    if len(sys.argv) >= 3 and sys.argv[1] == "--summarize-counters":
+        print(json.dumps(summarize_counters(sys.argv[2])))
+        return
     a = parse()
     global GRAPH, AUTOGRAD
     GRAPH = not a.eager
@@ -614,13 +763,17 @@ def main():
     from synth import rollout as R
     wl = WORKLOADS[a.workload]
     if a.pmc_probe:
-        pmc_probe(wl, 0, a.pmc_probe)
+        pmc_probe(wl, 0, a.pmc_probe, json.load(open(a.tiles_in)) if a.tiles_in else None)
         return
     seeds = list(range(a.seeds))
     progress(f"workload {a.workload}: selecting the dominant learner GEMM")
     sel = dominant_gemm(wl, 0)
     progress(f"timed runs, seeds {seeds[0]}..{seeds[-1]}")
-    res, w0 = run_seeds(wl, seeds, a.steps, a.warmup, wl.dtype)
+    tiles = json.load(open(a.tiles_in)) if a.tiles_in else None
+    res, w0 = run_seeds(wl, seeds, a.steps, a.warmup, wl.dtype, tiles)
+    if a.tiles_out:
+        with open(a.tiles_out, "w") as f:
+            json.dump(w0.net.tile_table(), f)
     fps = [r["frames"] / (r["gpu_ms"] / 1e3) for r in res]
     value, ci = median_ci(fps)
     frames_step = res[0]["frames"] / a.steps

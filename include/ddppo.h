@@ -326,9 +326,11 @@ ppo_status ppo_workspace_probe(const ppo_net* net, int op, int max_frames, int m
                                int index, const char** name, int* relu, size_t* offset, int dims[4]);
 
 /* Benchmark aid: enqueue `reps` launches of the convolution GEMM of trunk
- * unit `unit` (op 0 forward, 1 data gradient, 2 weight gradient) at `frames`
- * frames, with the tile shape and K split that ppo_loss_backward uses for it,
- * on workspace scratch data (workspace laid out as for ppo_loss_backward with
+ * unit `unit` (op 0 forward, 1 data gradient, 2 weight gradient, as
+ * ppo_loss_backward runs them; op 3 the forward product as ppo_act runs it at
+ * this frame count, its split-K partial tiles left for the GroupNorm) at
+ * `frames` frames, with the tile shape and K split of that call, on
+ * workspace scratch data (workspace laid out as for ppo_loss_backward with
  * max_frames = frames, max_envs = 1).  *flops = 2*M*N*K of one launch.  The
  * weight-gradient op writes that unit's slot of grad. */
 ppo_status ppo_bench_unit_gemm(ppo_net* net, int op, int unit, int frames, const float* params,
@@ -346,6 +348,16 @@ ppo_status ppo_bench_unit_gemm(ppo_net* net, int op, int unit, int frames, const
  * *entries (optional) = problems in the table.  Not thread-safe with other
  * calls on the same net. */
 ppo_status ppo_autotune(ppo_net* net, int mode, int* entries);
+
+/* The autotuner's table as rows of 7 int64: the problem key (operand kind,
+ * M, N, K, precision/variant code) then the tile index (0..5: 128x128,
+ * 128x64, 64x128, 64x64, 128x32, 32x128) and the K split.  write 0: copy up
+ * to `capacity` rows into `table`, *entries = rows in the table (call with
+ * capacity 0 for the count).  write 1: add or replace the first *entries rows
+ * of `table` (e.g. a table read back from an earlier run, so that a profiled
+ * run uses the same tiles); *entries = rows in the table afterwards.
+ * Errors: PPO_EINVAL for a tile or split out of range. */
+ppo_status ppo_autotune_table(ppo_net* net, int write, int64_t* table, int capacity, int* entries);
 
 /* Benchmark aid: time the GEMM kernel launches of trunk unit `unit`
  * (PPO_TIMER_ALL_UNITS: every unit), op (0 forward, 1 data gradient, 2 weight

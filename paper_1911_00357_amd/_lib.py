@@ -89,6 +89,7 @@ EXPORTS = {
     "ppo_bench_unit_gemm": (c_int, [c_void_p, c_int, c_int, c_int, c_void_p, c_void_p, c_void_p, c_void_p,
                                     c_size_t, c_int, C.POINTER(C.c_double), c_void_p]),
     "ppo_autotune": (c_int, [c_void_p, c_int, C.POINTER(c_int)]),
+    "ppo_autotune_table": (c_int, [c_void_p, c_int, C.POINTER(C.c_int64), c_int, C.POINTER(c_int)]),
     "ppo_gemm_timer_arm": (c_int, [c_void_p, c_int, c_int, c_int]),
     "ppo_gemm_timer_read": (c_int, [c_void_p, C.POINTER(c_int), C.POINTER(C.c_double), C.POINTER(C.c_double),
                                     C.POINTER(C.c_double)]),

@@ -147,6 +147,20 @@ class Net:
         check(lib().ppo_autotune(self._h, mode, C.byref(n)), "ppo_autotune")
         return n.value
 
+    def tile_table(self, rows=None):
+        """The autotuner's table as a list of 7-int rows (key, tile, split);
+        with rows, load them into the table first."""
+        n = C.c_int(0)
+        if rows:
+            buf = (C.c_int64 * (7 * len(rows)))(*[int(v) for r in rows for v in r])
+            n.value = len(rows)
+            check(lib().ppo_autotune_table(self._h, 1, buf, len(rows), C.byref(n)), "ppo_autotune_table")
+        check(lib().ppo_autotune_table(self._h, 0, None, 0, C.byref(n)), "ppo_autotune_table")
+        buf = (C.c_int64 * (7 * max(n.value, 1)))()
+        cap = n.value
+        check(lib().ppo_autotune_table(self._h, 0, buf, cap, C.byref(n)), "ppo_autotune_table")
+        return [list(buf[7 * i:7 * i + 7]) for i in range(min(n.value, cap))]
+
     def gemm_timer_arm(self, unit: int, op: int, max_launches: int = 4096):
         """Time the GEMM kernel launches of one trunk unit (L.PPO_TIMER_ALL_UNITS:
         all) and op in later calls (benchmark aid; unit -1 disarms)."""

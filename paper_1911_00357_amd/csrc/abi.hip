@@ -1088,7 +1088,7 @@ ppo_status ppo_bench_unit_gemm(ppo_net* net, int op, int unit, int frames, const
                                double* flops, void* stream) {
   TuneScope tsc(net);
   if (!net || !params || !grad || !flops || (net->prec && !params_lp)) return fail(PPO_EINVAL, "null argument");
-  if (unit < 0 || unit >= (int)net->units.size() || op < 0 || op > 2 || frames <= 0 || reps <= 0)
+  if (unit < 0 || unit >= (int)net->units.size() || op < 0 || op > 3 || frames <= 0 || reps <= 0)
     return fail(PPO_EINVAL, "bad unit / op / frames / reps");
   const WsLayout w = plan(net, frames, 1, true);
   if (!ws || ws_bytes < w.total) return fail(PPO_EWORKSPACE, "workspace needs %zu bytes", w.total);
@@ -1101,9 +1101,11 @@ ppo_status ppo_bench_unit_gemm(ppo_net* net, int op, int unit, int frames, const
   *flops = 2.0 * M * N * K;
   // operands: scratch buffers sized for the largest unit of a learner call
   float *X = c.at(w.ga), *DY = c.at(w.gb), *OUT = c.at(w.gu);
+  // op 3: the act step's product, its split-K partial tiles left for the GroupNorm
+  const bool act_form = op == 3 && gn_one_launch(c, u);
   for (int r = 0; r < reps; ++r) {
-    if (op == 0)
-      gemm_conv_fwd(net->prec, g, X, c.wt(u.w), epi(OUT, u.Cout), kSplitKBytes, c.splitk(), s);
+    if (op == 0 || op == 3)
+      gemm_conv_fwd(net->prec, g, X, c.wt(u.w), epi(OUT, u.Cout), kSplitKBytes, c.splitk(), s, act_form);
     else if (op == 1)
       gemm_conv_dgrad(net->prec, g, DY, c.wt(u.w), c.at<void>(w.wT), epi(OUT, u.Cin), kSplitKBytes, c.splitk(), s);
     else
@@ -1122,6 +1124,33 @@ ppo_status ppo_autotune(ppo_net* net, int mode, int* entries) {
     net->tune.tuning = mode;
   }
   if (entries) *entries = (int)net->tune.best.size();
+  return PPO_OK;
+}
+
+ppo_status ppo_autotune_table(ppo_net* net, int write, int64_t* table, int capacity, int* entries) {
+  if (!net || !entries || (capacity > 0 && !table) || capacity < 0) return fail(PPO_EINVAL, "bad arguments");
+  if (write) {
+    const int n = *entries;
+    if (n < 0 || n > capacity) return fail(PPO_EINVAL, "entries outside the table");
+    for (int i = 0; i < n; ++i) {
+      const int64_t* r = table + 7 * i;
+      if (r[5] < 0 || r[5] > 5 || r[6] < 1 || r[6] > 256) return fail(PPO_EINVAL, "bad tile or split in row %d", i);
+      net->tune.best[{r[0], r[1], r[2], r[3], r[4]}] = {(int)r[5], (int)r[6]};
+    }
+    *entries = (int)net->tune.best.size();
+    return PPO_OK;
+  }
+  int i = 0;
+  for (const auto& kv : net->tune.best) {
+    if (i < capacity) {
+      int64_t* r = table + 7 * i;
+      for (int k = 0; k < 5; ++k) r[k] = kv.first[k];
+      r[5] = kv.second.first;
+      r[6] = kv.second.second;
+    }
+    ++i;
+  }
+  *entries = i;
   return PPO_OK;
 }
 
