@@ -129,6 +129,17 @@ ppo_status ppo_workspace_size(const ppo_net* net, int op, int max_frames, int ma
  * the start token) -> logits, value; action = the smallest k whose cumulative
  * softmax probability exceeds u[b] (the last action if rounding leaves none),
  * logp = log pi(action).
+ *
+ * `active` (device int32, or NULL = all rows) serves rollouts whose envs stop
+ * at different steps (preemption, Sec. 3) from one captured graph: every row
+ * is computed, but action, logp, value, logits, h_out and c_out are written
+ * only for rows b < *active, read on the device when the kernels run (so the
+ * host may change it between replays); rows >= *active keep their previous
+ * contents (with h_out aliasing h_in, their state).  Values outside
+ * [0, batch] act as the nearer bound.  Rows are independent, so rows
+ * b < *active are bit-for-bit those of a call without the count.  Needs the
+ * act core of at most 2 LSTM layers (every paper configuration); otherwise
+ * PPO_EUNSUPPORTED.
  */
 typedef struct ppo_act_io {
   int batch;                  /* B envs (rows) in this call                     */
@@ -148,6 +159,7 @@ typedef struct ppo_act_io {
   float* h_out;               /* device [L][state_rows][H] out, rows < B (may alias h_in) */
   float* c_out;               /* device [L][state_rows][H] out (may alias c_in) */
   float* logits;              /* device [B][A] out, or NULL                     */
+  const int32_t* active;      /* device [1] rows written (see above), or NULL   */
 } ppo_act_io;
 
 ppo_status ppo_act(ppo_net* net, const ppo_act_io* io, void* ws, size_t ws_bytes, void* stream);

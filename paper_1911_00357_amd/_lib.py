@@ -34,7 +34,7 @@ class ActIO(C.Structure):
                 ("mask", c_void_p), ("h_in", c_void_p), ("c_in", c_void_p), ("u", c_void_p),
                 ("params", c_void_p), ("params_lp", c_void_p), ("action", c_void_p),
                 ("logp", c_void_p), ("value", c_void_p), ("h_out", c_void_p), ("c_out", c_void_p),
-                ("logits", c_void_p)]
+                ("logits", c_void_p), ("active", c_void_p)]
 
 
 class Batch(C.Structure):

@@ -188,9 +188,11 @@ class Net:
 
     # ------------------------------------------------------------------ act
     def act(self, obs, goal, prev_action, mask, h_in, c_in, u, params, params_lp=None,
-            out=None, want_logits=False, state_rows=0):
+            out=None, want_logits=False, state_rows=0, active=None):
         """One act step for B = obs.shape[0] envs.  h_in/c_in [L, state_rows, H]
-        (state_rows = B by default); rows < B are read and written."""
+        (state_rows = B by default); rows < B are read and written.  active: a
+        one-element device int32 tensor; only rows < active[0] (read on the
+        device) are written."""
         B = obs.shape[0]
         SR = state_rows or B
         odt = torch.bfloat16 if self.bf16 else torch.float32
@@ -230,6 +232,9 @@ class Net:
                 raise ValueError(f"out.{nm} holds {out[nm].numel()} elements, needs {need_state}")
         io.h_out, io.c_out = _ptr(out["h"]), _ptr(out["c"])
         io.logits = _ptr(out.get("logits"))
+        if active is not None:
+            _need(active, torch.int32, "active", 1)
+        io.active = _ptr(active)
         ws = self.workspace(L.PPO_OP_ACT, B, 1, dev)
         check(lib().ppo_act(self._h, C.byref(io), _ptr(ws), ws.numel(), _stream(dev)), "ppo_act")
         return out

@@ -640,10 +640,14 @@ ppo_status ppo_act(ppo_net* net, const ppo_act_io* io, void* ws, size_t ws_bytes
   const WsLayout w = plan(net, B, 1, false);
   if (!ws || ws_bytes < w.total) return fail(PPO_EWORKSPACE, "workspace needs %zu bytes", w.total);
   if (!al256(ws)) return fail(PPO_EWORKSPACE, "workspace must be 256-byte aligned");
+  const int H = d.hidden, L = d.lstm_layers, A = d.num_actions;
+  bool fused = L <= 2;
+  for (int l = 0; l < L; ++l) fused = fused && act_layer_supported(l == 0 ? net->din0 : H, H, B);
+  if (io->active && !fused)
+    return fail(PPO_EUNSUPPORTED, "a device row count needs the one-launch-per-layer core (at most 2 layers)");
   hipStream_t s = strm(stream);
   Ctx c{net, &w, (char*)ws, io->params, io->params_lp, nullptr, s, B};
   c.keep_u = false;
-  const int H = d.hidden, L = d.lstm_layers, A = d.num_actions;
   // frames -> encoder -> features
   launch_prep(io->obs, net->prec, nullptr, B, d.in_ch, d.in_hw, d.in_hw, d.avgpool, c.at(w.x0), s);
   const float* feat = encoder_fwd(c);
@@ -654,8 +658,6 @@ ppo_status ppo_act(ppo_net* net, const ppo_act_io* io, void* ws, size_t ws_bytes
              d.vis_hidden, net->flat, epi(zh, ld0, c.pf(net->fc_b), 1),
              false, kSplitKBytes, c.splitk(), s);
   const bool polar = d.goal_mode == PPO_GOAL_POLAR;
-  bool fused = L <= 2;
-  for (int l = 0; l < L; ++l) fused = fused && act_layer_supported(l == 0 ? net->din0 : H, H, B);
   if (fused) {
     // goal / embedding inputs and every layer's masked state in one launch (all
     // of h_in, c_in read before any output is written), then one launch per
@@ -671,10 +673,10 @@ ppo_status ppo_act(ppo_net* net, const ppo_act_io* io, void* ws, size_t ws_bytes
       const float* X = l == 0 ? zh : io->h_out + (size_t)(l - 1) * SR * H;
       launch_lstm_act_layer(net->prec, X, l == 0 ? ld0 : H, din, hm + (size_t)l * B * H, cm + (size_t)l * B * H,
                             c.wt(net->lstm_w[l]), din + H, c.pf(net->lstm_b[l]), B, H,
-                            io->h_out + (size_t)l * SR * H, io->c_out + (size_t)l * SR * H, s);
+                            io->h_out + (size_t)l * SR * H, io->c_out + (size_t)l * SR * H, io->active, s);
     }
     launch_act_head(io->h_out + (size_t)(L - 1) * SR * H, B, H, A, c.pf(net->head_w), c.pf(net->head_b),
-                    io->u, io->action, io->logp, io->value, io->logits, s);
+                    io->u, io->action, io->logp, io->value, io->logits, io->active, s);
     return check_launch();
   }
   launch_embed_fwd(io->goal, io->prev_action, io->mask, nullptr, B, polar,
@@ -702,7 +704,7 @@ ppo_status ppo_act(ppo_net* net, const ppo_act_io* io, void* ws, size_t ws_bytes
     if (!top) launch_copy2d(hdst, ldh, B, H, io->h_out + (size_t)l * SR * H, H, s);
   }
   launch_act_head(io->h_out + (size_t)(L - 1) * SR * H, B, H, A, c.pf(net->head_w), c.pf(net->head_b),
-                  io->u, io->action, io->logp, io->value, io->logits, s);
+                  io->u, io->action, io->logp, io->value, io->logits, nullptr, s);
   return check_launch();
 }
 

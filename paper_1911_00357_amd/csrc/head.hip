@@ -43,9 +43,11 @@ __global__ void __launch_bounds__(256) act_head_kernel(const float* __restrict__
                                                        const float* __restrict__ u,
                                                        int32_t* __restrict__ action,
                                                        float* __restrict__ logp, float* __restrict__ value,
-                                                       float* __restrict__ logits) {
+                                                       float* __restrict__ logits,
+                                                       const int32_t* __restrict__ active) {
   const int r = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
-  if (r >= rows) return;
+  // rows >= *active (a device count, read when the kernel runs) are not written
+  if (r >= rows || (active && r >= *active)) return;
   float o[kMaxA];
   head_dots(htop + (size_t)r * H, W, bias, H, A + 1, o);
   if (lane == 0) {
@@ -74,9 +76,9 @@ __global__ void __launch_bounds__(256) act_head_kernel(const float* __restrict__
 
 void launch_act_head(const float* htop, int rows, int H, int A, const float* W, const float* b,
                      const float* u, int32_t* action, float* logp, float* value, float* logits,
-                     hipStream_t s) {
+                     const int32_t* active, hipStream_t s) {
   hipLaunchKernelGGL(act_head_kernel, dim3(cdiv(rows, 4)), dim3(256), 0, s, htop, rows, H, A, W, b, u,
-                     action, logp, value, logits);
+                     action, logp, value, logits, active);
 }
 
 // PPO loss terms of one frame (Eq. 2 with ratio r = exp(logp - logp_old);

@@ -188,12 +188,12 @@ void launch_act_core_prep(const float* goal, const int32_t* prev_a, const float*
 bool act_layer_supported(int din, int H, int B);
 void launch_lstm_act_layer(int prec, const float* X, int ldx, int din, const float* HM, const float* CM,
                            const void* W, int ldw, const float* bias, int B, int H, float* h_out, float* c_out,
-                           hipStream_t s);
+                           const int32_t* active, hipStream_t s);
 
 // head.hip
 void launch_act_head(const float* htop, int rows, int H, int A, const float* W, const float* b,
                      const float* u, int32_t* action, float* logp, float* value, float* logits,
-                     hipStream_t s);
+                     const int32_t* active, hipStream_t s);
 void launch_loss_head(const float* htop, int F, int H, int A, const float* W, const float* b,
                       const int32_t* src, const int32_t* actions, const float* logp_old, const float* adv,
                       const float* ret, const float* wf, float clip, float vcoef, float ecoef,

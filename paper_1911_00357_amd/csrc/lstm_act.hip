@@ -8,7 +8,9 @@
 //                          state (all read before any layer writes its
 //                          output, so h_out / c_out may alias h_in / c_in);
 //   lstm_act_layer_kernel  one layer: gates = [x | m h] [W_ih | W_hh]^T + b
-//                          and the cell, per workgroup for U hidden units.
+//                          and the cell, per workgroup for U hidden units;
+//                          with a device row count, only the rows below it
+//                          are written.
 //
 // The layer kernel keeps its 4U weight rows in registers (lane s of a gate
 // column holds k = s + TPC*i) and forms each gate with FMAs and a lane
@@ -63,7 +65,8 @@ __global__ void __launch_bounds__(256) lstm_act_layer_kernel(const float* __rest
                                                              const float* __restrict__ HM,
                                                              const float* __restrict__ CM, const TW* __restrict__ W,
                                                              int ldw, const float* __restrict__ bias, int B, int H,
-                                                             float* __restrict__ h_out, float* __restrict__ c_out) {
+                                                             float* __restrict__ h_out, float* __restrict__ c_out,
+                                                             const int32_t* __restrict__ active) {
   extern __shared__ float gates[];  // [B][4U]
   constexpr int TPC = 64 / U;
   constexpr bool BF = sizeof(TW) == 2;
@@ -118,7 +121,9 @@ __global__ void __launch_bounds__(256) lstm_act_layer_kernel(const float* __rest
     for (int i = 0; i < KMAX; ++i) xv[i] = xn[i];
   }
   __syncthreads();
-  for (int it = threadIdx.x; it < B * U; it += 256) {
+  // rows >= *active (a device count, read when the kernel runs) keep their state
+  const int nw = active ? min(max(*active, 0), B) : B;
+  for (int it = threadIdx.x; it < nw * U; it += 256) {
     const int r = it / U, u = it - r * U, j = j0 + u;
     const float* gr = gates + r * 4 * U + u;
     const bool first = it == it0;
@@ -166,7 +171,7 @@ bool act_layer_supported(int din, int H, int B) {
 
 void launch_lstm_act_layer(int prec, const float* X, int ldx, int din, const float* HM, const float* CM,
                            const void* W, int ldw, const float* bias, int B, int H, float* h_out, float* c_out,
-                           hipStream_t s) {
+                           const int32_t* active, hipStream_t s) {
   const int U = act_units(H);
   const int kpt = cdiv(din + H, 64 / U);
   const int kmax = kpt <= 8 ? 8 : kpt <= 16 ? 16 : kpt <= 32 ? 32 : 64;
@@ -175,6 +180,6 @@ void launch_lstm_act_layer(int prec, const float* X, int ldx, int din, const flo
   else k = U == 2 ? act_kernel_k<float, 2>(kmax) : act_kernel_k<float, 1>(kmax);
   const size_t shmem = (size_t)B * 4 * U * sizeof(float);
   void* args[] = {(void*)&X, (void*)&ldx, (void*)&din, (void*)&HM, (void*)&CM, (void*)&W, (void*)&ldw,
-                  (void*)&bias, (void*)&B, (void*)&H, (void*)&h_out, (void*)&c_out};
+                  (void*)&bias, (void*)&B, (void*)&H, (void*)&h_out, (void*)&c_out, (void*)&active};
   hipLaunchKernel(k, dim3(H / U), dim3(256), args, shmem, s);
 }
