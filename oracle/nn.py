@@ -72,6 +72,35 @@ def conv2d_backward(x, w, s, p, dy, need_dx=True):
     return dx, dw
 
 
+def conv2d_grouped(x, w, s, p, groups):
+    """Grouped convolution (the aggregated transform of ResNeXt): input and
+    output channels are split into `groups` equal consecutive slices, and
+    output slice g is the convolution of input slice g with its own filters
+    w[g*O/G : (g+1)*O/G], each of which reads only C/G input channels."""
+    if groups == 1:
+        return conv2d(x, w, s, p)
+    C, O = x.shape[1], w.shape[0]
+    cg, og = C // groups, O // groups
+    assert C == cg * groups and O == og * groups and w.shape[1] == cg
+    return np.concatenate([conv2d(x[:, g * cg:(g + 1) * cg], w[g * og:(g + 1) * og], s, p)
+                           for g in range(groups)], axis=1)
+
+
+def conv2d_grouped_backward(x, w, s, p, dy, groups, need_dx=True):
+    """Gradients of conv2d_grouped: each slice's own convolution gradient."""
+    if groups == 1:
+        return conv2d_backward(x, w, s, p, dy, need_dx)
+    C, O = x.shape[1], w.shape[0]
+    cg, og = C // groups, O // groups
+    dxs, dws = [], []
+    for g in range(groups):
+        dx, dw = conv2d_backward(x[:, g * cg:(g + 1) * cg], w[g * og:(g + 1) * og], s, p,
+                                 dy[:, g * og:(g + 1) * og], need_dx)
+        dxs.append(dx)
+        dws.append(dw)
+    return (np.concatenate(dxs, axis=1) if need_dx else None), np.concatenate(dws, axis=0)
+
+
 # ------------------------------------------------------------------ GroupNorm
 def group_norm(x, gamma, beta, G, eps=GN_EPS):
     """Normalise each (sample, group) over its C/G channels and all pixels
@@ -97,6 +126,36 @@ def group_norm_backward(cache, gamma, dy):
     m2 = (dxhat * xh).mean(axis=2, keepdims=True)
     dx = (rstd * (dxhat - m1 - xh * m2)).reshape(B, C, H, W)
     return dx, dgamma, dbeta
+
+
+# ------------------------------------------------------------ squeeze-excite
+def sigmoid(x):
+    return 1.0 / (1.0 + np.exp(-x))
+
+
+def se_squeeze(y):
+    """Per-sample, per-channel mean over the pixels: [B,C,H,W] -> [B,C]."""
+    return y.mean(axis=(2, 3))
+
+
+def se_excite(y, s):
+    """Each channel scaled by its gate: y[b,c,:,:] * s[b,c]."""
+    return y * s[:, :, None, None]
+
+
+def se_excite_backward(y, s, dout):
+    """Gradients of se_excite with respect to y (the direct path) and s."""
+    return dout * s[:, :, None, None], (dout * y).sum(axis=(2, 3))
+
+
+def linear(x, w, b):
+    """x [B,I] -> x w^T + b, w [O,I]."""
+    return np.tensordot(x, w, axes=([1], [1])) + b
+
+
+def linear_backward(x, w, dy):
+    """Gradients of linear: (dx, dw, db)."""
+    return np.tensordot(dy, w, axes=([1], [0])), np.tensordot(dy, x, axes=([0], [0])), dy.sum(axis=0)
 
 
 # -------------------------------------------------------------------- pooling

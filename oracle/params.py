@@ -2,7 +2,10 @@
 
 Order of tensors (one contiguous float vector): encoder trunk (convolution
 weights stored output-channel, kernel-row, kernel-column, input-channel,
-each followed by its GroupNorm gamma and beta), visual FC weight (input
+each followed by its GroupNorm gamma and beta; a grouped convolution stores
+the input channels of its output channel's group only; an SE-ResNeXt block's
+two squeeze-excite FC weights and biases follow its third convolution),
+visual FC weight (input
 index in channel, row, column order) and bias, goal FC (polar goal only),
 previous-action embedding (if present), per LSTM layer the stacked
 [W_ih | W_hh] matrix with gate row blocks i, f, g, o and one bias, and the
@@ -33,15 +36,25 @@ def _arch(net):
         yield "stem.gn.g", (base,), False
         yield "stem.gn.b", (base,), False
         cin = base
+        se = net.trunk == "seresnext"
         for s in range(4):
             w = base << s
+            # bottleneck width; SE-ResNeXt: twice the ResNet's, split into groups
+            m = 2 * w if se else w
+            cg = m // net.cardinality if se else m
             for j in range(net.blocks[s]):
                 p = "s%d.b%d." % (s, j)
-                for nm, shp in (("c1", (w, 1, 1, cin)), ("c2", (w, 3, 3, w)),
-                                ("c3", (4 * w, 1, 1, w))):
+                for nm, shp in (("c1", (m, 1, 1, cin)), ("c2", (m, 3, 3, cg)),
+                                ("c3", (4 * w, 1, 1, m))):
                     yield p + nm, shp, True
                     yield p + nm + ".gn.g", (shp[0],), False
                     yield p + nm + ".gn.b", (shp[0],), False
+                if se:
+                    r = 4 * w // net.se_reduction
+                    yield p + "se1.w", (r, 4 * w), False
+                    yield p + "se1.b", (r,), False
+                    yield p + "se2.w", (4 * w, r), False
+                    yield p + "se2.b", (4 * w,), False
                 if j == 0:
                     yield p + "ds", (4 * w, 1, 1, cin), True
                     yield p + "ds.gn.g", (4 * w,), False

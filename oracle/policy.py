@@ -1,10 +1,14 @@
 """The agent of the paper's appendix "Agent Design", in float64.
 
   visual encoder  2x2 average pool, then either the tiny two-conv trunk or
-                  the ResNet50 bottleneck layout with every width halved and
-                  every BatchNorm replaced by GroupNorm (Sec. 4 "Agent";
-                  appendix "Visual Encoder"), then a 3x3 compression conv to
-                  a 128 x h x w map
+                  the ResNet50 or SE-ResNeXt50 bottleneck layout with every
+                  width halved and every BatchNorm replaced by GroupNorm
+                  (Sec. 4 "Agent"; appendix "Visual Encoder"), then a 3x3
+                  compression conv to a 128 x h x w map.  SE-ResNeXt blocks
+                  (Xie et al., Hu et al.): bottleneck twice the ResNet's width
+                  with its 3x3 convolution in `cardinality` groups, and a
+                  squeeze-excite gate (reduction r) scaling the residual
+                  branch per channel before the shortcut is added
   policy          flatten, FC to the hidden size (+ReLU), concatenated with
                   the goal encoding ([d, cos(theta), sin(theta)] -> FC-32)
                   and a 32-d embedding of the previous action (index 0 is the
@@ -15,7 +19,12 @@ stem 7x7/2 + GroupNorm + ReLU + 3x3/2 max pool; stride on the bottleneck's
 3x3; projection shortcut (1x1/s conv + GroupNorm) on the first block of a
 stage; convolutions without bias; 16 groups; compression conv followed by
 GroupNorm and ReLU; ReLU after the visual FC; the episode mask m_t
-multiplies h and c of every layer and selects the start token.
+multiplies h and c of every layer and selects the start token.  SE-ResNeXt
+(the paper gives only its name and the halving): the ResNeXt50 32x4d block
+with every width halved keeps 4-channel groups at the first stage, i.e. 16
+groups of a bottleneck 2w wide; squeeze-excite reduction 16 with biased FCs,
+its gate applied to the branch after the block's last GroupNorm, before the
+shortcut is added; stride, shortcut and stem as in the ResNet.
 
 Parity pins: forward against torch CPU float64 library modules, backward
 against torch autograd and central finite differences (tests/test_oracle_policy.py).
@@ -108,28 +117,55 @@ def _operand(x, key, q, decide, record):
     return q(x)
 
 
-def _conv_gn(P, net, name, x, s, p, relu, tape, decide=None, q=None, record=None, outputs=True):
+def _conv_gn(P, net, name, x, s, p, relu, tape, decide=None, q=None, record=None, outputs=True, groups=1):
     xq = _operand(x, "q:" + name, q, decide, record)
-    u = nn.conv2d(xq, P[name], s, p)
+    u = nn.conv2d_grouped(xq, P[name], s, p, groups)
     y, gc = nn.group_norm(u, P[name + ".gn.g"], P[name + ".gn.b"], net.gn_groups)
     m = None
     if relu:
         y, m = _relu(y, name, decide, record, outputs)
     if tape is not None:
-        tape[name] = (xq, s, p, gc, m)
+        tape[name] = (xq, s, p, gc, m, groups)
     return y
 
 
 def _conv_gn_bwd(P, name, dy, tape, grads, need_dx=True):
-    x, s, p, gc, m = tape[name]
+    x, s, p, gc, m, groups = tape[name]
     if m is not None:
         dy = dy * m
     du, dg, db = nn.group_norm_backward(gc, P[name + ".gn.g"], dy)
-    dx, dw = nn.conv2d_backward(x, P[name], s, p, du, need_dx)
+    dx, dw = nn.conv2d_grouped_backward(x, P[name], s, p, du, groups, need_dx)
     grads[name] = grads.get(name, 0) + dw
     grads[name + ".gn.g"] = grads.get(name + ".gn.g", 0) + dg
     grads[name + ".gn.b"] = grads.get(name + ".gn.b", 0) + db
     return dx
+
+
+def _se(P, pre, y, tape, decide, record, outputs):
+    """Squeeze-excite gate of an SE-ResNeXt block (Hu et al.) on its residual
+    branch y: z = per-channel pixel mean, h = ReLU(se1 z), s = sigmoid(se2 h),
+    y scaled by s per channel.  The two FCs stay in float64 in the precision
+    form (like the goal FC and the heads); the hidden ReLU is decision
+    pre + 'se'."""
+    z = nn.se_squeeze(y)
+    h, m = _relu(nn.linear(z, P[pre + "se1.w"], P[pre + "se1.b"]), pre + "se", decide, record, outputs)
+    s = nn.sigmoid(nn.linear(h, P[pre + "se2.w"], P[pre + "se2.b"]))
+    if tape is not None:
+        tape[pre + "se"] = (y, z, h, m, s)
+    return nn.se_excite(y, s)
+
+
+def _se_bwd(P, pre, d, tape, grads):
+    y, z, h, m, s = tape[pre + "se"]
+    dy, ds = nn.se_excite_backward(y, s, d)
+    da2 = ds * s * (1.0 - s)
+    dh, dw2, db2 = nn.linear_backward(h, P[pre + "se2.w"], da2)
+    da1 = dh * m
+    dz, dw1, db1 = nn.linear_backward(z, P[pre + "se1.w"], da1)
+    for k, v in (("se1.w", dw1), ("se1.b", db1), ("se2.w", dw2), ("se2.b", db2)):
+        grads[pre + k] = grads.get(pre + k, 0) + v
+    hw = y.shape[2] * y.shape[3]
+    return dy + dz[:, :, None, None] / hw
 
 
 def _blocks(net):
@@ -144,8 +180,9 @@ def _blocks(net):
 def encoder_forward(P, net, x, tape=None, decide=None, quant=None, record=None, record_outputs=True):
     """x: [F, C, h, w] after the optional pooling -> features [F, flat_dim]
     in channel, row, column order.  decide: optional imposed decisions keyed
-    by unit name (ReLU masks, NCHW), 'sS.bJ.out' (block output ReLU) and
-    'maxpool' (winner index).  P must already be quantize_params(.., quant).
+    by unit name (ReLU masks, NCHW), 'sS.bJ.out' (block output ReLU),
+    'sS.bJ.se' (squeeze-excite hidden ReLU, [F, C/r]) and 'maxpool' (winner
+    index).  P must already be quantize_params(.., quant).
     record: optional dict of lists receiving each ReLU's pre-activation
     (key) and output (key + ':out', unless record_outputs is False) and the
     max-pool input ('maxpool')."""
@@ -162,10 +199,17 @@ def encoder_forward(P, net, x, tape=None, decide=None, quant=None, record=None, 
     a, mc = nn.max_pool3s2(a, None if decide is None else decide.get("maxpool"))
     if tape is not None:
         tape["maxpool"] = mc
+    se = net.trunk == "seresnext"
     for pre, st, proj in _blocks(net):
         y = cg(pre + "c1", a, 1, 0, True)
-        y = cg(pre + "c2", y, st, 1, True)
+        if se:
+            y = _conv_gn(P, net, pre + "c2", y, st, 1, True, tape, decide, q, record, record_outputs,
+                         groups=net.cardinality)
+        else:
+            y = cg(pre + "c2", y, st, 1, True)
         y = cg(pre + "c3", y, 1, 0, False)
+        if se:
+            y = _se(P, pre, y, tape, decide, record, record_outputs)
         sc = cg(pre + "ds", a, st, 0, False) if proj else a
         a, m = _relu(y + sc, pre + "out", decide, record, record_outputs)
         if tape is not None:
@@ -188,7 +232,8 @@ def encoder_backward(P, net, tape, dfeat, grads):
     d = _conv_gn_bwd(P, "compress", d, tape, grads)
     for pre, st, proj in reversed(_blocks(net)):
         d = d * tape[pre + "out"]
-        dy = _conv_gn_bwd(P, pre + "c3", d, tape, grads)
+        dy = _se_bwd(P, pre, d, tape, grads) if net.trunk == "seresnext" else d
+        dy = _conv_gn_bwd(P, pre + "c3", dy, tape, grads)
         dy = _conv_gn_bwd(P, pre + "c2", dy, tape, grads)
         dx = _conv_gn_bwd(P, pre + "c1", dy, tape, grads)
         dx = dx + (_conv_gn_bwd(P, pre + "ds", d, tape, grads) if proj else d)

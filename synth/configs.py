@@ -25,11 +25,14 @@ from typing import Tuple
 @dataclass(frozen=True)
 class NetDesc:
     """Network shape.  trunk='tiny' is the two-conv encoder of the tiny
-    workload; trunk='resnet' is the halved ResNet50 bottleneck layout."""
+    workload; trunk='resnet' is the halved ResNet50 bottleneck layout;
+    trunk='seresnext' the halved SE-ResNeXt50 one (bottleneck twice as wide,
+    its 3x3 convolution split into `cardinality` groups, a squeeze-excite
+    gate with reduction `se_reduction` on the residual branch)."""
     in_ch: int = 4
     in_hw: int = 256
     avgpool: bool = True
-    trunk: str = "resnet"            # 'tiny' | 'resnet'
+    trunk: str = "resnet"            # 'tiny' | 'resnet' | 'seresnext'
     tiny_ch: Tuple[int, int] = (16, 32)
     base_width: int = 32
     blocks: Tuple[int, int, int, int] = (3, 4, 6, 3)
@@ -42,8 +45,15 @@ class NetDesc:
     lstm_layers: int = 2
     hidden: int = 512
     num_actions: int = 4
+    cardinality: int = 16            # seresnext: groups of the 3x3 convolution
+    se_reduction: int = 16           # seresnext: squeeze-excite hidden width = C / se_reduction
 
     # ---- derived shapes (pure bookkeeping) ----
+    def mid_width(self, s: int) -> int:
+        """Bottleneck width of stage s (output width 4 * base_width * 2**s)."""
+        w = self.base_width << s
+        return 2 * w if self.trunk == "seresnext" else w
+
     @property
     def enc_hw(self) -> int:
         """Spatial size after the optional 2x2 average pool."""
@@ -104,6 +114,7 @@ TINY_NET = NetDesc(in_hw=32, avgpool=False, trunk="tiny", gn_groups=8,
                    lstm_layers=1, hidden=64)
 RESNET_NET = NetDesc()
 RESNET_NET_128 = NetDesc(in_hw=128)
+SERESNEXT_NET = NetDesc(trunk="seresnext")
 
 # The five workloads: tiny FP32; paper-shaped worker in FP32 and in BF16;
 # the differentiation form at 128x128 frames; the ragged batching form.
@@ -114,5 +125,7 @@ C2 = Workload("resnet50h_bf16_T128_N4", RESNET_NET, T=128, N=4, dtype="bf16")
 C3 = Workload("resnet50h_bf16_128px_T128_N16", RESNET_NET_128, T=128, N=16, dtype="bf16")
 C4 = Workload("resnet50h_bf16_ragged_T128_N64", RESNET_NET, T=128, N=64, dtype="bf16",
               ragged=True)
+# the SE-ResNeXt50 encoder (halved widths) in the default worker configuration
+C5 = Workload("seresnext50h_bf16_T128_N4", SERESNEXT_NET, T=128, N=4, dtype="bf16")
 
-WORKLOADS = {"C0": C0, "C1": C1, "C2": C2, "C3": C3, "C4": C4}
+WORKLOADS = {"C0": C0, "C1": C1, "C2": C2, "C3": C3, "C4": C4, "C5": C5}

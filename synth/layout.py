@@ -15,6 +15,11 @@ Order (tensor, shape):
                    c3 [4w][1][1][w], gn3.g/b [4w],
                    (block 0 only) ds [4w][1][1][cin], ds.gn.g/b [4w];
                  compress [cc][3][3][8*w0*4], compress.gn.g/b [cc]
+  seresnext    : as resnet with m = 2w: c1 [m][1][1][cin], c2 [m][3][3][m/card]
+                 (grouped: output channel o reads input channels of group
+                 o // (m/card)), c3 [4w][1][1][m], each with its GroupNorm, then
+                 se1.w [4w/r][4w], se1.b [4w/r], se2.w [4w][4w/r], se2.b [4w],
+                 then (block 0 only) ds
   visual FC    : fc.w [vis_hidden][flat_dim] (input index in C,H,W order), fc.b
   goal FC      : goal.w [goal_dim][3], goal.b [goal_dim]     (polar goal only)
   prev action  : emb [A+1][prev_act_dim]                     (if prev_act_dim > 0)
@@ -68,16 +73,24 @@ def tensor_list(net: NetDesc) -> List[Tensor]:
         conv("enc.stem", w0, 7, net.in_ch)
         gn("enc.stem.gn", w0)
         cin = w0
+        se = net.trunk == "seresnext"
         for s, nb in enumerate(net.blocks):
             w = w0 * (2 ** s)
+            m = net.mid_width(s)
             for j in range(nb):
                 p = f"enc.s{s}.b{j}"
-                conv(p + ".c1", w, 1, cin)
-                gn(p + ".gn1", w)
-                conv(p + ".c2", w, 3, w)
-                gn(p + ".gn2", w)
-                conv(p + ".c3", 4 * w, 1, w)
+                conv(p + ".c1", m, 1, cin)
+                gn(p + ".gn1", m)
+                conv(p + ".c2", m, 3, m // net.cardinality if se else m)
+                gn(p + ".gn2", m)
+                conv(p + ".c3", 4 * w, 1, m)
                 gn(p + ".gn3", 4 * w)
+                if se:
+                    r = 4 * w // net.se_reduction
+                    add(p + ".se1.w", (r, 4 * w), "fc", 4 * w)
+                    add(p + ".se1.b", (r,), "bias")
+                    add(p + ".se2.w", (4 * w, r), "fc", r)
+                    add(p + ".se2.b", (4 * w,), "bias")
                 if j == 0:
                     conv(p + ".ds", 4 * w, 1, cin)
                     gn(p + ".ds.gn", 4 * w)

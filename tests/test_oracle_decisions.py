@@ -19,7 +19,7 @@ import torch
 from oracle import nn, params, policy, ppo
 from synth import rollout as R
 from tests import torch_ref
-from tests.nets import MINI_RESNET, TINY_PLUS, wl
+from tests.nets import MINI_RESNET, MINI_SERESNEXT, TINY_PLUS, wl
 from tests.test_oracle_policy import random_minibatch
 
 
@@ -67,7 +67,8 @@ def test_round_bf16_brute_force_nearest_ties_even():
 
 # ------------------------------------------------------------ decisions
 @pytest.mark.parametrize("quant", [None, "bf16"])
-@pytest.mark.parametrize("net,seed", [(TINY_PLUS, 3), (MINI_RESNET, 4)], ids=["tiny+", "mini_resnet"])
+@pytest.mark.parametrize("net,seed", [(TINY_PLUS, 3), (MINI_RESNET, 4), (MINI_SERESNEXT, 5)],
+                         ids=["tiny+", "mini_resnet", "mini_seresnext"])
 def test_imposing_own_decisions_reproduces_the_free_run(net, seed, quant):
     flat, mb = _case(net, seed)
     s0, g0, _, dec = _free_run(net, flat, mb, quant)
@@ -86,9 +87,9 @@ def _fd_check(net, flat, mb, dec, g, seed, n_dir=4):
         assert abs(fd - g @ d) <= 1e-6 * max(abs(fd), 1e-4), (fd, g @ d)
 
 
-@pytest.mark.parametrize("key", ["s1.b0.c2", "s0.b0.out", "compress"])
+@pytest.mark.parametrize("key", ["s1.b0.c2", "s0.b0.out", "compress", "s1.b0.se"])
 def test_flipped_relu_changes_one_element_by_its_preactivation(key):
-    net = MINI_RESNET
+    net = MINI_SERESNEXT if key.endswith(".se") else MINI_RESNET
     flat, mb = _case(net, 5)
     s0, g0, rec, dec = _free_run(net, flat, mb)
     pre = rec[key]
@@ -101,9 +102,9 @@ def test_flipped_relu_changes_one_element_by_its_preactivation(key):
     diff = rec1[key + ":out"] - rec[key + ":out"]
     assert np.count_nonzero(diff) == 1 and diff[j] == (pre[j] if flip[key][j] else -pre[j])
     # the imposed flip is used (the loss moves), and less than a flip far from the kink
-    far = np.unravel_index(np.argmax(np.abs(pre) * (pre < 0)), pre.shape)
+    far = np.unravel_index(np.argmax(np.abs(pre)), pre.shape)
     flip2 = {k: v.copy() for k, v in dec.items()}
-    flip2[key][far] = True
+    flip2[key][far] = ~flip2[key][far]
     s2, _ = ppo.loss_grad(flat, net, wl(net).ppo, mb, decide=flip2, with_grad=False)
     assert 0 < abs(s1[0] - s0[0]) < abs(s2[0] - s0[0])
     _fd_check(net, flat, mb, flip, g1, seed=7)
@@ -153,7 +154,8 @@ def test_flipped_visual_fc_relu():
 
 
 # ------------------------------------------------------- precision form
-@pytest.mark.parametrize("net,seed", [(TINY_PLUS, 11), (MINI_RESNET, 12)], ids=["tiny+", "mini_resnet"])
+@pytest.mark.parametrize("net,seed", [(TINY_PLUS, 11), (MINI_RESNET, 12), (MINI_SERESNEXT, 13)],
+                         ids=["tiny+", "mini_resnet", "mini_seresnext"])
 def test_bf16_form_matches_torch_with_straight_through_rounding(net, seed):
     flat, mb = _case(net, seed)
     s, g = ppo.loss_grad(flat, net, wl(net).ppo, mb, quant="bf16")

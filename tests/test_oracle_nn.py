@@ -111,3 +111,61 @@ def test_log_softmax_vs_torch_and_normalised():
     lp = nn.log_softmax(z)
     np.testing.assert_allclose(lp, F.log_softmax(T64(z), -1).numpy(), rtol=1e-13, atol=1e-13)
     np.testing.assert_allclose(np.exp(lp).sum(-1), 1.0, rtol=1e-14)
+
+
+@pytest.mark.parametrize("C,O,G,H,s", [(8, 8, 2, 9, 1), (16, 16, 4, 10, 2), (32, 32, 16, 8, 2), (6, 9, 3, 7, 1)])
+def test_grouped_conv2d_vs_torch(C, O, G, H, s):
+    """Grouped 3x3 convolution against torch's conv2d(groups=G), forward and
+    autograd; groups=1 is the plain convolution."""
+    x = R.standard_normal((2, C, H, H + 1))
+    w = R.standard_normal((O, C // G, 3, 3))
+    y = nn.conv2d_grouped(x, w, s, 1, G)
+    xt, wt = T64(x).requires_grad_(), T64(w).requires_grad_()
+    yt = F.conv2d(xt, wt, stride=s, padding=1, groups=G)
+    np.testing.assert_allclose(y, yt.detach().numpy(), rtol=1e-12, atol=1e-12)
+    dy = R.standard_normal(y.shape)
+    yt.backward(T64(dy))
+    dx, dw = nn.conv2d_grouped_backward(x, w, s, 1, dy, G)
+    np.testing.assert_allclose(dx, xt.grad.numpy(), rtol=1e-11, atol=1e-11)
+    np.testing.assert_allclose(dw, wt.grad.numpy(), rtol=1e-11, atol=1e-11)
+    # an output channel reads its own group only: zeroing another group's input leaves it unchanged
+    x2 = x.copy()
+    x2[:, C // G:] = 0.0
+    np.testing.assert_array_equal(nn.conv2d_grouped(x2, w, s, 1, G)[:, :O // G], y[:, :O // G])
+
+
+def test_squeeze_excite_vs_torch_and_fd():
+    """The SE gate's pieces (pixel mean, FC, ReLU, FC, sigmoid, channel scale)
+    composed as the encoder does, against torch autograd; the sigmoid against
+    its closed form at 0 and its symmetry."""
+    B, C, r, H = 3, 8, 2, 5
+    y = R.standard_normal((B, C, H, H))
+    w1, b1 = R.standard_normal((r, C)), R.standard_normal(r)
+    w2, b2 = R.standard_normal((C, r)), R.standard_normal(C)
+
+    def fwd(y):
+        z = nn.se_squeeze(y)
+        a1 = nn.linear(z, w1, b1)
+        h = np.maximum(a1, 0.0)
+        s = nn.sigmoid(nn.linear(h, w2, b2))
+        return nn.se_excite(y, s), (z, a1, h, s)
+
+    out, (z, a1, h, s) = fwd(y)
+    tt = [T64(a).requires_grad_() for a in (y, w1, b1, w2, b2)]
+    zt = tt[0].mean(dim=(2, 3))
+    st = torch.sigmoid(F.linear(F.relu(F.linear(zt, tt[1], tt[2])), tt[3], tt[4]))
+    ot = tt[0] * st[:, :, None, None]
+    np.testing.assert_allclose(out, ot.detach().numpy(), rtol=1e-13, atol=1e-13)
+    d = R.standard_normal(out.shape)
+    ot.backward(T64(d))
+    dy, ds = nn.se_excite_backward(y, s, d)
+    da2 = ds * s * (1 - s)
+    dh, dw2, db2 = nn.linear_backward(h, w2, da2)
+    da1 = dh * (a1 > 0)
+    dz, dw1, db1 = nn.linear_backward(z, w1, da1)
+    dy = dy + dz[:, :, None, None] / (H * H)
+    for got, ref in zip((dy, dw1, db1, dw2, db2), tt):
+        np.testing.assert_allclose(got, ref.grad.numpy(), rtol=1e-11, atol=1e-12)
+    assert nn.sigmoid(np.array(0.0)) == 0.5
+    v = R.standard_normal(7)
+    np.testing.assert_allclose(nn.sigmoid(v) + nn.sigmoid(-v), 1.0, rtol=0, atol=1e-15)

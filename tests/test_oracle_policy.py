@@ -12,7 +12,7 @@ import synth
 from oracle import params, policy, ppo
 from synth import rollout as R
 from tests import torch_ref
-from tests.nets import TINY_NET, TINY_PLUS, MINI_RESNET, wl
+from tests.nets import TINY_NET, TINY_PLUS, MINI_RESNET, MINI_SERESNEXT, wl
 
 GOLD = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "paper_facts.json")))
 
@@ -73,7 +73,7 @@ def test_oracle_encoder_shapes_match_paper():
 def test_param_format_readers_agree():
     """The oracle's reader and the generator's reader of the flat format
     place every tensor at the same offset."""
-    for net in (TINY_NET, TINY_PLUS, MINI_RESNET, synth.C1.net, synth.C3.net):
+    for net in (TINY_NET, TINY_PLUS, MINI_RESNET, MINI_SERESNEXT, synth.C1.net, synth.C3.net, synth.C5.net):
         o = params.offsets(net)
         s = synth.tensor_list(net)
         assert params.count(net) == synth.param_count(net)
@@ -82,7 +82,8 @@ def test_param_format_readers_agree():
 
 
 # ----------------------------------------------- loss + gradient vs autograd
-@pytest.mark.parametrize("net", [TINY_NET, TINY_PLUS, MINI_RESNET], ids=["tiny", "tiny+", "mini_resnet"])
+@pytest.mark.parametrize("net", [TINY_NET, TINY_PLUS, MINI_RESNET, MINI_SERESNEXT],
+                         ids=["tiny", "tiny+", "mini_resnet", "mini_seresnext"])
 def test_loss_and_grad_vs_torch_autograd(net):
     w = wl(net)
     flat = R.init_params(net, 1, random_affine=True).astype(np.float64)
@@ -106,8 +107,36 @@ def test_resnet_full_width_forward_vs_torch():
     assert np.linalg.norm(g - g_t) / np.linalg.norm(g_t) < 1e-9
 
 
+def test_seresnext_full_width_forward_vs_torch():
+    """The real-width SE-ResNeXt trunk (16 groups, reduction 16) on one 64x64
+    frame, loss and gradient against the torch model."""
+    from tests.nets import SERESNEXT_64 as net
+    flat = R.init_params(net, 3, random_affine=True).astype(np.float64)
+    mb = random_minibatch(net, 2, 2, seed=4, ragged=False)
+    stats, g = ppo.loss_grad(flat, net, wl(net).ppo, mb)
+    L_t, g_t, _, _ = torch_ref.ppo_loss(net, wl(net).ppo, flat, mb)
+    assert abs(stats[0] - L_t) <= 1e-10 * max(1.0, abs(L_t))
+    assert np.linalg.norm(g - g_t) / np.linalg.norm(g_t) < 1e-9
+
+
+def test_seresnext_shapes():
+    """SE-ResNeXt50 with halved widths: the same 1024 x 4 x 4 backbone output
+    and 2048-d flattened feature as the ResNet, 16 groups of 4 channels in the
+    first stage's 3x3, SE hidden width C/16."""
+    net = synth.C5.net
+    P = params.unpack(net, R.init_params(net, 0))
+    assert P["s0.b0.c2"].shape == (64, 4, 3, 3) and P["s3.b0.c2"].shape == (512, 32, 3, 3)
+    assert P["s0.b0.se1.w"].shape == (8, 128) and P["s3.b2.se2.w"].shape == (1024, 64)
+    x = policy.prep_obs(net, np.random.default_rng(0).random((1, 4, 256, 256)))
+    tape = {}
+    feat = policy.encoder_forward(P, net, x, tape)
+    assert list(tape["s3.b2.out"].shape[1:]) == gold("backbone_out")
+    assert feat.shape == (1, gold("flatten_dim"))
+
+
 # ------------------------------------------------------ finite differences
-@pytest.mark.parametrize("net,seed", [(TINY_PLUS, 5), (MINI_RESNET, 6)], ids=["tiny+", "mini_resnet"])
+@pytest.mark.parametrize("net,seed", [(TINY_PLUS, 5), (MINI_RESNET, 6), (MINI_SERESNEXT, 8)],
+                         ids=["tiny+", "mini_resnet", "mini_seresnext"])
 def test_grad_central_finite_differences(net, seed):
     w = wl(net)
     flat = R.init_params(net, seed, random_affine=True).astype(np.float64)

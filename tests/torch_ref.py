@@ -43,8 +43,8 @@ def unpack(net, flat, requires_grad=True):
     return flat_t, P
 
 
-def _cgn(P, net, x, conv, gn, s, p, relu, q=lambda a: a):
-    y = F.conv2d(q(x), q(P[conv]), stride=s, padding=p)
+def _cgn(P, net, x, conv, gn, s, p, relu, q=lambda a: a, groups=1):
+    y = F.conv2d(q(x), q(P[conv]), stride=s, padding=p, groups=groups)
     y = F.group_norm(y, net.gn_groups, P[gn + ".g"], P[gn + ".b"], eps=GN_EPS)
     return F.relu(y) if relu else y
 
@@ -65,9 +65,15 @@ def encoder(P, net, obs, quant=None):
         for j in range(nb):
             p = f"enc.s{s}.b{j}"
             st = 2 if (j == 0 and s > 0) else 1
+            se = net.trunk == "seresnext"
             y = cgn(x, p + ".c1", p + ".gn1", 1, 0, True)
-            y = cgn(y, p + ".c2", p + ".gn2", st, 1, True)
+            y = _cgn(P, net, y, p + ".c2", p + ".gn2", st, 1, True, q, net.cardinality if se else 1)
             y = cgn(y, p + ".c3", p + ".gn3", 1, 0, False)
+            if se:     # squeeze-excite: pooled channels -> FC -> ReLU -> FC -> sigmoid gate
+                z = F.adaptive_avg_pool2d(y, 1).flatten(1)
+                g = torch.sigmoid(F.linear(F.relu(F.linear(z, P[p + ".se1.w"], P[p + ".se1.b"])),
+                                           P[p + ".se2.w"], P[p + ".se2.b"]))
+                y = y * g[:, :, None, None]
             sc = cgn(x, p + ".ds", p + ".ds.gn", st, 0, False) if j == 0 else x
             x = F.relu(y + sc)
     x = cgn(x, "enc.compress", "enc.compress.gn", 1, 1, True)
