@@ -68,16 +68,25 @@ typedef enum {
 } ppo_status;
 
 enum { PPO_F32 = 0, PPO_BF16 = 1 };
-enum { PPO_TRUNK_TINY = 0, PPO_TRUNK_RESNET = 1 };
+enum { PPO_TRUNK_TINY = 0, PPO_TRUNK_RESNET = 1, PPO_TRUNK_SERESNEXT = 2 };
 enum { PPO_GOAL_RAW = 0, PPO_GOAL_POLAR = 1 };
 enum { PPO_OP_ACT = 0, PPO_OP_LEARN = 1, PPO_OP_LOSS = 2 };
 
-/* Network shape (appendix "Agent Design"; Sec. 4 "Agent"). */
+/* Network shape (appendix "Agent Design"; Sec. 4 "Agent").  The visual
+ * encoder is the tiny two-conv trunk, or ResNet50 or SE-ResNeXt50 (Sec. 6,
+ * Table 1) with every width halved and GroupNorm.  An SE-ResNeXt bottleneck
+ * of stage s (w = base_width 2^s) is: 1x1 conv to 2w, 3x3 conv in
+ * `cardinality` groups (stride on the first block of stages 1-3), 1x1 conv to
+ * 4w, each with GroupNorm (and ReLU but the last), then a squeeze-excite gate
+ * s = sigmoid(W2 relu(W1 mean_pixels(y) + b1) + b2) with W1 [4w/r][4w],
+ * scaling the branch per channel before the shortcut is added and the ReLU;
+ * its parameters follow the third convolution's in the flat format (se1.w,
+ * se1.b, se2.w, se2.b). */
 typedef struct ppo_net_desc {
   int in_ch;          /* frame channels (4: RGB-D)                              */
   int in_hw;          /* frame height = width (256)                             */
   int avgpool;        /* 1: 2x2 average pool before the trunk                   */
-  int trunk;          /* PPO_TRUNK_TINY | PPO_TRUNK_RESNET                       */
+  int trunk;          /* PPO_TRUNK_TINY | PPO_TRUNK_RESNET | PPO_TRUNK_SERESNEXT  */
   int tiny_ch[2];     /* tiny trunk widths (16, 32)                             */
   int base_width;     /* resnet stem width; stage widths w0*2^s (32)            */
   int blocks[4];      /* bottlenecks per stage (3, 4, 6, 3)                     */
@@ -91,6 +100,8 @@ typedef struct ppo_net_desc {
   int hidden;         /* LSTM hidden size (512)                                 */
   int num_actions;    /* 4                                                      */
   int dtype;          /* PPO_F32 | PPO_BF16: GEMM operand precision             */
+  int cardinality;    /* seresnext: groups of each bottleneck's 3x3 convolution (16) */
+  int se_reduction;   /* seresnext: squeeze-excite hidden width = C / se_reduction (16) */
 } ppo_net_desc;
 
 typedef struct ppo_net ppo_net;
@@ -328,6 +339,12 @@ ppo_status ppo_adam_step(float* master, const float* grad, float* m, float* v, v
  *   kind 6: LSTM layer `index`'s masked previous state m_t h_{t-1}, float32
  *           [F][H] (the recurrent operand of the gate products); dims = {H, ..}
  *   kind 7: LSTM layer `index`'s output h_t, float32 [F][H]; dims = {H, ..}
+ *   kind 8: squeeze-excite gate of bottleneck block `index` (SE-ResNeXt):
+ *           its hidden pre-activation W1 z + b1, float32 [F][R]; dims = {R, C, 0, 0}
+ *   kind 9 (op PPO_OP_LEARN): the operand buffers of ppo_bench_unit_gemm,
+ *           float32 NHWC: index 0 the unit's input, 1 the gradient at its
+ *           output, 2 the output written (forward / data gradient);
+ *           dims[0] = floats each holds
  *   kind 4 (op PPO_OP_LEARN): the learner's recurrence status, one uint32;
  *           nonzero after a call means a device-wide barrier of the persistent
  *           LSTM launches gave up waiting (bounded wait) and the call's

@@ -12,7 +12,7 @@ P_i32 = C.POINTER(C.c_int32)
 
 PPO_OK, PPO_EINVAL, PPO_ESHAPE, PPO_EUNSUPPORTED, PPO_EWORKSPACE, PPO_EDEVICE = 0, -1, -2, -3, -4, -5
 PPO_F32, PPO_BF16 = 0, 1
-PPO_TRUNK_TINY, PPO_TRUNK_RESNET = 0, 1
+PPO_TRUNK_TINY, PPO_TRUNK_RESNET, PPO_TRUNK_SERESNEXT = 0, 1, 2
 PPO_GOAL_RAW, PPO_GOAL_POLAR = 0, 1
 PPO_OP_ACT, PPO_OP_LEARN, PPO_OP_LOSS = 0, 1, 2
 PPO_TIMER_ALL_UNITS = -2
@@ -26,7 +26,8 @@ class NetDesc(C.Structure):
                 ("tiny_ch", c_int * 2), ("base_width", c_int), ("blocks", c_int * 4),
                 ("gn_groups", c_int), ("compress_ch", c_int), ("vis_hidden", c_int),
                 ("goal_mode", c_int), ("goal_dim", c_int), ("prev_act_dim", c_int),
-                ("lstm_layers", c_int), ("hidden", c_int), ("num_actions", c_int), ("dtype", c_int)]
+                ("lstm_layers", c_int), ("hidden", c_int), ("num_actions", c_int), ("dtype", c_int),
+                ("cardinality", c_int), ("se_reduction", c_int)]
 
 
 class ActIO(C.Structure):

@@ -44,12 +44,18 @@ def _stream(device=None):
 
 def desc_from(spec, dtype: str) -> L.NetDesc:
     """Build the C description from any object with the network fields
-    (in_ch, in_hw, avgpool, trunk 'tiny'|'resnet', tiny_ch, base_width, blocks,
-    gn_groups, compress_ch, vis_hidden, goal_mode 'raw'|'polar', goal_dim,
-    prev_act_dim, lstm_layers, hidden, num_actions)."""
+    (in_ch, in_hw, avgpool, trunk 'tiny'|'resnet'|'seresnext', tiny_ch,
+    base_width, blocks, gn_groups, compress_ch, vis_hidden, goal_mode
+    'raw'|'polar', goal_dim, prev_act_dim, lstm_layers, hidden, num_actions,
+    and for seresnext cardinality, se_reduction)."""
     d = L.NetDesc()
     d.in_ch, d.in_hw, d.avgpool = spec.in_ch, spec.in_hw, int(bool(spec.avgpool))
-    d.trunk = L.PPO_TRUNK_TINY if spec.trunk == "tiny" else L.PPO_TRUNK_RESNET
+    trunks = {"tiny": L.PPO_TRUNK_TINY, "resnet": L.PPO_TRUNK_RESNET, "seresnext": L.PPO_TRUNK_SERESNEXT}
+    if spec.trunk not in trunks:
+        raise ValueError(f"unknown trunk {spec.trunk!r}")
+    d.trunk = trunks[spec.trunk]
+    d.cardinality = getattr(spec, "cardinality", 0)
+    d.se_reduction = getattr(spec, "se_reduction", 0)
     d.tiny_ch[0], d.tiny_ch[1] = spec.tiny_ch
     d.base_width = spec.base_width
     for i in range(4):

@@ -12,7 +12,7 @@ from concurrent.futures import ThreadPoolExecutor
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libddppo.so")
-SOURCES = ["abi.hip", "gemm.hip", "norm.hip", "lstm.hip", "lstm_step.hip", "lstm_seq.hip", "lstm_act.hip", "head.hip", "gae_adam.hip"]
+SOURCES = ["abi.hip", "gemm.hip", "norm.hip", "lstm.hip", "lstm_step.hip", "lstm_seq.hip", "lstm_act.hip", "head.hip", "gae_adam.hip", "seresnext.hip"]
 ARCH = "gfx950"
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",

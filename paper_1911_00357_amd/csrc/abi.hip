@@ -41,11 +41,14 @@ struct Unit {
   int Cin, Cout, K, stride, pad;
   int Hin, Win, Hout, Wout;
   int S;                      // GroupNorm pixel chunks
+  int groups;                 // convolution groups (1: dense, implicit GEMM)
   size_t u, a, st;            // workspace offsets: conv out, norm out, stats (per frame sizes below)
 };
 
 struct Block {
   int c1, c2, c3, ds;         // unit indices (ds = -1: identity shortcut)
+  int R;                      // squeeze-excite hidden width (0: no gate)
+  size_t se1w, se1b, se2w, se2b;  // gate parameters: W1 [R][C], b1 [R], W2 [C][R], b2 [C]
 };
 
 }  // namespace
@@ -69,6 +72,7 @@ struct ppo_net {
   size_t max_unit = 0;        // largest conv output per frame
   size_t gn_part = 0;         // largest S*C per frame
   int max_G = 0;
+  int se_C = 0, se_R = 0;     // widest squeeze-excite gate (channels, hidden)
   // GEMM launch timer (benchmark aid, ppo_gemm_timer_arm)
   mutable int timer_unit = -1, timer_op = -1;
   mutable std::vector<hipEvent_t> timer_ev;
@@ -91,11 +95,12 @@ size_t add_tensor(ppo_net* n, const std::string& name, size_t count) {
 }
 
 int add_unit(ppo_net* n, const std::string& name, int cin, int cout, int k, int stride, int pad, int hin,
-             int win) {
+             int win, int groups = 1) {
   Unit u{};
   u.name = name;
   u.relu = 1;
-  u.w = add_tensor(n, name, (size_t)cout * k * k * cin);
+  u.groups = groups;
+  u.w = add_tensor(n, name, (size_t)cout * k * k * (cin / groups));
   u.g = add_tensor(n, name + ".gn.g", cout);
   u.b = add_tensor(n, name + ".gn.b", cout);
   u.Cin = cin;
@@ -114,6 +119,8 @@ int add_unit(ppo_net* n, const std::string& name, int cin, int cout, int k, int 
   n->gn_part = std::max(n->gn_part, (size_t)u.S * cout);
   return (int)n->units.size() - 1;
 }
+
+ConvGeo geo(const Unit& u, int F);
 
 ppo_status build(ppo_net* n) {
   const ppo_net_desc& d = n->d;
@@ -137,11 +144,14 @@ ppo_status build(ppo_net* n) {
     n->feat_c = c2;
     n->feat_hw = n->units[u2].Hout;
     if (n->units[u2].Hout != n->units[u2].Wout) return fail(PPO_ESHAPE, "non-square map");
-  } else if (d.trunk == PPO_TRUNK_RESNET) {
+  } else if (d.trunk == PPO_TRUNK_RESNET || d.trunk == PPO_TRUNK_SERESNEXT) {
     const int w0 = d.base_width;
+    const bool se = d.trunk == PPO_TRUNK_SERESNEXT;
     if (hw % 32) return fail(PPO_ESHAPE, "resnet trunk needs a multiple of 32 after pooling");
     if (w0 % G || w0 % 4 || d.compress_ch % G || d.compress_ch % 4)
       return fail(PPO_ESHAPE, "widths must divide by the group count and 4");
+    if (se && (d.cardinality <= 0 || d.se_reduction <= 0))
+      return fail(PPO_ESHAPE, "seresnext needs a positive cardinality and squeeze-excite reduction");
     n->stem = add_unit(n, "enc.stem", d.in_ch, w0, 7, 2, 3, hw, hw);
     const Unit& S = n->units[n->stem];
     n->pool_h = (S.Hout - 1) / 2 + 1;
@@ -154,10 +164,27 @@ ppo_status build(ppo_net* n) {
         char p[64];
         snprintf(p, sizeof(p), "enc.s%d.b%d", s, j);
         Block b{};
-        b.c1 = add_unit(n, std::string(p) + ".c1", cin, w, 1, 1, 0, h, h);
-        b.c2 = add_unit(n, std::string(p) + ".c2", w, w, 3, st, 1, h, h);
+        // SE-ResNeXt: a bottleneck twice as wide, its 3x3 in `cardinality` groups
+        const int m = se ? 2 * w : w, card = se ? d.cardinality : 1;
+        if (se && m % card) return fail(PPO_ESHAPE, "bottleneck width %d does not divide into %d groups", m, card);
+        b.c1 = add_unit(n, std::string(p) + ".c1", cin, m, 1, 1, 0, h, h);
+        b.c2 = add_unit(n, std::string(p) + ".c2", m, m, 3, st, 1, h, h, card);
+        if (se && !gconv_supported(geo(n->units[b.c2], 1), card))
+          return fail(PPO_ESHAPE, "grouped convolution of %d channels in %d groups not supported", m, card);
         const int ho = n->units[b.c2].Hout;
-        b.c3 = add_unit(n, std::string(p) + ".c3", w, 4 * w, 1, 1, 0, ho, ho);
+        b.c3 = add_unit(n, std::string(p) + ".c3", m, 4 * w, 1, 1, 0, ho, ho);
+        if (se) {
+          const int C = 4 * w;
+          if (C % d.se_reduction) return fail(PPO_ESHAPE, "%d channels do not divide by the reduction", C);
+          b.R = C / d.se_reduction;
+          if ((size_t)(C + b.R) * sizeof(float) > 65536) return fail(PPO_ESHAPE, "squeeze-excite gate too wide");
+          b.se1w = add_tensor(n, std::string(p) + ".se1.w", (size_t)b.R * C);
+          b.se1b = add_tensor(n, std::string(p) + ".se1.b", b.R);
+          b.se2w = add_tensor(n, std::string(p) + ".se2.w", (size_t)C * b.R);
+          b.se2b = add_tensor(n, std::string(p) + ".se2.b", C);
+          n->se_C = std::max(n->se_C, C);
+          n->se_R = std::max(n->se_R, b.R);
+        }
         b.ds = (j == 0) ? add_unit(n, std::string(p) + ".ds", cin, 4 * w, 1, st, 0, h, h) : -1;
         if (b.ds >= 0) n->units[b.ds].relu = 0;  // projection shortcut: GroupNorm only
         if (j != 0 && cin != 4 * w) return fail(PPO_ESHAPE, "identity shortcut with a width change");
@@ -213,6 +240,7 @@ struct WsLayout {
   // encoder
   size_t x0;                       // [F][h0][w0][in_ch]
   std::vector<size_t> u, a, st;    // per unit
+  std::vector<size_t> sey, sez, sea, ses;  // per block with a gate: branch y, pooled z, hidden a1, gate s
   size_t pool, arg;                // resnet max pool out + argmax
   size_t gpart, gbpart, gcoef;     // GroupNorm partials
   size_t ga, gb, gu, gd, gr;       // backward scratch (max unit size)
@@ -227,6 +255,7 @@ struct WsLayout {
   size_t fstat, dout, dh0, dh1, dG, dG2, dhp, dcp, dvis, whT;
   size_t sync;                     // persistent recurrence barrier words
   size_t wT;                       // one unit's weights reordered for its data gradient
+  size_t se_ds, se_da2, se_da1, se_dz;  // gate backward scratch (widest gate)
   size_t total;
 };
 
@@ -243,7 +272,15 @@ WsLayout plan(const ppo_net* n, int F, int nb, bool learn) {
     w.a.push_back(A.take(sz));
     w.st.push_back(A.take((size_t)F * d.gn_groups * sizeof(float2)));
   }
-  if (d.trunk == PPO_TRUNK_RESNET) {
+  for (const Block& b : n->blocks) {
+    const Unit& u3 = n->units[b.c3];
+    const bool se = b.R > 0;
+    w.sey.push_back(se ? A.take((size_t)F * u3.Hout * u3.Wout * u3.Cout * f4) : 0);
+    w.sez.push_back(se ? A.take((size_t)F * u3.Cout * f4) : 0);
+    w.sea.push_back(se ? A.take((size_t)F * b.R * f4) : 0);
+    w.ses.push_back(se ? A.take((size_t)F * u3.Cout * f4) : 0);
+  }
+  if (d.trunk != PPO_TRUNK_TINY) {
     const size_t ps = (size_t)F * n->pool_h * n->pool_w * d.base_width;
     w.pool = A.take(ps * f4);
     w.arg = A.take(ps);
@@ -290,6 +327,10 @@ WsLayout plan(const ppo_net* n, int F, int nb, bool learn) {
     size_t wt_max = 0;
     for (const Unit& u : n->units) wt_max = std::max(wt_max, (size_t)u.Cout * u.K * u.K * u.Cin);
     w.wT = A.take(wt_max * f4);
+    w.se_ds = A.take((size_t)F * n->se_C * f4);
+    w.se_da2 = A.take((size_t)F * n->se_C * f4);
+    w.se_da1 = A.take((size_t)F * n->se_R * f4);
+    w.se_dz = A.take((size_t)F * n->se_C * f4);
   }
   w.total = A.off;
   return w;
@@ -351,7 +392,10 @@ void unit_fwd(const Ctx& c, int ui, const float* x, const float* res, bool relu,
     // conv (split-K partials left in place) -> one fused GroupNorm launch
     float* y = c.at(c.w->u[ui]);
     int splits;
-    {
+    if (u.groups > 1) {
+      launch_gconv_fwd(c.n->prec, g, u.groups, x, c.wt(u.w), y, c.s);
+      splits = 1;
+    } else {
       TimerScope ts(c.n, ui, 0);
       splits = gemm_conv_fwd(c.n->prec, g, x, c.wt(u.w), epi(y, u.Cout), kSplitKBytes, c.splitk(), c.s, true);
     }
@@ -361,7 +405,9 @@ void unit_fwd(const Ctx& c, int ui, const float* x, const float* res, bool relu,
                     c.at<float2>(c.w->st[ui]), c.s);
     return;
   }
-  {
+  if (u.groups > 1) {
+    launch_gconv_fwd(c.n->prec, g, u.groups, x, c.wt(u.w), c.at(c.w->u[ui]), c.s);
+  } else {
     TimerScope ts(c.n, ui, 0);
     gemm_conv_fwd(c.n->prec, g, x, c.wt(u.w), epi(c.at(c.w->u[ui]), u.Cout), kSplitKBytes, c.splitk(), c.s);
   }
@@ -385,7 +431,8 @@ const float* encoder_fwd(const Ctx& c) {
   launch_maxpool_fwd(c.at(c.w->a[n->stem]), c.F, S.Hout, S.Wout, S.Cout, c.at(c.w->pool),
                      c.at<uint8_t>(c.w->arg), c.s);
   const float* x = c.at(c.w->pool);
-  for (const Block& b : n->blocks) {
+  for (size_t bi = 0; bi < n->blocks.size(); ++bi) {
+    const Block& b = n->blocks[bi];
     unit_fwd(c, b.c1, x, nullptr, true, c.at(c.w->a[b.c1]), false);
     unit_fwd(c, b.c2, c.at(c.w->a[b.c1]), nullptr, true, c.at(c.w->a[b.c2]), false);
     const float* res = x;
@@ -393,7 +440,16 @@ const float* encoder_fwd(const Ctx& c) {
       unit_fwd(c, b.ds, x, nullptr, false, c.at(c.w->a[b.ds]), false);
       res = c.at(c.w->a[b.ds]);
     }
-    unit_fwd(c, b.c3, c.at(c.w->a[b.c2]), res, true, c.at(c.w->a[b.c3]), false);
+    if (b.R > 0) {
+      // branch y = GN(conv3), gated per channel, then the shortcut and ReLU
+      const Unit& u3 = n->units[b.c3];
+      unit_fwd(c, b.c3, c.at(c.w->a[b.c2]), nullptr, false, c.at(c.w->sey[bi]), false);
+      launch_se_forward(c.at(c.w->sey[bi]), res, c.F, u3.Hout * u3.Wout, u3.Cout, b.R, c.pf(b.se1w), c.pf(b.se1b),
+                        c.pf(b.se2w), c.pf(b.se2b), c.at(c.w->sez[bi]), c.at(c.w->sea[bi]), c.at(c.w->ses[bi]),
+                        c.at(c.w->a[b.c3]), c.s);
+    } else {
+      unit_fwd(c, b.c3, c.at(c.w->a[b.c2]), res, true, c.at(c.w->a[b.c3]), false);
+    }
     x = c.at(c.w->a[b.c3]);
   }
   unit_fwd(c, n->compress, x, nullptr, true, c.at(c.w->a[n->compress]), true);
@@ -426,6 +482,11 @@ void unit_bwd(const Ctx& c, int ui, const float* dout, const float* mask_out, bo
   const int P = u.Hout * u.Wout;
   gn_bwd(c, ui, dout, mask_out, chw, du, dres);
   const ConvGeo g = geo(u, c.F);
+  if (u.groups > 1) {
+    launch_gconv_wgrad(n->prec, g, u.groups, x, du, c.grad + u.w, c.splitk(), kSplitKBytes, c.s);
+    if (dx) launch_gconv_dgrad(n->prec, g, u.groups, du, c.wt(u.w), dx, dx_acc ? 1 : 0, c.s);
+    return;
+  }
   const long Kw = (long)u.K * u.K * u.Cin;
   {
     TimerScope ts(n, ui, 2);
@@ -457,7 +518,17 @@ void encoder_bwd(const Ctx& c, const float* dfeat) {
     const float* xin = bi == 0 ? c.at(w.pool) : c.at(w.a[n->blocks[bi - 1].c3]);
     // GA: gradient at the block output (before its ReLU mask)
     float* dres = b.ds >= 0 ? GR : GB;  // identity: the shortcut gradient seeds dX
-    unit_bwd(c, b.c3, GA, c.at(w.a[b.c3]), false, c.at(w.a[b.c2]), GU, GD, false, dres);
+    if (b.R > 0) {
+      // gate backward: the masked gradient to the shortcut (dres), the branch's into GA
+      const Unit& u3 = n->units[b.c3];
+      launch_se_backward(GA, c.at(w.a[b.c3]), c.at(w.sey[bi]), c.at(w.sez[bi]), c.at(w.sea[bi]), c.at(w.ses[bi]),
+                         c.F, u3.Hout * u3.Wout, u3.Cout, b.R, c.pf(b.se1w), c.pf(b.se2w), dres, c.at(w.se_ds),
+                         c.at(w.se_da2), c.at(w.se_da1), c.at(w.se_dz), c.grad + b.se1w, c.grad + b.se1b,
+                         c.grad + b.se2w, c.grad + b.se2b, GA, c.s);
+      unit_bwd(c, b.c3, GA, nullptr, false, c.at(w.a[b.c2]), GU, GD, false, nullptr);
+    } else {
+      unit_bwd(c, b.c3, GA, c.at(w.a[b.c3]), false, c.at(w.a[b.c2]), GU, GD, false, dres);
+    }
     unit_bwd(c, b.c2, GD, c.at(w.a[b.c2]), false, c.at(w.a[b.c1]), GU, GD, false, nullptr);
     if (b.ds >= 0) {
       // c1 first (its du must not be overwritten before its data gradient)
@@ -1099,13 +1170,18 @@ ppo_status ppo_bench_unit_gemm(ppo_net* net, int op, int unit, int frames, const
   Ctx c{net, &w, (char*)ws, params, params_lp, grad, s, frames};
   const Unit& u = net->units[unit];
   const ConvGeo g = geo(u, frames);
-  const double M = (double)frames * u.Hout * u.Wout, N = u.Cout, K = (double)u.K * u.K * u.Cin;
+  const double M = (double)frames * u.Hout * u.Wout, N = u.Cout, K = (double)u.K * u.K * u.Cin / u.groups;
   *flops = 2.0 * M * N * K;
   // operands: scratch buffers sized for the largest unit of a learner call
   float *X = c.at(w.ga), *DY = c.at(w.gb), *OUT = c.at(w.gu);
   // op 3: the act step's product, its split-K partial tiles left for the GroupNorm
   const bool act_form = op == 3 && gn_one_launch(c, u);
-  for (int r = 0; r < reps; ++r) {
+  for (int r = 0; r < reps && u.groups > 1; ++r) {   // grouped: the direct convolution kernels
+    if (op == 0 || op == 3) launch_gconv_fwd(net->prec, g, u.groups, X, c.wt(u.w), OUT, s);
+    else if (op == 1) launch_gconv_dgrad(net->prec, g, u.groups, DY, c.wt(u.w), OUT, 0, s);
+    else launch_gconv_wgrad(net->prec, g, u.groups, X, DY, grad + u.w, c.splitk(), kSplitKBytes, s);
+  }
+  for (int r = 0; r < reps && u.groups == 1; ++r) {
     if (op == 0 || op == 3)
       gemm_conv_fwd(net->prec, g, X, c.wt(u.w), epi(OUT, u.Cout), kSplitKBytes, c.splitk(), s, act_form);
     else if (op == 1)
@@ -1220,7 +1296,7 @@ ppo_status ppo_workspace_probe(const ppo_net* net, int op, int max_frames, int m
     return PPO_OK;
   }
   if (kind == 1) {
-    if (net->d.trunk != PPO_TRUNK_RESNET) return fail(PPO_EINVAL, "no max pool in this trunk");
+    if (net->d.trunk == PPO_TRUNK_TINY) return fail(PPO_EINVAL, "no max pool in this trunk");
     *offset = w.arg;
     dims[0] = net->pool_h;
     dims[1] = net->pool_w;
@@ -1238,7 +1314,7 @@ ppo_status ppo_workspace_probe(const ppo_net* net, int op, int max_frames, int m
     return PPO_OK;
   }
   if (kind == 5) {
-    if (net->d.trunk != PPO_TRUNK_RESNET) return fail(PPO_EINVAL, "no max pool in this trunk");
+    if (net->d.trunk == PPO_TRUNK_TINY) return fail(PPO_EINVAL, "no max pool in this trunk");
     *offset = w.pool;
     dims[0] = net->pool_h;
     dims[1] = net->pool_w;
@@ -1249,6 +1325,21 @@ ppo_status ppo_workspace_probe(const ppo_net* net, int op, int max_frames, int m
     if (index < 0 || index >= net->d.lstm_layers) return fail(PPO_EINVAL, "layer index out of range");
     *offset = kind == 6 ? w.hp[index] : w.hout[index];
     dims[0] = net->d.hidden;
+    return PPO_OK;
+  }
+  if (kind == 9) {
+    if (op != PPO_OP_LEARN || index < 0 || index > 2)
+      return fail(PPO_EINVAL, "benchmark operands: op PPO_OP_LEARN, index 0..2");
+    *offset = index == 0 ? w.ga : index == 1 ? w.gb : w.gu;
+    dims[0] = (int)std::min<size_t>((size_t)max_frames * net->max_unit, INT32_MAX);
+    return PPO_OK;
+  }
+  if (kind == 8) {
+    if (index < 0 || index >= (int)net->blocks.size() || net->blocks[index].R == 0)
+      return fail(PPO_EINVAL, "block %d has no squeeze-excite gate", index);
+    *offset = w.sea[index];
+    dims[0] = net->blocks[index].R;
+    dims[1] = net->units[net->blocks[index].c3].Cout;
     return PPO_OK;
   }
   if (kind == 4) {

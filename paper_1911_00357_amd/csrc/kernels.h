@@ -186,6 +186,25 @@ void launch_act_core_prep(const float* goal, const int32_t* prev_a, const float*
                           int zoff, const float* h_in, const float* c_in, int L, int SR, int H, float* hm, float* cm,
                           hipStream_t s);
 bool act_layer_supported(int din, int H, int B);
+// SE-ResNeXt blocks (seresnext.hip): grouped 3x3 convolution (G groups,
+// weights [Co][3][3][C/G]) forward, data gradient (accumulate: add into dx)
+// and weight gradient (partials of at most part_bytes, then summed in order
+// into dw); squeeze-excite gate forward (z, a1, gate kept for the backward)
+// and backward (dres: the shortcut's gradient, dy: the branch's).
+bool gconv_supported(const ConvGeo& g, int G);
+void launch_gconv_fwd(int prec, const ConvGeo& g, int G, const float* x, const void* w, float* y, hipStream_t s);
+void launch_gconv_dgrad(int prec, const ConvGeo& g, int G, const float* dy, const void* w, float* dx,
+                        int accumulate, hipStream_t s);
+void launch_gconv_wgrad(int prec, const ConvGeo& g, int G, const float* x, const float* dy, float* dw,
+                        float* part, size_t part_bytes, hipStream_t s);
+void launch_se_forward(const float* y, const float* res, int F, int HW, int C, int R, const float* w1,
+                       const float* b1, const float* w2, const float* b2, float* z, float* a1, float* gate,
+                       float* out, hipStream_t s);
+void launch_se_backward(const float* dout, const float* out, const float* y, const float* z, const float* a1,
+                        const float* gate, int F, int HW, int C, int R, const float* w1, const float* w2,
+                        float* dres, float* ds, float* da2, float* da1, float* dz, float* gw1, float* gb1,
+                        float* gw2, float* gb2, float* dy, hipStream_t s);
+
 void launch_lstm_act_layer(int prec, const float* X, int ldx, int din, const float* HM, const float* CM,
                            const void* W, int ldw, const float* bias, int B, int H, float* h_out, float* c_out,
                            const int32_t* active, hipStream_t s);

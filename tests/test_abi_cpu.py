@@ -11,7 +11,7 @@ import pytest
 import synth
 from paper_1911_00357_amd import _lib as L
 from synth.layout import tensor_list
-from tests.nets import MINI_RESNET, TINY_BIGCORE, TINY_PLUS
+from tests.nets import MINI_RESNET, MINI_SERESNEXT, SERESNEXT_64, TINY_BIGCORE, TINY_PLUS
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 HEADER = os.path.join(ROOT, "include", "ddppo.h")
@@ -56,7 +56,7 @@ def test_struct_layouts_match_header(tmp_path):
             assert got[(cname, f)] == getattr(py, f).offset, (cname, f)
 
 
-@pytest.mark.parametrize("wl", ["C0", "C1", "C3"])
+@pytest.mark.parametrize("wl", ["C0", "C1", "C3", "C5"])
 def test_param_layout_matches_generator(wl):
     import paper_1911_00357_amd as P
     net = synth.WORKLOADS[wl].net
@@ -67,11 +67,30 @@ def test_param_layout_matches_generator(wl):
     assert n.P == synth.param_count(net)
 
 
-@pytest.mark.parametrize("net", [TINY_PLUS, MINI_RESNET, TINY_BIGCORE])
+@pytest.mark.parametrize("net", [TINY_PLUS, MINI_RESNET, TINY_BIGCORE, MINI_SERESNEXT, SERESNEXT_64])
 def test_test_nets_create(net):
     import paper_1911_00357_amd as P
     assert P.Net(net, "f32").P == synth.param_count(net)
-    assert P.Net(net, "bf16").P == synth.param_count(net)
+    n = P.Net(net, "bf16")
+    assert n.P == synth.param_count(net)
+    got = [(off, cnt) for name, off, cnt in n.tensors()]
+    assert got == [(t.offset, int(np.prod(t.shape))) for t in tensor_list(net)]
+
+
+@pytest.mark.parametrize("bad", [dict(cardinality=0), dict(cardinality=3), dict(se_reduction=0),
+                                 dict(se_reduction=7), dict(cardinality=1)])
+def test_seresnext_create_rejects_bad_groups(bad):
+    """Groups that do not divide the bottleneck, a reduction that does not
+    divide the block width, or a grouped 3x3 too wide for the direct kernels
+    (one group: 512 channels per group) are refused before anything runs."""
+    import paper_1911_00357_amd.api as A
+    lib = L.lib()
+    d = A.desc_from(synth.C5.net, "bf16")
+    for k, v in bad.items():
+        setattr(d, k, v)
+    h = C.c_void_p()
+    assert lib.ppo_net_create(C.byref(d), C.byref(h)) == L.PPO_ESHAPE
+    assert not h.value
 
 
 def _desc(**kw):

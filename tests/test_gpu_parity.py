@@ -239,9 +239,16 @@ def gpu_decisions(n, net, F, nb, mb, codes=False):
             dec[key[:-2] + "out" if key.endswith(".c3") else key] = a > 0
         if codes:
             outs[key] = round_bf16(a)
-    if net.trunk == "resnet":
+    if net.trunk != "tiny":
         _, _, off, (h, w, C, _) = n.probe(PPO_OP_LEARN, F, nb, 1)
         dec["maxpool"] = ws[off:off + F * h * w * C].cpu().numpy().reshape(F, h, w, C).transpose(0, 3, 1, 2)
+    if net.trunk == "seresnext":          # each block's squeeze-excite hidden ReLU
+        bi = 0
+        for s_ in range(4):
+            for j in range(net.blocks[s_]):
+                _, _, off, (R, _, _, _) = n.probe(PPO_OP_LEARN, F, nb, 8, bi)
+                dec["s%d.b%d.se" % (s_, j)] = _ws_f32(ws, off, F * R).reshape(F, R) > 0
+                bi += 1
     TB, B = mb["action"].shape
     valid = np.arange(TB)[:, None] < mb["lens"][None, :]
     tt, jj = np.nonzero(valid)
@@ -255,7 +262,7 @@ def gpu_decisions(n, net, F, nb, mb, codes=False):
     z = _ws_f32(ws, off, F * d0).reshape(F, d0)
     dec["vis"] = tm(z[:, :vis] > 0)
     if codes:
-        if net.trunk == "resnet":
+        if net.trunk != "tiny":
             _, _, off, (h, w, C, _) = n.probe(PPO_OP_LEARN, F, nb, 5)
             prev = round_bf16(_ws_f32(ws, off, F * h * w * C).reshape(F, h, w, C).transpose(0, 3, 1, 2))
             for s_ in range(4):
