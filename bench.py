@@ -49,7 +49,8 @@ def parse():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--seeds", type=int, default=10, help="seeds 0..S-1 (median and bootstrap 95%% CI)")
-    ap.add_argument("--workload", default="C2", help="C0..C4 (C2 = bf16 paper-shaped worker)")
+    ap.add_argument("--workload", default="C2", help="C0..C6 (C2 = bf16 paper-shaped worker; C5, C6 the "
+                                                     "SE-ResNeXt50 and SE-ResNeXt101 + 1024-d LSTM agents)")
     ap.add_argument("--no-fp32", action="store_true", help="skip the float32 comparison run")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--eager", action="store_true", help="launch the act loop eagerly (no HIP graph)")
@@ -203,6 +204,16 @@ def run_seeds(wl, seeds, steps, warmup, label, tiles=None):
         gc.collect()
         torch.cuda.empty_cache()
     return out, first
+
+
+def encoder_label(net):
+    if net.trunk == "tiny":
+        return "tiny"
+    depth = {(3, 4, 6, 3): "50", (3, 4, 23, 3): "101"}.get(tuple(net.blocks), str(tuple(net.blocks)))
+    if net.trunk == "seresnext":
+        return (f"se-resnext{depth} halved widths ({net.cardinality} groups, squeeze-excite 1/"
+                f"{net.se_reduction}), GroupNorm")
+    return f"resnet{depth} halved widths, GroupNorm"
 
 
 def median_ci(x, n_boot=10000, seed=0):
@@ -783,7 +794,7 @@ def main():
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
            "dtype": "bf16" if wl.dtype == "bf16" else "f32", "data": "synthetic",
            "config": {"workload": wl.name, "T": wl.T, "N": wl.N, "frame": f"{wl.net.in_ch}x{wl.net.in_hw}x{wl.net.in_hw}",
-                      "encoder": "resnet50 halved widths, GroupNorm" if wl.net.trunk == "resnet" else "tiny",
+                      "encoder": encoder_label(wl.net),
                       "lstm": f"{wl.net.lstm_layers}x{wl.net.hidden}", "epochs": wl.ppo.epochs,
                       "minibatches": wl.ppo.minibatches, "frames_per_step": frames_step,
                       "parallelism": "single worker",

@@ -148,9 +148,7 @@ ppo_status ppo_workspace_size(const ppo_net* net, int op, int max_frames, int ma
  * host may change it between replays); rows >= *active keep their previous
  * contents (with h_out aliasing h_in, their state).  Values outside
  * [0, batch] act as the nearer bound.  Rows are independent, so rows
- * b < *active are bit-for-bit those of a call without the count.  Needs the
- * act core of at most 2 LSTM layers (every paper configuration); otherwise
- * PPO_EUNSUPPORTED.
+ * b < *active are bit-for-bit those of a call without the count.
  */
 typedef struct ppo_act_io {
   int batch;                  /* B envs (rows) in this call                     */

@@ -714,8 +714,6 @@ ppo_status ppo_act(ppo_net* net, const ppo_act_io* io, void* ws, size_t ws_bytes
   const int H = d.hidden, L = d.lstm_layers, A = d.num_actions;
   bool fused = L <= 2;
   for (int l = 0; l < L; ++l) fused = fused && act_layer_supported(l == 0 ? net->din0 : H, H, B);
-  if (io->active && !fused)
-    return fail(PPO_EUNSUPPORTED, "a device row count needs the one-launch-per-layer core (at most 2 layers)");
   hipStream_t s = strm(stream);
   Ctx c{net, &w, (char*)ws, io->params, io->params_lp, nullptr, s, B};
   c.keep_u = false;
@@ -763,19 +761,24 @@ ppo_status ppo_act(ppo_net* net, const ppo_act_io* io, void* ws, size_t ws_bytes
     launch_mask_state(io->h_in + (size_t)l * SR * H, io->c_in + (size_t)l * SR * H, io->mask, B, H,
                       zl[l] + din, din + H, cpl[l], s);
   }
+  // with a device row count, every layer's h and c go to workspace rows first
+  // and only the active rows are copied out
+  const bool masked = io->active != nullptr;
   for (int l = 0; l < L; ++l) {
     const int din = l == 0 ? net->din0 : H;
     const bool top = l == L - 1;
-    float* hdst = top ? io->h_out + (size_t)l * SR * H : zl[l + 1];
+    float* hdst = top ? (masked ? c.at(w.hout[l]) : io->h_out + (size_t)l * SR * H) : zl[l + 1];
+    float* cdst = masked ? c.at(w.c[l]) : io->c_out + (size_t)l * SR * H;
     const int ldh = top ? H : 2 * H;
     // gates = [x | m h] [W_ih | W_hh]^T + b and the cell, in one launch
     launch_lstm_step_fwd(net->prec, zl[l], din + H, din + H, c.wt(net->lstm_w[l]), din + H, nullptr,
-                         c.pf(net->lstm_b[l]), cpl[l], B, H, nullptr, hdst, ldh,
-                         io->c_out + (size_t)l * SR * H, nullptr, 0, nullptr, 0, nullptr, s);
-    if (!top) launch_copy2d(hdst, ldh, B, H, io->h_out + (size_t)l * SR * H, H, s);
+                         c.pf(net->lstm_b[l]), cpl[l], B, H, nullptr, hdst, ldh, cdst, nullptr, 0, nullptr, 0,
+                         nullptr, s);
+    if (!top || masked) launch_copy2d(hdst, ldh, B, H, io->h_out + (size_t)l * SR * H, H, s, io->active);
+    if (masked) launch_copy2d(cdst, H, B, H, io->c_out + (size_t)l * SR * H, H, s, io->active);
   }
   launch_act_head(io->h_out + (size_t)(L - 1) * SR * H, B, H, A, c.pf(net->head_w), c.pf(net->head_b),
-                  io->u, io->action, io->logp, io->value, io->logits, nullptr, s);
+                  io->u, io->action, io->logp, io->value, io->logits, io->active, s);
   return check_launch();
 }
 

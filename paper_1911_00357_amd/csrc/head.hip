@@ -417,9 +417,12 @@ void launch_gather_state(const float* srcs, int L, int N, int nb, int H, const i
                      nb, H, env_row, dst);
 }
 
-// Copy of a [rows][cols] window between two strided buffers.
+// Copy of a [rows][cols] window between two strided buffers; with a device
+// row count, rows >= *active are left as they are.
 __global__ void __launch_bounds__(256) copy2d_kernel(const float* __restrict__ s, int lds, int rows,
-                                                     int cols, float* __restrict__ d, int ldd) {
+                                                     int cols, float* __restrict__ d, int ldd,
+                                                     const int32_t* __restrict__ active) {
+  if (active) rows = min(rows, max(*active, 0));
   const int n = rows * cols;
   for (int e = blockIdx.x * 256 + threadIdx.x; e < n; e += gridDim.x * 256) {
     const int r = e / cols, c = e - r * cols;
@@ -427,11 +430,12 @@ __global__ void __launch_bounds__(256) copy2d_kernel(const float* __restrict__ s
   }
 }
 
-void launch_copy2d(const float* s_, int lds, int rows, int cols, float* d, int ldd, hipStream_t s) {
+void launch_copy2d(const float* s_, int lds, int rows, int cols, float* d, int ldd, hipStream_t s,
+                   const int32_t* active) {
   const int n = rows * cols;
   if (n <= 0) return;
   hipLaunchKernelGGL(copy2d_kernel, dim3(std::min(4096, cdiv(n, 256))), dim3(256), 0, s, s_, lds, rows,
-                     cols, d, ldd);
+                     cols, d, ldd, active);
 }
 
 // Policy/value head over frames: logits[f][k], values[f] (one wavefront per frame).

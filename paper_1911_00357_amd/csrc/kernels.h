@@ -235,7 +235,8 @@ void launch_frame_map(const MapArgs& m, const float* mask, int32_t* src, float* 
                       int32_t* env_row, hipStream_t s);
 void launch_gather_state(const float* srcs, int L, int N, int nb, int H, const int32_t* env_row,
                          float* dst, hipStream_t s);
-void launch_copy2d(const float* s_, int lds, int rows, int cols, float* d, int ldd, hipStream_t s);
+void launch_copy2d(const float* s_, int lds, int rows, int cols, float* d, int ldd, hipStream_t s,
+                   const int32_t* active = nullptr);
 void launch_head_fwd(const float* htop, int F, int H, int A, const float* W, const float* b, float* logits,
                      float* values, hipStream_t s);
 void launch_head_bwd(const float* dlogits, const float* dvalues, int F, int H, int A, const float* W, float* dout,

@@ -115,6 +115,9 @@ TINY_NET = NetDesc(in_hw=32, avgpool=False, trunk="tiny", gn_groups=8,
 RESNET_NET = NetDesc()
 RESNET_NET_128 = NetDesc(in_hw=128)
 SERESNEXT_NET = NetDesc(trunk="seresnext")
+# the paper's largest agent: SE-ResNeXt101 (halved) and a 2 x 1024 LSTM, the
+# visual FC mapping to the hidden size
+SERESNEXT101_NET = NetDesc(trunk="seresnext", blocks=(3, 4, 23, 3), vis_hidden=1024, hidden=1024)
 
 # The five workloads: tiny FP32; paper-shaped worker in FP32 and in BF16;
 # the differentiation form at 128x128 frames; the ragged batching form.
@@ -127,5 +130,6 @@ C4 = Workload("resnet50h_bf16_ragged_T128_N64", RESNET_NET, T=128, N=64, dtype="
               ragged=True)
 # the SE-ResNeXt50 encoder (halved widths) in the default worker configuration
 C5 = Workload("seresnext50h_bf16_T128_N4", SERESNEXT_NET, T=128, N=4, dtype="bf16")
+C6 = Workload("seresnext101h_lstm1024_bf16_T128_N4", SERESNEXT101_NET, T=128, N=4, dtype="bf16")
 
-WORKLOADS = {"C0": C0, "C1": C1, "C2": C2, "C3": C3, "C4": C4, "C5": C5}
+WORKLOADS = {"C0": C0, "C1": C1, "C2": C2, "C3": C3, "C4": C4, "C5": C5, "C6": C6}

@@ -43,9 +43,14 @@ def _outs(B, L, H, A, fill):
             "logits": torch.full((B, A), fill, **f)}
 
 
-@pytest.mark.parametrize("netname", ["tiny", "mini_resnet"])
+# tiny_3layer: a core of three LSTM layers, run by the per-layer step kernel
+# (h and c written to workspace rows, then the active rows copied out)
+NETS = {"tiny": TINY_NET, "mini_resnet": MINI_RESNET, "tiny_3layer": dataclasses.replace(TINY_NET, lstm_layers=3)}
+
+
+@pytest.mark.parametrize("netname", list(NETS))
 def test_act_row_count(P, netname):
-    net = {"tiny": TINY_NET, "mini_resnet": MINI_RESNET}[netname]
+    net = NETS[netname]
     B = 5
     n = P.Net(net, "f32")
     L, H, A = net.lstm_layers, net.hidden, net.num_actions
@@ -78,19 +83,6 @@ def test_act_row_count(P, netname):
     torch.cuda.synchronize()
     assert torch.equal(h[:, :3], full["h"][:, :3]) and torch.equal(h[:, 3:], x["h_in"][:, 3:])
     assert torch.equal(c[:, :3], full["c"][:, :3]) and torch.equal(c[:, 3:], x["c_in"][:, 3:])
-
-
-def test_act_row_count_unsupported_core(P):
-    from paper_1911_00357_amd._lib import PPOError
-    net = dataclasses.replace(TINY_NET, lstm_layers=3)
-    n = P.Net(net, "f32")
-    L, H, A = net.lstm_layers, net.hidden, net.num_actions
-    params = torch.tensor(R.init_params(net, 1), device="cuda")
-    x = _act_inputs(net, 2, L, H, 3)
-    cnt = torch.ones(1, dtype=torch.int32, device="cuda")
-    with pytest.raises(PPOError, match="row count"):
-        n.act(x["obs"], x["goal"], x["prev_action"], x["mask"], x["h_in"], x["c_in"], x["u"], params,
-              active=cnt)
 
 
 def _snap(w, T, lens):

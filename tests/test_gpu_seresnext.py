@@ -10,7 +10,7 @@ import torch
 
 from oracle import nn as onn
 from synth import rollout as R
-from synth.configs import C5
+from synth.configs import C5, C6
 from tests.gpu_util import assert_close
 from tests.nets import MINI_SERESNEXT, SERESNEXT_64
 from tests.test_gpu_parity import GN_FORMS, _act_case, _loss_case, check_act, check_loss, say
@@ -34,6 +34,15 @@ def test_act_parity_seresnext_paper_shape(P, dtype):
     say(f"act seresnext paper shape {dtype}")
     out, ref = _act_case(P, C5.net, dtype, 4, seed=31, state_rows=5)
     check_act(out, ref, dtype, 4, "seresnext")
+
+
+@pytest.mark.parametrize("dtype", ["f32", "bf16"])
+def test_act_parity_seresnext101_lstm1024(P, dtype):
+    """The paper's largest agent (SE-ResNeXt101 halved, 2 x 1024 LSTM) at
+    256x256 frames, batch 4; its core takes the per-layer step kernel."""
+    say(f"act seresnext101 + 1024-d LSTM {dtype}")
+    out, ref = _act_case(P, C6.net, dtype, 4, seed=33)
+    check_act(out, ref, dtype, 4, "seresnext101")
 
 
 @pytest.mark.parametrize("dtype", ["f32", "bf16"])

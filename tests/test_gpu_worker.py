@@ -23,13 +23,14 @@ import torch
 from oracle import nn as onn
 from oracle import ppo
 from synth import rollout as R
-from synth.configs import C0, C1, C2
+from synth.configs import C0, C1, C2, C5
 from tests.gpu_util import assert_close, errs, flip_summary, rel_err
 from tests.test_gpu_parity import AT_RISK, TOL, LossCase, _loss_rel, gpu_decisions, oracle_refs, say
 
 pytestmark = pytest.mark.gpu
 
-CASES = {"tiny_f32": C0, "resnet_f32_T4": C1.with_(T=4), "resnet_bf16_T4": C2.with_(T=4)}
+CASES = {"tiny_f32": C0, "resnet_f32_T4": C1.with_(T=4), "resnet_bf16_T4": C2.with_(T=4),
+         "seresnext_f32_T4": C5.with_(T=4, dtype="f32"), "seresnext_bf16_T4": C5.with_(T=4)}
 
 
 def _stage(wl, seed):
