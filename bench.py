@@ -637,6 +637,7 @@ def _is_marker(r):
 
 
 def _short(n):
+    n = n.replace("(anonymous namespace)::", "")
     return n.split("(")[0].replace("unsigned short", "bf16")[:110]
 
 

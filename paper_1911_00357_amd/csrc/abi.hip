@@ -177,7 +177,7 @@ ppo_status build(ppo_net* n) {
           const int C = 4 * w;
           if (C % d.se_reduction) return fail(PPO_ESHAPE, "%d channels do not divide by the reduction", C);
           b.R = C / d.se_reduction;
-          if ((size_t)(C + b.R) * sizeof(float) > 65536) return fail(PPO_ESHAPE, "squeeze-excite gate too wide");
+          if ((size_t)(C + b.R + 256) * sizeof(float) > 65536) return fail(PPO_ESHAPE, "squeeze-excite gate too wide");
           b.se1w = add_tensor(n, std::string(p) + ".se1.w", (size_t)b.R * C);
           b.se1b = add_tensor(n, std::string(p) + ".se1.b", b.R);
           b.se2w = add_tensor(n, std::string(p) + ".se2.w", (size_t)C * b.R);
@@ -255,7 +255,8 @@ struct WsLayout {
   size_t fstat, dout, dh0, dh1, dG, dG2, dhp, dcp, dvis, whT;
   size_t sync;                     // persistent recurrence barrier words
   size_t wT;                       // one unit's weights reordered for its data gradient
-  size_t se_ds, se_da2, se_da1, se_dz;  // gate backward scratch (widest gate)
+  size_t se_part;                  // squeeze partial sums [kSeMaxSlices][F][widest gate]
+  size_t se_da2, se_da1, se_dz;    // gate backward scratch (widest gate)
   size_t total;
 };
 
@@ -272,6 +273,7 @@ WsLayout plan(const ppo_net* n, int F, int nb, bool learn) {
     w.a.push_back(A.take(sz));
     w.st.push_back(A.take((size_t)F * d.gn_groups * sizeof(float2)));
   }
+  w.se_part = A.take((size_t)kSeMaxSlices * F * n->se_C * f4);
   for (const Block& b : n->blocks) {
     const Unit& u3 = n->units[b.c3];
     const bool se = b.R > 0;
@@ -327,7 +329,6 @@ WsLayout plan(const ppo_net* n, int F, int nb, bool learn) {
     size_t wt_max = 0;
     for (const Unit& u : n->units) wt_max = std::max(wt_max, (size_t)u.Cout * u.K * u.K * u.Cin);
     w.wT = A.take(wt_max * f4);
-    w.se_ds = A.take((size_t)F * n->se_C * f4);
     w.se_da2 = A.take((size_t)F * n->se_C * f4);
     w.se_da1 = A.take((size_t)F * n->se_R * f4);
     w.se_dz = A.take((size_t)F * n->se_C * f4);
@@ -445,8 +446,8 @@ const float* encoder_fwd(const Ctx& c) {
       const Unit& u3 = n->units[b.c3];
       unit_fwd(c, b.c3, c.at(c.w->a[b.c2]), nullptr, false, c.at(c.w->sey[bi]), false);
       launch_se_forward(c.at(c.w->sey[bi]), res, c.F, u3.Hout * u3.Wout, u3.Cout, b.R, c.pf(b.se1w), c.pf(b.se1b),
-                        c.pf(b.se2w), c.pf(b.se2b), c.at(c.w->sez[bi]), c.at(c.w->sea[bi]), c.at(c.w->ses[bi]),
-                        c.at(c.w->a[b.c3]), c.s);
+                        c.pf(b.se2w), c.pf(b.se2b), c.at(c.w->se_part), c.at(c.w->sez[bi]), c.at(c.w->sea[bi]),
+                        c.at(c.w->ses[bi]), c.at(c.w->a[b.c3]), c.s);
     } else {
       unit_fwd(c, b.c3, c.at(c.w->a[b.c2]), res, true, c.at(c.w->a[b.c3]), false);
     }
@@ -522,7 +523,7 @@ void encoder_bwd(const Ctx& c, const float* dfeat) {
       // gate backward: the masked gradient to the shortcut (dres), the branch's into GA
       const Unit& u3 = n->units[b.c3];
       launch_se_backward(GA, c.at(w.a[b.c3]), c.at(w.sey[bi]), c.at(w.sez[bi]), c.at(w.sea[bi]), c.at(w.ses[bi]),
-                         c.F, u3.Hout * u3.Wout, u3.Cout, b.R, c.pf(b.se1w), c.pf(b.se2w), dres, c.at(w.se_ds),
+                         c.F, u3.Hout * u3.Wout, u3.Cout, b.R, c.pf(b.se1w), c.pf(b.se2w), dres, c.at(w.se_part),
                          c.at(w.se_da2), c.at(w.se_da1), c.at(w.se_dz), c.grad + b.se1w, c.grad + b.se1b,
                          c.grad + b.se2w, c.grad + b.se2b, GA, c.s);
       unit_bwd(c, b.c3, GA, nullptr, false, c.at(w.a[b.c2]), GU, GD, false, nullptr);
@@ -557,6 +558,17 @@ void encoder_bwd(const Ctx& c, const float* dfeat) {
 }
 
 hipStream_t strm(void* s) { return (hipStream_t)s; }
+
+// The direct SE-ResNeXt kernels index with 31-bit integers: refuse frame
+// counts whose tensors would not fit.
+ppo_status check_frames(const ppo_net* n, int F) {
+  for (const Unit& u : n->units)
+    if (u.groups > 1 && !gconv_fits(geo(u, F))) return fail(PPO_ESHAPE, "%d frames exceed the grouped kernels' indexing", F);
+  for (const Block& b : n->blocks)
+    if (b.R > 0 && (long)F * n->units[b.c3].Hout * n->units[b.c3].Wout * n->units[b.c3].Cout >= (1L << 31))
+      return fail(PPO_ESHAPE, "%d frames exceed the squeeze-excite kernels' indexing", F);
+  return PPO_OK;
+}
 
 ppo_status check_launch() {
   const hipError_t e = hipGetLastError();
@@ -709,6 +721,7 @@ ppo_status ppo_act(ppo_net* net, const ppo_act_io* io, void* ws, size_t ws_bytes
   const int SR = io->state_rows > 0 ? io->state_rows : B;
   if (SR < B) return fail(PPO_ESHAPE, "state_rows < batch");
   const WsLayout w = plan(net, B, 1, false);
+  if (const ppo_status fs = check_frames(net, B); fs != PPO_OK) return fs;
   if (!ws || ws_bytes < w.total) return fail(PPO_EWORKSPACE, "workspace needs %zu bytes", w.total);
   if (!al256(ws)) return fail(PPO_EWORKSPACE, "workspace must be 256-byte aligned");
   const int H = d.hidden, L = d.lstm_layers, A = d.num_actions;
@@ -1066,6 +1079,7 @@ ppo_status ppo_loss_backward(ppo_net* net, const ppo_batch* b, const ppo_loss_cf
   const ppo_status st = schedule(net, b, S);
   if (st != PPO_OK) return st;
   const WsLayout w = plan(net, S.F, b->nb, true);
+  if (const ppo_status fs = check_frames(net, S.F); fs != PPO_OK) return fs;
   if (!ws || ws_bytes < w.total) return fail(PPO_EWORKSPACE, "workspace needs %zu bytes", w.total);
   if (!al256(ws)) return fail(PPO_EWORKSPACE, "workspace must be 256-byte aligned");
   hipStream_t s = strm(stream);
@@ -1089,6 +1103,7 @@ ppo_status ppo_policy_forward(ppo_net* net, const ppo_batch* b, float* logits, f
   const ppo_status st = schedule(net, b, S);
   if (st != PPO_OK) return st;
   const WsLayout w = plan(net, S.F, b->nb, true);
+  if (const ppo_status fs = check_frames(net, S.F); fs != PPO_OK) return fs;
   if (!ws || ws_bytes < w.total) return fail(PPO_EWORKSPACE, "workspace needs %zu bytes", w.total);
   if (!al256(ws)) return fail(PPO_EWORKSPACE, "workspace must be 256-byte aligned");
   hipStream_t s = strm(stream);
@@ -1109,6 +1124,7 @@ ppo_status ppo_policy_backward(ppo_net* net, const ppo_batch* b, const float* dl
   const ppo_status st = schedule(net, b, S);
   if (st != PPO_OK) return st;
   const WsLayout w = plan(net, S.F, b->nb, true);
+  if (const ppo_status fs = check_frames(net, S.F); fs != PPO_OK) return fs;
   if (!ws || ws_bytes < w.total) return fail(PPO_EWORKSPACE, "workspace needs %zu bytes", w.total);
   if (!al256(ws)) return fail(PPO_EWORKSPACE, "workspace must be 256-byte aligned");
   hipStream_t s = strm(stream);
@@ -1167,6 +1183,7 @@ ppo_status ppo_bench_unit_gemm(ppo_net* net, int op, int unit, int frames, const
   if (unit < 0 || unit >= (int)net->units.size() || op < 0 || op > 3 || frames <= 0 || reps <= 0)
     return fail(PPO_EINVAL, "bad unit / op / frames / reps");
   const WsLayout w = plan(net, frames, 1, true);
+  if (const ppo_status fs = check_frames(net, frames); fs != PPO_OK) return fs;
   if (!ws || ws_bytes < w.total) return fail(PPO_EWORKSPACE, "workspace needs %zu bytes", w.total);
   if (!al256(ws)) return fail(PPO_EWORKSPACE, "workspace must be 256-byte aligned");
   hipStream_t s = strm(stream);

@@ -189,20 +189,23 @@ bool act_layer_supported(int din, int H, int B);
 // SE-ResNeXt blocks (seresnext.hip): grouped 3x3 convolution (G groups,
 // weights [Co][3][3][C/G]) forward, data gradient (accumulate: add into dx)
 // and weight gradient (partials of at most part_bytes, then summed in order
-// into dw); squeeze-excite gate forward (z, a1, gate kept for the backward)
-// and backward (dres: the shortcut's gradient, dy: the branch's).
+// into dw); squeeze-excite gate forward (z, a1, gate kept for the backward;
+// zpart: [kSeMaxSlices][F][C] scratch) and backward (dres: the shortcut's
+// gradient, dy: the branch's; dspart: the same scratch).
+constexpr int kSeMaxSlices = 16;   // pixel slices of a squeeze reduction (partial sums [S][F][C])
 bool gconv_supported(const ConvGeo& g, int G);
+bool gconv_fits(const ConvGeo& g);   // element counts within 31-bit indices
 void launch_gconv_fwd(int prec, const ConvGeo& g, int G, const float* x, const void* w, float* y, hipStream_t s);
 void launch_gconv_dgrad(int prec, const ConvGeo& g, int G, const float* dy, const void* w, float* dx,
                         int accumulate, hipStream_t s);
 void launch_gconv_wgrad(int prec, const ConvGeo& g, int G, const float* x, const float* dy, float* dw,
                         float* part, size_t part_bytes, hipStream_t s);
 void launch_se_forward(const float* y, const float* res, int F, int HW, int C, int R, const float* w1,
-                       const float* b1, const float* w2, const float* b2, float* z, float* a1, float* gate,
-                       float* out, hipStream_t s);
+                       const float* b1, const float* w2, const float* b2, float* zpart, float* z, float* a1,
+                       float* gate, float* out, hipStream_t s);
 void launch_se_backward(const float* dout, const float* out, const float* y, const float* z, const float* a1,
                         const float* gate, int F, int HW, int C, int R, const float* w1, const float* w2,
-                        float* dres, float* ds, float* da2, float* da1, float* dz, float* gw1, float* gb1,
+                        float* dres, float* dspart, float* da2, float* da1, float* dz, float* gw1, float* gb1,
                         float* gw2, float* gb2, float* dy, hipStream_t s);
 
 void launch_lstm_act_layer(int prec, const float* X, int ldx, int din, const float* HM, const float* CM,
