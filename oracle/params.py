@@ -22,7 +22,9 @@ import numpy as np
 
 def _arch(net):
     """Yield (name, shape-as-stored, is_conv) in storage order."""
-    if net.trunk == "tiny":
+    if net.trunk == "none":
+        pass                       # features in: no encoder tensors
+    elif net.trunk == "tiny":
         c1, c2 = net.tiny_ch
         yield "conv1", (c1, 3, 3, net.in_ch), True
         yield "conv1.gn.g", (c1,), False
@@ -66,11 +68,11 @@ def _arch(net):
     flat = net.feat_ch * net.feat_hw * net.feat_hw
     yield "fc.w", (net.vis_hidden, flat), False
     yield "fc.b", (net.vis_hidden,), False
-    if net.goal_mode == "polar":
+    if net.goal_mode in ("polar", "vec3"):
         yield "goal.w", (net.goal_dim, 3), False
         yield "goal.b", (net.goal_dim,), False
     if net.prev_act_dim:
-        yield "emb", (net.num_actions + 1, net.prev_act_dim), False
+        yield "emb", (net.emb_rows, net.prev_act_dim), False
     H = net.hidden
     din = net.vis_hidden + net.goal_dim + net.prev_act_dim
     for l in range(net.lstm_layers):

@@ -90,7 +90,7 @@ def quantize_params(net, P, quant):
 # ------------------------------------------------------------------ encoder
 def prep_obs(net, obs):
     x = np.asarray(obs, dtype=np.float64)
-    return nn.avg_pool2(x) if net.avgpool else x
+    return nn.avg_pool2(x) if net.avgpool and net.trunk != "none" else x
 
 
 def _relu(y, key, decide, record=None, outputs=True):
@@ -189,6 +189,8 @@ def encoder_forward(P, net, x, tape=None, decide=None, quant=None, record=None, 
     q = None if quant is None else quantizer(quant)
     cg = lambda name, a, s, p, relu: _conv_gn(P, net, name, a, s, p, relu, tape, decide, q, record,
                                               record_outputs)
+    if net.trunk == "none":            # the input already is the feature vector
+        return np.asarray(x, np.float64).reshape(x.shape[0], -1)
     if net.trunk == "tiny":
         a = cg("conv1", x, 2, 1, True)
         a = cg("conv2", a, 2, 1, True)
@@ -220,6 +222,8 @@ def encoder_forward(P, net, x, tape=None, decide=None, quant=None, record=None, 
 
 def encoder_backward(P, net, tape, dfeat, grads):
     """Accumulate parameter gradients for one recorded encoder forward."""
+    if net.trunk == "none":
+        return
     if net.trunk == "tiny":
         c2 = net.tiny_ch[1]
         hw = net.feat_hw
@@ -251,6 +255,8 @@ def encode(P, net, obs, chunk=64, decide=None, quant=None, record=None, record_o
     im2col memory (frames are independent).  record: as for encoder_forward,
     with the chunks' arrays concatenated along frames at the end."""
     F = obs.shape[0]
+    if net.trunk == "none":
+        return np.asarray(obs, np.float64).reshape(F, net.flat_dim)
     out = np.zeros((F, net.flat_dim))
     rec = None if record is None else {}
     for s in range(0, F, chunk):
@@ -267,6 +273,8 @@ def encode_backward(P, net, obs, dfeat, grads, chunk=64, decide=None, quant=None
     """Recompute each chunk's forward with a tape, then run its backward;
     the chunk gradients are summed."""
     F = obs.shape[0]
+    if net.trunk == "none":
+        return
     for s in range(0, F, chunk):
         tape = {}
         encoder_forward(P, net, prep_obs(net, obs[s:s + chunk]), tape, _slice(decide, s, s + chunk), quant)
@@ -329,10 +337,12 @@ def core_forward(P, net, feat, goal, prev_a, masks, h0, c0, keep=False, vis_mask
         vis, vmask = _relu(pre, t, None if vis_mask is None else {t: vis_mask[t]})
         parts = [vis]
         g3 = None
-        if net.goal_mode == "polar":
-            g3 = polar(np.asarray(goal[t], np.float64))
+        if net.goal_mode in ("polar", "vec3"):
+            # polar: (d, theta) -> [d, cos, sin]; vec3: the 3-vector as given
+            g3 = polar(np.asarray(goal[t], np.float64)) if net.goal_mode == "polar" else \
+                np.asarray(goal[t], np.float64)
             parts.append(nn.linear(g3, P["goal.w"], P["goal.b"]))
-        else:
+        elif net.goal_mode == "raw":
             parts.append(np.asarray(goal[t], np.float64))
         idx = None
         if net.prev_act_dim:
@@ -353,9 +363,10 @@ def core_forward(P, net, feat, goal, prev_a, masks, h0, c0, keep=False, vis_mask
     return logits, values, (np.stack(h), np.stack(c)), tape
 
 
-def core_backward(P, net, tape, dlogits, dvalues, grads):
+def core_backward(P, net, tape, dlogits, dvalues, grads, dgoal=None):
     """BPTT through the policy core; accumulates parameter gradients and
-    returns d(feat) [T,B,flat]."""
+    returns d(feat) [T,B,flat].  dgoal (array [T,B,3], 'vec3' goal mode)
+    receives the gradient with respect to the goal input."""
     T = len(tape)
     L, A = net.lstm_layers, net.num_actions
     B = dlogits.shape[1]
@@ -367,7 +378,7 @@ def core_backward(P, net, tape, dlogits, dvalues, grads):
     for l in range(L):
         g["lstm%d.w" % l] = 0
         g["lstm%d.b" % l] = 0
-    emb_grad = np.zeros((A + 1, net.prev_act_dim)) if net.prev_act_dim else None
+    emb_grad = np.zeros((net.emb_rows, net.prev_act_dim)) if net.prev_act_dim else None
     for t in reversed(range(T)):
         f_t, vmask, g3, idx, m, cells, top = tape[t]
         dout = np.concatenate([dlogits[t], dvalues[t][:, None]], axis=1)
@@ -389,11 +400,13 @@ def core_backward(P, net, tape, dlogits, dvalues, grads):
         dfeat[t] = dft
         g["fc.w"] = g["fc.w"] + dwf
         g["fc.b"] = g["fc.b"] + dbf
-        if net.goal_mode == "polar":
+        if net.goal_mode in ("polar", "vec3"):
             dgf = dx[:, nv:nv + net.goal_dim]
-            _, dwg, dbg = nn.linear_backward(g3, P["goal.w"], dgf)
+            dg3, dwg, dbg = nn.linear_backward(g3, P["goal.w"], dgf)
             g["goal.w"] = g["goal.w"] + dwg
             g["goal.b"] = g["goal.b"] + dbg
+            if dgoal is not None:
+                dgoal[t] = dg3
         if net.prev_act_dim:
             de = dx[:, nv + net.goal_dim:]
             np.add.at(emb_grad, idx, de)

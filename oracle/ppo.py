@@ -114,6 +114,49 @@ def minibatch_inputs(net, inp, rec, adv, ret, envs):
     }
 
 
+def objective(logits, values, mb, ppo, adv_norm=None, with_grad=True):
+    """The PPO objective of one minibatch on given policy outputs (logits
+    [T_B,B,A], values [T_B,B]):
+      L = -sum_n w_n sum_t min(r A, clip(r, 1-eps, 1+eps) A)
+          + c_v sum_n w_n sum_t 1/2 (V - R)^2 - c_e sum_n w_n sum_t H(pi),
+      w_n = 1 / (|B| T_n) (Eq. 2, Sec. 3).  Returns the statistics [8] and,
+    with_grad, dL/dlogits and dL/dvalues (else None, None)."""
+    lens = mb["lens"]
+    TB, B = mb["action"].shape
+    A_ = logits.shape[2]
+    valid = np.arange(TB)[:, None] < lens[None, :]
+    w = valid / (B * lens[None, :].astype(np.float64))
+    lp = nn.log_softmax(logits)
+    p = np.exp(lp)
+    a = mb["action"]
+    lpa = np.take_along_axis(lp, a[..., None], axis=2)[..., 0]
+    adv = np.asarray(mb["adv"], np.float64)
+    if adv_norm is not None:
+        adv = (adv - adv_norm[0]) / (np.sqrt(adv_norm[1]) + 1e-5)
+    ratio = np.exp(lpa - mb["logp_old"])
+    s1 = ratio * adv
+    s2 = np.clip(ratio, 1 - ppo.clip, 1 + ppo.clip) * adv
+    surr = np.minimum(s1, s2)
+    ent = -(p * lp).sum(axis=2)
+    L_pg = -(w * surr).sum()
+    L_v = (w * 0.5 * (values - mb["ret"]) ** 2).sum()
+    L_H = (w * ent).sum()
+    loss = L_pg + ppo.value_coef * L_v - ppo.entropy_coef * L_H
+    clipped = np.abs(ratio - 1.0) > ppo.clip
+    stats = np.array([loss, L_pg, L_v, L_H, (w * clipped).sum(),
+                      (w * (mb["logp_old"] - lpa)).sum(),
+                      ratio[valid].min(), ratio[valid].max()])
+    if not with_grad:
+        return stats, None, None
+    # d/d logp(a): the unclipped branch (taken at ties) carries r*A
+    dlpa = np.where(s1 <= s2, -w * adv * ratio, 0.0)
+    onehot = np.eye(A_)[a]
+    dlogits = dlpa[..., None] * (onehot - p)
+    dlogits += ppo.entropy_coef * w[..., None] * p * (lp + ent[..., None])
+    dvalues = ppo.value_coef * w * (values - mb["ret"])
+    return stats, dlogits, dvalues
+
+
 def loss_grad(flat, net, ppo, mb, with_grad=True, adv_norm=None, decide=None, quant=None, record=None,
               record_outputs=True):
     """PPO loss of one minibatch and (optionally) its flat gradient.
@@ -157,34 +200,9 @@ def loss_grad(flat, net, ppo, mb, with_grad=True, adv_norm=None, decide=None, qu
         record["vis"] = np.where(valid[..., None], vis_pre, 0.0)
         for k, v in qrec.items():     # time-major [T_B, B, .]; invalid frames 0
             record[k] = np.where(valid[..., None], np.stack(v), 0.0)
-    lp = nn.log_softmax(logits)
-    p = np.exp(lp)
-    a = mb["action"]
-    lpa = np.take_along_axis(lp, a[..., None], axis=2)[..., 0]
-    adv = np.asarray(mb["adv"], np.float64)
-    if adv_norm is not None:
-        adv = (adv - adv_norm[0]) / (np.sqrt(adv_norm[1]) + 1e-5)
-    ratio = np.exp(lpa - mb["logp_old"])
-    s1 = ratio * adv
-    s2 = np.clip(ratio, 1 - ppo.clip, 1 + ppo.clip) * adv
-    surr = np.minimum(s1, s2)
-    ent = -(p * lp).sum(axis=2)
-    L_pg = -(w * surr).sum()
-    L_v = (w * 0.5 * (values - mb["ret"]) ** 2).sum()
-    L_H = (w * ent).sum()
-    loss = L_pg + ppo.value_coef * L_v - ppo.entropy_coef * L_H
-    clipped = np.abs(ratio - 1.0) > ppo.clip
-    stats = np.array([loss, L_pg, L_v, L_H, (w * clipped).sum(),
-                      (w * (mb["logp_old"] - lpa)).sum(),
-                      ratio[valid].min(), ratio[valid].max()])
+    stats, dlogits, dvalues = objective(logits, values, mb, ppo, adv_norm, with_grad)
     if not with_grad:
         return stats, None
-    # d/d logp(a): the unclipped branch (taken at ties) carries r*A
-    dlpa = np.where(s1 <= s2, -w * adv * ratio, 0.0)
-    onehot = np.eye(A_)[a]
-    dlogits = dlpa[..., None] * (onehot - p)
-    dlogits += ppo.entropy_coef * w[..., None] * p * (lp + ent[..., None])
-    dvalues = ppo.value_coef * w * (values - mb["ret"])
     grads = {}
     dfeat = policy.core_backward(P, net, tape, dlogits, dvalues, grads)
     policy.encode_backward(P, net, mb["obs"][tt, jj], dfeat[tt, jj], grads, decide=enc_decide, quant=quant)

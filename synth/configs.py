@@ -32,19 +32,21 @@ class NetDesc:
     in_ch: int = 4
     in_hw: int = 256
     avgpool: bool = True
-    trunk: str = "resnet"            # 'tiny' | 'resnet' | 'seresnext'
+    trunk: str = "resnet"            # 'tiny' | 'resnet' | 'seresnext' | 'none' (in_ch-wide features in)
     tiny_ch: Tuple[int, int] = (16, 32)
     base_width: int = 32
     blocks: Tuple[int, int, int, int] = (3, 4, 6, 3)
     gn_groups: int = 16
     compress_ch: int = 128
     vis_hidden: int = 512
-    goal_mode: str = "polar"         # 'raw' (2-vector concatenated) | 'polar' ([d,cos,sin] -> FC)
+    goal_mode: str = "polar"         # 'raw' (2-vector concatenated) | 'polar' ([d,cos,sin] -> FC) |
+                                     # 'vec3' (a given [magnitude, direction] 3-vector -> FC) | 'none
     goal_dim: int = 32               # width of the goal features fed to the LSTM
     prev_act_dim: int = 32           # 0: no previous-action embedding
     lstm_layers: int = 2
     hidden: int = 512
     num_actions: int = 4
+    prev_actions: int = 0            # previous-action vocabulary (0: num_actions); + 1 start token
     cardinality: int = 16            # seresnext: groups of the 3x3 convolution
     se_reduction: int = 16           # seresnext: squeeze-excite hidden width = C / se_reduction
 
@@ -62,12 +64,16 @@ class NetDesc:
     @property
     def feat_hw(self) -> int:
         """Spatial size of the map that is flattened into the visual FC."""
+        if self.trunk == "none":
+            return 1
         if self.trunk == "tiny":
             return self.enc_hw // 4
         return self.enc_hw // 32
 
     @property
     def feat_ch(self) -> int:
+        if self.trunk == "none":
+            return self.in_ch
         return self.tiny_ch[1] if self.trunk == "tiny" else self.compress_ch
 
     @property
@@ -75,8 +81,29 @@ class NetDesc:
         return self.feat_ch * self.feat_hw * self.feat_hw
 
     @property
+    def emb_rows(self) -> int:
+        """Rows of the previous-action embedding: every action and the start token."""
+        return (self.prev_actions or self.num_actions) + 1
+
+    @property
     def lstm_in(self) -> int:
         return self.vis_hidden + self.goal_dim + self.prev_act_dim
+
+
+def controller_nets(agent: NetDesc, plan_hidden: int = 512):
+    """The two features-in nets of the neural-controller system built on a
+    trained agent (Sec. 6, appendix "Neural controller additional details"):
+    the controller core (the agent's policy core, its goal FC fed a given
+    [magnitude, direction] 3-vector) and the planner (the same policy layout
+    with a plan_hidden-wide visual FC and LSTM, no goal input, the agent's
+    previous actions, and 3 head outputs besides the value)."""
+    if agent.goal_mode != "polar":
+        raise ValueError("the controller's goal FC must read a 3-vector (polar goal agents)")
+    feat = dict(trunk="none", in_ch=agent.flat_dim, in_hw=1, avgpool=False)
+    ctrl = replace(agent, goal_mode="vec3", **feat)
+    plan = replace(agent, goal_mode="none", goal_dim=0, num_actions=3, prev_actions=agent.num_actions,
+                   hidden=plan_hidden, vis_hidden=plan_hidden, **feat)
+    return ctrl, plan
 
 
 @dataclass(frozen=True)

@@ -21,8 +21,9 @@ Order (tensor, shape):
                  se1.w [4w/r][4w], se1.b [4w/r], se2.w [4w][4w/r], se2.b [4w],
                  then (block 0 only) ds
   visual FC    : fc.w [vis_hidden][flat_dim] (input index in C,H,W order), fc.b
-  goal FC      : goal.w [goal_dim][3], goal.b [goal_dim]     (polar goal only)
-  prev action  : emb [A+1][prev_act_dim]                     (if prev_act_dim > 0)
+  goal FC      : goal.w [goal_dim][3], goal.b [goal_dim]     (polar or 3-vector goal only)
+  trunk 'none' : no encoder tensors (the visual FC reads in_ch-wide features)
+  prev action  : emb [A'+1][prev_act_dim], A' = prev_actions or num_actions (if prev_act_dim > 0)
   LSTM layer l : lstm{l}.w [4H][in_l + H] (input columns, then recurrent columns;
                  gate row blocks i, f, g, o), lstm{l}.b [4H]
   heads        : head.w [A+1][H] (rows 0..A-1 policy logits, row A value), head.b [A+1]
@@ -62,7 +63,9 @@ def tensor_list(net: NetDesc) -> List[Tensor]:
         add(name + ".g", (c,), "gn_g")
         add(name + ".b", (c,), "gn_b")
 
-    if net.trunk == "tiny":
+    if net.trunk == "none":
+        pass                       # features in: no encoder tensors
+    elif net.trunk == "tiny":
         c1, c2 = net.tiny_ch
         conv("enc.conv1", c1, 3, net.in_ch)
         gn("enc.gn1", c1)
@@ -99,11 +102,11 @@ def tensor_list(net: NetDesc) -> List[Tensor]:
         gn("enc.compress.gn", net.compress_ch)
     add("fc.w", (net.vis_hidden, net.flat_dim), "fc", net.flat_dim)
     add("fc.b", (net.vis_hidden,), "bias")
-    if net.goal_mode == "polar":
+    if net.goal_mode in ("polar", "vec3"):
         add("goal.w", (net.goal_dim, 3), "fc", 3)
         add("goal.b", (net.goal_dim,), "bias")
     if net.prev_act_dim > 0:
-        add("emb", (net.num_actions + 1, net.prev_act_dim), "emb")
+        add("emb", (net.emb_rows, net.prev_act_dim), "emb")
     H = net.hidden
     for l in range(net.lstm_layers):
         nin = net.lstm_in if l == 0 else H

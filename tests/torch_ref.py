@@ -83,9 +83,16 @@ def encoder(P, net, obs, quant=None):
 def policy_seq(P, net, obs, goal, prev_a, masks, h0, c0, quant=None):
     """obs [T,B,C,H,W] -> logits [T,B,A], values [T,B].  quant: the
     precision form (every conv, visual-FC and LSTM operand rounded)."""
-    q = quantizer(quant)
     T, B = obs.shape[:2]
     feat = encoder(P, net, obs.reshape(T * B, *obs.shape[2:]), quant).reshape(T, B, -1)
+    return policy_core(P, net, feat, goal, prev_a, masks, h0, c0, quant)
+
+
+def policy_core(P, net, feat, goal, prev_a, masks, h0, c0, quant=None):
+    """feat [T,B,flat] -> logits [T,B,A], values [T,B]; goal [T,B,2] (raw or
+    polar goal modes), [T,B,3] (a given 3-vector: 'vec3') or unused ('none')."""
+    q = quantizer(quant)
+    T, B = feat.shape[:2]
     H = net.hidden
     cells = []
     for l in range(net.lstm_layers):
@@ -103,7 +110,9 @@ def policy_seq(P, net, obs, goal, prev_a, masks, h0, c0, quant=None):
             d, th = goal[t][:, 0], goal[t][:, 1]
             g3 = torch.stack([d, torch.cos(th), torch.sin(th)], 1)
             parts.append(F.linear(g3, P["goal.w"], P["goal.b"]))
-        else:
+        elif net.goal_mode == "vec3":
+            parts.append(F.linear(goal[t], P["goal.w"], P["goal.b"]))
+        elif net.goal_mode == "raw":
             parts.append(goal[t])
         if net.prev_act_dim:
             idx = torch.where(masks[t] == 0, torch.zeros_like(prev_a[t]), prev_a[t] + 1)
@@ -142,3 +151,35 @@ def ppo_loss(net, ppo, flat, mb, quant=None):
          - ppo.entropy_coef * (w * ent).sum())
     L.backward()
     return L.item(), flat_t.grad.numpy().copy(), logits.detach().numpy(), values.detach().numpy()
+
+
+def controller_system_loss(agent_net, agent_flat, ctrl_net, ctrl_flat, plan_net, plan_flat, ppo, mb):
+    """The neural-controller system's PPO loss and its gradient with respect
+    to the planner's parameters only, by autograd: frozen encoder features,
+    planner core -> [ELU(r0) + 0.75, tanh(r1), tanh(r2)] -> frozen controller
+    core -> PPO on the controller's logits and the planner's value."""
+    tt = lambda a, dt=torch.float64: torch.tensor(np.asarray(a), dtype=dt)
+    lens = tt(mb["lens"])
+    TB, B = mb["action"].shape
+    valid = (torch.arange(TB, dtype=torch.float64)[:, None] < lens[None, :]).double()
+    w = valid / (B * lens[None, :])
+    _, Pa = unpack(agent_net, agent_flat, requires_grad=False)
+    obs = tt(mb["obs"])
+    with torch.no_grad():
+        feat = encoder(Pa, agent_net, obs.reshape(TB * B, *obs.shape[2:])).reshape(TB, B, -1) * valid[..., None]
+    flat_p, Pp = unpack(plan_net, plan_flat, requires_grad=True)
+    _, Pc = unpack(ctrl_net, ctrl_flat, requires_grad=False)
+    pa, masks = tt(mb["prev_action"], torch.int64), tt(mb["mask"])
+    raw, values = policy_core(Pp, plan_net, feat, None, pa, masks, tt(mb["h0_plan"]), tt(mb["c0_plan"]))
+    goal = torch.stack([F.elu(raw[..., 0]) + 0.75, torch.tanh(raw[..., 1]), torch.tanh(raw[..., 2])], -1)
+    logits, _ = policy_core(Pc, ctrl_net, feat, goal, pa, masks, tt(mb["h0"]), tt(mb["c0"]))
+    lp = F.log_softmax(logits, -1)
+    lpa = lp.gather(2, tt(mb["action"], torch.int64)[..., None])[..., 0]
+    adv = tt(mb["adv"])
+    ratio = torch.exp(lpa - tt(mb["logp_old"]))
+    surr = torch.min(ratio * adv, torch.clamp(ratio, 1 - ppo.clip, 1 + ppo.clip) * adv)
+    ent = -(lp.exp() * lp).sum(-1)
+    L = (-(w * surr).sum() + ppo.value_coef * (w * 0.5 * (values - tt(mb["ret"])) ** 2).sum()
+         - ppo.entropy_coef * (w * ent).sum())
+    L.backward()
+    return L.item(), flat_p.grad.numpy().copy(), goal.detach().numpy()
