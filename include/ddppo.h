@@ -68,8 +68,8 @@ typedef enum {
 } ppo_status;
 
 enum { PPO_F32 = 0, PPO_BF16 = 1 };
-enum { PPO_TRUNK_TINY = 0, PPO_TRUNK_RESNET = 1, PPO_TRUNK_SERESNEXT = 2 };
-enum { PPO_GOAL_RAW = 0, PPO_GOAL_POLAR = 1 };
+enum { PPO_TRUNK_TINY = 0, PPO_TRUNK_RESNET = 1, PPO_TRUNK_SERESNEXT = 2, PPO_TRUNK_NONE = 3 };
+enum { PPO_GOAL_RAW = 0, PPO_GOAL_POLAR = 1, PPO_GOAL_VEC3 = 2, PPO_GOAL_NONE = 3 };
 enum { PPO_OP_ACT = 0, PPO_OP_LEARN = 1, PPO_OP_LOSS = 2 };
 
 /* Network shape (appendix "Agent Design"; Sec. 4 "Agent").  The visual
@@ -86,14 +86,17 @@ typedef struct ppo_net_desc {
   int in_ch;          /* frame channels (4: RGB-D)                              */
   int in_hw;          /* frame height = width (256)                             */
   int avgpool;        /* 1: 2x2 average pool before the trunk                   */
-  int trunk;          /* PPO_TRUNK_TINY | PPO_TRUNK_RESNET | PPO_TRUNK_SERESNEXT  */
+  int trunk;          /* PPO_TRUNK_TINY | _RESNET | _SERESNEXT | _NONE (features in:
+                         frames are float32 [in_ch] vectors; in_hw 1, no avgpool)   */
   int tiny_ch[2];     /* tiny trunk widths (16, 32)                             */
   int base_width;     /* resnet stem width; stage widths w0*2^s (32)            */
   int blocks[4];      /* bottlenecks per stage (3, 4, 6, 3)                     */
   int gn_groups;      /* GroupNorm groups (16 resnet, 8 tiny)                   */
   int compress_ch;    /* compression conv output channels (128)                 */
   int vis_hidden;     /* visual FC width (512)                                  */
-  int goal_mode;      /* PPO_GOAL_RAW: [2] concatenated; PPO_GOAL_POLAR: FC-32  */
+  int goal_mode;      /* PPO_GOAL_RAW: [2] concatenated; PPO_GOAL_POLAR: (d, theta)
+                         -> [d, cos, sin] -> FC; PPO_GOAL_VEC3: a given [3] -> FC;
+                         PPO_GOAL_NONE: no goal input (goal_dim 0, goal may be NULL) */
   int goal_dim;       /* 2 for raw, FC width for polar                          */
   int prev_act_dim;   /* previous-action embedding width, 0 = none              */
   int lstm_layers;    /* 1 or 2                                                 */
@@ -102,6 +105,8 @@ typedef struct ppo_net_desc {
   int dtype;          /* PPO_F32 | PPO_BF16: GEMM operand precision             */
   int cardinality;    /* seresnext: groups of each bottleneck's 3x3 convolution (16) */
   int se_reduction;   /* seresnext: squeeze-excite hidden width = C / se_reduction (16) */
+  int prev_actions;   /* previous-action vocabulary of the embedding (0: num_actions);
+                         the table has prev_actions + 1 rows (start token first)   */
 } ppo_net_desc;
 
 typedef struct ppo_net ppo_net;
@@ -251,6 +256,39 @@ ppo_status ppo_policy_forward(ppo_net* net, const ppo_batch* b, float* logits, f
 ppo_status ppo_policy_backward(ppo_net* net, const ppo_batch* b, const float* dlogits,
                                const float* dvalues, float* grad, void* ws, size_t ws_bytes,
                                void* stream);
+
+/* ppo_policy_backward_ex -- ppo_policy_backward for nets used inside a larger
+ * differentiable system (the neural controller of Sec. 6 "Transfer
+ * Learning": a planner trained through a frozen controller).  grad may be
+ * NULL: then no parameter gradient is formed (a frozen net) and only data
+ * gradients run.  dgoal (PPO_GOAL_VEC3 nets, or NULL) receives the gradient
+ * with respect to the goal input, [F][3] float32 in the packed frame order of
+ * ppo_policy_forward.  At least one of grad and dgoal must be given. */
+ppo_status ppo_policy_backward_ex(ppo_net* net, const ppo_batch* b, const float* dlogits,
+                                  const float* dvalues, float* grad, float* dgoal, void* ws,
+                                  size_t ws_bytes, void* stream);
+
+/* ppo_encode -- the visual encoder alone (App. "Agent Design": average pool,
+ * trunk, compression conv) on `frames` frames obs [frames][C][H][W] (float32,
+ * or bfloat16 for PPO_BF16 nets): feat [frames][flat] float32 (channel, row,
+ * column order: the visual FC's input).  No gradient, nothing kept.  The
+ * workspace is that of ppo_act (op PPO_OP_ACT, max_frames >= frames).  Used
+ * for a frozen encoder shared by several heads (the neural controller). */
+ppo_status ppo_encode(ppo_net* net, const void* obs, int frames, const float* params, const void* params_lp,
+                      float* feat, void* ws, size_t ws_bytes, void* stream);
+
+/* ppo_planner_goal -- the neural controller's PointGoal (appendix "Neural
+ * controller additional details") from the planner's raw head outputs:
+ * goal = [ELU(r0) + 0.75, tanh(r1), tanh(r2)] (the direction is not
+ * renormalised).  raw: row f at raw + f*ld_raw (the first 3 columns);
+ * goal row dst[f] (device int32, or NULL for f) of a [*][3] float32 array.
+ * ppo_planner_goal_backward: draw (rows of stride ld_raw, first 3 columns)
+ * = dgoal [frames][3] (dense, row f) times the transform's derivative at raw
+ * (ELU' = 1 for r > 0, exp(r) otherwise; tanh' = 1 - tanh^2). */
+ppo_status ppo_planner_goal(const float* raw, int ld_raw, const int32_t* dst, int frames, float* goal,
+                            void* stream);
+ppo_status ppo_planner_goal_backward(const float* raw, int ld_raw, const float* dgoal, int frames, float* draw,
+                                     void* stream);
 
 /* ppo_loss_head -- the objective of ppo_loss_backward (Eq. 2 with the value
  * and entropy terms, weights w_n = 1/(|B| T_n) of Sec. 3, optional advantage

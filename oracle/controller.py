@@ -55,53 +55,67 @@ def goal_transform_backward(raw, dgoal):
     return np.stack([d0, d1, d2], axis=-1)
 
 
-def features(agent_net, agent_flat, obs):
-    """The frozen encoder's features of frames [F, C, H, W] -> [F, flat]."""
-    P = params.unpack(agent_net, agent_flat)
-    return policy.encode(P, agent_net, obs)
+def features(agent_net, agent_flat, obs, quant=None):
+    """The frozen encoder's features of frames [F, C, H, W] -> [F, flat]
+    (quant: the precision form of oracle.policy)."""
+    P = policy.quantize_params(agent_net, params.unpack(agent_net, agent_flat), quant)
+    return policy.encode(P, agent_net, obs, quant=quant)
 
 
-def act(sys, obs, prev_a, mask, hp, cp, hc, cc, u):
+def _cores(sys, quant):
+    Pp = policy.quantize_params(sys.plan_net, params.unpack(sys.plan_net, sys.plan_flat), quant)
+    Pc = policy.quantize_params(sys.ctrl_net, params.unpack(sys.ctrl_net, sys.ctrl_flat), quant)
+    return Pp, Pc
+
+
+def act(sys, obs, prev_a, mask, hp, cp, hc, cc, u, feat=None, quant=None):
     """One act step of the system for B envs: features, planner step, goal,
     controller step, inverse-CDF sample.  hp/cp and hc/cc: the planner's and
-    the controller's [L, B, H] states.  Returns a dict: action, logp (the
-    controller's), value (the planner's), goal [B, 3], raw [B, 3], logits,
-    and the next states."""
-    feat = features(sys.agent_net, sys.agent_flat, obs)[None]
-    Pp = params.unpack(sys.plan_net, sys.plan_flat)
-    Pc = params.unpack(sys.ctrl_net, sys.ctrl_flat)
+    the controller's [L, B, H] states.  feat [B, flat]: given features (else
+    the encoder's of obs); quant: the precision form of oracle.policy for
+    every product operand.  Returns a dict: action, logp (the controller's),
+    value (the planner's), goal [B, 3], raw [B, 3], logits, and the next
+    states."""
+    if feat is None:
+        feat = features(sys.agent_net, sys.agent_flat, obs, quant)
+    feat = np.asarray(feat, np.float64)[None]
+    Pp, Pc = _cores(sys, quant)
     m = np.asarray(mask, np.float64)[None]
     pa = np.asarray(prev_a)[None]
-    raw, value, (hp2, cp2), _ = policy.core_forward(Pp, sys.plan_net, feat, None, pa, m, hp, cp)
+    raw, value, (hp2, cp2), _ = policy.core_forward(Pp, sys.plan_net, feat, None, pa, m, hp, cp, quant=quant)
     goal = goal_transform(raw[0])
-    logits, _, (hc2, cc2), _ = policy.core_forward(Pc, sys.ctrl_net, feat, goal[None], pa, m, hc, cc)
+    logits, _, (hc2, cc2), _ = policy.core_forward(Pc, sys.ctrl_net, feat, goal[None], pa, m, hc, cc, quant=quant)
     lp = nn.log_softmax(logits[0])
     a = policy.sample(lp, u)
     return {"action": a, "logp": np.take_along_axis(lp, a[:, None], axis=1)[:, 0], "value": value[0],
             "goal": goal, "raw": raw[0], "logits": logits[0], "hp": hp2, "cp": cp2, "hc": hc2, "cc": cc2}
 
 
-def loss_grad(sys, ppo_cfg, mb, with_grad=True, adv_norm=None):
+def loss_grad(sys, ppo_cfg, mb, with_grad=True, adv_norm=None, feat=None, quant=None):
     """PPO loss of one minibatch of the system and its gradient with respect
     to the planner's flat parameters.  mb as oppo.minibatch_inputs gives it
     (frames 'obs', 'prev_action', 'mask', 'action', 'logp_old', 'adv', 'ret',
     'lens'), with the controller's start state 'h0', 'c0' and the planner's
-    'h0_plan', 'c0_plan' [L, B, H].  Returns (stats [8], planner gradient or
-    None, extras) with extras holding the planner's raw outputs, the goals
-    and the controller's logits [T_B, B, .]."""
+    'h0_plan', 'c0_plan' [L, B, H].  feat [T_B, B, flat]: given features of
+    the frames (else the encoder's); quant: the precision form of
+    oracle.policy (every product operand of the encoder and the two cores
+    rounded; straight-through gradients).  Returns (stats [8], planner
+    gradient or None, extras) with extras holding the planner's raw outputs,
+    the goals and the controller's logits [T_B, B, .]."""
     lens = mb["lens"]
     TB, B = mb["action"].shape
     valid = np.arange(TB)[:, None] < lens[None, :]
     tt, jj = np.nonzero(valid)
-    feat = np.zeros((TB, B, sys.ctrl_net.flat_dim))
-    feat[tt, jj] = features(sys.agent_net, sys.agent_flat, mb["obs"][tt, jj])
-    Pp = params.unpack(sys.plan_net, sys.plan_flat)
-    Pc = params.unpack(sys.ctrl_net, sys.ctrl_flat)
+    if feat is None:
+        feat = np.zeros((TB, B, sys.ctrl_net.flat_dim))
+        feat[tt, jj] = features(sys.agent_net, sys.agent_flat, mb["obs"][tt, jj], quant)
+    feat = np.where(valid[..., None], np.asarray(feat, np.float64), 0.0)
+    Pp, Pc = _cores(sys, quant)
     raw, values, _, tape_p = policy.core_forward(Pp, sys.plan_net, feat, None, mb["prev_action"], mb["mask"],
-                                                 mb["h0_plan"], mb["c0_plan"], keep=with_grad)
+                                                 mb["h0_plan"], mb["c0_plan"], keep=with_grad, quant=quant)
     goal = goal_transform(raw)
     logits, _, _, tape_c = policy.core_forward(Pc, sys.ctrl_net, feat, goal, mb["prev_action"], mb["mask"],
-                                               mb["h0"], mb["c0"], keep=with_grad)
+                                               mb["h0"], mb["c0"], keep=with_grad, quant=quant)
     stats, dlogits, dvalues = oppo.objective(logits, values, mb, ppo_cfg, adv_norm, with_grad)
     extras = {"raw": raw, "goal": goal, "logits": logits, "values": values}
     if not with_grad:

@@ -12,8 +12,8 @@ P_i32 = C.POINTER(C.c_int32)
 
 PPO_OK, PPO_EINVAL, PPO_ESHAPE, PPO_EUNSUPPORTED, PPO_EWORKSPACE, PPO_EDEVICE = 0, -1, -2, -3, -4, -5
 PPO_F32, PPO_BF16 = 0, 1
-PPO_TRUNK_TINY, PPO_TRUNK_RESNET, PPO_TRUNK_SERESNEXT = 0, 1, 2
-PPO_GOAL_RAW, PPO_GOAL_POLAR = 0, 1
+PPO_TRUNK_TINY, PPO_TRUNK_RESNET, PPO_TRUNK_SERESNEXT, PPO_TRUNK_NONE = 0, 1, 2, 3
+PPO_GOAL_RAW, PPO_GOAL_POLAR, PPO_GOAL_VEC3, PPO_GOAL_NONE = 0, 1, 2, 3
 PPO_OP_ACT, PPO_OP_LEARN, PPO_OP_LOSS = 0, 1, 2
 PPO_TIMER_ALL_UNITS = -2
 
@@ -27,7 +27,7 @@ class NetDesc(C.Structure):
                 ("gn_groups", c_int), ("compress_ch", c_int), ("vis_hidden", c_int),
                 ("goal_mode", c_int), ("goal_dim", c_int), ("prev_act_dim", c_int),
                 ("lstm_layers", c_int), ("hidden", c_int), ("num_actions", c_int), ("dtype", c_int),
-                ("cardinality", c_int), ("se_reduction", c_int)]
+                ("cardinality", c_int), ("se_reduction", c_int), ("prev_actions", c_int)]
 
 
 class ActIO(C.Structure):
@@ -76,6 +76,11 @@ EXPORTS = {
                                    c_size_t, c_void_p]),
     "ppo_policy_backward": (c_int, [c_void_p, C.POINTER(Batch), c_void_p, c_void_p, c_void_p, c_void_p,
                                     c_size_t, c_void_p]),
+    "ppo_policy_backward_ex": (c_int, [c_void_p, C.POINTER(Batch), c_void_p, c_void_p, c_void_p, c_void_p,
+                                       c_void_p, c_size_t, c_void_p]),
+    "ppo_encode": (c_int, [c_void_p, c_void_p, c_int, c_void_p, c_void_p, c_void_p, c_void_p, c_size_t, c_void_p]),
+    "ppo_planner_goal": (c_int, [c_void_p, c_int, c_void_p, c_int, c_void_p, c_void_p]),
+    "ppo_planner_goal_backward": (c_int, [c_void_p, c_int, c_void_p, c_int, c_void_p, c_void_p]),
     "ppo_loss_head": (c_int, [c_void_p, C.POINTER(Batch), C.POINTER(LossCfg), c_void_p, c_void_p, c_void_p,
                               c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_size_t, c_void_p]),
     "ppo_loss_head_noalloc": (c_int, [c_void_p, C.POINTER(Batch), C.POINTER(LossCfg), c_void_p, c_void_p, c_void_p,

@@ -50,7 +50,8 @@ def desc_from(spec, dtype: str) -> L.NetDesc:
     and for seresnext cardinality, se_reduction)."""
     d = L.NetDesc()
     d.in_ch, d.in_hw, d.avgpool = spec.in_ch, spec.in_hw, int(bool(spec.avgpool))
-    trunks = {"tiny": L.PPO_TRUNK_TINY, "resnet": L.PPO_TRUNK_RESNET, "seresnext": L.PPO_TRUNK_SERESNEXT}
+    trunks = {"tiny": L.PPO_TRUNK_TINY, "resnet": L.PPO_TRUNK_RESNET, "seresnext": L.PPO_TRUNK_SERESNEXT,
+              "none": L.PPO_TRUNK_NONE}
     if spec.trunk not in trunks:
         raise ValueError(f"unknown trunk {spec.trunk!r}")
     d.trunk = trunks[spec.trunk]
@@ -61,7 +62,11 @@ def desc_from(spec, dtype: str) -> L.NetDesc:
     for i in range(4):
         d.blocks[i] = spec.blocks[i]
     d.gn_groups, d.compress_ch, d.vis_hidden = spec.gn_groups, spec.compress_ch, spec.vis_hidden
-    d.goal_mode = L.PPO_GOAL_POLAR if spec.goal_mode == "polar" else L.PPO_GOAL_RAW
+    goals = {"raw": L.PPO_GOAL_RAW, "polar": L.PPO_GOAL_POLAR, "vec3": L.PPO_GOAL_VEC3, "none": L.PPO_GOAL_NONE}
+    if spec.goal_mode not in goals:
+        raise ValueError(f"unknown goal mode {spec.goal_mode!r}")
+    d.goal_mode = goals[spec.goal_mode]
+    d.prev_actions = getattr(spec, "prev_actions", 0)
     d.goal_dim, d.prev_act_dim = spec.goal_dim, spec.prev_act_dim
     d.lstm_layers, d.hidden, d.num_actions = spec.lstm_layers, spec.hidden, spec.num_actions
     d.dtype = L.PPO_BF16 if dtype == "bf16" else L.PPO_F32
@@ -89,6 +94,7 @@ class Net:
         self._h = h
         self.P = int(lib().ppo_param_count(h))
         self.L, self.H, self.A = spec.lstm_layers, spec.hidden, spec.num_actions
+        self.flat = int(spec.flat_dim)      # width of the visual FC's input (the encoder's output)
         self._ws = {}
         self._last_learn = None   # (frames, envs) of the last learner call
 
@@ -201,9 +207,11 @@ class Net:
         device) are written."""
         B = obs.shape[0]
         SR = state_rows or B
-        odt = torch.bfloat16 if self.bf16 else torch.float32
+        odt = torch.bfloat16 if self.bf16 and self.spec.trunk != "none" else torch.float32
         _need(obs, odt, "obs")
-        _need(goal, torch.float32, "goal", B * 2)
+        gw = {"raw": 2, "polar": 2, "vec3": 3}.get(self.spec.goal_mode, 0)
+        if gw:
+            _need(goal, torch.float32, "goal", B * gw)
         _need(mask, torch.float32, "mask", B)
         # rows < B of every layer are read: at least (L-1)*SR*H + B*H elements
         need_state = (self.L - 1) * SR * self.H + B * self.H
@@ -253,9 +261,12 @@ class Net:
         T = T1 - 1
         fields = [("mask", torch.float32, T1 * N)]
         if inputs:
-            _need(ro["obs"], torch.bfloat16 if self.bf16 else torch.float32, "obs")
-            fields += [("goal", torch.float32, T1 * N * 2), ("h0", torch.float32, self.L * N * self.H),
-                       ("c0", torch.float32, self.L * N * self.H)]
+            # a features-in net reads float32 feature vectors in both precisions
+            _need(ro["obs"], torch.bfloat16 if self.bf16 and self.spec.trunk != "none" else torch.float32, "obs")
+            fields += [("h0", torch.float32, self.L * N * self.H), ("c0", torch.float32, self.L * N * self.H)]
+            gw = {"raw": 2, "polar": 2, "vec3": 3}.get(self.spec.goal_mode, 0)
+            if gw:
+                fields.append(("goal", torch.float32, T1 * N * gw))
         if learner:
             fields += [("action", torch.int32, T1 * N), ("logp", torch.float32, T1 * N),
                        ("adv", torch.float32, T * N), ("ret", torch.float32, T * N)]
@@ -279,7 +290,7 @@ class Net:
         b.lengths = C.cast(lens, L.P_i32) if lens is not None else None
         b.mask = _ptr(ro["mask"])
         if inputs:
-            b.obs, b.goal, b.prev_action = _ptr(ro["obs"]), _ptr(ro["goal"]), _ptr(ro.get("prev_action"))
+            b.obs, b.goal, b.prev_action = _ptr(ro["obs"]), _ptr(ro.get("goal")), _ptr(ro.get("prev_action"))
             b.h0, b.c0 = _ptr(ro["h0"]), _ptr(ro["c0"])
             b.params, b.params_lp = _ptr(params), _ptr(params_lp)
         if learner:
@@ -386,6 +397,66 @@ class Net:
         check(lib().ppo_policy_backward(self._h, C.byref(b), _ptr(dlogits), _ptr(dvalues), _ptr(grad),
                                         _ptr(ws), ws.numel(), _stream(dev)), "ppo_policy_backward")
         return grad
+
+
+    def policy_backward_ex(self, ro, env_ids, lengths, params, params_lp, dlogits, dvalues, grad=None,
+                           dgoal=None):
+        """ppo_policy_backward_ex: grad (parameter gradient, or None for a frozen
+        net) and/or dgoal [F, 3] (goal-input gradient, 3-vector goal nets)."""
+        b, keep, F, dev = self._batch(ro, env_ids, lengths, params, params_lp, learner=False)
+        _need(dlogits, torch.float32, "dlogits", F * self.A)
+        _need(dvalues, torch.float32, "dvalues", F)
+        if grad is not None:
+            _need(grad, torch.float32, "grad", self.P)
+        if dgoal is not None:
+            _need(dgoal, torch.float32, "dgoal", F * 3)
+        ws = self.workspace(L.PPO_OP_LEARN, F, len(env_ids), dev)
+        self._last_learn = (F, len(env_ids))
+        check(lib().ppo_policy_backward_ex(self._h, C.byref(b), _ptr(dlogits), _ptr(dvalues), _ptr(grad),
+                                           _ptr(dgoal), _ptr(ws), ws.numel(), _stream(dev)),
+              "ppo_policy_backward_ex")
+        return grad, dgoal
+
+    def encode(self, obs, params, params_lp=None, out=None):
+        """ppo_encode: features [F, flat] of frames obs [F, C, H, W]."""
+        F = obs.shape[0]
+        _need(obs, torch.bfloat16 if self.bf16 and self.spec.trunk != "none" else torch.float32, "obs")
+        _need(params, torch.float32, "params", self.P)
+        if self.bf16:
+            _need(params_lp, torch.bfloat16, "params_lp", self.P)
+        dev = obs.device
+        out = torch.empty(F, self.flat, dtype=torch.float32, device=dev) if out is None else out
+        _need(out, torch.float32, "out", F * self.flat)
+        ws = self.workspace(L.PPO_OP_ACT, F, 1, dev)
+        check(lib().ppo_encode(self._h, _ptr(obs), F, _ptr(params), _ptr(params_lp), _ptr(out), _ptr(ws),
+                               ws.numel(), _stream(dev)), "ppo_encode")
+        return out
+
+
+def planner_goal(raw, dst=None, out=None, rows=None):
+    """ppo_planner_goal: [ELU(r0) + 0.75, tanh(r1), tanh(r2)] of raw [F, ld]
+    (first 3 columns) into row dst[f] (or f) of out [rows, 3]."""
+    F, ld = raw.shape
+    _need(raw, torch.float32, "raw")
+    if dst is not None:
+        _need(dst, torch.int32, "dst", F)
+    if out is None:
+        out = torch.zeros(rows or F, 3, dtype=torch.float32, device=raw.device)
+    _need(out, torch.float32, "out")
+    check(lib().ppo_planner_goal(_ptr(raw), ld, _ptr(dst), F, _ptr(out), _stream(raw.device)), "ppo_planner_goal")
+    return out
+
+
+def planner_goal_backward(raw, dgoal, out=None):
+    """ppo_planner_goal_backward: d raw [F, ld] (first 3 columns) from dgoal [F, 3]."""
+    F, ld = raw.shape
+    _need(raw, torch.float32, "raw")
+    _need(dgoal, torch.float32, "dgoal", F * 3)
+    out = torch.zeros_like(raw) if out is None else out
+    _need(out, torch.float32, "out", F * ld)
+    check(lib().ppo_planner_goal_backward(_ptr(raw), ld, _ptr(dgoal), F, _ptr(out), _stream(raw.device)),
+          "ppo_planner_goal_backward")
+    return out
 
 
 def gae(rew, val, done, lengths, gamma, lam, adv=None, ret=None, stats=None):

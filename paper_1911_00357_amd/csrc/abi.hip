@@ -66,6 +66,7 @@ struct ppo_net {
   int pool_h, pool_w;         // resnet max pool output size
   int feat_c, feat_hw, flat;
   int din0;                   // LSTM layer-0 input width
+  int emb_rows = 0;           // previous-action embedding rows (actions + start token)
   size_t fc_w, fc_b, goal_w, goal_b, emb, head_w, head_b;
   std::vector<size_t> lstm_w, lstm_b;
   // per-frame float counts used by the workspace planner
@@ -134,7 +135,13 @@ ppo_status build(ppo_net* n) {
   n->h0 = n->w0 = hw;
   const int G = d.gn_groups;
   n->max_G = G;
-  if (d.trunk == PPO_TRUNK_TINY) {
+  if (d.trunk == PPO_TRUNK_NONE) {
+    // features in: the visual FC reads in_ch-wide float32 vectors
+    if (d.in_hw != 1 || d.avgpool) return fail(PPO_ESHAPE, "a features-in net has in_hw 1 and no pooling");
+    n->h0 = n->w0 = 1;
+    n->feat_c = d.in_ch;
+    n->feat_hw = 1;
+  } else if (d.trunk == PPO_TRUNK_TINY) {
     const int c1 = d.tiny_ch[0], c2 = d.tiny_ch[1];
     if (c1 % G || c2 % G || c1 % 4 || c2 % 4) return fail(PPO_ESHAPE, "tiny widths must divide by groups and 4");
     int u1 = add_unit(n, "enc.conv1", d.in_ch, c1, 3, 2, 1, hw, hw);
@@ -202,15 +209,19 @@ ppo_status build(ppo_net* n) {
   n->flat = n->feat_c * n->feat_hw * n->feat_hw;
   n->fc_w = add_tensor(n, "fc.w", (size_t)d.vis_hidden * n->flat);
   n->fc_b = add_tensor(n, "fc.b", d.vis_hidden);
-  if (d.goal_mode == PPO_GOAL_POLAR) {
+  if (d.goal_mode == PPO_GOAL_POLAR || d.goal_mode == PPO_GOAL_VEC3) {
     n->goal_w = add_tensor(n, "goal.w", (size_t)d.goal_dim * 3);
     n->goal_b = add_tensor(n, "goal.b", d.goal_dim);
   } else if (d.goal_mode == PPO_GOAL_RAW) {
     if (d.goal_dim != 2) return fail(PPO_ESHAPE, "raw goal has goal_dim 2");
+  } else if (d.goal_mode == PPO_GOAL_NONE) {
+    if (d.goal_dim != 0) return fail(PPO_ESHAPE, "no goal input: goal_dim 0");
   } else {
     return fail(PPO_EINVAL, "unknown goal mode");
   }
-  if (d.prev_act_dim > 0) n->emb = add_tensor(n, "emb", (size_t)(d.num_actions + 1) * d.prev_act_dim);
+  if (d.prev_actions < 0) return fail(PPO_ESHAPE, "negative previous-action count");
+  n->emb_rows = (d.prev_actions > 0 ? d.prev_actions : d.num_actions) + 1;
+  if (d.prev_act_dim > 0) n->emb = add_tensor(n, "emb", (size_t)n->emb_rows * d.prev_act_dim);
   const int H = d.hidden;
   n->din0 = d.vis_hidden + d.goal_dim + std::max(0, d.prev_act_dim);
   for (int l = 0; l < d.lstm_layers; ++l) {
@@ -282,7 +293,7 @@ WsLayout plan(const ppo_net* n, int F, int nb, bool learn) {
     w.sea.push_back(se ? A.take((size_t)F * b.R * f4) : 0);
     w.ses.push_back(se ? A.take((size_t)F * u3.Cout * f4) : 0);
   }
-  if (d.trunk != PPO_TRUNK_TINY) {
+  if (d.trunk == PPO_TRUNK_RESNET || d.trunk == PPO_TRUNK_SERESNEXT) {
     const size_t ps = (size_t)F * n->pool_h * n->pool_w * d.base_width;
     w.pool = A.take(ps * f4);
     w.arg = A.take(ps);
@@ -422,6 +433,7 @@ void unit_fwd(const Ctx& c, int ui, const float* x, const float* res, bool relu,
 const float* encoder_fwd(const Ctx& c) {
   const ppo_net* n = c.n;
   const float* x0 = c.at(c.w->x0);
+  if (n->d.trunk == PPO_TRUNK_NONE) return x0;  // the input already is [F][flat]
   if (n->d.trunk == PPO_TRUNK_TINY) {
     unit_fwd(c, 0, x0, nullptr, true, c.at(c.w->a[0]), false);
     unit_fwd(c, 1, c.at(c.w->a[0]), nullptr, true, c.at(c.w->a[1]), true);
@@ -502,6 +514,7 @@ void unit_bwd(const Ctx& c, int ui, const float* dout, const float* mask_out, bo
 
 void encoder_bwd(const Ctx& c, const float* dfeat) {
   const ppo_net* n = c.n;
+  if (n->d.trunk == PPO_TRUNK_NONE) return;
   const WsLayout& w = *c.w;
   const float* x0 = c.at(w.x0);
   float *GA = c.at(w.ga), *GB = c.at(w.gb), *GU = c.at(w.gu), *GD = c.at(w.gd), *GR = c.at(w.gr);
@@ -714,7 +727,8 @@ ppo_status ppo_act(ppo_net* net, const ppo_act_io* io, void* ws, size_t ws_bytes
   const ppo_net_desc& d = net->d;
   const int B = io->batch;
   if (B <= 0) return fail(PPO_ESHAPE, "batch must be positive");
-  if (!io->obs || !io->goal || !io->mask || !io->h_in || !io->c_in || !io->u || !io->params ||
+  if (!io->obs || (!io->goal && d.goal_mode != PPO_GOAL_NONE) || !io->mask || !io->h_in || !io->c_in || !io->u ||
+      !io->params ||
       !io->action || !io->logp || !io->value || !io->h_out || !io->c_out ||
       (d.prev_act_dim > 0 && !io->prev_action) || (net->prec && !io->params_lp))
     return fail(PPO_EINVAL, "null pointer in ppo_act_io");
@@ -731,7 +745,8 @@ ppo_status ppo_act(ppo_net* net, const ppo_act_io* io, void* ws, size_t ws_bytes
   Ctx c{net, &w, (char*)ws, io->params, io->params_lp, nullptr, s, B};
   c.keep_u = false;
   // frames -> encoder -> features
-  launch_prep(io->obs, net->prec, nullptr, B, d.in_ch, d.in_hw, d.in_hw, d.avgpool, c.at(w.x0), s);
+  launch_prep(io->obs, d.trunk == PPO_TRUNK_NONE ? 0 : net->prec, nullptr, B, d.in_ch, d.in_hw, d.in_hw, d.avgpool,
+              c.at(w.x0), s);
   const float* feat = encoder_fwd(c);
   // layer-0 input [B][din0 + H] = [relu(FC(feat)) | goal | emb | mask*h0]
   const int ld0 = net->din0 + H;
@@ -739,14 +754,15 @@ ppo_status ppo_act(ppo_net* net, const ppo_act_io* io, void* ws, size_t ws_bytes
   gemm_dense(net->prec, false, false, feat, net->flat, c.wt(net->fc_w), net->prec == 1, net->flat, B,
              d.vis_hidden, net->flat, epi(zh, ld0, c.pf(net->fc_b), 1),
              false, kSplitKBytes, c.splitk(), s);
-  const bool polar = d.goal_mode == PPO_GOAL_POLAR;
+  const int gmode = d.goal_mode;  // goal kernels: 0 raw, 1 polar, 2 3-vector, 3 none
+  const bool polar = gmode == PPO_GOAL_POLAR || gmode == PPO_GOAL_VEC3;  // a goal FC exists
   if (fused) {
     // goal / embedding inputs and every layer's masked state in one launch (all
     // of h_in, c_in read before any output is written), then one launch per
     // layer; the masked copies use the layer-0 gate slab (4 B H floats)
     float* hm = c.at(w.g[0]);
     float* cm = hm + (size_t)L * B * H;
-    launch_act_core_prep(io->goal, io->prev_action, io->mask, B, polar, d.goal_dim,
+    launch_act_core_prep(io->goal, io->prev_action, io->mask, B, gmode, d.goal_dim,
                          polar ? c.pf(net->goal_w) : nullptr, polar ? c.pf(net->goal_b) : nullptr,
                          std::max(0, d.prev_act_dim), d.prev_act_dim > 0 ? c.pf(net->emb) : nullptr, zh, ld0,
                          d.vis_hidden, io->h_in, io->c_in, L, SR, H, hm, cm, s);
@@ -761,7 +777,7 @@ ppo_status ppo_act(ppo_net* net, const ppo_act_io* io, void* ws, size_t ws_bytes
                     io->u, io->action, io->logp, io->value, io->logits, io->active, s);
     return check_launch();
   }
-  launch_embed_fwd(io->goal, io->prev_action, io->mask, nullptr, B, polar,
+  launch_embed_fwd(io->goal, io->prev_action, io->mask, nullptr, B, gmode,
                    d.goal_dim, polar ? c.pf(net->goal_w) : nullptr,
                    polar ? c.pf(net->goal_b) : nullptr, std::max(0, d.prev_act_dim),
                    d.prev_act_dim > 0 ? c.pf(net->emb) : nullptr, zh, ld0, d.vis_hidden, s);
@@ -823,7 +839,8 @@ struct Sched {
 ppo_status schedule(const ppo_net* net, const ppo_batch* b, Sched& S, bool inputs = true, bool per_step = true) {
   const ppo_net_desc& d = net->d;
   if (!b->env_ids || !b->mask ||
-      (inputs && (!b->obs || !b->goal || !b->h0 || !b->c0 || !b->params || (net->prec && !b->params_lp) ||
+      (inputs && (!b->obs || (!b->goal && d.goal_mode != PPO_GOAL_NONE) || !b->h0 || !b->c0 || !b->params ||
+                  (net->prec && !b->params_lp) ||
                   (d.prev_act_dim > 0 && !b->prev_action))))
     return fail(PPO_EINVAL, "null pointer in ppo_batch");
   if (b->T <= 0 || b->N <= 0 || b->nb <= 0 || b->nb > b->N || b->nb > kMaxMbEnvs)
@@ -880,15 +897,17 @@ const float* learner_fwd(const Ctx& c, const ppo_batch* b, const Sched& S) {
   launch_gather_state(b->h0, L, b->N, nb, H, envrow, c.at(w.h0g), s);
   launch_gather_state(b->c0, L, b->N, nb, H, envrow, c.at(w.c0g), s);
 
-  launch_prep(b->obs, net->prec, src, F, d.in_ch, d.in_hw, d.in_hw, d.avgpool, c.at(w.x0), s);
+  launch_prep(b->obs, d.trunk == PPO_TRUNK_NONE ? 0 : net->prec, src, F, d.in_ch, d.in_hw, d.in_hw, d.avgpool,
+              c.at(w.x0), s);
   const float* feat = encoder_fwd(c);
   const int D0 = net->din0;
   float* Z = c.at(w.z);
   gemm_dense(net->prec, false, false, feat, net->flat, c.wt(net->fc_w), net->prec == 1, net->flat, F,
              d.vis_hidden, net->flat, epi(Z, D0, c.pf(net->fc_b), 1), false, kSplitKBytes, c.splitk(), s);
-  const bool polar = d.goal_mode == PPO_GOAL_POLAR;
+  const int gmode = d.goal_mode;  // goal kernels: 0 raw, 1 polar, 2 3-vector, 3 none
+  const bool polar = gmode == PPO_GOAL_POLAR || gmode == PPO_GOAL_VEC3;  // a goal FC exists
   const int E = std::max(0, d.prev_act_dim);
-  launch_embed_fwd(b->goal, b->prev_action, b->mask, src, F, polar, d.goal_dim,
+  launch_embed_fwd(b->goal, b->prev_action, b->mask, src, F, gmode, d.goal_dim,
                    polar ? c.pf(net->goal_w) : nullptr, polar ? c.pf(net->goal_b) : nullptr, E,
                    E ? c.pf(net->emb) : nullptr, Z, D0, d.vis_hidden, s);
   if (L == 2) {
@@ -937,7 +956,10 @@ const float* learner_fwd(const Ctx& c, const ppo_batch* b, const Sched& S) {
 
 // Backward from dout [F][A+1] (w.dout) and the gradient at the top LSTM
 // output (w.dh0), through the LSTM, the FC and input parts and the encoder.
-void learner_bwd(const Ctx& c, const ppo_batch* b, const Sched& S, const float* feat) {
+// c.grad null: data gradients only (a frozen net: no parameter gradient, no
+// encoder backward); dgoal (3-vector goal mode, or null): the gradient at the
+// goal input [F][3] in packed frame order.
+void learner_bwd(const Ctx& c, const ppo_batch* b, const Sched& S, const float* feat, float* dgoal = nullptr) {
   const ppo_net* net = c.n;
   const ppo_net_desc& d = net->d;
   const WsLayout& w = *c.w;
@@ -951,15 +973,18 @@ void learner_bwd(const Ctx& c, const ppo_batch* b, const Sched& S, const float* 
   const float* mskf = c.at(w.mskf);
   const int D0 = net->din0;
   float* Z = c.at(w.z);
-  const bool polar = d.goal_mode == PPO_GOAL_POLAR;
+  const int gmode = d.goal_mode;  // goal kernels: 0 raw, 1 polar, 2 3-vector, 3 none
+  const bool polar = gmode == PPO_GOAL_POLAR || gmode == PPO_GOAL_VEC3;  // a goal FC exists
   const int E = std::max(0, d.prev_act_dim);
   const float* Htop = c.at(w.hout[L - 1]);
   float* dout = c.at(w.dout);
   float* dH = c.at(w.dh0);
   // the head is float32 in both precisions (forward and its weight gradient)
-  gemm_dense(0, true, true, dout, A + 1, Htop, false, H, A + 1, H, F,
-             epi(grad + net->head_w, H), false, kSplitKBytes, c.splitk(), s);
-  launch_colsum(dout, F, A + 1, A + 1, grad + net->head_b, s);
+  if (grad)
+    gemm_dense(0, true, true, dout, A + 1, Htop, false, H, A + 1, H, F,
+               epi(grad + net->head_w, H), false, kSplitKBytes, c.splitk(), s);
+  if (grad)
+    launch_colsum(dout, F, A + 1, A + 1, grad + net->head_b, s);
   float* dHn = c.at(w.dh1);
   int l_top = L - 1;
   if (L == 2) {
@@ -970,16 +995,22 @@ void learner_bwd(const Ctx& c, const ppo_batch* b, const Sched& S, const float* 
                              c.at(w.c[0]), c.at(w.g[1]), c.at(w.cp[1]), c.at(w.c[1]), dH, dG0, dG1, mskf,
                              c.at<unsigned>(w.sync), s) == 0) {
       const float* H0 = c.at(w.hout[0]);
-      gemm_dense(net->prec, true, true, dG1, 4 * H, H0, false, H, 4 * H, H, F, epi(grad + w1, 2 * H), true,
-                 kSplitKBytes, c.splitk(), s);
-      gemm_dense(net->prec, true, true, dG1, 4 * H, c.at(w.hp[1]), false, H, 4 * H, H, F,
-                 epi(grad + w1 + H, 2 * H), true, kSplitKBytes, c.splitk(), s);
-      launch_colsum(dG1, F, 4 * H, 4 * H, grad + net->lstm_b[1], s);
-      gemm_dense(net->prec, true, true, dG0, 4 * H, Z, false, D0, 4 * H, D0, F, epi(grad + w0, D0 + H), true,
-                 kSplitKBytes, c.splitk(), s);
-      gemm_dense(net->prec, true, true, dG0, 4 * H, c.at(w.hp[0]), false, H, 4 * H, H, F,
-                 epi(grad + w0 + D0, D0 + H), true, kSplitKBytes, c.splitk(), s);
-      launch_colsum(dG0, F, 4 * H, 4 * H, grad + net->lstm_b[0], s);
+      if (grad)
+        gemm_dense(net->prec, true, true, dG1, 4 * H, H0, false, H, 4 * H, H, F, epi(grad + w1, 2 * H), true,
+                   kSplitKBytes, c.splitk(), s);
+      if (grad)
+        gemm_dense(net->prec, true, true, dG1, 4 * H, c.at(w.hp[1]), false, H, 4 * H, H, F,
+                   epi(grad + w1 + H, 2 * H), true, kSplitKBytes, c.splitk(), s);
+      if (grad)
+        launch_colsum(dG1, F, 4 * H, 4 * H, grad + net->lstm_b[1], s);
+      if (grad)
+        gemm_dense(net->prec, true, true, dG0, 4 * H, Z, false, D0, 4 * H, D0, F, epi(grad + w0, D0 + H), true,
+                   kSplitKBytes, c.splitk(), s);
+      if (grad)
+        gemm_dense(net->prec, true, true, dG0, 4 * H, c.at(w.hp[0]), false, H, 4 * H, H, F,
+                   epi(grad + w0 + D0, D0 + H), true, kSplitKBytes, c.splitk(), s);
+      if (grad)
+        launch_colsum(dG0, F, 4 * H, 4 * H, grad + net->lstm_b[0], s);
       gemm_dense(net->prec, false, true, dG0, 4 * H, c.wt(w0), net->prec == 1, D0 + H, F, D0, 4 * H,
                  epi(dHn, D0), true, kSplitKBytes, c.splitk(), s);
       std::swap(dH, dHn);
@@ -1007,11 +1038,14 @@ void learner_bwd(const Ctx& c, const ppo_batch* b, const Sched& S, const float* 
                            Cs + r0 * H, CP + r0 * H, dH + r0 * H, H, act[t], H, dG + r0 * 4 * H, dcp, s);
     }
     // weight gradients over all frames
-    gemm_dense(net->prec, true, true, dG, 4 * H, X, false, din, 4 * H, din, F, epi(grad + wl, din + H),
-               true, kSplitKBytes, c.splitk(), s);
-    gemm_dense(net->prec, true, true, dG, 4 * H, HP, false, H, 4 * H, H, F, epi(grad + wl + din, din + H),
-               true, kSplitKBytes, c.splitk(), s);
-    launch_colsum(dG, F, 4 * H, 4 * H, grad + net->lstm_b[l], s);
+    if (grad)
+      gemm_dense(net->prec, true, true, dG, 4 * H, X, false, din, 4 * H, din, F, epi(grad + wl, din + H),
+                 true, kSplitKBytes, c.splitk(), s);
+    if (grad)
+      gemm_dense(net->prec, true, true, dG, 4 * H, HP, false, H, 4 * H, H, F, epi(grad + wl + din, din + H),
+                 true, kSplitKBytes, c.splitk(), s);
+    if (grad)
+      launch_colsum(dG, F, 4 * H, 4 * H, grad + net->lstm_b[l], s);
     // gradient into the layer input
     gemm_dense(net->prec, false, true, dG, 4 * H, c.wt(wl), net->prec == 1, din + H, F, din, 4 * H,
                epi(dHn, din), true, kSplitKBytes, c.splitk(), s);
@@ -1020,12 +1054,17 @@ void learner_bwd(const Ctx& c, const ppo_batch* b, const Sched& S, const float* 
   // dH = gradient at Z [F][D0]
   float* dvis = c.at(w.dvis);
   launch_relu_grad2d(dH, D0, Z, D0, F, d.vis_hidden, dvis, d.vis_hidden, s);
-  launch_embed_bwd(b->goal, b->prev_action, b->mask, src, F, polar, d.goal_dim, E, A + 1, dH, D0,
-                   d.vis_hidden, polar ? grad + net->goal_w : nullptr, polar ? grad + net->goal_b : nullptr,
-                   E ? grad + net->emb : nullptr, s);
-  gemm_dense(net->prec, true, true, dvis, d.vis_hidden, feat, false, net->flat, d.vis_hidden, net->flat, F,
-             epi(grad + net->fc_w, net->flat), true, kSplitKBytes, c.splitk(), s);
-  launch_colsum(dvis, F, d.vis_hidden, d.vis_hidden, grad + net->fc_b, s);
+  if (grad)
+    launch_embed_bwd(b->goal, b->prev_action, b->mask, src, F, gmode, d.goal_dim, E, net->emb_rows, dH, D0,
+                     d.vis_hidden, polar ? grad + net->goal_w : nullptr, polar ? grad + net->goal_b : nullptr,
+                     E ? grad + net->emb : nullptr, s);
+  if (grad)
+    gemm_dense(net->prec, true, true, dvis, d.vis_hidden, feat, false, net->flat, d.vis_hidden, net->flat, F,
+               epi(grad + net->fc_w, net->flat), true, kSplitKBytes, c.splitk(), s);
+  if (grad)
+    launch_colsum(dvis, F, d.vis_hidden, d.vis_hidden, grad + net->fc_b, s);
+  if (dgoal) launch_goal_dgrad(dH, D0, d.vis_hidden, F, d.goal_dim, c.pf(net->goal_w), dgoal, s);
+  if (!grad || d.trunk == PPO_TRUNK_NONE) return;  // nothing upstream to train
   float* dfeat = c.at(w.dfeat);
   gemm_dense(net->prec, false, true, dvis, d.vis_hidden, c.wt(net->fc_w), net->prec == 1, net->flat, F,
              net->flat, d.vis_hidden, epi(dfeat, net->flat), true, kSplitKBytes, c.splitk(),
@@ -1134,6 +1173,64 @@ ppo_status ppo_policy_backward(ppo_net* net, const ppo_batch* b, const float* dl
   launch_head_bwd(dlogits, dvalues, S.F, d.hidden, d.num_actions, c.pf(net->head_w), c.at(w.dout),
                   c.at(w.dh0), s);
   learner_bwd(c, b, S, feat);
+  return check_launch();
+}
+
+ppo_status ppo_policy_backward_ex(ppo_net* net, const ppo_batch* b, const float* dlogits, const float* dvalues,
+                                  float* grad, float* dgoal, void* ws, size_t ws_bytes, void* stream) {
+  TuneScope tsc(net);
+  if (!net || !b || !dlogits || !dvalues || (!grad && !dgoal)) return fail(PPO_EINVAL, "null argument");
+  if (dgoal && net->d.goal_mode != PPO_GOAL_VEC3) return fail(PPO_EINVAL, "a goal gradient needs PPO_GOAL_VEC3");
+  Sched S;
+  const ppo_status st = schedule(net, b, S);
+  if (st != PPO_OK) return st;
+  const WsLayout w = plan(net, S.F, b->nb, true);
+  if (const ppo_status fs = check_frames(net, S.F); fs != PPO_OK) return fs;
+  if (!ws || ws_bytes < w.total) return fail(PPO_EWORKSPACE, "workspace needs %zu bytes", w.total);
+  if (!al256(ws)) return fail(PPO_EWORKSPACE, "workspace must be 256-byte aligned");
+  hipStream_t s = strm(stream);
+  Ctx c{net, &w, (char*)ws, b->params, b->params_lp, grad, s, S.F};
+  const ppo_net_desc& d = net->d;
+  const float* feat = learner_fwd(c, b, S);
+  launch_head_bwd(dlogits, dvalues, S.F, d.hidden, d.num_actions, c.pf(net->head_w), c.at(w.dout),
+                  c.at(w.dh0), s);
+  learner_bwd(c, b, S, feat, dgoal);
+  return check_launch();
+}
+
+ppo_status ppo_encode(ppo_net* net, const void* obs, int frames, const float* params, const void* params_lp,
+                      float* feat, void* ws, size_t ws_bytes, void* stream) {
+  TuneScope tsc(net);
+  if (!net || !obs || !params || !feat || (net->prec && !params_lp)) return fail(PPO_EINVAL, "null argument");
+  if (frames <= 0) return fail(PPO_ESHAPE, "frames must be positive");
+  const WsLayout w = plan(net, frames, 1, false);
+  if (const ppo_status fs = check_frames(net, frames); fs != PPO_OK) return fs;
+  if (!ws || ws_bytes < w.total) return fail(PPO_EWORKSPACE, "workspace needs %zu bytes", w.total);
+  if (!al256(ws)) return fail(PPO_EWORKSPACE, "workspace must be 256-byte aligned");
+  hipStream_t s = strm(stream);
+  Ctx c{net, &w, (char*)ws, params, params_lp, nullptr, s, frames};
+  c.keep_u = false;
+  const ppo_net_desc& d = net->d;
+  launch_prep(obs, d.trunk == PPO_TRUNK_NONE ? 0 : net->prec, nullptr, frames, d.in_ch, d.in_hw, d.in_hw,
+              d.avgpool, c.at(w.x0), s);
+  const float* f = encoder_fwd(c);
+  launch_copy2d(f, net->flat, frames, net->flat, feat, net->flat, s);
+  return check_launch();
+}
+
+ppo_status ppo_planner_goal(const float* raw, int ld_raw, const int32_t* dst, int frames, float* goal,
+                            void* stream) {
+  if (!raw || !goal) return fail(PPO_EINVAL, "null argument");
+  if (frames < 0 || ld_raw < 3) return fail(PPO_ESHAPE, "bad sizes");
+  launch_planner_goal(raw, ld_raw, dst, frames, goal, strm(stream));
+  return check_launch();
+}
+
+ppo_status ppo_planner_goal_backward(const float* raw, int ld_raw, const float* dgoal, int frames, float* draw,
+                                     void* stream) {
+  if (!raw || !dgoal || !draw) return fail(PPO_EINVAL, "null argument");
+  if (frames < 0 || ld_raw < 3) return fail(PPO_ESHAPE, "bad sizes");
+  launch_planner_goal_bwd(raw, ld_raw, dgoal, frames, draw, strm(stream));
   return check_launch();
 }
 

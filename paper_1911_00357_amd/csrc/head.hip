@@ -5,6 +5,26 @@
 
 constexpr int kMaxA = 8;  // actions + value row handled per wavefront
 
+// Goal feature k of one frame (goal modes: 0 raw 2-vector, 1 polar
+// (d, theta) -> [d, cos, sin] -> FC, 2 a given 3-vector -> FC; 3 none).
+DEV float goal_feature(const float* __restrict__ goal, size_t si, int gmode, int k, const float* __restrict__ gw,
+                       const float* __restrict__ gb) {
+  if (gmode == 2) {
+    const float* g3 = goal + si * 3;
+    return gb[k] + gw[k * 3] * g3[0] + gw[k * 3 + 1] * g3[1] + gw[k * 3 + 2] * g3[2];
+  }
+  const float d = goal[si * 2], th = goal[si * 2 + 1];
+  if (gmode == 1) return gb[k] + gw[k * 3] * d + gw[k * 3 + 1] * cosf(th) + gw[k * 3 + 2] * sinf(th);
+  return (k == 0) ? d : th;
+}
+
+// Input i of the goal FC for one frame (polar or 3-vector mode).
+DEV float goal_input(const float* __restrict__ goal, size_t si, int gmode, int i) {
+  if (gmode == 2) return goal[si * 3 + i];
+  const float d = goal[si * 2], th = goal[si * 2 + 1];
+  return (i == 0) ? d : (i == 1 ? cosf(th) : sinf(th));
+}
+
 // One wavefront per row: out[k] = W[k] . h + b[k] for k < A+1.
 DEV void head_dots(const float* __restrict__ h, const float* __restrict__ W, const float* __restrict__ b,
                    int H, int A1, float out[kMaxA]) {
@@ -267,12 +287,7 @@ __global__ void __launch_bounds__(256) embed_fwd_kernel(const float* __restrict_
     const int si = src ? src[f] : f;
     float v;
     if (k < goal_dim) {
-      const float d = goal[(size_t)si * 2], th = goal[(size_t)si * 2 + 1];
-      if (polar) {
-        v = gb[k] + gw[k * 3] * d + gw[k * 3 + 1] * cosf(th) + gw[k * 3 + 2] * sinf(th);
-      } else {
-        v = (k == 0) ? d : th;
-      }
+      v = goal_feature(goal, (size_t)si, polar, k, gw, gb);
     } else {
       const int j = k - goal_dim;
       const int idx = (mask[si] == 0.f) ? 0 : prev_a[si] + 1;
@@ -302,7 +317,7 @@ __global__ void __launch_bounds__(256) embed_bwd_kernel(const float* __restrict_
                                                         float* __restrict__ dgw, float* __restrict__ dgb,
                                                         float* __restrict__ demb) {
   const int wid = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
-  const int ngoal = polar ? goal_dim * 4 : 0;
+  const int ngoal = (polar == 1 || polar == 2) ? goal_dim * 4 : 0;
   const int nemb = A1 * E;
   if (wid >= ngoal + nemb) return;
   float acc = 0.f;
@@ -311,11 +326,7 @@ __global__ void __launch_bounds__(256) embed_bwd_kernel(const float* __restrict_
     for (int f = lane; f < F; f += 64) {
       const int si = src ? src[f] : f;
       const float g = dZ[(size_t)f * ldz + zoff + k];
-      float x = 1.f;
-      if (i < 3) {
-        const float d = goal[(size_t)si * 2], th = goal[(size_t)si * 2 + 1];
-        x = (i == 0) ? d : (i == 1 ? cosf(th) : sinf(th));
-      }
+      const float x = i < 3 ? goal_input(goal, (size_t)si, polar, i) : 1.f;
       acc = fmaf(g, x, acc);
     }
     acc = wave_sum(acc);
@@ -338,7 +349,7 @@ __global__ void __launch_bounds__(256) embed_bwd_kernel(const float* __restrict_
 void launch_embed_bwd(const float* goal, const int32_t* prev_a, const float* mask, const int32_t* src,
                       int F, int polar, int goal_dim, int E, int A1, const float* dZ, int ldz, int zoff,
                       float* dgw, float* dgb, float* demb, hipStream_t s) {
-  const int n = (polar ? goal_dim * 4 : 0) + (E > 0 ? A1 * E : 0);
+  const int n = ((polar == 1 || polar == 2) ? goal_dim * 4 : 0) + (E > 0 ? A1 * E : 0);
   if (n <= 0) return;
   hipLaunchKernelGGL(embed_bwd_kernel, dim3(cdiv(n, 4)), dim3(256), 0, s, goal, prev_a, mask, src, F,
                      polar, goal_dim, E > 0 ? E : 1, E > 0 ? A1 : 0, dZ, ldz, zoff, dgw, dgb, demb);
@@ -436,6 +447,69 @@ void launch_copy2d(const float* s_, int lds, int rows, int cols, float* d, int l
   if (n <= 0) return;
   hipLaunchKernelGGL(copy2d_kernel, dim3(std::min(4096, cdiv(n, 256))), dim3(256), 0, s, s_, lds, rows,
                      cols, d, ldd, active);
+}
+
+// Gradient at a 3-vector goal input: dgoal[f][i] = sum_k dZ[f][zoff + k] gw[k][i]
+// (packed frame order).
+__global__ void __launch_bounds__(256) goal_dgrad_kernel(const float* __restrict__ dZ, int ldz, int zoff, int F,
+                                                         int goal_dim, const float* __restrict__ gw,
+                                                         float* __restrict__ dgoal) {
+  for (int e = blockIdx.x * 256 + threadIdx.x; e < F * 3; e += gridDim.x * 256) {
+    const int f = e / 3, i = e - f * 3;
+    const float* dz = dZ + (size_t)f * ldz + zoff;
+    float acc = 0.f;
+    for (int k = 0; k < goal_dim; ++k) acc = fmaf(dz[k], gw[k * 3 + i], acc);
+    dgoal[e] = acc;
+  }
+}
+
+void launch_goal_dgrad(const float* dZ, int ldz, int zoff, int F, int goal_dim, const float* gw, float* dgoal,
+                       hipStream_t s) {
+  if (F <= 0) return;
+  hipLaunchKernelGGL(goal_dgrad_kernel, dim3(std::min(4096, cdiv(F * 3, 256))), dim3(256), 0, s, dZ, ldz, zoff, F,
+                     goal_dim, gw, dgoal);
+}
+
+// The planner's PointGoal from its raw head outputs (magnitude ELU(r0) + 0.75,
+// direction tanh(r1), tanh(r2)): row f of raw (stride ldr) -> row dst[f] of goal.
+__global__ void __launch_bounds__(256) planner_goal_kernel(const float* __restrict__ raw, int ldr,
+                                                           const int32_t* __restrict__ dst, int F,
+                                                           float* __restrict__ goal) {
+  for (int e = blockIdx.x * 256 + threadIdx.x; e < F * 3; e += gridDim.x * 256) {
+    const int f = e / 3, i = e - f * 3;
+    const float r = raw[(size_t)f * ldr + i];
+    const float g = i == 0 ? (r > 0.f ? r : expm1f(r)) + 0.75f : tanhf(r);
+    goal[(size_t)(dst ? dst[f] : f) * 3 + i] = g;
+  }
+}
+
+// draw = dgoal * d goal / d raw (both [F][3], raw rows of stride ldr)
+__global__ void __launch_bounds__(256) planner_goal_bwd_kernel(const float* __restrict__ raw, int ldr,
+                                                               const float* __restrict__ dgoal, int F,
+                                                               float* __restrict__ draw) {
+  for (int e = blockIdx.x * 256 + threadIdx.x; e < F * 3; e += gridDim.x * 256) {
+    const int f = e / 3, i = e - f * 3;
+    const float r = raw[(size_t)f * ldr + i];
+    float d;
+    if (i == 0) d = r > 0.f ? 1.f : expf(r);
+    else {
+      const float t = tanhf(r);
+      d = 1.f - t * t;
+    }
+    draw[(size_t)f * ldr + i] = dgoal[e] * d;
+  }
+}
+
+void launch_planner_goal(const float* raw, int ldr, const int32_t* dst, int F, float* goal, hipStream_t s) {
+  if (F <= 0) return;
+  hipLaunchKernelGGL(planner_goal_kernel, dim3(std::min(4096, cdiv(F * 3, 256))), dim3(256), 0, s, raw, ldr, dst, F,
+                     goal);
+}
+
+void launch_planner_goal_bwd(const float* raw, int ldr, const float* dgoal, int F, float* draw, hipStream_t s) {
+  if (F <= 0) return;
+  hipLaunchKernelGGL(planner_goal_bwd_kernel, dim3(std::min(4096, cdiv(F * 3, 256))), dim3(256), 0, s, raw, ldr,
+                     dgoal, F, draw);
 }
 
 // Policy/value head over frames: logits[f][k], values[f] (one wavefront per frame).

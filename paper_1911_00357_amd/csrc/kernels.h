@@ -240,6 +240,10 @@ void launch_gather_state(const float* srcs, int L, int N, int nb, int H, const i
                          float* dst, hipStream_t s);
 void launch_copy2d(const float* s_, int lds, int rows, int cols, float* d, int ldd, hipStream_t s,
                    const int32_t* active = nullptr);
+void launch_goal_dgrad(const float* dZ, int ldz, int zoff, int F, int goal_dim, const float* gw, float* dgoal,
+                       hipStream_t s);
+void launch_planner_goal(const float* raw, int ldr, const int32_t* dst, int F, float* goal, hipStream_t s);
+void launch_planner_goal_bwd(const float* raw, int ldr, const float* dgoal, int F, float* draw, hipStream_t s);
 void launch_head_fwd(const float* htop, int F, int H, int A, const float* W, const float* b, float* logits,
                      float* values, hipStream_t s);
 void launch_head_bwd(const float* dlogits, const float* dvalues, int F, int H, int A, const float* W, float* dout,

@@ -33,9 +33,15 @@ __global__ void __launch_bounds__(256) act_core_prep_kernel(
       const int f = e / per, k = e - f * per;
       float v;
       if (k < goal_dim) {
-        const float d = goal[(size_t)f * 2], th = goal[(size_t)f * 2 + 1];
-        v = polar ? gb[k] + gw[k * 3] * d + gw[k * 3 + 1] * cosf(th) + gw[k * 3 + 2] * sinf(th)
-                  : (k == 0 ? d : th);
+        // goal modes: 0 raw 2-vector, 1 polar (d, theta) -> [d, cos, sin] -> FC, 2 a 3-vector -> FC
+        if (polar == 2) {
+          const float* g3 = goal + (size_t)f * 3;
+          v = gb[k] + gw[k * 3] * g3[0] + gw[k * 3 + 1] * g3[1] + gw[k * 3 + 2] * g3[2];
+        } else {
+          const float d = goal[(size_t)f * 2], th = goal[(size_t)f * 2 + 1];
+          v = polar ? gb[k] + gw[k * 3] * d + gw[k * 3 + 1] * cosf(th) + gw[k * 3 + 2] * sinf(th)
+                    : (k == 0 ? d : th);
+        }
       } else {
         const int idx = (mask[f] == 0.f) ? 0 : prev_a[f] + 1;
         v = emb[(size_t)idx * E + (k - goal_dim)];

@@ -5,10 +5,8 @@ whole system's PPO loss and planner gradient against an independent torch
 float64 model with autograd (controller and encoder frozen); central finite
 differences of the planner gradient; and the frozen parts receiving no
 gradient while the goal path carries one."""
-from dataclasses import replace
 
 import numpy as np
-import pytest
 import torch
 import torch.nn.functional as F
 
@@ -158,3 +156,20 @@ def test_system_act_step_matches_the_learner_forward():
     np.testing.assert_allclose(out["goal"], ex["goal"][0], rtol=1e-13, atol=1e-14)
     np.testing.assert_allclose(out["logits"], ex["logits"][0], rtol=1e-13, atol=1e-14)
     np.testing.assert_allclose(out["value"], ex["values"][0], rtol=1e-13, atol=1e-14)
+
+
+def test_given_features_and_precision_form():
+    """The learner with the encoder's own features passed in equals the
+    default; the bfloat16 precision form moves the loss at bfloat16 scale."""
+    sysm = _system(seed=11)
+    mb = _mb(sysm, seed=21)
+    p = wl(sysm.agent_net).ppo
+    s0, g0, _ = OC.loss_grad(sysm, p, mb)
+    TB, B = mb["action"].shape
+    feat = OC.features(sysm.agent_net, sysm.agent_flat, mb["obs"].reshape(TB * B, *mb["obs"].shape[2:]))
+    s1, g1, _ = OC.loss_grad(sysm, p, mb, feat=feat.reshape(TB, B, -1))
+    np.testing.assert_array_equal(s0, s1)
+    np.testing.assert_array_equal(g0, g1)
+    sq, gq, _ = OC.loss_grad(sysm, p, mb, quant="bf16")
+    assert 1e-6 < abs(sq[0] - s0[0]) / abs(s0[0]) < 1e-1
+    assert 1e-6 < np.linalg.norm(gq - g0) / np.linalg.norm(g0) < 2e-1
