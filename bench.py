@@ -134,7 +134,7 @@ def run_seed(wl, seed, steps, warmup, net=None, act_timer=True):
             torch.cuda.synchronize()
             ev[0].record()
             t_start = time.perf_counter()
-        w.collect(env, lengths, graph=GRAPH)
+        w.collect(env, lengths, graph=GRAPH, trim=wl.ragged)
         _update(w, env, parts, lengths)
         if i < warmup:
             torch.cuda.synchronize()
@@ -143,8 +143,14 @@ def run_seed(wl, seed, steps, warmup, net=None, act_timer=True):
     ev[1].record()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t_start
+    # run health, read after the timed region: Adam's skipped steps (a non-finite
+    # gradient), the last minibatch's loss statistics, the recurrence's barrier status
+    st = w.adam.state()
+    health = {"adam_steps": int(st["step"]), "adam_skipped": int(st["skipped"]), "loss_scale": float(st["scale"]),
+              "loss_finite": bool(torch.isfinite(w.stats).all()), "recurrence_failed": bool(w.net.recurrence_failed())}
     act = act_gemms_live(w, wl) if act_timer else None
-    return {"frames": frames, "gpu_ms": ev[0].elapsed_time(ev[1]), "wall_s": wall, "act": act, "worker": w}
+    return {"frames": frames, "gpu_ms": ev[0].elapsed_time(ev[1]), "wall_s": wall, "act": act, "worker": w,
+            "health": health}
 
 
 def act_gemms_live(w, wl, reps=ACT_REPS):
@@ -237,11 +243,11 @@ def act_update_split(wl, seed, net):
     lengths = None if not wl.ragged else lens
     parts = R.partitions(wl, seed)
     for _ in range(2):
-        w.collect(env, lengths, graph=GRAPH)
+        w.collect(env, lengths, graph=GRAPH, trim=wl.ragged)
         _update(w, env, parts, lengths)
     e = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
     e[0].record()
-    w.collect(env, lengths, graph=GRAPH)
+    w.collect(env, lengths, graph=GRAPH, trim=wl.ragged)
     e[1].record()
     _update(w, env, parts, lengths)
     e[2].record()
@@ -802,6 +808,10 @@ def main():
                       "gradient": "torch.autograd.Function, activations recomputed" if AUTOGRAD
                       else "ppo_loss_backward", "gemm_tiles": "autotuned in warm-up"},
            "seeds": len(seeds), "ci95": [round(c, 2) for c in ci],
+           "health": {"adam_steps": sum(r["health"]["adam_steps"] for r in res),
+                      "adam_skipped": sum(r["health"]["adam_skipped"] for r in res),
+                      "loss_finite": all(r["health"]["loss_finite"] for r in res),
+                      "recurrence_failed": any(r["health"]["recurrence_failed"] for r in res)},
            "per_seed": [round(x, 1) for x in fps],
            "wall_s": round(sum(r["wall_s"] for r in res), 3)}
     # roofline: the act step's convolution GEMMs (live, last timed replay of seed 0)
@@ -843,6 +853,9 @@ def main():
         out["fp32_ci95"] = [round(c, 2) for c in ci32]
         out["bf16_speedup_vs_fp32"] = round(sp, 3)
         out["bf16_speedup_ci95"] = [round(c, 3) for c in cisp]
+        out["fp32_health"] = {"adam_skipped": sum(r["health"]["adam_skipped"] for r in r32),
+                              "loss_finite": all(r["health"]["loss_finite"] for r in r32),
+                              "recurrence_failed": any(r["health"]["recurrence_failed"] for r in r32)}
         gc.collect()
         torch.cuda.empty_cache()
     if wl.ragged:
@@ -863,6 +876,12 @@ def main():
     gc.collect()
     torch.cuda.synchronize()
     print(json.dumps(out), flush=True)
+    h, h32 = out["health"], out.get("fp32_health", {"adam_skipped": 0, "loss_finite": True, "recurrence_failed": False})
+    if not h["loss_finite"] or h["recurrence_failed"] or (wl.dtype == "f32" and h["adam_skipped"]) or \
+            not h32["loss_finite"] or h32["recurrence_failed"] or h32["adam_skipped"]:
+        # a run whose updates were not all valid does not measure the method: say so and fail
+        sys.stderr.write(f"bench: unhealthy run {h} (float32 form {h32})\n")
+        sys.exit(3)
 
 
 if __name__ == "__main__":
