@@ -494,7 +494,6 @@ def learner_gemm_live(w, wl, env, parts, sel):
     stream around the kernel itself, over one update."""
     import torch
     u, op, name, all_tf = sel
-    w._graphs.clear()             # the act timer's events belong to the graphs: drop them first
     w.net.gemm_timer_arm(u, op)
     _update(w, env, parts, None)
     torch.cuda.synchronize()

@@ -15,7 +15,9 @@
  *     workspace (size from ppo_workspace_size).  The exceptions are
  *     benchmark and tuning aids, each documented below: a GEMM problem timed
  *     by the tile autotuner (ppo_autotune mode 1) allocates and frees a
- *     scratch output, and ppo_gemm_timer_arm creates HIP events.
+ *     scratch output, and ppo_gemm_timer_arm creates HIP events.  With
+ *     PPO_COLLECT_GRAPH, ppo_collect creates and keeps HIP graphs (the HIP
+ *     runtime's memory) and one private capture stream per net.
  *   - All work is enqueued on `stream` (a hipStream_t passed as void*;
  *     NULL = the null stream) and is asynchronous.  Shape, pointer and
  *     workspace errors are detected on the host before any launch and
@@ -177,6 +179,84 @@ typedef struct ppo_act_io {
 } ppo_act_io;
 
 ppo_status ppo_act(ppo_net* net, const ppo_act_io* io, void* ws, size_t ws_bytes, void* stream);
+
+/* ---------------------------------------------------------------------------
+ * ppo_collect -- the rollout's T+1 dependent act steps (Sec. 3 "inference":
+ * T = 128 steps of experience, plus the step that gives the bootstrap value
+ * V(s_T)), each one ppo_act over the rollout's buffers:
+ *
+ *   step t reads    obs[t], goal[t], mask[t], u[t], actions[t] (previous
+ *                   action), h_hist[t], c_hist[t];
+ *   step t writes   actions[t+1], logp[t], value[t], and its next state to
+ *                   h_hist[t+1], c_hist[t+1] (to h_last, c_last at t = T).
+ *
+ * Only steps t_begin <= t < t_end run (the full rollout: 0, T+1), so a
+ * caller that decides after each step whether the rollout ends (preemption,
+ * Sec. 3) runs one step per call.
+ *
+ * Rows: with `active` (device int32 [T+1], or NULL = all N) step t writes
+ * rows b < active[t] only, read on the device when the step runs (ppo_act's
+ * row count).  With PPO_COLLECT_TRIM, `lengths` (host int32 [N], T_n,
+ * non-increasing: envs ordered longest first) instead launches step t on
+ * its rows b with T_b >= t only, and the steps stop at the first step with
+ * none; `active` is then ignored.
+ *
+ * PPO_COLLECT_GRAPH: the steps run as a HIP graph the library captures and
+ * owns, one per distinct argument set (every field below, ws, ws_bytes, the
+ * flags and, with PPO_COLLECT_TRIM, the contents of `lengths`).  The first
+ * call with a new argument set runs the steps eagerly on `stream` (so the
+ * tile table is tuned when tuning is on; the results are that call's
+ * outputs) and then records them, on a private stream of the net's device,
+ * into a graph that later calls launch on `stream`.  A graph reads the
+ * buffers' contents when it runs, not when it was captured, so the host may
+ * refill obs, u, active, ... between launches; the buffers themselves must
+ * stay allocated while a graph keyed on them may still be launched.  At
+ * most 1024 graphs are kept per net (the oldest is dropped, after the device
+ * is idle); ppo_collect_clear drops them all.  When `stream` is itself
+ * being captured, the steps are recorded into the caller's graph as plain
+ * launches.
+ *
+ * Errors (null pointer, bad step range, unordered lengths, small workspace)
+ * are reported before any launch.  A graph that cannot be captured or
+ * instantiated gives PPO_EDEVICE; the eager results of that call stand.
+ */
+enum { PPO_COLLECT_GRAPH = 1, PPO_COLLECT_TRIM = 2 };
+
+typedef struct ppo_collect_io {
+  int T;                      /* rollout steps: act steps 0..T                  */
+  int N;                      /* envs (rows of every [..][N] array)             */
+  int t_begin, t_end;         /* steps run by this call, 0 <= t_begin <= t_end <= T+1 */
+  const void* obs;            /* device [T+1][N][C][H][W] (bfloat16 on a PPO_BF16 net
+                                 with a visual trunk, float32 otherwise)         */
+  const float* goal;          /* device [T+1][N][goal width], NULL for PPO_GOAL_NONE */
+  const float* mask;          /* device [T+1][N]                                 */
+  const float* u;             /* device [T+1][N] uniforms in [0,1)               */
+  const int32_t* active;      /* device [T+1] rows written per step, or NULL     */
+  const int32_t* lengths;     /* host [N] T_n (PPO_COLLECT_TRIM only), or NULL = all T */
+  const float* params;        /* device flat float32 parameters                  */
+  const void* params_lp;      /* device flat bfloat16 copy (PPO_BF16), else NULL  */
+  int32_t* actions;           /* device [T+2][N]: row 0 the action before step 0
+                                 (read), row t+1 step t's action (written)       */
+  float* logp;                /* device [T+1][N] out                             */
+  float* value;               /* device [T+1][N] out                             */
+  float* h_hist;              /* device [T+1][L][N][H]: row 0 read, rows 1..T written */
+  float* c_hist;              /* device [T+1][L][N][H]                           */
+  float* h_last;              /* device [L][N][H]: state written by step T       */
+  float* c_last;              /* device [L][N][H]                                */
+} ppo_collect_io;
+
+/* ws: ppo_act's workspace for max_frames = N.  stream: the caller's. */
+ppo_status ppo_collect(ppo_net* net, const ppo_collect_io* io, int flags, void* ws, size_t ws_bytes,
+                       void* stream);
+
+/* Drops every graph ppo_collect keeps for this net (after the device is
+ * idle); returns how many were dropped.  Call it before freeing buffers
+ * that a kept graph is keyed on if their addresses may be reused with other
+ * shapes, or to release the graphs' memory. */
+int ppo_collect_clear(ppo_net* net);
+
+/* Number of graphs ppo_collect keeps for this net. */
+int ppo_collect_graph_count(const ppo_net* net);
 
 /* ---------------------------------------------------------------------------
  * ppo_gae -- generalized advantage estimation (Sec. 4 "Training": gamma, GAE

@@ -16,6 +16,7 @@ PPO_TRUNK_TINY, PPO_TRUNK_RESNET, PPO_TRUNK_SERESNEXT, PPO_TRUNK_NONE = 0, 1, 2,
 PPO_GOAL_RAW, PPO_GOAL_POLAR, PPO_GOAL_VEC3, PPO_GOAL_NONE = 0, 1, 2, 3
 PPO_OP_ACT, PPO_OP_LEARN, PPO_OP_LOSS = 0, 1, 2
 PPO_TIMER_ALL_UNITS = -2
+PPO_COLLECT_GRAPH, PPO_COLLECT_TRIM = 1, 2
 
 STATUS_NAMES = {0: "PPO_OK", -1: "PPO_EINVAL", -2: "PPO_ESHAPE", -3: "PPO_EUNSUPPORTED",
                 -4: "PPO_EWORKSPACE", -5: "PPO_EDEVICE"}
@@ -36,6 +37,14 @@ class ActIO(C.Structure):
                 ("params", c_void_p), ("params_lp", c_void_p), ("action", c_void_p),
                 ("logp", c_void_p), ("value", c_void_p), ("h_out", c_void_p), ("c_out", c_void_p),
                 ("logits", c_void_p), ("active", c_void_p)]
+
+
+class CollectIO(C.Structure):
+    _fields_ = [("T", c_int), ("N", c_int), ("t_begin", c_int), ("t_end", c_int), ("obs", c_void_p),
+                ("goal", c_void_p), ("mask", c_void_p), ("u", c_void_p), ("active", c_void_p), ("lengths", P_i32),
+                ("params", c_void_p), ("params_lp", c_void_p), ("actions", c_void_p), ("logp", c_void_p),
+                ("value", c_void_p), ("h_hist", c_void_p), ("c_hist", c_void_p), ("h_last", c_void_p),
+                ("c_last", c_void_p)]
 
 
 class Batch(C.Structure):
@@ -68,6 +77,9 @@ EXPORTS = {
                                  C.POINTER(c_size_t)]),
     "ppo_workspace_size": (c_int, [c_void_p, c_int, c_int, c_int, C.POINTER(c_size_t)]),
     "ppo_act": (c_int, [c_void_p, C.POINTER(ActIO), c_void_p, c_size_t, c_void_p]),
+    "ppo_collect": (c_int, [c_void_p, C.POINTER(CollectIO), c_int, c_void_p, c_size_t, c_void_p]),
+    "ppo_collect_clear": (c_int, [c_void_p]),
+    "ppo_collect_graph_count": (c_int, [c_void_p]),
     "ppo_gae": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_int, c_int, c_float, c_float,
                         c_void_p, c_void_p, c_void_p, c_void_p]),
     "ppo_loss_backward": (c_int, [c_void_p, C.POINTER(Batch), C.POINTER(LossCfg), c_void_p, c_void_p,

@@ -253,6 +253,61 @@ class Net:
         check(lib().ppo_act(self._h, C.byref(io), _ptr(ws), ws.numel(), _stream(dev)), "ppo_act")
         return out
 
+    def collect(self, ro, params, params_lp=None, steps=None, active=None, lengths=None, trim=False,
+                graph=False):
+        """The rollout's act steps through ppo_collect.  ro: device tensors
+        'obs' [T+1, N, ...], 'goal' [T+1, N, gw] (or None), 'mask', 'u'
+        [T+1, N], 'actions' [T+2, N] int32 (row 0 read), 'logp', 'value'
+        [T+1, N], 'h_hist', 'c_hist' [T+1, L, N, H] (row 0 read), 'h_last',
+        'c_last' [L, N, H].  steps: (t_begin, t_end), default all T+1.
+        active: device int32 [T+1] row counts; lengths with trim=True: host
+        T_n (non-increasing) for per-step batches.  graph=True: launch the
+        library's captured graph of these arguments."""
+        T1, N = ro["mask"].shape[0], ro["mask"].shape[1]
+        T = T1 - 1
+        odt = torch.bfloat16 if self.bf16 and self.spec.trunk != "none" else torch.float32
+        _need(ro["obs"], odt, "obs")
+        if ro["obs"].numel() != T1 * N * self.spec.in_ch * self.spec.in_hw * self.spec.in_hw:
+            raise ValueError("obs must be [T+1, N, C, H, W]")
+        gw = {"raw": 2, "polar": 2, "vec3": 3}.get(self.spec.goal_mode, 0)
+        if gw:
+            _need(ro["goal"], torch.float32, "goal", T1 * N * gw)
+        for k in ("mask", "u", "logp", "value"):
+            _need(ro[k], torch.float32, k, T1 * N)
+        _need(ro["actions"], torch.int32, "actions", (T + 2) * N)
+        state = self.L * N * self.H
+        for k, n in (("h_hist", T1 * state), ("c_hist", T1 * state), ("h_last", state), ("c_last", state)):
+            _need(ro[k], torch.float32, k, n)
+        _need(params, torch.float32, "params", self.P)
+        if self.bf16:
+            _need(params_lp, torch.bfloat16, "params_lp", self.P)
+        if active is not None:
+            _need(active, torch.int32, "active", T1)
+        t0, t1 = steps if steps is not None else (0, T1)
+        io = L.CollectIO()
+        io.T, io.N, io.t_begin, io.t_end = T, N, t0, t1
+        io.obs, io.goal, io.mask, io.u = _ptr(ro["obs"]), _ptr(ro.get("goal")), _ptr(ro["mask"]), _ptr(ro["u"])
+        io.active = _ptr(active)
+        lens = None
+        if trim and lengths is not None:
+            lens = (C.c_int32 * N)(*[int(x) for x in lengths])
+            io.lengths = C.cast(lens, L.P_i32)
+        io.params, io.params_lp = _ptr(params), _ptr(params_lp)
+        io.actions, io.logp, io.value = _ptr(ro["actions"]), _ptr(ro["logp"]), _ptr(ro["value"])
+        io.h_hist, io.c_hist, io.h_last, io.c_last = (_ptr(ro[k]) for k in ("h_hist", "c_hist", "h_last", "c_last"))
+        flags = (L.PPO_COLLECT_GRAPH if graph else 0) | (L.PPO_COLLECT_TRIM if trim else 0)
+        dev = ro["obs"].device
+        ws = self.workspace(L.PPO_OP_ACT, N, 1, dev)
+        check(lib().ppo_collect(self._h, C.byref(io), flags, _ptr(ws), ws.numel(), _stream(dev)), "ppo_collect")
+
+    def clear_graphs(self) -> int:
+        """Drop the act graphs the library keeps for this net (waits for the device)."""
+        return int(lib().ppo_collect_clear(self._h))
+
+    def graph_count(self) -> int:
+        """Act graphs the library keeps for this net."""
+        return int(lib().ppo_collect_graph_count(self._h))
+
     # -------------------------------------------------------------- learner
     def _batch(self, ro, env_ids, lengths, params, params_lp, learner=True, inputs=True):
         """The ppo_batch of a minibatch.  learner: the loss fields (actions,

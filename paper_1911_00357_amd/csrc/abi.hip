@@ -5,8 +5,10 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <deque>
 #include <mutex>
 #include <string>
+#include <unordered_map>
 #include <vector>
 
 #include "kernels.h"
@@ -79,6 +81,11 @@ struct ppo_net {
   mutable std::vector<hipEvent_t> timer_ev;
   mutable GemmTimer timer{};
   mutable GemmTune tune;      // tile / K-split choices (ppo_autotune)
+  // ppo_collect's captured act loops, keyed on the call's arguments, oldest first
+  std::unordered_map<std::string, hipGraphExec_t> graphs;
+  std::deque<std::string> graph_order;
+  hipStream_t cap_stream = nullptr;  // private capture stream (default priority)
+  int cap_device = -1;
 };
 
 // Makes the net's tile table visible to the GEMM launchers for one call.
@@ -675,8 +682,27 @@ ppo_status ppo_net_create(const ppo_net_desc* desc, ppo_net** out) {
   return PPO_OK;
 }
 
+// Waits for the device, then destroys the graphs (none may be in flight).
+static int collect_drop(ppo_net* net, size_t keep) {
+  if (net->graph_order.size() <= keep) return 0;
+  (void)hipDeviceSynchronize();
+  int n = 0;
+  while (net->graph_order.size() > keep) {
+    auto it = net->graphs.find(net->graph_order.front());
+    if (it != net->graphs.end()) {
+      (void)hipGraphExecDestroy(it->second);
+      net->graphs.erase(it);
+      ++n;
+    }
+    net->graph_order.pop_front();
+  }
+  return n;
+}
+
 void ppo_net_destroy(ppo_net* net) {
   if (!net) return;
+  collect_drop(net, 0);
+  if (net->cap_stream) (void)hipStreamDestroy(net->cap_stream);
   for (hipEvent_t e : net->timer_ev)
     if (e) (void)hipEventDestroy(e);
   delete net;
@@ -721,9 +747,8 @@ ppo_status ppo_workspace_size(const ppo_net* net, int op, int max_frames, int ma
   return PPO_OK;
 }
 
-ppo_status ppo_act(ppo_net* net, const ppo_act_io* io, void* ws, size_t ws_bytes, void* stream) {
-  TuneScope tsc(net);
-  if (!net || !io) return fail(PPO_EINVAL, "null argument");
+// Host-side checks of one ppo_act call, before any launch.
+static ppo_status act_check(const ppo_net* net, const ppo_act_io* io, const void* ws, size_t ws_bytes) {
   const ppo_net_desc& d = net->d;
   const int B = io->batch;
   if (B <= 0) return fail(PPO_ESHAPE, "batch must be positive");
@@ -732,12 +757,22 @@ ppo_status ppo_act(ppo_net* net, const ppo_act_io* io, void* ws, size_t ws_bytes
       !io->action || !io->logp || !io->value || !io->h_out || !io->c_out ||
       (d.prev_act_dim > 0 && !io->prev_action) || (net->prec && !io->params_lp))
     return fail(PPO_EINVAL, "null pointer in ppo_act_io");
-  const int SR = io->state_rows > 0 ? io->state_rows : B;
-  if (SR < B) return fail(PPO_ESHAPE, "state_rows < batch");
-  const WsLayout w = plan(net, B, 1, false);
+  if (io->state_rows > 0 && io->state_rows < B) return fail(PPO_ESHAPE, "state_rows < batch");
   if (const ppo_status fs = check_frames(net, B); fs != PPO_OK) return fs;
-  if (!ws || ws_bytes < w.total) return fail(PPO_EWORKSPACE, "workspace needs %zu bytes", w.total);
+  const size_t need = plan(net, B, 1, false).total;
+  if (!ws || ws_bytes < need) return fail(PPO_EWORKSPACE, "workspace needs %zu bytes", need);
   if (!al256(ws)) return fail(PPO_EWORKSPACE, "workspace must be 256-byte aligned");
+  return PPO_OK;
+}
+
+ppo_status ppo_act(ppo_net* net, const ppo_act_io* io, void* ws, size_t ws_bytes, void* stream) {
+  TuneScope tsc(net);
+  if (!net || !io) return fail(PPO_EINVAL, "null argument");
+  if (const ppo_status cs = act_check(net, io, ws, ws_bytes); cs != PPO_OK) return cs;
+  const ppo_net_desc& d = net->d;
+  const int B = io->batch;
+  const int SR = io->state_rows > 0 ? io->state_rows : B;
+  const WsLayout w = plan(net, B, 1, false);
   const int H = d.hidden, L = d.lstm_layers, A = d.num_actions;
   bool fused = L <= 2;
   for (int l = 0; l < L; ++l) fused = fused && act_layer_supported(l == 0 ? net->din0 : H, H, B);
@@ -810,6 +845,139 @@ ppo_status ppo_act(ppo_net* net, const ppo_act_io* io, void* ws, size_t ws_bytes
                   io->u, io->action, io->logp, io->value, io->logits, io->active, s);
   return check_launch();
 }
+
+// Step t's ppo_act arguments inside a rollout's buffers (rows: its batch).
+static ppo_act_io collect_step(const ppo_net* net, const ppo_collect_io* io, int t, int rows, bool trim) {
+  const ppo_net_desc& d = net->d;
+  const size_t N = (size_t)io->N;
+  const size_t esz = net->prec && d.trunk != PPO_TRUNK_NONE ? 2 : 4;
+  const size_t frame = (size_t)d.in_ch * d.in_hw * d.in_hw;
+  const size_t gw = d.goal_mode == PPO_GOAL_NONE ? 0 : d.goal_mode == PPO_GOAL_VEC3 ? 3 : 2;
+  const size_t state = (size_t)d.lstm_layers * N * d.hidden;
+  ppo_act_io a{};
+  a.batch = rows;
+  a.state_rows = io->N;
+  a.obs = (const char*)io->obs + (size_t)t * N * frame * esz;
+  a.goal = io->goal ? io->goal + (size_t)t * N * gw : nullptr;
+  a.prev_action = io->actions + (size_t)t * N;
+  a.mask = io->mask + (size_t)t * N;
+  a.h_in = io->h_hist + (size_t)t * state;
+  a.c_in = io->c_hist + (size_t)t * state;
+  a.u = io->u + (size_t)t * N;
+  a.params = io->params;
+  a.params_lp = io->params_lp;
+  a.action = io->actions + (size_t)(t + 1) * N;
+  a.logp = io->logp + (size_t)t * N;
+  a.value = io->value + (size_t)t * N;
+  a.h_out = t < io->T ? io->h_hist + (size_t)(t + 1) * state : io->h_last;
+  a.c_out = t < io->T ? io->c_hist + (size_t)(t + 1) * state : io->c_last;
+  a.logits = nullptr;
+  a.active = trim || !io->active ? nullptr : io->active + t;
+  return a;
+}
+
+// The steps of one ppo_collect call, launched on s (rows[t]: step t's batch;
+// the steps stop at the first with none).
+static ppo_status collect_run(ppo_net* net, const ppo_collect_io* io, const std::vector<int>& rows, bool trim,
+                              void* ws, size_t ws_bytes, hipStream_t s) {
+  for (int t = io->t_begin; t < io->t_end && rows[t] > 0; ++t) {
+    const ppo_act_io a = collect_step(net, io, t, rows[t], trim);
+    if (const ppo_status st = ppo_act(net, &a, ws, ws_bytes, s); st != PPO_OK) return st;
+  }
+  return PPO_OK;
+}
+
+constexpr size_t kMaxCollectGraphs = 1024;
+
+ppo_status ppo_collect(ppo_net* net, const ppo_collect_io* io, int flags, void* ws, size_t ws_bytes,
+                       void* stream) {
+  if (!net || !io) return fail(PPO_EINVAL, "null argument");
+  const ppo_net_desc& d = net->d;
+  const int T = io->T, N = io->N;
+  if (T < 0 || N <= 0) return fail(PPO_ESHAPE, "need T >= 0 and N > 0");
+  if (io->t_begin < 0 || io->t_begin > io->t_end || io->t_end > T + 1)
+    return fail(PPO_ESHAPE, "step range [%d, %d) outside [0, %d]", io->t_begin, io->t_end, T + 1);
+  if (!io->actions || !io->h_hist || !io->c_hist || !io->h_last || !io->c_last)
+    return fail(PPO_EINVAL, "null pointer in ppo_collect_io");
+  if (flags & ~(PPO_COLLECT_GRAPH | PPO_COLLECT_TRIM)) return fail(PPO_EINVAL, "unknown flags %d", flags);
+  const bool trim = flags & PPO_COLLECT_TRIM;
+  // every step's batch (host), and the checks of the largest step's call
+  std::vector<int> rows(T + 1, N);
+  if (trim && io->lengths) {
+    for (int n = 0; n < N; ++n) {
+      if (io->lengths[n] < 0 || io->lengths[n] > T) return fail(PPO_ESHAPE, "length %d outside [0, %d]", io->lengths[n], T);
+      if (n > 0 && io->lengths[n] > io->lengths[n - 1])
+        return fail(PPO_ESHAPE, "lengths must be non-increasing (envs ordered longest first)");
+    }
+    for (int t = 0; t <= T; ++t) {
+      int b = 0;
+      while (b < N && io->lengths[b] >= t) ++b;
+      rows[t] = b;
+    }
+  }
+  if (io->t_begin == io->t_end) return PPO_OK;
+  {
+    const ppo_act_io a = collect_step(net, io, io->t_begin, N, trim);
+    if (const ppo_status cs = act_check(net, &a, ws, ws_bytes); cs != PPO_OK) return cs;
+  }
+  hipStream_t s = strm(stream);
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(s, &cs) != hipSuccess) return check_launch();
+  if (!(flags & PPO_COLLECT_GRAPH) || cs != hipStreamCaptureStatusNone)
+    return collect_run(net, io, rows, trim, ws, ws_bytes, s);
+  // the graph of this argument set: every field, the workspace, the flags, the lengths
+  std::string key;
+  auto put = [&key](const void* p, size_t n) { key.append((const char*)p, n); };
+  const void* ptrs[] = {io->obs, io->goal, io->mask, io->u, io->active, io->params, io->params_lp, io->actions,
+                        io->logp, io->value, io->h_hist, io->c_hist, io->h_last, io->c_last, ws};
+  const int ints[] = {T, N, io->t_begin, io->t_end, flags};
+  put(ptrs, sizeof(ptrs));
+  put(ints, sizeof(ints));
+  put(&ws_bytes, sizeof(ws_bytes));
+  if (trim) put(rows.data(), rows.size() * sizeof(int));
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return check_launch();
+  if (net->cap_stream && net->cap_device != dev)
+    return fail(PPO_EINVAL, "the net's act graphs live on device %d, not %d", net->cap_device, dev);
+  auto hit = net->graphs.find(key);
+  if (hit != net->graphs.end()) {
+    if (hipGraphLaunch(hit->second, s) != hipSuccess) return check_launch();
+    return PPO_OK;
+  }
+  // first call: eager steps (their results stand), then capture on the private stream
+  if (const ppo_status st = collect_run(net, io, rows, trim, ws, ws_bytes, s); st != PPO_OK) return st;
+  if (!net->cap_stream) {
+    if (hipStreamCreateWithFlags(&net->cap_stream, hipStreamNonBlocking) != hipSuccess) return check_launch();
+    net->cap_device = dev;
+  }
+  collect_drop(net, kMaxCollectGraphs - 1);
+  // the launch timer stays out of captured graphs (its events are re-armed and destroyed by the host)
+  const int tu = net->timer_unit;
+  net->timer_unit = -1;
+  hipGraph_t g = nullptr;
+  ppo_status st = PPO_OK;
+  if (hipStreamBeginCapture(net->cap_stream, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+    st = check_launch();
+  } else {
+    st = collect_run(net, io, rows, trim, ws, ws_bytes, net->cap_stream);
+    const hipError_t e = hipStreamEndCapture(net->cap_stream, &g);
+    if (st == PPO_OK && (e != hipSuccess || !g)) st = fail(PPO_EDEVICE, "act graph capture failed: %s", hipGetErrorString(e));
+  }
+  net->timer_unit = tu;
+  hipGraphExec_t exec = nullptr;
+  if (st == PPO_OK && hipGraphInstantiate(&exec, g, nullptr, nullptr, 0) != hipSuccess)
+    st = fail(PPO_EDEVICE, "act graph instantiation failed: %s", hipGetErrorString(hipGetLastError()));
+  if (g) (void)hipGraphDestroy(g);
+  (void)hipGetLastError();
+  if (st != PPO_OK) return st;
+  net->graphs.emplace(key, exec);
+  net->graph_order.push_back(key);
+  return PPO_OK;
+}
+
+int ppo_collect_clear(ppo_net* net) { return net ? collect_drop(net, 0) : 0; }
+
+int ppo_collect_graph_count(const ppo_net* net) { return net ? (int)net->graphs.size() : 0; }
 
 ppo_status ppo_gae(const float* rew, const float* val, const uint8_t* done, const int32_t* len, int T,
                    int N, float gamma, float lambda, float* adv, float* ret, double* adv_stats,

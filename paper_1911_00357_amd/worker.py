@@ -62,57 +62,50 @@ class Worker:
         self.h_scr = torch.zeros(L, N, H, **f32)
         self.c_scr = torch.zeros(L, N, H, **f32)
         self.d_active = torch.full((T + 1,), N, dtype=torch.int32, device=dev)  # rows written per act step
-        self._graphs = {}
+        self._own_net = net is None
 
     def release(self):
-        """Drop the captured graphs and the library state now (before the
-        interpreter's teardown), after the device has finished with them."""
+        """Drop the library state now (before the interpreter's teardown),
+        after the device has finished with it: the act graphs kept for this
+        worker's buffers (all of a net it created; a shared net's owner clears
+        its own) and the handles."""
         torch.cuda.synchronize()
-        self._graphs.clear()
+        if self.net is not None and self._own_net:
+            self.net.clear_graphs()
         self.net = None
         self.adam = None
 
     # ------------------------------------------------------------- rollout
-    def collect(self, env: dict, lengths=None, graph: bool = False, before_capture=None, trim: bool = False,
-                monitor=None, iteration: int = 0):
+    def collect(self, env: dict, lengths=None, graph: bool = False, trim: bool = False, monitor=None,
+                iteration: int = 0):
         """env: device tensors obs [T+1,N,C,H,W], goal [T+1,N,2], mask [T+1,N],
         u [T+1,N].  lengths: host ints [N] (non-increasing) or None (all T).
 
-        Act step t writes the rows of the envs still collecting (T_n >= t)
-        through a device row count (ppo_act's `active`, set from `lengths`
-        before the steps run), so with graph=True one captured graph of the
-        T+1 act calls serves any lengths: it is keyed on the env buffers only
-        (captured on the first call, after one eager pass; before_capture() runs
-        between the two).  trim=True instead launches step t on its active rows
-        only (less computed, a graph per set of lengths).
+        The T+1 act steps run in the library (ppo_collect).  Act step t writes
+        the rows of the envs still collecting (T_n >= t) through a device row
+        count (set from `lengths` before the steps run), so with graph=True one
+        library-owned graph of the T+1 steps serves any lengths: the first call
+        runs them eagerly and captures them, later calls launch the graph.
+        trim=True instead launches step t on its active rows only (less
+        computed, a graph per set of lengths).
 
         monitor: a PreemptionMonitor (Sec. 3).  The steps then run one at a
-        time (with graph=True each replays its own captured graph), each waited
-        for, and after each the monitor decides whether this worker's rollout
-        ends there; the next step supplies the bootstrap value.  Returns the
-        rollout length T_w, every env's length for the update (None without a
-        monitor)."""
+        time (with graph=True each launches its own captured graph), each
+        waited for, and after each the monitor decides whether this worker's
+        rollout ends there; the next step supplies the bootstrap value.
+        Returns the rollout length T_w (None without a monitor)."""
         if monitor is not None:
-            return self._collect_preemptible(env, graph, before_capture, monitor, iteration)
+            return self._collect_preemptible(env, graph, monitor, iteration)
         if not trim:
             self._set_active(lengths)
-        if graph:
-            key = (env["obs"].data_ptr(), env["u"].data_ptr(),
-                   tuple(lengths) if trim and lengths is not None else trim)
-            g = self._graphs.get(key)
-            if g is None:
-                self._collect(env, lengths, trim)   # eager pass: workspaces exist before capture
-                torch.cuda.synchronize()
-                if before_capture is not None:
-                    before_capture()
-                g = torch.cuda.CUDAGraph()
-                with torch.cuda.graph(g):
-                    self._collect(env, lengths, trim)
-                self._graphs[key] = g
-            g.replay()
-            return None
-        self._collect(env, lengths, trim)
+        self.net.collect(self._rollout_io(env), self.params, self.lp, active=None if trim else self.d_active,
+                         lengths=lengths, trim=trim, graph=graph)
         return None
+
+    def _rollout_io(self, env):
+        return {"obs": env["obs"], "goal": env.get("goal"), "mask": env["mask"], "u": env["u"],
+                "actions": self.act_rec, "logp": self.logp, "value": self.value, "h_hist": self.h_hist,
+                "c_hist": self.c_hist, "h_last": self.h_scr, "c_last": self.c_scr}
 
     def _set_active(self, lengths):
         """Rows written at each act step: #{n : T_n >= t}, t = 0..T."""
@@ -122,52 +115,13 @@ class Worker:
         counts = (lens[None, :] >= np.arange(T + 1)[:, None]).sum(axis=1).astype(np.int32)
         self.d_active.copy_(torch.from_numpy(counts))
 
-    def _collect(self, env: dict, lengths=None, trim: bool = False):
-        T, N = self.T, self.N
-        lens = np.full(N, T) if lengths is None else np.asarray(lengths)
-        assert np.all(np.diff(lens) <= 0), "envs must be ordered longest first"
-        for t in range(T + 1):
-            if trim:
-                B = int((lens >= t).sum())
-                if B == 0:
-                    break
-                self._act_step(env, t, B, None)
-            else:
-                self._act_step(env, t, N, self.d_active[t:t + 1])
-
-    def _act_step(self, env: dict, t: int, B: int, active):
-        T, N = self.T, self.N
-        out = {"action": self.act_rec[t + 1, :B], "logp": self.logp[t, :B],
-               "value": self.value[t, :B], "h": self.h_hist[min(t + 1, T)],
-               "c": self.c_hist[min(t + 1, T)]}
-        if t == T:  # bootstrap step of full-length envs: its state is discarded
-            out["h"], out["c"] = self.h_scr, self.c_scr
-        self.net.act(env["obs"][t, :B], env["goal"][t, :B], self.act_rec[t, :B],
-                     env["mask"][t, :B], self.h_hist[t], self.c_hist[t], env["u"][t, :B],
-                     self.params, self.lp, out=out, state_rows=N, active=active)
-
-    def _collect_preemptible(self, env, graph, before_capture, monitor, iteration):
+    def _collect_preemptible(self, env, graph, monitor, iteration):
         from .preempt import collect as run_steps
         stream = torch.cuda.current_stream(self.dev)
-        captured = [False]
+        io = self._rollout_io(env)
 
         def step(t):
-            if not graph:
-                self._act_step(env, t, self.N, None)
-            else:
-                key = (env["obs"].data_ptr(), env["u"].data_ptr(), "step", t)
-                g = self._graphs.get(key)
-                if g is None:
-                    self._act_step(env, t, self.N, None)     # eager pass, then capture
-                    torch.cuda.synchronize()
-                    if before_capture is not None and not captured[0]:
-                        before_capture()
-                        captured[0] = True
-                    g = torch.cuda.CUDAGraph()
-                    with torch.cuda.graph(g):
-                        self._act_step(env, t, self.N, None)
-                    self._graphs[key] = g
-                g.replay()
+            self.net.collect(io, self.params, self.lp, steps=(t, t + 1), graph=graph)
             stream.synchronize()     # the monitor counts steps the device has finished
 
         Tw = run_steps(monitor, iteration, step)

@@ -36,7 +36,7 @@ def test_struct_layouts_match_header(tmp_path):
     """Compile the header with the host C compiler and compare every struct's
     size and field offsets with the binding's ctypes declarations."""
     import subprocess
-    pairs = {"ppo_net_desc": L.NetDesc, "ppo_act_io": L.ActIO, "ppo_batch": L.Batch,
+    pairs = {"ppo_net_desc": L.NetDesc, "ppo_act_io": L.ActIO, "ppo_collect_io": L.CollectIO, "ppo_batch": L.Batch,
              "ppo_loss_cfg": L.LossCfg, "ppo_adam_cfg": L.AdamCfg, "ppo_scaler": L.Scaler}
     lines = ['#include <stdio.h>', '#include <stddef.h>', f'#include "{HEADER}"', 'int main(void){']
     for cname, py in pairs.items():
@@ -176,6 +176,43 @@ def test_calls_reject_null_and_bad_sizes_before_any_launch():
             == L.PPO_EINVAL
         assert lib.ppo_workspace_probe(h, 1, 8, 2, 3, 0, None, None, C.byref(off), dims) == L.PPO_OK
         assert dims[0] == 54
+    finally:
+        lib.ppo_net_destroy(h)
+
+
+def test_collect_rejects_bad_arguments_before_any_launch():
+    """ppo_collect's host checks: step range, null buffers, unknown flags,
+    unordered or out-of-range lengths, and the per-step ppo_act checks
+    (workspace size) of its largest step; an empty step range is a no-op.
+    Nothing here reaches a HIP call."""
+    lib = L.lib()
+    h = C.c_void_p()
+    assert lib.ppo_net_create(C.byref(_desc()), C.byref(h)) == L.PPO_OK
+    try:
+        fake = C.c_void_p(256)
+        io = L.CollectIO()
+        io.T, io.N, io.t_begin, io.t_end = 8, 4, 0, 9
+        assert lib.ppo_collect(h, C.byref(io), 0, fake, 1 << 40, None) == L.PPO_EINVAL   # null buffers
+        for f in ("obs", "goal", "mask", "u", "params", "actions", "logp", "value", "h_hist", "c_hist",
+                  "h_last", "c_last"):
+            setattr(io, f, fake)
+        assert lib.ppo_collect(h, C.byref(io), 0, fake, 16, None) == L.PPO_EWORKSPACE
+        assert lib.ppo_collect(h, C.byref(io), 8, fake, 1 << 40, None) == L.PPO_EINVAL   # unknown flag
+        io.t_end = 10
+        assert lib.ppo_collect(h, C.byref(io), 0, fake, 1 << 40, None) == L.PPO_ESHAPE
+        io.t_begin, io.t_end = 5, 4
+        assert lib.ppo_collect(h, C.byref(io), 0, fake, 1 << 40, None) == L.PPO_ESHAPE
+        io.t_begin = io.t_end = 3
+        assert lib.ppo_collect(h, C.byref(io), L.PPO_COLLECT_GRAPH, fake, 16, None) == L.PPO_OK
+        io.t_begin, io.t_end = 0, 9
+        lens = (C.c_int32 * 4)(8, 6, 7, 1)
+        io.lengths = C.cast(lens, L.P_i32)
+        assert lib.ppo_collect(h, C.byref(io), L.PPO_COLLECT_TRIM, fake, 1 << 40, None) == L.PPO_ESHAPE
+        lens[1], lens[3] = 7, 9
+        assert lib.ppo_collect(h, C.byref(io), L.PPO_COLLECT_TRIM, fake, 1 << 40, None) == L.PPO_ESHAPE
+        io.N = 0
+        assert lib.ppo_collect(h, C.byref(io), 0, fake, 1 << 40, None) == L.PPO_ESHAPE
+        assert lib.ppo_collect_graph_count(h) == 0 and lib.ppo_collect_clear(h) == 0
     finally:
         lib.ppo_net_destroy(h)
 

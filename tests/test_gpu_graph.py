@@ -1,6 +1,7 @@
-"""The act loop captured as one HIP graph: every replay (with eager library
-work and synchronisations between replays) reproduces the eager rollout
-bitwise, for equal and ragged rollout lengths."""
+"""The act loop as one HIP graph that the library captures and owns
+(ppo_collect): every launch (with eager library work and synchronisations
+between launches) reproduces the eager rollout bitwise, for equal and ragged
+rollout lengths, on the caller's stream, whole or one step per call."""
 import numpy as np
 import pytest
 import torch
@@ -47,3 +48,44 @@ def test_graph_replays_match_eager(P, lengths):
             assert torch.equal(a, b), rep
         w.collect(other, lengths)      # eager work between replays
         torch.cuda.synchronize()
+
+
+def test_library_graph_on_a_side_stream_and_per_step(P):
+    """The library's act graphs: one per argument set (count checked), each
+    launched on the caller's current stream (a side stream here, with the
+    results read on that stream before any synchronisation), and the
+    per-step graphs of a rollout run one step at a time equal to the whole
+    rollout's graph."""
+    from paper_1911_00357_amd.worker import Worker
+    say("library act graphs: side stream, per-step graphs")
+    net, T, N = MINI_RESNET, 5, 3
+    w = Worker(net, "f32", T, N, R.init_params(net, 4, random_affine=True), device="cuda")
+    env = _env(net, T, N, 6, "cuda")
+    w.collect(env)
+    torch.cuda.synchronize()
+    ref = _snap(w)
+    assert w.net.graph_count() == 0
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        for rep in range(3):
+            w.logp.zero_()
+            w.value.fill_(7.0)
+            w.collect(env, graph=True)            # captured on the first call, launched after
+            got = [x.clone() for x in _snap(w)]   # ordered after the graph on the same stream
+            side.synchronize()
+            for a, b in zip(got, ref):
+                assert torch.equal(a, b), rep
+    assert w.net.graph_count() == 1
+    io = w._rollout_io(env)
+    for rep in range(2):
+        w.logp.zero_()
+        w.value.zero_()
+        for t in range(T + 1):
+            w.net.collect(io, w.params, None, steps=(t, t + 1), graph=True)
+        torch.cuda.synchronize()
+        for a, b in zip(_snap(w), ref):
+            assert torch.equal(a, b), rep
+    assert w.net.graph_count() == 1 + (T + 1)
+    assert w.net.clear_graphs() == T + 2 and w.net.graph_count() == 0
+    w.release()
