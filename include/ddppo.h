@@ -485,12 +485,13 @@ ppo_status ppo_bench_unit_gemm(ppo_net* net, int op, int unit, int frames, const
 /* GEMM tile autotuner of this net.  mode 1: from now on, every GEMM problem
  * (operand kind, M, N, K, precision) that a call on this net meets and that
  * is not yet in the net's table is timed over the candidate tile shapes
- * (128x128 ... 32x128) and K splits before it runs; the call then waits for
- * those timings (so tune in warm-up, never under stream capture, where
- * tuning is skipped) and allocates a scratch output for them.  mode 0: stop
- * tuning, keep using the table.  mode -1: clear the table (heuristic choice).
- * Problems whose split-K partial tiles a GroupNorm consumes are not tuned.
- * *entries (optional) = problems in the table.  Not thread-safe with other
+ * (128x128 ... 32x128) and K splits before it runs; the call then
+ * waits for those timings (so tune in warm-up, never under stream capture,
+ * where tuning is skipped) and allocates a scratch output for them.  mode 0:
+ * stop tuning, keep using the table.  mode -1: clear the table (heuristic
+ * choice).  A product whose split-K partial tiles a GroupNorm sums is tuned
+ * on a key of its own, timed with an ordered reduction standing in for the
+ * GroupNorm's sum.  *entries (optional) = problems in the table.  Not thread-safe with other
  * calls on the same net. */
 ppo_status ppo_autotune(ppo_net* net, int mode, int* entries);
 

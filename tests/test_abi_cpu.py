@@ -217,6 +217,25 @@ def test_collect_rejects_bad_arguments_before_any_launch():
         lib.ppo_net_destroy(h)
 
 
+def test_tile_table_accepts_every_tile_shape_and_rejects_others():
+    """The autotuner's table takes tile indices 0..5 and splits 1..256, and
+    refuses anything else."""
+    lib = L.lib()
+    h = C.c_void_p()
+    assert lib.ppo_net_create(C.byref(_desc()), C.byref(h)) == L.PPO_OK
+    try:
+        n = C.c_int(0)
+        for tile, split, ok in ((0, 1, True), (5, 256, True), (6, 1, False), (-1, 1, False), (3, 0, False),
+                                (3, 257, False)):
+            row = (C.c_int64 * 7)(1, 64, 64, 576, 6, tile, split)
+            n.value = 1
+            st = lib.ppo_autotune_table(h, 1, row, 1, C.byref(n))
+            assert (st == L.PPO_OK) == ok, (tile, split)
+        assert lib.ppo_autotune_table(h, 0, None, 0, C.byref(n)) == L.PPO_OK and n.value == 1
+    finally:
+        lib.ppo_net_destroy(h)
+
+
 def test_binding_fails_loudly_without_library(monkeypatch, tmp_path):
     monkeypatch.setattr(L, "LIB_PATH", str(tmp_path / "missing.so"))
     monkeypatch.setattr(L, "_lib", None)

@@ -552,3 +552,43 @@ def test_autotuned_act(P, dtype):
         ref["form"] = policy.act(OP.unpack(net, flat), net, obs, goal, prev, mask, h, c, u, quant="bf16")
         ref["form"]["u"] = u
     check_act(out2, ref, dtype, B, "autotuned")
+
+
+TILE_NAMES = ["128x128", "128x64", "64x128", "64x64", "128x32", "32x128"]
+
+
+def test_every_tile_shape_on_the_act_products(P):
+    """Every GEMM tile shape the autotuner may choose forced onto every
+    product of a bfloat16 act step of the paper network (the tuned K split
+    kept, and a split of 1): each within the tolerance of the oracle."""
+    say("every tile shape on the act products (bf16, paper net)")
+    net, B = C1.net, 4
+    flat = R.init_params(net, 29, random_affine=True)
+    g = np.random.default_rng(30)
+    obs = R.round_bf16(g.random((B, net.in_ch, net.in_hw, net.in_hw), dtype=np.float32))
+    goal = g.standard_normal((B, 2)).astype(np.float32)
+    prev = g.integers(0, net.num_actions, B).astype(np.int32)
+    mask = np.ones(B, np.float32)
+    h = (0.5 * g.standard_normal((net.lstm_layers, B, net.hidden))).astype(np.float32)
+    c = (0.5 * g.standard_normal((net.lstm_layers, B, net.hidden))).astype(np.float32)
+    u = g.random(B).astype(np.float32)
+    n = P.Net(net, "bf16")
+    params = torch.tensor(flat, device=DEV)
+    lp = P.cast_bf16(params)
+    td = lambda a: torch.tensor(a, device=DEV)
+    args = (td(obs).to(torch.bfloat16), td(goal), td(prev), td(mask), td(h), td(c), td(u), params, lp)
+    n.autotune(1)
+    n.act(*args, want_logits=True)
+    n.autotune(0)
+    tuned = n.tile_table()
+    assert tuned and all(r[5] < len(TILE_NAMES) for r in tuned)
+    ref = policy.act(OP.unpack(net, flat), net, obs, goal, prev, mask, h, c, u)
+    ref["u"] = u
+    ref["form"] = policy.act(OP.unpack(net, flat), net, obs, goal, prev, mask, h, c, u, quant="bf16")
+    ref["form"]["u"] = u
+    for tile in range(len(TILE_NAMES)):
+        for one_split in (False, True):
+            n.tile_table([r[:5] + [tile, 1 if one_split else r[6]] for r in tuned])
+            out = n.act(*args, want_logits=True)
+            torch.cuda.synchronize()
+            check_act(out, ref, "bf16", B, f"tile {TILE_NAMES[tile]}{' split 1' if one_split else ''}")
