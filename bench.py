@@ -679,6 +679,7 @@ def summarize_trace(csv_path, log_path=None, ref_path=None):
         conv = [dur(r) for r in timed[:gae] if "ConvFwdProb" in r["Kernel_Name"]]
         out.append(f"\nact convolution GEMMs in the graph replay: {len(conv)} launches, average "
                    f"{sum(conv) / max(len(conv), 1):.3f} us")
+        out.extend(act_step_positions(timed[:gae], dur))
         table(timed[gae:], "update of the timed iteration")
         after = [r for r in rows[marks[1] + 1:] if "ConvFwdProb" in r["Kernel_Name"]]
         line = None
@@ -721,6 +722,42 @@ def summarize_trace(csv_path, log_path=None, ref_path=None):
     for k, (n, t) in sorted(agg.items(), key=lambda kv: -kv[1][1])[:15]:
         out.append(f"| {n} | {t / 1000:.2f} | {t / n:.2f} | `{k}` |")
     return "\n".join(out) + "\n"
+
+
+def act_step_positions(act, dur):
+    """In-graph duration of each launch position of an act step (averaged over
+    the steps of the replay, the first two and the last left out), grouped by
+    kernel kind and convolution grid: which launches of the step take longest."""
+    import collections
+    steps, cur = [], []
+    for r in act:
+        if "prep_kernel<" in r["Kernel_Name"] and "core_prep" not in r["Kernel_Name"] and cur:
+            steps.append(cur)
+            cur = []
+        cur.append(r)
+    steps.append(cur)
+    full = [s for s in steps[2:-1] if len(s) == len(steps[2])]
+    if not full:
+        return []
+    n = len(full[0])
+    avg = [sum(dur(s[i]) for s in full) / len(full) for i in range(n)]
+    grp = collections.OrderedDict()
+    for i in range(n):
+        r = full[0][i]
+        k = _short(r["Kernel_Name"])
+        if "gemm_kernel" in k:
+            k = f"{k.split(',')[0]}...> grid {r.get('Grid_Size_X', '?')}x{r.get('Grid_Size_Y', '?')}"
+        g = grp.setdefault(k, [0, 0.0, []])
+        g[0] += 1
+        g[1] += avg[i]
+        g[2].append(i)
+    out = [f"\n## one act step by launch position ({n} launches, {len(full)} steps averaged): "
+           f"kernel sum {sum(avg):.1f} us\n",
+           "| launches per step | avg us | positions | kernel (GEMMs by grid: tiles x K splits) |",
+           "|---:|---:|---|---|"]
+    for k, (c, t, pos) in sorted(grp.items(), key=lambda kv: -kv[1][1] / kv[1][0]):
+        out.append(f"| {c} | {t / c:.2f} | {','.join(map(str, pos[:8]))}{',...' if len(pos) > 8 else ''} | `{k}` |")
+    return out
 
 
 def summarize_counters(csv_path):
@@ -874,6 +911,8 @@ def main():
         out["cpu_baseline"] = cpu_baseline(wl, 0)
     gc.collect()
     torch.cuda.synchronize()
+    from paper_1911_00357_amd.api import live_nets
+    out["library_handles_at_end"] = live_nets()   # 0: no graph, event or stream outlives the run
     print(json.dumps(out), flush=True)
     h, h32 = out["health"], out.get("fp32_health", {"adam_skipped": 0, "loss_finite": True, "recurrence_failed": False})
     if not h["loss_finite"] or h["recurrence_failed"] or (wl.dtype == "f32" and h["adam_skipped"]) or \

@@ -19,6 +19,14 @@ from ._lib import check, lib
 # Test aid: fill workspaces with NaN bytes before every call.
 POISON_WS = os.environ.get("DDPPO_POISON_WS", "0") == "1"
 
+_live_nets = [0]   # ppo_net handles not yet destroyed
+
+
+def live_nets() -> int:
+    """Library handles (ppo_net) alive now: 0 once every Net is gone, so that
+    no library state (graphs, events, streams) outlives the caller's work."""
+    return _live_nets[0]
+
 
 def _ptr(t):
     return None if t is None else C.c_void_p(t.data_ptr())
@@ -92,6 +100,7 @@ class Net:
         h = C.c_void_p()
         check(lib().ppo_net_create(C.byref(d), C.byref(h)), "ppo_net_create")
         self._h = h
+        _live_nets[0] += 1
         self.P = int(lib().ppo_param_count(h))
         self.L, self.H, self.A = spec.lstm_layers, spec.hidden, spec.num_actions
         self.flat = int(spec.flat_dim)      # width of the visual FC's input (the encoder's output)
@@ -103,6 +112,7 @@ class Net:
         if h is not None and h.value:
             try:
                 lib().ppo_net_destroy(h)
+                _live_nets[0] -= 1
             except Exception:
                 pass
 
