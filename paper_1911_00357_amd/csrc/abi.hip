@@ -1497,7 +1497,7 @@ ppo_status ppo_autotune_table(ppo_net* net, int write, int64_t* table, int capac
     if (n < 0 || n > capacity) return fail(PPO_EINVAL, "entries outside the table");
     for (int i = 0; i < n; ++i) {
       const int64_t* r = table + 7 * i;
-      if (r[5] < 0 || r[5] > 5 || r[6] < 1 || r[6] > 256) return fail(PPO_EINVAL, "bad tile or split in row %d", i);
+      if (r[5] < 0 || r[5] >= kGemmTiles || r[6] < 1 || r[6] > 256) return fail(PPO_EINVAL, "bad tile or split in row %d", i);
       net->tune.best[{r[0], r[1], r[2], r[3], r[4]}] = {(int)r[5], (int)r[6]};
     }
     *entries = (int)net->tune.best.size();

@@ -11,6 +11,8 @@
 // vector loads, for operands contiguous along rows (transposed reads) the
 // lanes of a wavefront walk the rows so each of the 8 scalar loads is
 // coalesced; either way the chunk lands in LDS with one 16-byte write.
+// Operands read as 8-row vectors at one k (RT: the stem's weight gradient)
+// are staged two k at a time and stored as 8 row pairs (put8t2).
 //
 // bfloat16: v_mfma_f32_32x32x16_bf16 on 32x32 fragments.  float32: four
 // v_mfma_f32_16x16x4_f32 per 16-k step on 16x16 fragments.  A and B use the
@@ -476,22 +478,23 @@ DEV void put8(bf16_t* d, const float v[8], bf16_t* lo) {
   }
 }
 
-// 8 floats -> one k column of 8 consecutive LDS rows (stride ld elements).
-DEV void put8t(float* d, int ld, const float v[8], float*) {
+// Two chunks at k and k+1 -> columns k, k+1 of 8 consecutive LDS rows
+// (stride ld elements; k even): one 64-bit (float pair) or 32-bit (bfloat16
+// pair) store per row.  The lanes of a wavefront walk k, so each store
+// instruction covers consecutive LDS words of a row: a column of 16-bit
+// stores down the rows would put most lanes of a wavefront on a few banks.
+DEV void put8t2(float* d, int ld, const float v0[8], const float v1[8], float*) {
 #pragma unroll
-  for (int e = 0; e < 8; ++e) d[e * ld] = v[e];
+  for (int e = 0; e < 8; ++e) *(float2*)(d + e * ld) = make_float2(v0[e], v1[e]);
 }
-DEV void put8t(bf16_t* d, int ld, const float v[8], bf16_t* lo) {
+DEV void put8t2(bf16_t* d, int ld, const float v0[8], const float v1[8], bf16_t* lo) {
 #pragma unroll
-  for (int e = 0; e < 8; e += 2) {
-    const uint32_t h = pk_bf16(v[e], v[e + 1]);
-    d[e * ld] = (bf16_t)(h & 0xffffu);
-    d[(e + 1) * ld] = (bf16_t)(h >> 16);
+  for (int e = 0; e < 8; ++e) {
+    const uint32_t h = pk_bf16(v0[e], v1[e]);
+    *(uint32_t*)(d + e * ld) = h;
     if (lo) {
       const float a = __uint_as_float(h << 16), b = __uint_as_float(h & 0xffff0000u);
-      const uint32_t l = pk_bf16(v[e] - a, v[e + 1] - b);
-      lo[e * ld] = (bf16_t)(l & 0xffffu);
-      lo[(e + 1) * ld] = (bf16_t)(l >> 16);
+      *(uint32_t*)(lo + e * ld) = pk_bf16(v0[e] - a, v1[e] - b);
     }
   }
 }
@@ -506,10 +509,13 @@ __global__ void __launch_bounds__(256) gemm_kernel(Prob p, Epi e, int tiles_n, i
   constexpr int FM = WTM / FR, FN = WTN / FR;
   static_assert(WGM * WGN == 4 && FM >= 1 && FN >= 1, "bad tile");
   constexpr int LDK = BK + 16 / (int)sizeof(TC);  // padded LDS row (elements)
-  constexpr int CA = BM * BK / 8, CB = BN * BK / 8;
-  constexpr int QA = (CA + 255) / 256, QB = (CB + 255) / 256;
   constexpr bool AR = Layout<Prob>::A_ROWS, BR = Layout<Prob>::B_ROWS;
   constexpr bool ART = Layout<Prob>::A_RT, BRT = Layout<Prob>::B_RT;
+  // work units per K tile: a chunk (one row, 8 k), or for RT operands two
+  // chunks (8 rows at k and k+1, stored by put8t2)
+  constexpr int CA = ART ? (BM / 8) * (BK / 2) : BM * BK / 8, CB = BRT ? (BN / 8) * (BK / 2) : BN * BK / 8;
+  constexpr int QA = (CA + 255) / 256, QB = (CB + 255) / 256;
+  constexpr int VA = ART ? 2 : 1, VB = BRT ? 2 : 1;
   constexpr int NSPL = SPLIT ? 2 : 1;
   __shared__ __attribute__((aligned(16))) TC sA[NSPL][2][BM * LDK];
   __shared__ __attribute__((aligned(16))) TC sB[2][BN * LDK];
@@ -521,13 +527,14 @@ __global__ void __launch_bounds__(256) gemm_kernel(Prob p, Epi e, int tiles_n, i
   const int kend = min(p.K, kbeg + k_per_split);
   const int wm0 = (wave / WGN) * WTM, wn0 = (wave % WGN) * WTN;
 
-  // chunk c -> (row, k offset): lanes walk k for k-contiguous operands and
+  // unit c -> (row, k offset): lanes walk k for k-contiguous operands and
   // rows for row-contiguous ones
-  // (RT: chunk c -> first row 8*(c % (rows/8)) of an 8-row group and one k)
-  auto a_row = [&](int c) { return ART ? (c % (BM / 8)) * 8 : AR ? c % BM : c / (BK / 8); };
-  auto a_kc = [&](int c) { return ART ? c / (BM / 8) : AR ? (c / BM) * 8 : (c % (BK / 8)) * 8; };
-  auto b_row = [&](int c) { return BRT ? (c % (BN / 8)) * 8 : BR ? c % BN : c / (BK / 8); };
-  auto b_kc = [&](int c) { return BRT ? c / (BN / 8) : BR ? (c / BN) * 8 : (c % (BK / 8)) * 8; };
+  // (RT: unit c -> first row 8*(c / (BK/2)) of an 8-row group and the k
+  // pair 2*(c % (BK/2)): lanes walk the k pairs)
+  auto a_row = [&](int c) { return ART ? (c / (BK / 2)) * 8 : AR ? c % BM : c / (BK / 8); };
+  auto a_kc = [&](int c) { return ART ? (c % (BK / 2)) * 2 : AR ? (c / BM) * 8 : (c % (BK / 8)) * 8; };
+  auto b_row = [&](int c) { return BRT ? (c / (BK / 2)) * 8 : BR ? c % BN : c / (BK / 8); };
+  auto b_kc = [&](int c) { return BRT ? (c % (BK / 2)) * 2 : BR ? (c / BN) * 8 : (c % (BK / 8)) * 8; };
 
   typename Prob::RA ra[QA];
   typename Prob::RB rb[QB];
@@ -548,21 +555,27 @@ __global__ void __launch_bounds__(256) gemm_kernel(Prob p, Epi e, int tiles_n, i
 #pragma unroll
     for (int j = 0; j < FN; ++j) acc[i][j] = MM::zero();
 
-  float va[QA][8], vb[QB][8];
+  float va[QA][VA][8], vb[QB][VB][8];
   auto gload = [&](int k0) {
 #pragma unroll
     for (int q = 0; q < QA; ++q) {
       const int c = tid + 256 * q;
       const int k = k0 + a_kc(c);
-      if (c < CA && k < kend) p.a8(ra[q], k, va[q]);
-      else zero8(va[q]);
+#pragma unroll
+      for (int h = 0; h < VA; ++h) {
+        if (c < CA && k + h < kend) p.a8(ra[q], k + h, va[q][h]);
+        else zero8(va[q][h]);
+      }
     }
 #pragma unroll
     for (int q = 0; q < QB; ++q) {
       const int c = tid + 256 * q;
       const int k = k0 + b_kc(c);
-      if (c < CB && k < kend) p.b8(rb[q], k, vb[q]);
-      else zero8(vb[q]);
+#pragma unroll
+      for (int h = 0; h < VB; ++h) {
+        if (c < CB && k + h < kend) p.b8(rb[q], k + h, vb[q][h]);
+        else zero8(vb[q][h]);
+      }
     }
   };
   auto sstore = [&](int buf) {
@@ -572,9 +585,9 @@ __global__ void __launch_bounds__(256) gemm_kernel(Prob p, Epi e, int tiles_n, i
       if (c < CA) {
         const int o = a_row(c) * LDK + a_kc(c);
         if constexpr (ART)
-          put8t(&sA[0][buf][o], LDK, va[q], SPLIT ? &sA[NSPL - 1][buf][o] : (TC*)nullptr);
+          put8t2(&sA[0][buf][o], LDK, va[q][0], va[q][VA - 1], SPLIT ? &sA[NSPL - 1][buf][o] : (TC*)nullptr);
         else
-          put8(&sA[0][buf][o], va[q], SPLIT ? &sA[NSPL - 1][buf][o] : (TC*)nullptr);
+          put8(&sA[0][buf][o], va[q][0], SPLIT ? &sA[NSPL - 1][buf][o] : (TC*)nullptr);
       }
     }
 #pragma unroll
@@ -582,9 +595,9 @@ __global__ void __launch_bounds__(256) gemm_kernel(Prob p, Epi e, int tiles_n, i
       const int c = tid + 256 * q;
       if (c < CB) {
         if constexpr (BRT)
-          put8t(&sB[buf][b_row(c) * LDK + b_kc(c)], LDK, vb[q], (TC*)nullptr);
+          put8t2(&sB[buf][b_row(c) * LDK + b_kc(c)], LDK, vb[q][0], vb[q][VB - 1], (TC*)nullptr);
         else
-          put8(&sB[buf][b_row(c) * LDK + b_kc(c)], vb[q], (TC*)nullptr);
+          put8(&sB[buf][b_row(c) * LDK + b_kc(c)], vb[q][0], (TC*)nullptr);
       }
     }
   };

@@ -51,6 +51,7 @@ GemmTimer* active_timer(hipStream_t s) {
 }
 
 enum Tile { T128x128, T128x64, T64x128, T64x64, T128x32, T32x128 };
+static_assert((int)T32x128 + 1 == kGemmTiles, "tile table range");
 
 struct TileDim {
   int bm, bn;
@@ -154,7 +155,7 @@ std::pair<int, int> tune(const Prob& p, const Epi& e, long cap, float* partial, 
   float best_ms = 1e30f;
   if (hipEventCreate(&a) == hipSuccess && hipEventCreate(&b) == hipSuccess) {
     const long kmax = std::max<long>(1, (long)cdiv(p.K, BK));
-    for (int ti = 0; ti <= (int)T32x128; ++ti) {
+    for (int ti = 0; ti < kGemmTiles; ++ti) {
       const TileDim d = dim_of((Tile)ti);
       const long tiles = (long)cdiv(p.M, d.bm) * cdiv(p.N, d.bn);
       const int s0 = p.K > 0 ? splits_for(tiles, p.K) : 1;

@@ -92,6 +92,7 @@ extern thread_local GemmTune* g_gemm_tune;
 
 // gemm.hip (prec: 0 float32 operands, 1 bfloat16 operands)
 int gemm_max_splits_for(long M, long N, long K, int prec);
+constexpr int kGemmTiles = 6;  // tile shapes the autotuner's table may name
 // pb: bytes of `partial` available for split-K partial tiles
 // defer: leave split-K partial tiles [splits][M][N] in `partial` (no reduction
 // launch); returns the split count

@@ -592,3 +592,35 @@ def test_every_tile_shape_on_the_act_products(P):
             out = n.act(*args, want_logits=True)
             torch.cuda.synchronize()
             check_act(out, ref, "bf16", B, f"tile {TILE_NAMES[tile]}{' split 1' if one_split else ''}")
+
+
+@pytest.mark.parametrize("dtype", ["f32", "bf16"])
+def test_stem_weight_gradient_tiles(P, dtype):
+    """The channel-vector weight gradient (the stem's 4-channel input, k-pair
+    LDS stores) forced onto every tile shape, with the tuned K split and with
+    none: the whole gradient equals the tuned run's up to float32
+    accumulation order."""
+    say(f"stem weight-gradient tiles {dtype}")
+    net, T, N, envs, lengths = RESNET_64, 3, 3, [2, 1, 0], [3, 2, 3]
+    assert net.in_ch % 8 != 0 and net.in_ch % 4 == 0 and net.base_width % 8 == 0
+    flat = R.init_params(net, 45, random_affine=True)
+    rec = random_record(net, T, N, 46, lengths=lengths, bf16=dtype == "bf16")
+    envs = sorted(envs, key=lambda e: -lengths[e])
+    n = P.Net(net, dtype)
+    params = torch.tensor(flat, device=DEV)
+    lp = P.cast_bf16(params) if dtype == "bf16" else None
+    ro = to_device(rec, bf16=dtype == "bf16")
+    scale = torch.tensor([1.0], device=DEV)
+    n.autotune(1)
+    g0, _ = n.loss_backward(ro, envs, rec["lengths"], params, lp, P.LossCfg(), loss_scale=scale)
+    n.autotune(0)
+    g0 = g0.cpu().numpy().astype(np.float64)
+    tuned = n.tile_table()
+    rt = [r for r in tuned if r[0] == 4]          # the channel-vector weight-gradient problems
+    assert rt, "no channel-vector weight gradient in the table"
+    for tile in range(len(TILE_NAMES)):
+        for split in (None, 1):
+            n.tile_table([r[:5] + [tile, split or r[6]] for r in rt])
+            g1, _ = n.loss_backward(ro, envs, rec["lengths"], params, lp, P.LossCfg(), loss_scale=scale)
+            torch.cuda.synchronize()
+            assert_close(f"gradient, tile {TILE_NAMES[tile]} split {split or 'tuned'}", g1.cpu().numpy(), g0, 1e-5)
