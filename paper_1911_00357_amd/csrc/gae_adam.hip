@@ -3,48 +3,82 @@
 #include "kernels.h"
 
 // ---------------------------------------------------------------------------
-// GAE (Sec. 4 "Training"; Schulman et al. 2015).  One wavefront per env.  The
-// recurrence A_t = delta_t + c_t A_{t+1} (c_t = gamma lambda (1 - d_t)) is a
-// composition of affine maps, so each 64-step chunk is solved with a suffix
-// scan across lanes (lane = time step), chunks walked from the end; steps at
-// or past len[n] have delta = c = 0, which leaves A = 0 there.
+// GAE (Sec. 4 "Training"; Schulman et al. 2015).  A workgroup covers 64 envs.
+// The rollout is walked in 64-step chunks from the end; each chunk of rew,
+// done and val ([T][N] rows, val one row longer) is staged through LDS with
+// loads coalesced along the env axis, and the results leave the same way.
+// Each wavefront then solves the recurrence A_t = delta_t + c_t A_{t+1}
+// (c_t = gamma lambda (1 - d_t)) for 16 of the envs, one at a time: it is a
+// composition of affine maps, so a chunk is a suffix scan across lanes
+// (lane = time step) continued from the carried A of the chunk after it;
+// steps at or past len[n] have delta = c = 0, which leaves A = 0 there.
+constexpr int kGaeEnvs = 64;
 __global__ void __launch_bounds__(256) gae_kernel(const float* __restrict__ rew,
                                                   const float* __restrict__ val,
                                                   const uint8_t* __restrict__ done,
                                                   const int32_t* __restrict__ len, int T, int N,
                                                   float gamma, float lambda, float* __restrict__ adv,
                                                   float* __restrict__ ret) {
-  const int lane = threadIdx.x & 63;
-  const int n = blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (n >= N) return;
-  const int Tn = len ? min(max(len[n], 0), T) : T;
-  float carry = 0.f;  // A at the first step of the chunk after this one
+  // [t][env], rows padded to 65 so that a wavefront reading one env's column
+  // (lane = t) touches 64 different banks; s_r / s_k are overwritten in place
+  // by A and the return
+  __shared__ float s_r[64][kGaeEnvs + 1], s_k[64][kGaeEnvs + 1], s_v[65][kGaeEnvs + 1];
+  __shared__ float s_carry[kGaeEnvs];
+  __shared__ int s_len[kGaeEnvs];
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int n0 = blockIdx.x * kGaeEnvs;
+  if (tid < kGaeEnvs) {
+    const int n = n0 + tid;
+    s_carry[tid] = 0.f;  // A at the first step of the chunk after this one
+    s_len[tid] = n < N ? (len ? min(max(len[n], 0), T) : T) : 0;
+  }
   const int nchunks = (T + 63) / 64;
   for (int ch = nchunks - 1; ch >= 0; --ch) {
-    const int t = ch * 64 + lane;
-    float a = 0.f, b = 0.f, v = 0.f;
-    if (t < Tn) {
-      const float keep = done[(size_t)t * N + n] ? 0.f : 1.f;
-      v = val[(size_t)t * N + n];
-      b = rew[(size_t)t * N + n] + gamma * keep * val[(size_t)(t + 1) * N + n] - v;
-      a = gamma * lambda * keep;
+    const int t0 = ch * 64;
+    __syncthreads();  // the previous chunk's results have left s_r / s_k
+    for (int i = tid; i < 65 * kGaeEnvs; i += 256) {
+      const int r = i / kGaeEnvs, c = i - r * kGaeEnvs, t = t0 + r, n = n0 + c;
+      const bool in = n < N;
+      if (r < 64) {
+        s_r[r][c] = in && t < T ? rew[(size_t)t * N + n] : 0.f;
+        s_k[r][c] = in && t < T ? (done[(size_t)t * N + n] ? 0.f : 1.f) : 0.f;
+      }
+      s_v[r][c] = in && t <= T ? val[(size_t)t * N + n] : 0.f;
     }
-    // inclusive suffix scan of f_t o f_{t+1} o ... : (a, b) with F(x) = b + a x
+    __syncthreads();
+    for (int j = w; j < kGaeEnvs && n0 + j < N; j += 4) {
+      const int t = t0 + lane, Tn = s_len[j];
+      float a = 0.f, b = 0.f, v = 0.f;
+      if (t < Tn) {
+        const float keep = s_k[lane][j];
+        v = s_v[lane][j];
+        b = s_r[lane][j] + gamma * keep * s_v[lane + 1][j] - v;
+        a = gamma * lambda * keep;
+      }
+      // inclusive suffix scan of f_t o f_{t+1} o ... : (a, b) with F(x) = b + a x
 #pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-      const float a2 = __shfl_down(a, o, 64);
-      const float b2 = __shfl_down(b, o, 64);
-      if (lane + o < 64) {
-        b = b + a * b2;
-        a = a * a2;
+      for (int o = 1; o < 64; o <<= 1) {
+        const float a2 = __shfl_down(a, o, 64);
+        const float b2 = __shfl_down(b, o, 64);
+        if (lane + o < 64) {
+          b = b + a * b2;
+          a = a * a2;
+        }
+      }
+      const float A = b + a * s_carry[j];
+      s_r[lane][j] = A;
+      s_k[lane][j] = t < Tn ? A + v : 0.f;
+      const float first = __shfl(A, 0, 64);
+      if (lane == 0) s_carry[j] = first;
+    }
+    __syncthreads();
+    for (int i = tid; i < 64 * kGaeEnvs; i += 256) {
+      const int r = i / kGaeEnvs, c = i - r * kGaeEnvs, t = t0 + r, n = n0 + c;
+      if (t < T && n < N) {
+        adv[(size_t)t * N + n] = s_r[r][c];
+        ret[(size_t)t * N + n] = s_k[r][c];
       }
     }
-    const float A = b + a * carry;
-    if (t < T) {
-      adv[(size_t)t * N + n] = A;
-      ret[(size_t)t * N + n] = (t < Tn) ? A + v : 0.f;
-    }
-    carry = __shfl(A, 0, 64);
   }
 }
 
@@ -99,7 +133,7 @@ __global__ void __launch_bounds__(256) adv_stats_kernel(const float* __restrict_
 void launch_gae(const float* rew, const float* val, const uint8_t* done, const int32_t* len,
                 int T, int N, float gamma, float lambda, float* adv, float* ret, double* stats,
                 hipStream_t s) {
-  hipLaunchKernelGGL(gae_kernel, dim3(cdiv(N, 4)), dim3(256), 0, s, rew, val, done, len, T, N,
+  hipLaunchKernelGGL(gae_kernel, dim3(cdiv(N, kGaeEnvs)), dim3(256), 0, s, rew, val, done, len, T, N,
                      gamma, lambda, adv, ret);
   if (stats) hipLaunchKernelGGL(adv_stats_kernel, dim3(1), dim3(256), 0, s, adv, len, T, N, stats);
 }

@@ -26,7 +26,8 @@ def say(*a):
 
 # ---------------------------------------------------------------- GAE
 @pytest.mark.parametrize("T,N,ragged,seed", [(16, 2, False, 0), (128, 4, False, 1), (128, 64, True, 2),
-                                             (1, 3, False, 3), (200, 5, True, 4), (64, 1, False, 5)])
+                                             (1, 3, False, 3), (200, 5, True, 4), (64, 1, False, 5),
+                                             (70, 130, True, 6), (65, 64, False, 7)])
 def test_gae_parity(P, T, N, ragged, seed):
     say(f"gae T={T} N={N} ragged={ragged}")
     g = np.random.default_rng(seed)
