@@ -388,6 +388,16 @@ bool gn_one_launch(const Ctx& c, const Unit& u, bool bwd = false) {
   return gn_fused_npt(P, u.Cout / G) && (long)c.F * P * u.Cout <= limit;
 }
 
+// Whether the one-launch GroupNorm of a call that keeps no convolution outputs
+// (act, encode) reads its convolution's output group-major (Epi::gm_p): its
+// (image, group) slabs are then contiguous instead of Cg floats every C.  The
+// values are the same either way; DDPPO_ACT_GROUP_MAJOR=0 selects the plain
+// layout (a test compares the two).
+bool act_group_major() {
+  const char* e = getenv("DDPPO_ACT_GROUP_MAJOR");
+  return !(e && e[0] == '0');
+}
+
 // Arms the launch timer for the duration of one unit GEMM call when that
 // (unit, op) was selected with ppo_gemm_timer_arm.
 struct TimerScope {
@@ -411,17 +421,24 @@ void unit_fwd(const Ctx& c, int ui, const float* x, const float* res, bool relu,
     // conv (split-K partials left in place) -> one fused GroupNorm launch
     float* y = c.at(c.w->u[ui]);
     int splits;
+    // group-major only where no backward reads y in the plain layout
+    const bool gm = u.groups == 1 && !c.keep_u && act_group_major();
     if (u.groups > 1) {
       launch_gconv_fwd(c.n->prec, g, u.groups, x, c.wt(u.w), y, c.s);
       splits = 1;
     } else {
       TimerScope ts(c.n, ui, 0);
-      splits = gemm_conv_fwd(c.n->prec, g, x, c.wt(u.w), epi(y, u.Cout), kSplitKBytes, c.splitk(), c.s, true);
+      Epi e = epi(y, u.Cout);
+      if (gm) {
+        e.gm_p = P;
+        e.gm_cg = u.Cout / G;
+      }
+      splits = gemm_conv_fwd(c.n->prec, g, x, c.wt(u.w), e, kSplitKBytes, c.splitk(), c.s, true);
     }
     const float* src = splits > 1 ? c.splitk() : y;
     launch_gn_fused(src, splits, (size_t)c.F * P * u.Cout, (splits > 1 && c.keep_u) ? y : nullptr, c.F, P,
                     u.Cout, G, kGnEps, c.pf(u.g), c.pf(u.b), res, relu ? 1 : 0, out, chw ? 1 : 0,
-                    c.at<float2>(c.w->st[ui]), c.s);
+                    c.at<float2>(c.w->st[ui]), c.s, gm ? 1 : 0);
     return;
   }
   if (u.groups > 1) {
@@ -1466,9 +1483,15 @@ ppo_status ppo_bench_unit_gemm(ppo_net* net, int op, int unit, int frames, const
     else if (op == 1) launch_gconv_dgrad(net->prec, g, u.groups, DY, c.wt(u.w), OUT, 0, s);
     else launch_gconv_wgrad(net->prec, g, u.groups, X, DY, grad + u.w, c.splitk(), kSplitKBytes, s);
   }
+  Epi eact = epi(OUT, u.Cout);
+  if (act_form && act_group_major()) {   // the act step's group-major stores
+    eact.gm_p = u.Hout * u.Wout;
+    eact.gm_cg = u.Cout / net->d.gn_groups;
+  }
   for (int r = 0; r < reps && u.groups == 1; ++r) {
     if (op == 0 || op == 3)
-      gemm_conv_fwd(net->prec, g, X, c.wt(u.w), epi(OUT, u.Cout), kSplitKBytes, c.splitk(), s, act_form);
+      gemm_conv_fwd(net->prec, g, X, c.wt(u.w), op == 3 ? eact : epi(OUT, u.Cout), kSplitKBytes, c.splitk(), s,
+                    act_form);
     else if (op == 1)
       gemm_conv_dgrad(net->prec, g, DY, c.wt(u.w), c.at<void>(w.wT), epi(OUT, u.Cin), kSplitKBytes, c.splitk(), s);
     else

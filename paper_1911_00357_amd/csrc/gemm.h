@@ -629,6 +629,36 @@ __global__ void __launch_bounds__(256) gemm_kernel(Prob p, Epi e, int tiles_n, i
     }
   }
 
+  if (e.gm_p > 0) {
+    // group-major stores (plain values): the image and pixel of the fragment's
+    // first row once, later rows step from it
+    float* dst = e.partial ? e.partial + (size_t)blockIdx.y * p.M * p.N : e.C;
+#pragma unroll
+    for (int j = 0; j < FN; ++j) {
+      const int n = n0 + wn0 + j * FR + MM::ocol(lane);
+      if (n >= p.N) continue;
+      const int g = n / e.gm_cg, cc = n - g * e.gm_cg, G = p.N / e.gm_cg;
+#pragma unroll
+      for (int i = 0; i < FM; ++i) {
+        const int mb = m0 + wm0 + i * FR;
+        const int b0 = mb / e.gm_p, pb = mb - b0 * e.gm_p;
+#pragma unroll
+        for (int r = 0; r < MM::NOUT; ++r) {
+          const int m = mb + MM::orow(lane, r);
+          if (m < p.M) {
+            int b = b0, px = pb + MM::orow(lane, r);
+            if (px >= e.gm_p) {  // the fragment crosses into later images
+              const int q = px / e.gm_p;
+              b += q;
+              px -= q * e.gm_p;
+            }
+            dst[(((size_t)b * G + g) * e.gm_p + px) * e.gm_cg + cc] = acc[i][j][r];
+          }
+        }
+      }
+    }
+    return;
+  }
 #pragma unroll
   for (int i = 0; i < FM; ++i)
 #pragma unroll

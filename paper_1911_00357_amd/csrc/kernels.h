@@ -47,10 +47,15 @@ struct Epi {
   int accumulate;
   float* partial;  // set by the launcher for split-K
   int rq, rwq, rs1, rs2, rs3, r0;
+  // group-major output (gm_p > 0; plain stores only: alpha 1, no bias, ReLU or
+  // accumulation): rows m = (image b, pixel p < gm_p), columns n = (group g,
+  // channel c < gm_cg) go to ((b G + g) gm_p + p) gm_cg + c, so every (image,
+  // group) slab of a GroupNorm is contiguous; split-K partial z at z M N + that
+  int gm_p, gm_cg;
 };
 
 inline Epi epi(float* C, int ldc, const float* bias = nullptr, int relu = 0, int accumulate = 0) {
-  return Epi{C, ldc, bias, 1.0f, relu, accumulate, nullptr, 0, 1, 0, 0, 0, 0};
+  return Epi{C, ldc, bias, 1.0f, relu, accumulate, nullptr, 0, 1, 0, 0, 0, 0, 0, 0};
 }
 
 __device__ __forceinline__ size_t crow(const Epi& e, int m) {
@@ -124,9 +129,10 @@ void launch_prep(const void* obs, int bf16, const int32_t* src, int F, int C, in
 void launch_relu_grad(const float* dy, const float* y, size_t n, float* dx, hipStream_t s);
 // fused GroupNorm (one workgroup per image and group); 0 = group too large
 int gn_fused_npt(int P, int Cg);
+// src_gm: the input (or its split-K partials) is group-major (Epi::gm_p)
 void launch_gn_fused(const float* src, int nsplit, size_t zstride, float* u_out, int B, int P, int C, int G,
                      float eps, const float* gamma, const float* beta, const float* res, int relu, float* out,
-                     int out_chw, float2* stats, hipStream_t s);
+                     int out_chw, float2* stats, hipStream_t s, int src_gm = 0);
 void launch_gnb_fused(const float* dout, const float* outm, int chw, const float* y, int B, int P, int C, int G,
                       const float2* stats, const float* gamma, float* dy, float* dres, float* dgamma,
                       float* dbeta, float2* bpart, hipStream_t s);

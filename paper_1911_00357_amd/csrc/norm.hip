@@ -520,13 +520,17 @@ __global__ void __launch_bounds__(NT) gn_fused_kernel(const float* __restrict__ 
                                                        const float* __restrict__ beta,
                                                        const float* __restrict__ res, int relu,
                                                        float* __restrict__ out, int out_chw,
-                                                       float2* __restrict__ stats) {
+                                                       float2* __restrict__ stats, int src_gm) {
   __shared__ float red[NT / 64];
   const int b = blockIdx.x / G, g = blockIdx.x - b * G;
   const int Cg = C / G, n = P * Cg;
   // element j of this thread: pixel p0 + j*pstep, channel c (NT % Cg == 0)
   const int cc = threadIdx.x % Cg, p0 = threadIdx.x / Cg, pstep = NT / Cg, c = g * Cg + cc;
   const size_t base = ((size_t)b * P + p0) * C + c, jstr = (size_t)pstep * C;
+  // a group-major input holds this (b, g) slab contiguously, element (p, cc) at
+  // p Cg + cc: this thread's element j at threadIdx.x + j NT (coalesced)
+  const size_t sbase = src_gm ? (size_t)blockIdx.x * n + threadIdx.x : base;
+  const size_t sjstr = src_gm ? (size_t)NT : jstr;
   // the split-K partials, ZB splits per round with every load of a round in
   // flight together (summed in split order: deterministic)
   constexpr int ZB = NPT >= 16 ? 1 : 16 / NPT;
@@ -545,7 +549,7 @@ __global__ void __launch_bounds__(NT) gn_fused_kernel(const float* __restrict__ 
     for (int q = 0; q < ZB; ++q)
 #pragma unroll
       for (int j = 0; j < NPT; ++j)
-        y[q][j] = (z0 + q < nsplit && p0 + j * pstep < P) ? src[(size_t)(z0 + q) * zstride + base + j * jstr] : 0.f;
+        y[q][j] = (z0 + q < nsplit && p0 + j * pstep < P) ? src[(size_t)(z0 + q) * zstride + sbase + j * sjstr] : 0.f;
 #pragma unroll
     for (int q = 0; q < ZB; ++q)
 #pragma unroll
@@ -672,11 +676,11 @@ int gn_fused_npt(int P, int Cg) {
 
 void launch_gn_fused(const float* src, int nsplit, size_t zstride, float* u_out, int B, int P, int C, int G,
                      float eps, const float* gamma, const float* beta, const float* res, int relu, float* out,
-                     int out_chw, float2* stats, hipStream_t s) {
+                     int out_chw, float2* stats, hipStream_t s, int src_gm) {
   const int npt = gn_fused_npt(P, C / G), nt = (long)P * (C / G) <= 256 * 2 ? 256 : 1024;
 #define GN_CALL(K, T)                                                                                        \
   hipLaunchKernelGGL((gn_fused_kernel<K, T>), dim3(B * G), dim3(T), 0, s, src, nsplit, zstride, u_out, P, C, \
-                     G, eps, gamma, beta, res, relu, out, out_chw, stats)
+                     G, eps, gamma, beta, res, relu, out, out_chw, stats, src_gm)
   GN_NPT_SWITCH(nt, npt, GN_CALL)
 #undef GN_CALL
 }

@@ -555,6 +555,43 @@ def test_autotuned_act(P, dtype):
     check_act(out2, ref, dtype, B, "autotuned")
 
 
+@pytest.mark.parametrize("name,net,dtype,B", [("tiny", TINY_NET, "f32", 3), ("mini_resnet", MINI_RESNET, "bf16", 5),
+                                              ("paper", C1.net, "f32", 4), ("paper", C1.net, "bf16", 4)])
+def test_act_group_major_partials_are_bit_identical(P, monkeypatch, name, net, dtype, B):
+    """The act step's convolutions store their outputs (or split-K partials)
+    group-major for the GroupNorm that reads them: the same values in
+    another place, so every act output equals the plain layout's bit for
+    bit (tuned tiles, so that split-K partials are exercised)."""
+    say(f"act group-major partials {name} {dtype}")
+    flat = R.init_params(net, 31, random_affine=True)
+    g = np.random.default_rng(32)
+    obs = g.random((B, net.in_ch, net.in_hw, net.in_hw), dtype=np.float32)
+    if dtype == "bf16":
+        obs = R.round_bf16(obs)
+    gw = {"raw": 2, "polar": 2}[net.goal_mode]
+    goal = g.standard_normal((B, gw)).astype(np.float32)
+    prev = g.integers(0, net.num_actions, B).astype(np.int32)
+    mask = (g.random(B) > 0.3).astype(np.float32)
+    h = (0.5 * g.standard_normal((net.lstm_layers, B, net.hidden))).astype(np.float32)
+    c = (0.5 * g.standard_normal((net.lstm_layers, B, net.hidden))).astype(np.float32)
+    u = g.random(B).astype(np.float32)
+    n = P.Net(net, dtype)
+    params = torch.tensor(flat, device=DEV)
+    lp = P.cast_bf16(params) if dtype == "bf16" else None
+    td = lambda a: torch.tensor(a, device=DEV)
+    o = td(obs).to(torch.bfloat16) if dtype == "bf16" else td(obs)
+    args = (o, td(goal), td(prev), td(mask), td(h), td(c), td(u), params, lp)
+    n.autotune(1)
+    gm = n.act(*args, want_logits=True)
+    n.autotune(0)
+    gm = {k: v.clone() for k, v in gm.items()}
+    monkeypatch.setenv("DDPPO_ACT_GROUP_MAJOR", "0")
+    plain = n.act(*args, want_logits=True)
+    torch.cuda.synchronize()
+    for k in ("logits", "value", "logp", "h", "c", "action"):
+        assert torch.equal(gm[k], plain[k]), k
+
+
 TILE_NAMES = ["128x128", "128x64", "64x128", "64x64", "128x32", "32x128"]
 
 
