@@ -388,13 +388,14 @@ bool gn_one_launch(const Ctx& c, const Unit& u, bool bwd = false) {
   return gn_fused_npt(P, u.Cout / G) && (long)c.F * P * u.Cout <= limit;
 }
 
-// Whether the one-launch GroupNorm of a call that keeps no convolution outputs
-// (act, encode) reads its convolution's output group-major (Epi::gm_p): its
-// (image, group) slabs are then contiguous instead of Cg floats every C.  The
-// values are the same either way; DDPPO_ACT_GROUP_MAJOR=0 selects the plain
-// layout (a test compares the two).
-bool act_group_major() {
-  const char* e = getenv("DDPPO_ACT_GROUP_MAJOR");
+// The forms of a call that keeps no convolution outputs (act, encode): the
+// one-launch GroupNorm reads its convolution's output group-major
+// (Epi::gm_p), its (image, group) slabs contiguous instead of Cg floats every
+// C, and the stem's GroupNorm writes the max pool of its slab instead of the
+// plain map.  The values are the same either way; DDPPO_ACT_FUSED=0 selects
+// the plain forms (a test compares the two).
+bool act_fused_forms() {
+  const char* e = getenv("DDPPO_ACT_FUSED");
   return !(e && e[0] == '0');
 }
 
@@ -412,8 +413,10 @@ ConvGeo geo(const Unit& u, int F) {
   return ConvGeo{F, u.Hin, u.Win, u.Cin, u.Hout, u.Wout, u.Cout, u.K, u.K, u.stride, u.pad};
 }
 
-// conv -> GroupNorm (+ residual) (+ ReLU); output NHWC (or channel-major).
-void unit_fwd(const Ctx& c, int ui, const float* x, const float* res, bool relu, float* out, bool chw) {
+// conv -> GroupNorm (+ residual) (+ ReLU); output NHWC (or channel-major), or
+// with pool_out (one-launch form only) its 3x3 / 2 max pool instead.
+void unit_fwd(const Ctx& c, int ui, const float* x, const float* res, bool relu, float* out, bool chw,
+              float* pool_out = nullptr) {
   const Unit& u = c.n->units[ui];
   const ConvGeo g = geo(u, c.F);
   const int P = u.Hout * u.Wout, G = c.n->d.gn_groups;
@@ -422,7 +425,7 @@ void unit_fwd(const Ctx& c, int ui, const float* x, const float* res, bool relu,
     float* y = c.at(c.w->u[ui]);
     int splits;
     // group-major only where no backward reads y in the plain layout
-    const bool gm = u.groups == 1 && !c.keep_u && act_group_major();
+    const bool gm = u.groups == 1 && !c.keep_u && act_fused_forms();
     if (u.groups > 1) {
       launch_gconv_fwd(c.n->prec, g, u.groups, x, c.wt(u.w), y, c.s);
       splits = 1;
@@ -438,7 +441,7 @@ void unit_fwd(const Ctx& c, int ui, const float* x, const float* res, bool relu,
     const float* src = splits > 1 ? c.splitk() : y;
     launch_gn_fused(src, splits, (size_t)c.F * P * u.Cout, (splits > 1 && c.keep_u) ? y : nullptr, c.F, P,
                     u.Cout, G, kGnEps, c.pf(u.g), c.pf(u.b), res, relu ? 1 : 0, out, chw ? 1 : 0,
-                    c.at<float2>(c.w->st[ui]), c.s, gm ? 1 : 0);
+                    c.at<float2>(c.w->st[ui]), c.s, gm ? 1 : 0, pool_out, u.Hout, u.Wout);
     return;
   }
   if (u.groups > 1) {
@@ -464,9 +467,15 @@ const float* encoder_fwd(const Ctx& c) {
     return c.at(c.w->a[1]);
   }
   const Unit& S = n->units[n->stem];
-  unit_fwd(c, n->stem, x0, nullptr, true, c.at(c.w->a[n->stem]), false);
-  launch_maxpool_fwd(c.at(c.w->a[n->stem]), c.F, S.Hout, S.Wout, S.Cout, c.at(c.w->pool),
-                     c.at<uint8_t>(c.w->arg), c.s);
+  // without a backward the stem's GroupNorm pools its own slab (no plain map,
+  // no max-pool launch, no winner indices)
+  if (!c.keep_u && act_fused_forms() && gn_one_launch(c, S) && gn_pool_fits(S.Hout * S.Wout, S.Cout / n->d.gn_groups)) {
+    unit_fwd(c, n->stem, x0, nullptr, true, c.at(c.w->a[n->stem]), false, c.at(c.w->pool));
+  } else {
+    unit_fwd(c, n->stem, x0, nullptr, true, c.at(c.w->a[n->stem]), false);
+    launch_maxpool_fwd(c.at(c.w->a[n->stem]), c.F, S.Hout, S.Wout, S.Cout, c.at(c.w->pool),
+                       c.at<uint8_t>(c.w->arg), c.s);
+  }
   const float* x = c.at(c.w->pool);
   for (size_t bi = 0; bi < n->blocks.size(); ++bi) {
     const Block& b = n->blocks[bi];
@@ -1484,7 +1493,7 @@ ppo_status ppo_bench_unit_gemm(ppo_net* net, int op, int unit, int frames, const
     else launch_gconv_wgrad(net->prec, g, u.groups, X, DY, grad + u.w, c.splitk(), kSplitKBytes, s);
   }
   Epi eact = epi(OUT, u.Cout);
-  if (act_form && act_group_major()) {   // the act step's group-major stores
+  if (act_form && act_fused_forms()) {   // the act step's group-major stores
     eact.gm_p = u.Hout * u.Wout;
     eact.gm_cg = u.Cout / net->d.gn_groups;
   }

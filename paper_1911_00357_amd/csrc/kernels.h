@@ -129,10 +129,15 @@ void launch_prep(const void* obs, int bf16, const int32_t* src, int F, int C, in
 void launch_relu_grad(const float* dy, const float* y, size_t n, float* dx, hipStream_t s);
 // fused GroupNorm (one workgroup per image and group); 0 = group too large
 int gn_fused_npt(int P, int Cg);
-// src_gm: the input (or its split-K partials) is group-major (Epi::gm_p)
+// src_gm: the input (or its split-K partials) is group-major (Epi::gm_p).
+// pool_out: instead of `out`, write the 3x3 / 2 (pad 1) max pool of the
+// normalised H x W map (NHWC, ceil(H/2) x ceil(W/2)); needs gn_pool_fits.
+constexpr long kGnPoolLds = 64 * 1024;
+bool gn_pool_fits(int P, int Cg);
 void launch_gn_fused(const float* src, int nsplit, size_t zstride, float* u_out, int B, int P, int C, int G,
                      float eps, const float* gamma, const float* beta, const float* res, int relu, float* out,
-                     int out_chw, float2* stats, hipStream_t s, int src_gm = 0);
+                     int out_chw, float2* stats, hipStream_t s, int src_gm = 0, float* pool_out = nullptr,
+                     int H = 0, int W = 0);
 void launch_gnb_fused(const float* dout, const float* outm, int chw, const float* y, int B, int P, int C, int G,
                       const float2* stats, const float* gamma, float* dy, float* dres, float* dgamma,
                       float* dbeta, float2* bpart, hipStream_t s);

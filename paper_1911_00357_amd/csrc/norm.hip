@@ -520,8 +520,10 @@ __global__ void __launch_bounds__(NT) gn_fused_kernel(const float* __restrict__ 
                                                        const float* __restrict__ beta,
                                                        const float* __restrict__ res, int relu,
                                                        float* __restrict__ out, int out_chw,
-                                                       float2* __restrict__ stats, int src_gm) {
+                                                       float2* __restrict__ stats, int src_gm,
+                                                       float* __restrict__ pool_out, int H, int W) {
   __shared__ float red[NT / 64];
+  extern __shared__ float s_slab[];  // pool_out: the normalised slab [p][cc] (P Cg floats)
   const int b = blockIdx.x / G, g = blockIdx.x - b * G;
   const int Cg = C / G, n = P * Cg;
   // element j of this thread: pixel p0 + j*pstep, channel c (NT % Cg == 0)
@@ -577,7 +579,30 @@ __global__ void __launch_bounds__(NT) gn_fused_kernel(const float* __restrict__ 
       const size_t idx = base + j * jstr;
       float o = (x[j] - mean) * ga + be + rv[j];
       if (relu) o = fmaxf(o, 0.f);
-      out[out_chw ? ((size_t)b * C + c) * P + p : idx] = o;
+      if (pool_out)
+        s_slab[p * Cg + cc] = o;
+      else
+        out[out_chw ? ((size_t)b * C + c) * P + p : idx] = o;
+    }
+  }
+  if (pool_out) {
+    // 3x3 / 2 max pool (pad 1) of this group's channels from LDS; the plain
+    // output is not written.  The window maximum over the in-bounds taps is
+    // the same value max_pool's first maximum takes.
+    __syncthreads();
+    const int Ho = (H - 1) / 2 + 1, Wo = (W - 1) / 2 + 1, no = Ho * Wo * Cg;
+    for (int e = threadIdx.x; e < no; e += NT) {
+      const int c2 = e % Cg, q = e / Cg, wo = q % Wo, ho = q / Wo;
+      float best = -INFINITY;
+#pragma unroll
+      for (int t = 0; t < 9; ++t) {
+        const int hi = 2 * ho - 1 + t / 3, wi = 2 * wo - 1 + t % 3;
+        if (hi >= 0 && hi < H && wi >= 0 && wi < W) {
+          const float v = s_slab[(hi * W + wi) * Cg + c2];
+          if (v > best) best = v;
+        }
+      }
+      pool_out[(((size_t)b * Ho + ho) * Wo + wo) * C + g * Cg + c2] = best;
     }
   }
 }
@@ -674,13 +699,16 @@ int gn_fused_npt(int P, int Cg) {
     }                                  \
   }
 
+bool gn_pool_fits(int P, int Cg) { return (long)P * Cg * (long)sizeof(float) <= kGnPoolLds; }
+
 void launch_gn_fused(const float* src, int nsplit, size_t zstride, float* u_out, int B, int P, int C, int G,
                      float eps, const float* gamma, const float* beta, const float* res, int relu, float* out,
-                     int out_chw, float2* stats, hipStream_t s, int src_gm) {
+                     int out_chw, float2* stats, hipStream_t s, int src_gm, float* pool_out, int H, int W) {
   const int npt = gn_fused_npt(P, C / G), nt = (long)P * (C / G) <= 256 * 2 ? 256 : 1024;
-#define GN_CALL(K, T)                                                                                        \
-  hipLaunchKernelGGL((gn_fused_kernel<K, T>), dim3(B * G), dim3(T), 0, s, src, nsplit, zstride, u_out, P, C, \
-                     G, eps, gamma, beta, res, relu, out, out_chw, stats, src_gm)
+  const size_t lds = pool_out ? (size_t)P * (C / G) * sizeof(float) : 0;
+#define GN_CALL(K, T)                                                                                          \
+  hipLaunchKernelGGL((gn_fused_kernel<K, T>), dim3(B * G), dim3(T), lds, s, src, nsplit, zstride, u_out, P, C, \
+                     G, eps, gamma, beta, res, relu, out, out_chw, stats, src_gm, pool_out, H, W)
   GN_NPT_SWITCH(nt, npt, GN_CALL)
 #undef GN_CALL
 }

@@ -557,12 +557,13 @@ def test_autotuned_act(P, dtype):
 
 @pytest.mark.parametrize("name,net,dtype,B", [("tiny", TINY_NET, "f32", 3), ("mini_resnet", MINI_RESNET, "bf16", 5),
                                               ("paper", C1.net, "f32", 4), ("paper", C1.net, "bf16", 4)])
-def test_act_group_major_partials_are_bit_identical(P, monkeypatch, name, net, dtype, B):
+def test_act_fused_forms_are_bit_identical(P, monkeypatch, name, net, dtype, B):
     """The act step's convolutions store their outputs (or split-K partials)
-    group-major for the GroupNorm that reads them: the same values in
-    another place, so every act output equals the plain layout's bit for
-    bit (tuned tiles, so that split-K partials are exercised)."""
-    say(f"act group-major partials {name} {dtype}")
+    group-major for the GroupNorm that reads them, and the stem's GroupNorm
+    pools its own slab: the same values in another place and the same
+    window maxima, so every act output equals the plain forms' bit for bit
+    (tuned tiles, so that split-K partials are exercised)."""
+    say(f"act fused forms {name} {dtype}")
     flat = R.init_params(net, 31, random_affine=True)
     g = np.random.default_rng(32)
     obs = g.random((B, net.in_ch, net.in_hw, net.in_hw), dtype=np.float32)
@@ -585,7 +586,7 @@ def test_act_group_major_partials_are_bit_identical(P, monkeypatch, name, net, d
     gm = n.act(*args, want_logits=True)
     n.autotune(0)
     gm = {k: v.clone() for k, v in gm.items()}
-    monkeypatch.setenv("DDPPO_ACT_GROUP_MAJOR", "0")
+    monkeypatch.setenv("DDPPO_ACT_FUSED", "0")
     plain = n.act(*args, want_logits=True)
     torch.cuda.synchronize()
     for k in ("logits", "value", "logp", "h", "c", "action"):
