@@ -432,6 +432,7 @@ void unit_fwd(const Ctx& c, int ui, const float* x, const float* res, bool relu,
     } else {
       TimerScope ts(c.n, ui, 0);
       Epi e = epi(y, u.Cout);
+      e.act = c.keep_u ? 0 : 1;
       if (gm) {
         e.gm_p = P;
         e.gm_cg = u.Cout / G;
@@ -1493,6 +1494,7 @@ ppo_status ppo_bench_unit_gemm(ppo_net* net, int op, int unit, int frames, const
     else launch_gconv_wgrad(net->prec, g, u.groups, X, DY, grad + u.w, c.splitk(), kSplitKBytes, s);
   }
   Epi eact = epi(OUT, u.Cout);
+  eact.act = act_form ? 1 : 0;
   if (act_form && act_fused_forms()) {   // the act step's group-major stores
     eact.gm_p = u.Hout * u.Wout;
     eact.gm_cg = u.Cout / net->d.gn_groups;

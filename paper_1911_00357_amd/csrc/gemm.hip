@@ -135,7 +135,7 @@ bool capturing(hipStream_t s) {
 // returns the fastest; falls back to `dflt` when timing is not possible.
 template <class Prob, typename TC, bool SPLIT>
 std::pair<int, int> tune(const Prob& p, const Epi& e, long cap, float* partial, hipStream_t s,
-                         std::pair<int, int> dflt) {
+                         std::pair<int, int> dflt, int min_split) {
   // rows of C written: up to the row of m = M-1 (the row map is monotone in m)
   size_t rows = (size_t)p.M;
   if (e.rq > 0) {
@@ -162,7 +162,7 @@ std::pair<int, int> tune(const Prob& p, const Epi& e, long cap, float* partial, 
       int cand[6] = {1, s0 / 2, s0, 2 * s0, 4 * s0, 8 * s0};
       int last = -1;
       for (int z : cand) {
-        z = (int)std::min<long>({(long)z, cap, kmax, 256L});
+        z = (int)std::min<long>({(long)std::max(z, min_split), cap, kmax, 256L});
         if (z < 1 || z == last) continue;
         last = z;
         launch_tile<Prob, TC, SPLIT>((Tile)ti, p, et, z, partial, s, false);
@@ -210,18 +210,30 @@ int run(const Prob& p, Epi e, size_t partial_bytes, float* partial, hipStream_t 
   int splits = p.K > 0 ? splits_for(tiles, p.K) : 1;
   const long cap = (long)(partial_bytes / (sizeof(float) * (size_t)p.M * p.N));
   if (splits > cap) splits = (int)std::max<long>(1, cap);
+  // An act-step product (Epi::act, its partials summed by a GroupNorm) is split into
+  // at least min(4, K/64) parts: in the act graph each product reads its
+  // weights past a cold L2 right after its producer, where more workgroups
+  // fetching a share each pay more than back-to-back timing shows (measured
+  // on the whole act loop; the learner's products are better left as tuned).
+  const bool act = e.act && defer;
+  const int min_split = act ? (int)std::max<long>(1, std::min<long>({4L, (long)p.K / 64, cap})) : 1;
+  splits = std::max(splits, min_split);
   GemmTune* tu = g_gemm_tune;
   if (tu) {
     // a deferred product (its partial tiles summed by the consumer) is tuned
-    // on its own key, timed with the ordered reduction as the consumer's stand-in
-    const std::array<long long, 5> key{Prob::kKind, p.M, p.N, p.K, 2 * prec + (int)SPLIT + 4 * (int)defer};
+    // on its own key, timed with the ordered reduction as the consumer's
+    // stand-in; an act-step product on another
+    const std::array<long long, 5> key{Prob::kKind, p.M, p.N, p.K,
+                                       2 * prec + (int)SPLIT + 4 * (int)defer + 8 * (int)act};
     auto it = tu->best.find(key);
     if (it == tu->best.end() && tu->tuning && !capturing(s))
-      it = tu->best.emplace(key, tune<Prob, TC, SPLIT>(p, e, std::max<long>(1, cap), partial, s, {(int)t, splits}))
+      it = tu->best
+               .emplace(key, tune<Prob, TC, SPLIT>(p, e, std::max<long>(1, cap), partial, s, {(int)t, splits},
+                                                   min_split))
                .first;
     if (it != tu->best.end()) {
       t = (Tile)it->second.first;
-      splits = (int)std::max<long>(1, std::min<long>(it->second.second, std::max<long>(1, cap)));
+      splits = (int)std::max<long>(min_split, std::min<long>(it->second.second, std::max<long>(1, cap)));
     }
   }
   return launch_tile<Prob, TC, SPLIT>(t, p, e, splits, partial, s, defer);
