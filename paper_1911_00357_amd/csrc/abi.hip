@@ -388,12 +388,13 @@ bool gn_one_launch(const Ctx& c, const Unit& u, bool bwd = false) {
   return gn_fused_npt(P, u.Cout / G) && (long)c.F * P * u.Cout <= limit;
 }
 
-// The forms of a call that keeps no convolution outputs (act, encode): the
-// one-launch GroupNorm reads its convolution's output group-major
+// The one-launch GroupNorm reads its convolution's output (in a call that
+// keeps outputs for a backward: its split-K partials only) group-major
 // (Epi::gm_p), its (image, group) slabs contiguous instead of Cg floats every
-// C, and the stem's GroupNorm writes the max pool of its slab instead of the
-// plain map.  The values are the same either way; DDPPO_ACT_FUSED=0 selects
-// the plain forms (a test compares the two).
+// C; in a call that keeps no outputs (act, encode) the stem's GroupNorm also
+// writes the max pool of its slab instead of the plain map.  The values are
+// the same either way; DDPPO_ACT_FUSED=0 selects the plain forms (tests
+// compare the two).
 bool act_fused_forms() {
   const char* e = getenv("DDPPO_ACT_FUSED");
   return !(e && e[0] == '0');
@@ -424,8 +425,9 @@ void unit_fwd(const Ctx& c, int ui, const float* x, const float* res, bool relu,
     // conv (split-K partials left in place) -> one fused GroupNorm launch
     float* y = c.at(c.w->u[ui]);
     int splits;
-    // group-major only where no backward reads y in the plain layout
-    const bool gm = u.groups == 1 && !c.keep_u && act_fused_forms();
+    // group-major stores; where a backward reads y in the plain layout, only
+    // for split-K partials (the GroupNorm then writes y plainly as it sums them)
+    const bool gm = u.groups == 1 && act_fused_forms();
     if (u.groups > 1) {
       launch_gconv_fwd(c.n->prec, g, u.groups, x, c.wt(u.w), y, c.s);
       splits = 1;
@@ -436,13 +438,15 @@ void unit_fwd(const Ctx& c, int ui, const float* x, const float* res, bool relu,
       if (gm) {
         e.gm_p = P;
         e.gm_cg = u.Cout / G;
+        e.gm_split_only = c.keep_u ? 1 : 0;
       }
       splits = gemm_conv_fwd(c.n->prec, g, x, c.wt(u.w), e, kSplitKBytes, c.splitk(), c.s, true);
     }
     const float* src = splits > 1 ? c.splitk() : y;
+    const bool src_gm = gm && (splits > 1 || !c.keep_u);
     launch_gn_fused(src, splits, (size_t)c.F * P * u.Cout, (splits > 1 && c.keep_u) ? y : nullptr, c.F, P,
                     u.Cout, G, kGnEps, c.pf(u.g), c.pf(u.b), res, relu ? 1 : 0, out, chw ? 1 : 0,
-                    c.at<float2>(c.w->st[ui]), c.s, gm ? 1 : 0, pool_out, u.Hout, u.Wout);
+                    c.at<float2>(c.w->st[ui]), c.s, src_gm ? 1 : 0, pool_out, u.Hout, u.Wout);
     return;
   }
   if (u.groups > 1) {

@@ -629,7 +629,7 @@ __global__ void __launch_bounds__(256) gemm_kernel(Prob p, Epi e, int tiles_n, i
     }
   }
 
-  if (e.gm_p > 0) {
+  if (e.gm_p > 0 && (e.partial || !e.gm_split_only)) {
     // group-major stores (plain values): the image and pixel of the fragment's
     // first row once, later rows step from it
     float* dst = e.partial ? e.partial + (size_t)blockIdx.y * p.M * p.N : e.C;

@@ -52,13 +52,14 @@ struct Epi {
   // channel c < gm_cg) go to ((b G + g) gm_p + p) gm_cg + c, so every (image,
   // group) slab of a GroupNorm is contiguous; split-K partial z at z M N + that
   int gm_p, gm_cg;
+  int gm_split_only;  // group-major for split-K partials only (a single split stores plainly)
   // a product of a call that keeps no outputs for a backward (act, encode):
   // tuned on a key of its own with a minimum K split (see the launcher)
   int act;
 };
 
 inline Epi epi(float* C, int ldc, const float* bias = nullptr, int relu = 0, int accumulate = 0) {
-  return Epi{C, ldc, bias, 1.0f, relu, accumulate, nullptr, 0, 1, 0, 0, 0, 0, 0, 0, 0};
+  return Epi{C, ldc, bias, 1.0f, relu, accumulate, nullptr, 0, 1, 0, 0, 0, 0, 0, 0, 0, 0};
 }
 
 __device__ __forceinline__ size_t crow(const Epi& e, int m) {

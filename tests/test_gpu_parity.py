@@ -593,6 +593,34 @@ def test_act_fused_forms_are_bit_identical(P, monkeypatch, name, net, dtype, B):
         assert torch.equal(gm[k], plain[k]), k
 
 
+@pytest.mark.parametrize("net,dtype", [(RESNET_64, "f32"), (RESNET_64, "bf16"), (MINI_RESNET, "bf16")],
+                         ids=["resnet64-f32", "resnet64-bf16", "mini_resnet-bf16"])
+def test_learner_group_major_partials_are_bit_identical(P, monkeypatch, net, dtype):
+    """In the learner the one-launch GroupNorms read their split-K partials
+    group-major (the summed convolution output the backward needs is still
+    stored plainly): loss statistics and the whole gradient equal the plain
+    layout's bit for bit (tuned tiles)."""
+    say(f"learner group-major partials {dtype}")
+    T, N, envs, lengths = 3, 3, [2, 1, 0], [3, 2, 3]
+    flat = R.init_params(net, 47, random_affine=True)
+    rec = random_record(net, T, N, 48, lengths=lengths, bf16=dtype == "bf16")
+    envs = sorted(envs, key=lambda e: -lengths[e])
+    n = P.Net(net, dtype)
+    params = torch.tensor(flat, device=DEV)
+    lp = P.cast_bf16(params) if dtype == "bf16" else None
+    ro = to_device(rec, bf16=dtype == "bf16")
+    scale = torch.tensor([1.0], device=DEV)
+    n.autotune(1)
+    n.loss_backward(ro, envs, rec["lengths"], params, lp, P.LossCfg(), loss_scale=scale)
+    n.autotune(0)
+    g0, s0 = n.loss_backward(ro, envs, rec["lengths"], params, lp, P.LossCfg(), loss_scale=scale)
+    g0, s0 = g0.clone(), s0.clone()
+    monkeypatch.setenv("DDPPO_ACT_FUSED", "0")
+    g1, s1 = n.loss_backward(ro, envs, rec["lengths"], params, lp, P.LossCfg(), loss_scale=scale)
+    torch.cuda.synchronize()
+    assert torch.equal(g0, g1) and torch.equal(s0, s1)
+
+
 TILE_NAMES = ["128x128", "128x64", "64x128", "64x64", "128x32", "32x128"]
 
 
