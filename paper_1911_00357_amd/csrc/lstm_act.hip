@@ -66,7 +66,27 @@ DEV float op_round(float x, bool bf) {
   return __uint_as_float((uint32_t)__builtin_bit_cast(uint32_t, r) << 16);
 }
 
-template <typename TW, int U, int KMAX>
+// 8 consecutive values as floats: two 16-byte loads (float) or one (bfloat16)
+DEV void act_ld8(const float* p, float v[8]) {
+  const float4 a = *(const float4*)p, b = *(const float4*)(p + 4);
+  v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w;
+  v[4] = b.x; v[5] = b.y; v[6] = b.z; v[7] = b.w;
+}
+DEV void act_ld8(const bf16_t* p, float v[8]) {
+  const uint4 a = *(const uint4*)p;
+  const uint32_t w4[4] = {a.x, a.y, a.z, a.w};
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    v[2 * i] = __uint_as_float(w4[i] << 16);
+    v[2 * i + 1] = __uint_as_float(w4[i] & 0xffff0000u);
+  }
+}
+
+// V8 = false: thread s of a gate column holds k = s + TPC i (i < KMAX), one
+// element per load.  V8 = true (din, H, ldx, ldw multiples of 8, operands
+// 16-byte aligned): it holds the 8-element chunks c = s + TPC i (i < KMAX)
+// of k, one or two 16-byte loads per chunk.
+template <typename TW, int U, int KMAX, bool V8>
 __global__ void __launch_bounds__(256) lstm_act_layer_kernel(const float* __restrict__ X, int ldx, int din,
                                                              const float* __restrict__ HM,
                                                              const float* __restrict__ CM, const TW* __restrict__ W,
@@ -75,21 +95,27 @@ __global__ void __launch_bounds__(256) lstm_act_layer_kernel(const float* __rest
                                                              const int32_t* __restrict__ active) {
   extern __shared__ float gates[];  // [B][4U]
   constexpr int TPC = 64 / U;
+  constexpr int E = V8 ? 8 : 1;  // elements per chunk
   constexpr bool BF = sizeof(TW) == 2;
-  const int K = din + H;
+  const int K = din + H, KC = K / E;  // chunks (V8: K % 8 == 0)
   const int j0 = blockIdx.x * U;
   const int col = threadIdx.x / TPC, s = threadIdx.x % TPC;
   const int q = col / U, uc = col % U;
-  float w[KMAX];
+  float w[KMAX][E];
   {
     const TW* wr = W + (size_t)(q * H + j0 + uc) * ldw;
-    // unconditional loads (k >= K re-reads element K-1, then zeroed): a load
-    // inside a branch would wait for its own result before the next is issued
+    // unconditional loads (a chunk past K re-reads the last one, then zeroed):
+    // a load inside a branch would wait for its own result before the next is issued
 #pragma unroll
     for (int i = 0; i < KMAX; ++i) {
-      const int k = s + TPC * i;
-      const float t = ldf(wr + min(k, K - 1));
-      w[i] = k < K ? t : 0.f;
+      const int c = s + TPC * i;
+      if constexpr (V8) {
+        act_ld8(wr + (size_t)min(c, KC - 1) * 8, w[i]);
+      } else {
+        w[i][0] = ldf(wr + min(c, K - 1));
+      }
+#pragma unroll
+      for (int e = 0; e < E; ++e) w[i][e] = c < KC ? w[i][e] : 0.f;
     }
   }
   // pointwise operands of this thread's first item, loaded before the products
@@ -103,28 +129,35 @@ __global__ void __launch_bounds__(256) lstm_act_layer_kernel(const float* __rest
   // every load unconditional (k >= K reads a valid element that meets a zero
   // weight), so all of them are in flight together; row r + 1 is loaded while
   // row r is reduced
-  auto load_row = [&](int r, float (&v)[KMAX]) {
+  auto load_row = [&](int r, float (&v)[KMAX][E]) {
     const float* xr = X + (size_t)r * ldx;
     const float* hr = HM + (size_t)r * H;
 #pragma unroll
     for (int i = 0; i < KMAX; ++i) {
-      const int k = s + TPC * i;
-      const float* p = k < din ? xr + k : hr + min(k - din, H - 1);
-      v[i] = *p;
+      const int k = min(s + TPC * i, KC - 1) * E;
+      const float* p = k < din ? xr + k : hr + min(k - din, H - E);
+      if constexpr (V8)
+        act_ld8(p, v[i]);
+      else
+        v[i][0] = *p;
     }
   };
-  float xv[KMAX], xn[KMAX];
+  float xv[KMAX][E], xn[KMAX][E];
   load_row(0, xv);
   for (int r = 0; r < B; ++r) {
     load_row(min(r + 1, B - 1), xn);
     float acc = 0.f;
 #pragma unroll
-    for (int i = 0; i < KMAX; ++i) acc = fmaf(op_round(xv[i], BF), w[i], acc);
+    for (int i = 0; i < KMAX; ++i)
+#pragma unroll
+      for (int e = 0; e < E; ++e) acc = fmaf(op_round(xv[i][e], BF), w[i][e], acc);
 #pragma unroll
     for (int o = TPC / 2; o > 0; o >>= 1) acc += __shfl_xor(acc, o, kWave);
     if (s == 0) gates[r * 4 * U + col] = acc;
 #pragma unroll
-    for (int i = 0; i < KMAX; ++i) xv[i] = xn[i];
+    for (int i = 0; i < KMAX; ++i)
+#pragma unroll
+      for (int e = 0; e < E; ++e) xv[i][e] = xn[i][e];
   }
   __syncthreads();
   // rows >= *active (a device count, read when the kernel runs) keep their state
@@ -148,12 +181,34 @@ int act_units(int H) { return H >= 512 ? 2 : 1; }
 template <typename TW, int U>
 const void* act_kernel_k(int kmax) {
   switch (kmax) {
-    case 8: return (const void*)lstm_act_layer_kernel<TW, U, 8>;
-    case 16: return (const void*)lstm_act_layer_kernel<TW, U, 16>;
-    case 32: return (const void*)lstm_act_layer_kernel<TW, U, 32>;
-    case 64: return (const void*)lstm_act_layer_kernel<TW, U, 64>;
+    case 8: return (const void*)lstm_act_layer_kernel<TW, U, 8, false>;
+    case 16: return (const void*)lstm_act_layer_kernel<TW, U, 16, false>;
+    case 32: return (const void*)lstm_act_layer_kernel<TW, U, 32, false>;
+    case 64: return (const void*)lstm_act_layer_kernel<TW, U, 64, false>;
     default: return nullptr;
   }
+}
+// chunks of 8 per thread
+template <typename TW, int U>
+const void* act_kernel_v8(int kc) {
+  switch (kc) {
+    case 1: return (const void*)lstm_act_layer_kernel<TW, U, 1, true>;
+    case 2: return (const void*)lstm_act_layer_kernel<TW, U, 2, true>;
+    case 3: return (const void*)lstm_act_layer_kernel<TW, U, 3, true>;
+    case 4: return (const void*)lstm_act_layer_kernel<TW, U, 4, true>;
+    case 5: return (const void*)lstm_act_layer_kernel<TW, U, 5, true>;
+    case 6: return (const void*)lstm_act_layer_kernel<TW, U, 6, true>;
+    case 8: return (const void*)lstm_act_layer_kernel<TW, U, 8, true>;
+    default: return nullptr;
+  }
+}
+int v8_chunks(int K, int U) {
+  const int kc = cdiv(K / 8, 64 / U);
+  return kc <= 6 ? kc : kc <= 8 ? 8 : 0;
+}
+bool v8_ok(const float* X, int ldx, int din, const float* HM, const void* W, int ldw, int H) {
+  return din % 8 == 0 && H % 8 == 0 && ldx % 8 == 0 && ldw % 8 == 0 && ((uintptr_t)X & 15) == 0 &&
+         ((uintptr_t)HM & 15) == 0 && ((uintptr_t)W & 15) == 0;
 }
 
 }  // namespace
@@ -179,11 +234,17 @@ void launch_lstm_act_layer(int prec, const float* X, int ldx, int din, const flo
                            const void* W, int ldw, const float* bias, int B, int H, float* h_out, float* c_out,
                            const int32_t* active, hipStream_t s) {
   const int U = act_units(H);
-  const int kpt = cdiv(din + H, 64 / U);
-  const int kmax = kpt <= 8 ? 8 : kpt <= 16 ? 16 : kpt <= 32 ? 32 : 64;
   const void* k = nullptr;
-  if (prec == 1) k = U == 2 ? act_kernel_k<bf16_t, 2>(kmax) : act_kernel_k<bf16_t, 1>(kmax);
-  else k = U == 2 ? act_kernel_k<float, 2>(kmax) : act_kernel_k<float, 1>(kmax);
+  const int kc = v8_chunks(din + H, U);
+  if (kc && v8_ok(X, ldx, din, HM, W, ldw, H)) {
+    if (prec == 1) k = U == 2 ? act_kernel_v8<bf16_t, 2>(kc) : act_kernel_v8<bf16_t, 1>(kc);
+    else k = U == 2 ? act_kernel_v8<float, 2>(kc) : act_kernel_v8<float, 1>(kc);
+  } else {
+    const int kpt = cdiv(din + H, 64 / U);
+    const int kmax = kpt <= 8 ? 8 : kpt <= 16 ? 16 : kpt <= 32 ? 32 : 64;
+    if (prec == 1) k = U == 2 ? act_kernel_k<bf16_t, 2>(kmax) : act_kernel_k<bf16_t, 1>(kmax);
+    else k = U == 2 ? act_kernel_k<float, 2>(kmax) : act_kernel_k<float, 1>(kmax);
+  }
   const size_t shmem = (size_t)B * 4 * U * sizeof(float);
   void* args[] = {(void*)&X, (void*)&ldx, (void*)&din, (void*)&HM, (void*)&CM, (void*)&W, (void*)&ldw,
                   (void*)&bias, (void*)&B, (void*)&H, (void*)&h_out, (void*)&c_out, (void*)&active};
