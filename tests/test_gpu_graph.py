@@ -89,3 +89,34 @@ def test_library_graph_on_a_side_stream_and_per_step(P):
     assert w.net.graph_count() == 1 + (T + 1)
     assert w.net.clear_graphs() == T + 2 and w.net.graph_count() == 0
     w.release()
+
+
+def test_library_graph_trim_mode_per_length_set(P):
+    """ppo_collect with trim (each step launched on its active rows only,
+    host lengths in the graph's key): a graph per set of lengths, each
+    launch bit for bit the eager trimmed loop, the same lengths again
+    reusing their graph."""
+    from paper_1911_00357_amd.worker import Worker
+    say("library act graphs, trim mode")
+    net, T, N = MINI_RESNET, 6, 4
+    w = Worker(net, "f32", T, N, R.init_params(net, 5, random_affine=True), device="cuda")
+    env = _env(net, T, N, 7, "cuda")
+    sets = ([6, 5, 3, 2], [6, 6, 1, 1], [6, 5, 3, 2])
+    for k, lens in enumerate(sets):
+        w.collect(env, lens, trim=True)           # eager
+        torch.cuda.synchronize()
+        ref = _snap(w)
+        for rep in range(2):
+            w.logp.zero_()
+            w.value.zero_()
+            w.collect(env, lens, trim=True, graph=True)
+            torch.cuda.synchronize()
+            got = _snap(w)
+            # rows past an env's length are not written in trim mode: compare the written ones
+            for t in range(T + 1):
+                rows = sum(1 for x in lens if x >= t)
+                assert torch.equal(got[1][t, :rows], ref[1][t, :rows]), (lens, rep, t)
+                assert torch.equal(got[2][t, :rows], ref[2][t, :rows]), (lens, rep, t)
+                assert torch.equal(got[0][t + 1, :rows], ref[0][t + 1, :rows]), (lens, rep, t)
+        assert w.net.graph_count() == min(k + 1, 2)   # the third set repeats the first
+    w.release()
