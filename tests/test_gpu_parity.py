@@ -123,7 +123,7 @@ def test_adam_static_scale_kept_on_skip(P):
 
 
 # ---------------------------------------------------------------- act
-def _act_case(P, net, dtype, B, seed, state_rows=0):
+def _act_case(P, net, dtype, B, seed, state_rows=0, mask=None, u=None):
     flat = R.init_params(net, seed, random_affine=True)
     g = np.random.default_rng(seed + 100)
     obs = g.random((B, net.in_ch, net.in_hw, net.in_hw), dtype=np.float32)
@@ -131,11 +131,13 @@ def _act_case(P, net, dtype, B, seed, state_rows=0):
         obs = R.round_bf16(obs)
     goal = g.standard_normal((B, 2)).astype(np.float32)
     prev = g.integers(0, net.num_actions, B).astype(np.int32)
-    mask = (g.random(B) > 0.3).astype(np.float32)
+    rmask = (g.random(B) > 0.3).astype(np.float32)
+    mask = rmask if mask is None else np.full(B, mask, np.float32)
     SR = state_rows or B
     h = (0.5 * g.standard_normal((net.lstm_layers, SR, net.hidden))).astype(np.float32)
     c = (0.5 * g.standard_normal((net.lstm_layers, SR, net.hidden))).astype(np.float32)
-    u = g.random(B).astype(np.float32)
+    ru = g.random(B).astype(np.float32)
+    u = ru if u is None else np.full(B, u, np.float32)
     n = P.Net(net, dtype)
     params = torch.tensor(flat, device=DEV)
     lp = P.cast_bf16(params) if dtype == "bf16" else None
@@ -190,6 +192,22 @@ def test_act_parity_small(P, name, net, dtype, B):
     say(f"act {name} {dtype} B={B}")
     out, ref = _act_case(P, net, dtype, B, seed=B)
     check_act(out, ref, dtype, B, name)
+
+
+@pytest.mark.parametrize("name,net,dtype,B,mask,u", [
+    ("tiny", TINY_NET, "f32", 1, 0.0, None),                     # one env, an episode start
+    ("mini_resnet", MINI_RESNET, "f32", 1, 1.0, 0.0),            # u = 0: the first action
+    ("mini_resnet", MINI_RESNET, "f32", 3, 0.0, 0.99999994),     # u just below 1: the last CDF step
+    ("tiny+", TINY_PLUS, "bf16", 2, 0.0, 0.0),
+])
+def test_act_parity_degenerate(P, name, net, dtype, B, mask, u):
+    """A single env, every row an episode start (the state zeroed, the
+    start-token embedding), and the sample's extreme uniforms."""
+    say(f"act degenerate {name} {dtype} B={B} mask={mask} u={u}")
+    out, ref = _act_case(P, net, dtype, B, seed=40 + B, mask=mask, u=u)
+    check_act(out, ref, dtype, B, name)
+    if u == 0.0:
+        assert (out["action"].cpu().numpy() == ref["action"]).all()
 
 
 @pytest.mark.parametrize("dtype", ["f32", "bf16"])
@@ -421,6 +439,8 @@ def check_loss(net, dtype, c, tag):
     ("tiny_ragged", TINY_NET, 9, 4, [3, 0, 2], [9, 4, 7, 2]),
     ("tiny+", TINY_PLUS, 6, 3, [0, 2], [6, 5, 3]),
     ("mini_resnet", MINI_RESNET, 5, 3, [2, 1, 0], [5, 3, 4]),
+    ("tiny_one_frame", TINY_NET, 5, 3, [1], [5, 1, 3]),          # one env of length 1: a single frame
+    ("tiny_one_env", TINY_NET, 4, 1, [0], None),
 ])
 def test_loss_backward_parity_f32(P, name, net, T, N, envs, lengths):
     say(f"loss f32 {name}")
