@@ -460,6 +460,44 @@ void unit_fwd(const Ctx& c, int ui, const float* x, const float* res, bool relu,
                     c.at<float4>(c.w->gpart), u.S, c.s);
 }
 
+// A bottleneck's last unit and its projection shortcut in a call that keeps no
+// outputs (act, encode): both products deferred (their split-K partials in the
+// two halves of the split-K region, group-major), then one GroupNorm launch
+// that normalises both and adds the shortcut before the ReLU; the shortcut's
+// map is not stored.  Same values as unit_fwd of ds, then of c3 with that residual.
+bool pair_fwd_ok(const Ctx& c, int ui, int di) {
+  const Unit &u = c.n->units[ui], &d = c.n->units[di];
+  return !c.keep_u && act_fused_forms() && u.groups == 1 && d.groups == 1 && u.Cout == d.Cout &&
+         u.Hout == d.Hout && u.Wout == d.Wout && gn_one_launch(c, u);
+}
+
+void unit_pair_fwd(const Ctx& c, int ui, const float* x, int di, const float* xd, float* out) {
+  const Unit &u = c.n->units[ui], &ud = c.n->units[di];
+  const int P = u.Hout * u.Wout, G = c.n->d.gn_groups;
+  const size_t half = kSplitKBytes / 2;
+  float* part_d = (float*)((char*)c.splitk() + half);
+  float *y = c.at(c.w->u[ui]), *yd = c.at(c.w->u[di]);
+  auto act_epi = [&](float* dst) {
+    Epi e = epi(dst, u.Cout);
+    e.act = 1;
+    e.gm_p = P;
+    e.gm_cg = u.Cout / G;
+    return e;
+  };
+  int sd, s3;
+  {
+    TimerScope ts(c.n, di, 0);
+    sd = gemm_conv_fwd(c.n->prec, geo(ud, c.F), xd, c.wt(ud.w), act_epi(yd), half, part_d, c.s, true);
+  }
+  {
+    TimerScope ts(c.n, ui, 0);
+    s3 = gemm_conv_fwd(c.n->prec, geo(u, c.F), x, c.wt(u.w), act_epi(y), half, c.splitk(), c.s, true);
+  }
+  const GnSecond sec{sd > 1 ? part_d : yd, sd, 1, c.pf(ud.g), c.pf(ud.b), c.at<float2>(c.w->st[di])};
+  launch_gn_fused(s3 > 1 ? c.splitk() : y, s3, (size_t)c.F * P * u.Cout, nullptr, c.F, P, u.Cout, G, kGnEps,
+                  c.pf(u.g), c.pf(u.b), nullptr, 1, out, 0, c.at<float2>(c.w->st[ui]), c.s, 1, nullptr, 0, 0, &sec);
+}
+
 // Encoder forward over c.F frames already in x0; returns the flat features
 // (channel-major per frame, i.e. [F][flat]).
 const float* encoder_fwd(const Ctx& c) {
@@ -486,6 +524,11 @@ const float* encoder_fwd(const Ctx& c) {
     const Block& b = n->blocks[bi];
     unit_fwd(c, b.c1, x, nullptr, true, c.at(c.w->a[b.c1]), false);
     unit_fwd(c, b.c2, c.at(c.w->a[b.c1]), nullptr, true, c.at(c.w->a[b.c2]), false);
+    if (b.ds >= 0 && b.R == 0 && pair_fwd_ok(c, b.c3, b.ds)) {
+      unit_pair_fwd(c, b.c3, c.at(c.w->a[b.c2]), b.ds, x, c.at(c.w->a[b.c3]));
+      x = c.at(c.w->a[b.c3]);
+      continue;
+    }
     const float* res = x;
     if (b.ds >= 0) {
       unit_fwd(c, b.ds, x, nullptr, false, c.at(c.w->a[b.ds]), false);

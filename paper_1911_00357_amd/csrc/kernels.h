@@ -136,12 +136,21 @@ int gn_fused_npt(int P, int Cg);
 // src_gm: the input (or its split-K partials) is group-major (Epi::gm_p).
 // pool_out: instead of `out`, write the 3x3 / 2 (pad 1) max pool of the
 // normalised H x W map (NHWC, ceil(H/2) x ceil(W/2)); needs gn_pool_fits.
+// second: a GroupNorm of the same shape (its input or split-K partials, own
+// affine parameters and statistics, no ReLU) whose output is the residual
+// (res must then be null): a projection shortcut normalised in the same launch.
 constexpr long kGnPoolLds = 64 * 1024;
+struct GnSecond {
+  const float* src;
+  int nsplit, src_gm;
+  const float *gamma, *beta;
+  float2* stats;
+};
 bool gn_pool_fits(int P, int Cg);
 void launch_gn_fused(const float* src, int nsplit, size_t zstride, float* u_out, int B, int P, int C, int G,
                      float eps, const float* gamma, const float* beta, const float* res, int relu, float* out,
                      int out_chw, float2* stats, hipStream_t s, int src_gm = 0, float* pool_out = nullptr,
-                     int H = 0, int W = 0);
+                     int H = 0, int W = 0, const GnSecond* second = nullptr);
 void launch_gnb_fused(const float* dout, const float* outm, int chw, const float* y, int B, int P, int C, int G,
                       const float2* stats, const float* gamma, float* dy, float* dres, float* dgamma,
                       float* dbeta, float2* bpart, hipStream_t s);

@@ -521,8 +521,13 @@ __global__ void __launch_bounds__(NT) gn_fused_kernel(const float* __restrict__ 
                                                        const float* __restrict__ res, int relu,
                                                        float* __restrict__ out, int out_chw,
                                                        float2* __restrict__ stats, int src_gm,
-                                                       float* __restrict__ pool_out, int H, int W) {
+                                                       float* __restrict__ pool_out, int H, int W,
+                                                       const float* __restrict__ src2, int nsplit2, int src2_gm,
+                                                       const float* __restrict__ gamma2,
+                                                       const float* __restrict__ beta2,
+                                                       float2* __restrict__ stats2) {
   __shared__ float red[NT / 64];
+  __shared__ float2 red2[NT / 64];
   extern __shared__ float s_slab[];  // pool_out: the normalised slab [p][cc] (P Cg floats)
   const int b = blockIdx.x / G, g = blockIdx.x - b * G;
   const int Cg = C / G, n = P * Cg;
@@ -563,12 +568,58 @@ __global__ void __launch_bounds__(NT) gn_fused_kernel(const float* __restrict__ 
     if (u_out && p0 + j * pstep < P) u_out[base + j * jstr] = x[j];
     s += x[j];
   }
-  const float mean = block_sum<NT>(s, red) / n;
-  float q = 0.f;
+  float mean, var;
+  if (src2) {
+    // a second GroupNorm of the same shape (a projection shortcut) whose
+    // output is this one's residual: its partials summed, its statistics and
+    // apply taken with the same per-thread sums and reductions as a launch of
+    // its own, so the residual is that launch's output bit for bit
+    const size_t sbase2 = src2_gm ? (size_t)blockIdx.x * n + threadIdx.x : base;
+    const size_t sjstr2 = src2_gm ? (size_t)NT : jstr;
+    float x2[NPT];
 #pragma unroll
-  for (int j = 0; j < NPT; ++j)
-    if (p0 + j * pstep < P) q += (x[j] - mean) * (x[j] - mean);
-  const float var = block_sum<NT>(q, red) / n;
+    for (int j = 0; j < NPT; ++j) x2[j] = 0.f;
+    for (int z0 = 0; z0 < nsplit2; z0 += ZB) {
+      float y[ZB][NPT];
+#pragma unroll
+      for (int q = 0; q < ZB; ++q)
+#pragma unroll
+        for (int j = 0; j < NPT; ++j)
+          y[q][j] = (z0 + q < nsplit2 && p0 + j * pstep < P) ? src2[(size_t)(z0 + q) * zstride + sbase2 + j * sjstr2]
+                                                               : 0.f;
+#pragma unroll
+      for (int q = 0; q < ZB; ++q)
+#pragma unroll
+        for (int j = 0; j < NPT; ++j) x2[j] += y[q][j];
+    }
+    float s2 = 0.f;
+#pragma unroll
+    for (int j = 0; j < NPT; ++j) s2 += x2[j];
+    const float2 m12 = block_sum2<NT>(s, s2, red2);
+    const float mean1 = m12.x / n, mean2 = m12.y / n;
+    float q1 = 0.f, q2 = 0.f;
+#pragma unroll
+    for (int j = 0; j < NPT; ++j)
+      if (p0 + j * pstep < P) {
+        q1 += (x[j] - mean1) * (x[j] - mean1);
+        q2 += (x2[j] - mean2) * (x2[j] - mean2);
+      }
+    const float2 v12 = block_sum2<NT>(q1, q2, red2);
+    const float rstd2 = 1.0f / sqrtf(v12.y / n + eps);
+    if (threadIdx.x == 0) stats2[blockIdx.x] = make_float2(mean2, rstd2);
+    const float ga2 = gamma2[c] * rstd2, be2 = beta2[c];
+#pragma unroll
+    for (int j = 0; j < NPT; ++j) rv[j] = (x2[j] - mean2) * ga2 + be2 + 0.f;
+    mean = mean1;       // this GroupNorm's statistics from the same sums as a launch of its own
+    var = v12.x / n;
+  } else {
+    mean = block_sum<NT>(s, red) / n;
+    float q = 0.f;
+#pragma unroll
+    for (int j = 0; j < NPT; ++j)
+      if (p0 + j * pstep < P) q += (x[j] - mean) * (x[j] - mean);
+    var = block_sum<NT>(q, red) / n;
+  }
   const float rstd = 1.0f / sqrtf(var + eps);
   if (threadIdx.x == 0) stats[blockIdx.x] = make_float2(mean, rstd);
   const float ga = gm * rstd;
@@ -703,12 +754,19 @@ bool gn_pool_fits(int P, int Cg) { return (long)P * Cg * (long)sizeof(float) <= 
 
 void launch_gn_fused(const float* src, int nsplit, size_t zstride, float* u_out, int B, int P, int C, int G,
                      float eps, const float* gamma, const float* beta, const float* res, int relu, float* out,
-                     int out_chw, float2* stats, hipStream_t s, int src_gm, float* pool_out, int H, int W) {
+                     int out_chw, float2* stats, hipStream_t s, int src_gm, float* pool_out, int H, int W,
+                     const GnSecond* second) {
+  const float* src2 = second ? second->src : nullptr;
+  const int nsplit2 = second ? second->nsplit : 0, src2_gm = second ? second->src_gm : 0;
+  const float* gamma2 = second ? second->gamma : nullptr;
+  const float* beta2 = second ? second->beta : nullptr;
+  float2* stats2 = second ? second->stats : nullptr;
   const int npt = gn_fused_npt(P, C / G), nt = (long)P * (C / G) <= 256 * 2 ? 256 : 1024;
   const size_t lds = pool_out ? (size_t)P * (C / G) * sizeof(float) : 0;
 #define GN_CALL(K, T)                                                                                          \
   hipLaunchKernelGGL((gn_fused_kernel<K, T>), dim3(B * G), dim3(T), lds, s, src, nsplit, zstride, u_out, P, C, \
-                     G, eps, gamma, beta, res, relu, out, out_chw, stats, src_gm, pool_out, H, W)
+                     G, eps, gamma, beta, res, relu, out, out_chw, stats, src_gm, pool_out, H, W, src2, nsplit2,   \
+                     src2_gm, gamma2, beta2, stats2)
   GN_NPT_SWITCH(nt, npt, GN_CALL)
 #undef GN_CALL
 }
