@@ -513,7 +513,7 @@ DEV float block_sum(float v, float* red) {
   return t;
 }
 
-template <int NPT, int NT>
+template <int NPT, int NT, bool DUAL>
 __global__ void __launch_bounds__(NT) gn_fused_kernel(const float* __restrict__ src, int nsplit, size_t zstride,
                                                        float* __restrict__ u_out, int P, int C, int G, float eps,
                                                        const float* __restrict__ gamma,
@@ -527,7 +527,7 @@ __global__ void __launch_bounds__(NT) gn_fused_kernel(const float* __restrict__ 
                                                        const float* __restrict__ beta2,
                                                        float2* __restrict__ stats2) {
   __shared__ float red[NT / 64];
-  __shared__ float2 red2[NT / 64];
+  __shared__ float2 red2[DUAL ? NT / 64 : 1];
   extern __shared__ float s_slab[];  // pool_out: the normalised slab [p][cc] (P Cg floats)
   const int b = blockIdx.x / G, g = blockIdx.x - b * G;
   const int Cg = C / G, n = P * Cg;
@@ -569,7 +569,7 @@ __global__ void __launch_bounds__(NT) gn_fused_kernel(const float* __restrict__ 
     s += x[j];
   }
   float mean, var;
-  if (src2) {
+  if constexpr (DUAL) {
     // a second GroupNorm of the same shape (a projection shortcut) whose
     // output is this one's residual: its partials summed, its statistics and
     // apply taken with the same per-thread sums and reductions as a launch of
@@ -763,12 +763,20 @@ void launch_gn_fused(const float* src, int nsplit, size_t zstride, float* u_out,
   float2* stats2 = second ? second->stats : nullptr;
   const int npt = gn_fused_npt(P, C / G), nt = (long)P * (C / G) <= 256 * 2 ? 256 : 1024;
   const size_t lds = pool_out ? (size_t)P * (C / G) * sizeof(float) : 0;
-#define GN_CALL(K, T)                                                                                          \
-  hipLaunchKernelGGL((gn_fused_kernel<K, T>), dim3(B * G), dim3(T), lds, s, src, nsplit, zstride, u_out, P, C, \
-                     G, eps, gamma, beta, res, relu, out, out_chw, stats, src_gm, pool_out, H, W, src2, nsplit2,   \
+#define GN_CALL_D(K, T, D)                                                                                        \
+  hipLaunchKernelGGL((gn_fused_kernel<K, T, D>), dim3(B * G), dim3(T), lds, s, src, nsplit, zstride, u_out, P, C, \
+                     G, eps, gamma, beta, res, relu, out, out_chw, stats, src_gm, pool_out, H, W, src2, nsplit2,      \
                      src2_gm, gamma2, beta2, stats2)
-  GN_NPT_SWITCH(nt, npt, GN_CALL)
+#define GN_CALL(K, T) GN_CALL_D(K, T, false)
+#define GN_CALL2(K, T) GN_CALL_D(K, T, true)
+  if (second) {
+    GN_NPT_SWITCH(nt, npt, GN_CALL2)
+  } else {
+    GN_NPT_SWITCH(nt, npt, GN_CALL)
+  }
 #undef GN_CALL
+#undef GN_CALL2
+#undef GN_CALL_D
 }
 
 void launch_gnb_fused(const float* dout, const float* outm, int chw, const float* y, int B, int P, int C, int G,
