@@ -27,6 +27,14 @@
  *     thread-local message describing the last failure.
  *   - A ppo_net is a host-side descriptor.  It is not re-entrant across
  *     streams: calls that share one ppo_net must be ordered.
+ *   - Environment switches (read at each call; for tests and measurement):
+ *     DDPPO_GN_FUSED_MAX / DDPPO_GNB_FUSED_MAX (element count below which a
+ *     GroupNorm forward / backward runs as one launch per image and group;
+ *     4M / 1M), DDPPO_ACT_FUSED=0 (the act step's plain forms: convolution
+ *     outputs stored NHWC, a separate max pool and projection-shortcut
+ *     GroupNorm; the results are the same bit for bit), DDPPO_LSTM_SEQ=0 /
+ *     DDPPO_LSTM_SEQ2=0 (the learner's recurrence one step per launch / one
+ *     persistent launch per layer instead of both layers in one).
  *
  * Flat parameter format (float32 master, grads, Adam moments; the bfloat16
  * working copy has the same order).  Tensors in order:
