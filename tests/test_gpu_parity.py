@@ -10,10 +10,11 @@ import torch
 import oracle
 from oracle import params as OP, policy, ppo
 from synth import rollout as R
-from synth.configs import C0, C1, PPOCfg
+from synth.configs import C0, C1, SERESNEXT_NET, PPOCfg
 from tests.gpu_util import (DEV, assert_close, errs, flip_summary, oracle_minibatch, random_record, rel_err,
                             tensor_errors, to_device, validate_decisions)
-from tests.nets import MINI_RESNET, RESNET_64, RESNET_SMALLCORE, TINY_BIGCORE, TINY_CORE1024, TINY_NET, TINY_PLUS
+from tests.nets import (MINI_RESNET, MINI_SERESNEXT, RESNET_64, RESNET_SMALLCORE, TINY_BIGCORE, TINY_CORE1024,
+                        TINY_NET, TINY_PLUS)
 
 pytestmark = pytest.mark.gpu
 TOL = {"f32": 1e-4, "bf16": 2e-2}
@@ -576,7 +577,9 @@ def test_autotuned_act(P, dtype):
 
 
 @pytest.mark.parametrize("name,net,dtype,B", [("tiny", TINY_NET, "f32", 3), ("mini_resnet", MINI_RESNET, "bf16", 5),
-                                              ("paper", C1.net, "f32", 4), ("paper", C1.net, "bf16", 4)])
+                                              ("paper", C1.net, "f32", 4), ("paper", C1.net, "bf16", 4),
+                                              ("mini_seresnext", MINI_SERESNEXT, "bf16", 3),
+                                              ("seresnext_paper", SERESNEXT_NET, "f32", 4)])
 def test_act_fused_forms_are_bit_identical(P, monkeypatch, name, net, dtype, B):
     """The act step's convolutions store their outputs (or split-K partials)
     group-major for the GroupNorm that reads them, and the stem's GroupNorm
